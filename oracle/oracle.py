@@ -1,0 +1,331 @@
+"""ctypes wrapper of the FP64 CPU oracle (``telbm_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the
+benchmark's CPU-baseline leg are the only callers.  Nothing here imports the
+GPU library, and the GPU library never imports this module.
+
+Arrays are numpy float64.  Population arrays have shape ``(Q, nz, ny, nx)``
+(x fastest), fields ``(nz, ny, nx)``, vector fields ``(3, nz, ny, nx)``.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "telbm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+D2Q9, D3Q27 = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP, no fused multiply-add)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+                               "-std=c11", "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class OrcParams(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("nz", ctypes.c_int32),
+        ("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double),
+        ("T", ctypes.c_double), ("rho_g", ctypes.c_double), ("rho_l", ctypes.c_double),
+        ("C", ctypes.c_double),
+        ("lambda1", ctypes.c_double), ("lambda2", ctypes.c_double), ("lambda3", ctypes.c_double),
+        ("kappa1", ctypes.c_double), ("kappa2", ctypes.c_double), ("kappa3", ctypes.c_double),
+        ("chi", ctypes.c_double), ("nu", ctypes.c_double), ("mobility", ctypes.c_double),
+        ("tau_phi", ctypes.c_double),
+    ]
+
+
+@dataclasses.dataclass
+class Params:
+    """Physical and lattice parameters, with the paper's symbols."""
+    lattice: int = D2Q9
+    nx: int = 32
+    ny: int = 32
+    nz: int = 1
+    a: float = 0.037
+    b: float = 0.2
+    R: float = 1.0
+    T: float = 0.0
+    rho_g: float = 0.0
+    rho_l: float = 0.0
+    C: float = 0.0
+    lambda1: float = 0.6
+    lambda2: float = 0.140625
+    lambda3: float = 0.140625
+    kappa1: float = 1e-3
+    kappa2: float = 0.045
+    kappa3: float = 0.045
+    chi: float = 5.0
+    nu: float = 0.167
+    mobility: float = 0.5
+    tau_phi: float = 1.0
+
+    def c_struct(self) -> OrcParams:
+        return OrcParams(**{f: getattr(self, f) for f, _ in OrcParams._fields_})
+
+    @property
+    def Q(self) -> int:
+        return 9 if self.lattice == D2Q9 else 27
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        d, i32, vp, P = ctypes.c_double, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(OrcParams)
+        L.orc_lattice_info.argtypes = [ctypes.c_int, vp, vp]
+        L.orc_lattice_info.restype = ctypes.c_int
+        for name in ("orc_psi_eos", "orc_psi_prime"):
+            getattr(L, name).argtypes = [d, d, d, d, d, d]
+            getattr(L, name).restype = d
+        for name in ("orc_pressure", "orc_dpdrho"):
+            getattr(L, name).argtypes = [d, d, d, d, d]
+            getattr(L, name).restype = d
+        L.orc_critical_temperature.argtypes = [d, d, d, vp]
+        L.orc_critical_temperature.restype = d
+        L.orc_maxwell.argtypes = [d, d, d, d, vp]
+        L.orc_maxwell.restype = ctypes.c_int
+        L.orc_temperature_for_ratio.argtypes = [d, d, d, d, vp]
+        L.orc_temperature_for_ratio.restype = ctypes.c_int
+        L.orc_concentrations.argtypes = [P, d, d, vp, vp]
+        L.orc_gradient_coefficients.argtypes = [P, vp]
+        L.orc_mu_bulk.argtypes = [P, d, d, vp]
+        L.orc_laplacian.argtypes = [P, vp, vp]
+        L.orc_gradient.argtypes = [P, vp, vp]
+        L.orc_feq.argtypes = [ctypes.c_int, d, vp, vp]
+        L.orc_geq.argtypes = [ctypes.c_int, d, d, d, vp, vp]
+        L.orc_kbc_split.argtypes = [ctypes.c_int, vp, vp, vp]
+        L.orc_kbc_gamma.argtypes = [ctypes.c_int, d, vp, vp, vp]
+        L.orc_kbc_gamma.restype = d
+        L.orc_collide_node.argtypes = [ctypes.c_int, d, vp, vp, vp, vp]
+        L.orc_init.argtypes = [P, vp, vp, vp, vp, vp]
+        L.orc_init.restype = ctypes.c_int
+        L.orc_run.argtypes = [P, vp, vp, ctypes.c_int64, vp]
+        L.orc_run.restype = ctypes.c_int
+        L.orc_fields.argtypes = [P, vp, vp] + [vp] * 8
+        L.orc_fields.restype = ctypes.c_int
+        L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
+        _lib = L
+        del i32
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"], "oracle arrays must be C-contiguous float64"
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+# Lattice and thermodynamics
+# ---------------------------------------------------------------------------
+
+def lattice_info(lattice: int):
+    Q = 9 if lattice == D2Q9 else 27
+    c = np.zeros((Q, 3), dtype=np.int32)
+    w = np.zeros(Q, dtype=np.float64)
+    lib().orc_lattice_info(lattice, c.ctypes.data_as(ctypes.c_void_p), _ptr(w))
+    return c, w
+
+
+def psi_eos(a, b, R, T, C, rho):
+    return lib().orc_psi_eos(a, b, R, T, C, rho)
+
+
+def psi_prime(a, b, R, T, C, rho):
+    return lib().orc_psi_prime(a, b, R, T, C, rho)
+
+
+def pressure(a, b, R, T, rho):
+    return lib().orc_pressure(a, b, R, T, rho)
+
+
+def dpdrho(a, b, R, T, rho):
+    return lib().orc_dpdrho(a, b, R, T, rho)
+
+
+def critical_temperature(a=0.037, b=0.2, R=1.0):
+    rc = ctypes.c_double()
+    Tc = lib().orc_critical_temperature(a, b, R, ctypes.byref(rc))
+    return Tc, rc.value
+
+
+def maxwell(T, a=0.037, b=0.2, R=1.0):
+    """Returns (rho_g, rho_l, C, Psi0) or raises ValueError for T >= T_c."""
+    out = np.zeros(4)
+    if lib().orc_maxwell(a, b, R, T, _ptr(out)) != 0:
+        raise ValueError("T outside (0, T_c)")
+    return tuple(out)
+
+
+def temperature_for_ratio(ratio, a=0.037, b=0.2, R=1.0):
+    """Returns (T, rho_g, rho_l, C, Psi0) with rho_l / rho_g == ratio."""
+    out = np.zeros(5)
+    if lib().orc_temperature_for_ratio(a, b, R, ratio, _ptr(out)) != 0:
+        raise ValueError("ratio must exceed 1")
+    return tuple(out)
+
+
+def coexisting_params(ratio: float, **kw) -> Params:
+    """Params at the temperature whose Maxwell density ratio is ``ratio``."""
+    p = Params(**kw)
+    T, rg, rl, C, _ = temperature_for_ratio(ratio, p.a, p.b, p.R)
+    p.T, p.rho_g, p.rho_l, p.C = T, rg, rl, C
+    return p
+
+
+# ---------------------------------------------------------------------------
+# Free energy pieces
+# ---------------------------------------------------------------------------
+
+def concentrations(p: Params, rho, phi):
+    c1, c2 = ctypes.c_double(), ctypes.c_double()
+    lib().orc_concentrations(ctypes.byref(p.c_struct()), rho, phi, ctypes.byref(c1), ctypes.byref(c2))
+    return c1.value, c2.value
+
+
+def gradient_coefficients(p: Params):
+    out = np.zeros(3)
+    lib().orc_gradient_coefficients(ctypes.byref(p.c_struct()), _ptr(out))
+    return tuple(out)
+
+
+def mu_bulk(p: Params, rho, phi):
+    out = np.zeros(2)
+    lib().orc_mu_bulk(ctypes.byref(p.c_struct()), rho, phi, _ptr(out))
+    return tuple(out)
+
+
+def laplacian(p: Params, psi: np.ndarray) -> np.ndarray:
+    psi = np.ascontiguousarray(psi, dtype=np.float64).reshape(p.shape)
+    out = np.zeros_like(psi)
+    lib().orc_laplacian(ctypes.byref(p.c_struct()), _ptr(psi), _ptr(out))
+    return out
+
+
+def gradient(p: Params, psi: np.ndarray) -> np.ndarray:
+    psi = np.ascontiguousarray(psi, dtype=np.float64).reshape(p.shape)
+    out = np.zeros((3,) + p.shape)
+    lib().orc_gradient(ctypes.byref(p.c_struct()), _ptr(psi), _ptr(out))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Node-level collision pieces
+# ---------------------------------------------------------------------------
+
+def feq(lattice, rho, u):
+    Q = 9 if lattice == D2Q9 else 27
+    u = np.ascontiguousarray(np.resize(np.asarray(u, dtype=np.float64), 3))
+    out = np.zeros(Q)
+    lib().orc_feq(lattice, rho, _ptr(u), _ptr(out))
+    return out
+
+
+def geq(lattice, phi, mu_phi, Gamma, u):
+    Q = 9 if lattice == D2Q9 else 27
+    u = np.ascontiguousarray(np.resize(np.asarray(u, dtype=np.float64), 3))
+    out = np.zeros(Q)
+    lib().orc_geq(lattice, phi, mu_phi, Gamma, _ptr(u), _ptr(out))
+    return out
+
+
+def kbc_split(lattice, df):
+    df = np.ascontiguousarray(df, dtype=np.float64)
+    ds, dh = np.zeros_like(df), np.zeros_like(df)
+    lib().orc_kbc_split(lattice, _ptr(df), _ptr(ds), _ptr(dh))
+    return ds, dh
+
+
+def kbc_gamma(lattice, beta, feq_, ds, dh):
+    return lib().orc_kbc_gamma(lattice, beta, _ptr(np.ascontiguousarray(feq_)),
+                               _ptr(np.ascontiguousarray(ds)), _ptr(np.ascontiguousarray(dh)))
+
+
+def collide_node(lattice, beta, f, force=(0.0, 0.0, 0.0)):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    F = np.ascontiguousarray(np.resize(np.asarray(force, dtype=np.float64), 3))
+    out = np.zeros_like(f)
+    g = ctypes.c_double()
+    lib().orc_collide_node(lattice, beta, _ptr(f), _ptr(F), _ptr(out), ctypes.byref(g))
+    return out, g.value
+
+
+# ---------------------------------------------------------------------------
+# Whole lattice
+# ---------------------------------------------------------------------------
+
+class State:
+    """Post-streaming populations f, g of shape (Q, nz, ny, nx)."""
+
+    def __init__(self, p: Params, rho0, phi0, u0=None):
+        self.p = p
+        self.f = np.zeros((p.Q,) + p.shape)
+        self.g = np.zeros((p.Q,) + p.shape)
+        rho0 = np.ascontiguousarray(rho0, dtype=np.float64).reshape(p.shape)
+        phi0 = np.ascontiguousarray(phi0, dtype=np.float64).reshape(p.shape)
+        u = None
+        if u0 is not None:
+            u = np.zeros((3,) + p.shape)
+            u0 = np.asarray(u0, dtype=np.float64)
+            u[: u0.shape[0]] = u0.reshape((u0.shape[0],) + p.shape)
+        rc = lib().orc_init(ctypes.byref(p.c_struct()), _ptr(rho0), _ptr(phi0), _ptr(u),
+                            _ptr(self.f), _ptr(self.g))
+        if rc != 0:
+            raise MemoryError("oracle init failed")
+        self.steps = 0
+
+    def run(self, nsteps: int, diag: bool = False):
+        d = np.zeros((max(nsteps, 1), 10)) if diag else None
+        rc = lib().orc_run(ctypes.byref(self.p.c_struct()), _ptr(self.f), _ptr(self.g),
+                           int(nsteps), _ptr(d))
+        if rc != 0:
+            raise MemoryError("oracle run failed")
+        self.steps += nsteps
+        return d
+
+    def fields(self):
+        p = self.p
+        sh = p.shape
+        out = {k: np.zeros(sh) for k in ("rho", "phi", "c1", "c2", "mu_rho", "mu_phi")}
+        out["u"] = np.zeros((3,) + sh)
+        out["force"] = np.zeros((3,) + sh)
+        rc = lib().orc_fields(ctypes.byref(p.c_struct()), _ptr(self.f), _ptr(self.g),
+                              _ptr(out["rho"]), _ptr(out["phi"]), _ptr(out["u"]), _ptr(out["c1"]),
+                              _ptr(out["c2"]), _ptr(out["mu_rho"]), _ptr(out["mu_phi"]),
+                              _ptr(out["force"]))
+        if rc != 0:
+            raise MemoryError("oracle fields failed")
+        return out
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    lib().orc_set_num_threads(int(n))

@@ -1,0 +1,792 @@
+/*
+ * telbm_oracle.c -- plain FP64 CPU oracle for the ternary free-energy
+ * entropic lattice Boltzmann update of Woehrwag, Semprebon, Mazloomi,
+ * Karlin and Kusumaatmaja, "Ternary free-energy entropic lattice Boltzmann
+ * model with high density ratio" (arXiv:1710.07486).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg may load it.  It
+ * shares no code, header, table or constant with the GPU library.
+ *
+ * Every lattice-wide quantity is computed in its own full pass, in the order
+ * the method defines it: moments -> Laplacians -> chemical potentials ->
+ * gradients -> thermodynamic force -> entropic (KBC) collision with
+ * exact-difference forcing -> phase-field BGK -> streaming.  Arithmetic is
+ * IEEE double; build with -ffp-contract=off so that no multiply-add is fused.
+ *
+ * Readings of points the paper leaves to its (unavailable) supplement are
+ * marked "Reading:" at the place they are used.
+ *
+ * Parity status: every function here is pinned by the CPU test-suite against
+ * closed forms, invariants or independent numerics (see the docstrings of
+ * tests/test_oracle_*.py).  None is "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------- */
+/* Parameters.                                                               */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t lattice;              /* 0: D2Q9, 1: D3Q27                       */
+    int32_t nx, ny, nz;           /* periodic box; nz == 1 for D2Q9          */
+    double a, b, R, T;            /* Carnahan-Starling EOS, Eq. (4)          */
+    double rho_g, rho_l;          /* coexisting gas / liquid densities       */
+    double C;                     /* EOS constant C of Eq. (4)               */
+    double lambda1, lambda2, lambda3; /* bulk free energy, Eq. (2)           */
+    double kappa1, kappa2, kappa3;    /* interfacial free energy, Eq. (3)    */
+    double chi;                   /* scale of the phase field phi            */
+    double nu;                    /* kinematic viscosity eta/rho             */
+    double mobility;              /* M of the Cahn-Hilliard equation (7)     */
+    double tau_phi;               /* relaxation time of the phi populations  */
+} orc_params;
+
+/* ------------------------------------------------------------------------- */
+/* Lattice.  Directions are the tensor product of the D1Q3 set {0,+1,-1} per  */
+/* axis: index i = kx + 3 ky + 9 kz with k = 0,1,2 meaning c = 0,+1,-1.      */
+/* D2Q9 is the first nine of D3Q27 (kz = 0).  Weights are products of the    */
+/* D1Q3 weights 2/3 (c = 0) and 1/6 (c = +-1), which gives 4/9, 1/9, 1/36 in */
+/* 2D and 8/27, 2/27, 1/54, 1/216 in 3D.                                     */
+/* ------------------------------------------------------------------------- */
+
+static const int K2C[3] = {0, 1, -1};
+
+static int lattice_Q(int lattice) { return lattice == 0 ? 9 : 27; }
+static int lattice_D(int lattice) { return lattice == 0 ? 2 : 3; }
+
+static void direction(int i, int c[3])
+{
+    c[0] = K2C[i % 3];
+    c[1] = K2C[(i / 3) % 3];
+    c[2] = K2C[i / 9];
+}
+
+static double w1(int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+
+/* The D2Q9 weight is the product over two axes only. */
+static double weight_lat(int lattice, int i)
+{
+    int c[3];
+    direction(i, c);
+    if (lattice == 0) return w1(c[0]) * w1(c[1]);
+    return w1(c[0]) * w1(c[1]) * w1(c[2]);
+}
+
+int orc_lattice_info(int lattice, int32_t *c_out, double *w_out)
+{
+    int Q = lattice_Q(lattice);
+    for (int i = 0; i < Q; ++i) {
+        int c[3];
+        direction(i, c);
+        c_out[3 * i + 0] = c[0];
+        c_out[3 * i + 1] = c[1];
+        c_out[3 * i + 2] = c[2];
+        w_out[i] = weight_lat(lattice, i);
+    }
+    return Q;
+}
+
+static const double CS2 = 1.0 / 3.0;  /* lattice speed of sound squared */
+
+/* ------------------------------------------------------------------------- */
+/* Thermodynamics of the Carnahan-Starling EOS, Eq. (4).                     */
+/* ------------------------------------------------------------------------- */
+
+/* Psi_eos(rho) of Eq. (4) with the constant C. */
+double orc_psi_eos(double a, double b, double R, double T, double C, double rho)
+{
+    double br = b * rho;
+    return rho * (C - a * rho - 8.0 * R * T * (br - 6.0) / ((br - 4.0) * (br - 4.0))
+                  + R * T * log(rho));
+}
+
+/* d Psi_eos / d rho, differentiated term by term from Eq. (4):
+ *   C - 2 a rho + RT (ln rho + 1) - 8RT (b rho - 6)/(b rho - 4)^2
+ *     - 8 RT b rho (8 - b rho)/(b rho - 4)^3.                               */
+double orc_psi_prime(double a, double b, double R, double T, double C, double rho)
+{
+    double br = b * rho;
+    double d = br - 4.0;
+    return C - 2.0 * a * rho + R * T * (log(rho) + 1.0)
+           - 8.0 * R * T * (br - 6.0) / (d * d)
+           - 8.0 * R * T * br * (8.0 - br) / (d * d * d);
+}
+
+/* The EOS pressure p = rho Psi' - Psi, the relation stated after Eq. (3). */
+double orc_pressure(double a, double b, double R, double T, double rho)
+{
+    return rho * orc_psi_prime(a, b, R, T, 0.0, rho) - orc_psi_eos(a, b, R, T, 0.0, rho);
+}
+
+/* dp/drho = rho Psi''; Psi'' from differentiating Psi' once more. */
+static double psi_second(double a, double b, double R, double T, double rho)
+{
+    double br = b * rho;
+    double d = br - 4.0;
+    /* d/drho [-8RT (br-6)/d^2] = -8RT b (8 - br)/d^3                        */
+    /* d/drho [-8RT br (8-br)/d^3] = -8RT b [ (8 - 2 br) d - 3 br (8 - br) ]/d^4 */
+    double t1 = -8.0 * R * T * b * (8.0 - br) / (d * d * d);
+    double t2 = -8.0 * R * T * b * ((8.0 - 2.0 * br) * d - 3.0 * br * (8.0 - br)) / (d * d * d * d);
+    return -2.0 * a + R * T / rho + t1 + t2;
+}
+
+double orc_dpdrho(double a, double b, double R, double T, double rho)
+{
+    return rho * psi_second(a, b, R, T, rho);
+}
+
+/* Critical temperature: the spinodal condition dp/drho = 0 can be solved for
+ * T at each density; the critical point is the maximum of that curve.  With
+ * p = rho Psi' - Psi, dp/drho = rho Psi''(rho; T), and Psi'' is linear in T:
+ * Psi'' = -2a + T * q(rho), so T_spin(rho) = 2a / q(rho).  Golden-section
+ * search for its maximum on (0, 4/b).                                        */
+static double q_of_rho(double a, double b, double R, double rho)
+{
+    /* psi_second with a = 0 and T = 1 gives q(rho). */
+    return psi_second(0.0, b, R, 1.0, rho);
+    (void)a;
+}
+
+double orc_critical_temperature(double a, double b, double R, double *rho_c)
+{
+    double lo = 1e-6, hi = 4.0 / b - 1e-6;
+    const double gr = 0.5 * (sqrt(5.0) - 1.0);
+    double x1 = hi - gr * (hi - lo), x2 = lo + gr * (hi - lo);
+    double f1 = 2.0 * a / q_of_rho(a, b, R, x1), f2 = 2.0 * a / q_of_rho(a, b, R, x2);
+    for (int it = 0; it < 300; ++it) {
+        if (f1 < f2) {
+            lo = x1; x1 = x2; f1 = f2;
+            x2 = lo + gr * (hi - lo);
+            f2 = 2.0 * a / q_of_rho(a, b, R, x2);
+        } else {
+            hi = x2; x2 = x1; f2 = f1;
+            x1 = hi - gr * (hi - lo);
+            f1 = 2.0 * a / q_of_rho(a, b, R, x1);
+        }
+    }
+    double rc = 0.5 * (lo + hi);
+    if (rho_c) *rho_c = rc;
+    return 2.0 * a / q_of_rho(a, b, R, rc);
+}
+
+/* Bisection for p(rho) = P on an interval where p is monotonic increasing. */
+static double solve_p(double a, double b, double R, double T, double P, double lo, double hi)
+{
+    for (int it = 0; it < 400; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (orc_pressure(a, b, R, T, mid) < P) lo = mid; else hi = mid;
+        if (hi - lo <= 1e-17 * hi) break;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* Root of dp/drho on [lo, hi] where it changes sign. */
+static double solve_dp(double a, double b, double R, double T, double lo, double hi)
+{
+    double flo = orc_dpdrho(a, b, R, T, lo);
+    for (int it = 0; it < 400; ++it) {
+        double mid = 0.5 * (lo + hi);
+        double fm = orc_dpdrho(a, b, R, T, mid);
+        if ((fm > 0) == (flo > 0)) { lo = mid; flo = fm; } else hi = mid;
+        if (hi - lo <= 1e-17 * hi) break;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* Maxwell construction for the coexisting densities at temperature T: the two
+ * phases have equal pressure and equal chemical potential Psi' (the common
+ * tangent of Psi stated below Eq. (4)).  For a trial pressure P between the
+ * spinodal pressures, bisection gives the gas root and the liquid root of
+ * p = P; the chemical-potential difference is monotonic in P and is bisected
+ * to zero.  Then C = -Psi'_0(rho_g) (Psi'_0: Psi' with C = 0) so that
+ * Psi'(rho_g) = Psi'(rho_l) = 0, and Psi0 = Psi(rho_g) = Psi(rho_l), which with
+ * that C equals -p_coex.  Returns 0 on success, -1 if T >= T_c.
+ * out = {rho_g, rho_l, C, Psi0}.                                            */
+int orc_maxwell(double a, double b, double R, double T, double *out)
+{
+    double rc;
+    double Tc = orc_critical_temperature(a, b, R, &rc);
+    if (!(T > 0.0) || !(T < Tc)) return -1;
+    double rmax = 4.0 / b;
+    /* spinodals: dp/drho > 0 below rho_s1, < 0 between, > 0 above rho_s2 */
+    double s1 = solve_dp(a, b, R, T, 1e-12, rc);
+    double s2 = solve_dp(a, b, R, T, rc, rmax * (1.0 - 1e-12));
+    double pmax = orc_pressure(a, b, R, T, s1);
+    double pmin = orc_pressure(a, b, R, T, s2);
+    double Plo = pmin > 0.0 ? pmin : 0.0, Phi = pmax;
+    double rg = 0, rl = 0;
+    for (int it = 0; it < 300; ++it) {
+        double P = 0.5 * (Plo + Phi);
+        rg = solve_p(a, b, R, T, P, 1e-300, s1);
+        rl = solve_p(a, b, R, T, P, s2, rmax * (1.0 - 1e-15));
+        double dmu = orc_psi_prime(a, b, R, T, 0.0, rl) - orc_psi_prime(a, b, R, T, 0.0, rg);
+        /* along an isotherm d mu = dp / rho, so d(mu_l - mu_g)/dP =
+         * 1/rho_l - 1/rho_g < 0: a positive difference means P is too low */
+        if (dmu > 0) Plo = P; else Phi = P;
+        if (Phi - Plo <= 1e-17 * Phi) break;
+    }
+    double C = -orc_psi_prime(a, b, R, T, 0.0, rg);
+    out[0] = rg;
+    out[1] = rl;
+    out[2] = C;
+    out[3] = orc_psi_eos(a, b, R, T, C, rg);
+    return 0;
+}
+
+/* Temperature at which the Maxwell ratio rho_l / rho_g equals `ratio`
+ * (the ratio decreases monotonically as T rises to T_c).  Bisection in T.
+ * out = {T, rho_g, rho_l, C, Psi0}.                                         */
+int orc_temperature_for_ratio(double a, double b, double R, double ratio, double *out)
+{
+    if (!(ratio > 1.0)) return -1;
+    double Tc = orc_critical_temperature(a, b, R, NULL);
+    double lo = 0.05 * Tc, hi = Tc * (1.0 - 1e-9);
+    double m[4];
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (orc_maxwell(a, b, R, mid, m) != 0) { hi = mid; continue; }
+        if (m[1] / m[0] > ratio) lo = mid; else hi = mid;
+        if (hi - lo <= 1e-16 * hi) break;
+    }
+    out[0] = 0.5 * (lo + hi);
+    if (orc_maxwell(a, b, R, out[0], m) != 0) return -1;
+    out[1] = m[0]; out[2] = m[1]; out[3] = m[2]; out[4] = m[3];
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Free energy: concentrations, bulk energy and chemical potentials.         */
+/* ------------------------------------------------------------------------- */
+
+/* Concentrations of the two liquids from (rho, phi), as defined in the text
+ * below Fig. 1: C_l1 = [1 + phi/chi - (rho - rho_l)/(rho_g - rho_l)]/2 and
+ * C_l2 = [1 - phi/chi - (rho - rho_l)/(rho_g - rho_l)]/2.                     */
+void orc_concentrations(const orc_params *p, double rho, double phi, double *c1, double *c2)
+{
+    double cg = (rho - p->rho_l) / (p->rho_g - p->rho_l);
+    *c1 = 0.5 * (1.0 + phi / p->chi - cg);
+    *c2 = 0.5 * (1.0 - phi / p->chi - cg);
+}
+
+/* Coefficients of the interfacial energy rewritten in (rho, phi) (the f_I
+ * expansion after Eq. (3)): f_I = A (grad rho)^2 + B (grad phi)^2
+ * + D grad rho . grad phi.  out = {A, B, D}.                                 */
+void orc_gradient_coefficients(const orc_params *p, double *out)
+{
+    double dlt = p->rho_g - p->rho_l;
+    out[0] = 0.5 * p->kappa1 + (p->kappa2 + p->kappa3) / (8.0 * dlt * dlt);
+    out[1] = (p->kappa2 + p->kappa3) / (8.0 * p->chi * p->chi);
+    out[2] = (p->kappa3 - p->kappa2) / (4.0 * p->chi * dlt);
+}
+
+/* Half the derivative of the double well C^2 (1-C)^2 of Eq. (2). */
+static double dwell_half(double c) { return c * (1.0 - c) * (1.0 - 2.0 * c); }
+
+/* Bulk parts of mu_rho = dF/drho and mu_phi = dF/dphi (the definitions after
+ * Eq. (7)), from Eq. (2) with the chain rule through C_l1, C_l2:
+ *   mu_rho = (lambda1/2) Psi'(rho) - [lambda2 W(C1) + lambda3 W(C2)]/(2 (rho_g - rho_l))
+ *   mu_phi = [lambda2 W(C1) - lambda3 W(C2)]/(2 chi)
+ * with W(C) = C (1-C)(1-2C).  Reading: no clamping of the concentrations.   */
+void orc_mu_bulk(const orc_params *p, double rho, double phi, double *out)
+{
+    double c1, c2;
+    orc_concentrations(p, rho, phi, &c1, &c2);
+    double w1v = dwell_half(c1), w2v = dwell_half(c2);
+    double dlt = p->rho_g - p->rho_l;
+    out[0] = 0.5 * p->lambda1 * orc_psi_prime(p->a, p->b, p->R, p->T, p->C, rho)
+             - (p->lambda2 * w1v + p->lambda3 * w2v) / (2.0 * dlt);
+    out[1] = (p->lambda2 * w1v - p->lambda3 * w2v) / (2.0 * p->chi);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Lattice stencils (Reading: the isotropic stencils with the lattice        */
+/* weights; the paper does not state its discretisation).                    */
+/*   laplacian psi(x) = (2/cs2) sum_i w_i [psi(x + c_i) - psi(x)]            */
+/*   d_alpha psi(x)   = (1/cs2) sum_i w_i c_i,alpha psi(x + c_i)             */
+/* ------------------------------------------------------------------------- */
+
+static int64_t node_index(const orc_params *p, int64_t x, int64_t y, int64_t z)
+{
+    return (z * p->ny + y) * p->nx + x;
+}
+
+static int64_t wrap(int64_t v, int64_t n) { v %= n; return v < 0 ? v + n : v; }
+
+static int64_t neighbour(const orc_params *p, int64_t node, const int c[3])
+{
+    int64_t x = node % p->nx;
+    int64_t y = (node / p->nx) % p->ny;
+    int64_t z = node / ((int64_t)p->nx * p->ny);
+    return node_index(p, wrap(x + c[0], p->nx), wrap(y + c[1], p->ny), wrap(z + c[2], p->nz));
+}
+
+static int64_t num_nodes(const orc_params *p) { return (int64_t)p->nx * p->ny * p->nz; }
+
+void orc_laplacian(const orc_params *p, const double *psi, double *out)
+{
+    int Q = lattice_Q(p->lattice);
+    int64_t N = num_nodes(p);
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n) {
+        double s = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            int c[3];
+            direction(i, c);
+            s += weight_lat(p->lattice, i) * (psi[neighbour(p, n, c)] - psi[n]);
+        }
+        out[n] = (2.0 / CS2) * s;
+    }
+}
+
+/* out is [3][N]; component z stays 0 on D2Q9. */
+void orc_gradient(const orc_params *p, const double *psi, double *out)
+{
+    int Q = lattice_Q(p->lattice);
+    int64_t N = num_nodes(p);
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n) {
+        double s[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < Q; ++i) {
+            int c[3];
+            direction(i, c);
+            double v = weight_lat(p->lattice, i) * psi[neighbour(p, n, c)];
+            s[0] += v * c[0];
+            s[1] += v * c[1];
+            s[2] += v * c[2];
+        }
+        out[n] = s[0] / CS2;
+        out[N + n] = s[1] / CS2;
+        out[2 * N + n] = s[2] / CS2;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Equilibria.                                                               */
+/* ------------------------------------------------------------------------- */
+
+/* Reading: the entropic equilibrium of the entropic LBM the paper adopts, in
+ * its product form f_i = rho prod_alpha Psi_{c_i,alpha}(u_alpha) over the
+ * D1Q3 factors (S = sqrt(1 + 3 u^2)):
+ *   Psi_0 = (2/3)(2 - S), Psi_+ = (1/6)(2 - S)(2u + S)/(1 - u),
+ *   Psi_- = (1/6)(2 - S)(1 - u)/(2u + S).
+ * Defined for |u_alpha| < 1.                                                */
+static void d1q3_factors(double u, double psi[3])
+{
+    double S = sqrt(1.0 + 3.0 * u * u);
+    psi[0] = (2.0 / 3.0) * (2.0 - S);
+    psi[1] = (1.0 / 6.0) * (2.0 - S) * (2.0 * u + S) / (1.0 - u);
+    psi[2] = (1.0 / 6.0) * (2.0 - S) * (1.0 - u) / (2.0 * u + S);
+}
+
+void orc_feq(int lattice, double rho, const double *u, double *feq)
+{
+    int Q = lattice_Q(lattice);
+    double px[3], py[3], pz[3];
+    d1q3_factors(u[0], px);
+    d1q3_factors(u[1], py);
+    if (lattice == 1) d1q3_factors(u[2], pz);
+    for (int i = 0; i < Q; ++i) {
+        int kx = i % 3, ky = (i / 3) % 3, kz = i / 9;
+        double v = rho * px[kx] * py[ky];
+        if (lattice == 1) v *= pz[kz];
+        feq[i] = v;
+    }
+}
+
+/* Phase-field equilibrium of the standard free-energy BGK scheme for the
+ * Cahn-Hilliard equation (7):
+ *   geq_i = w_i [Gamma mu_phi / cs2 + phi c_i.u / cs2 + phi (c_i.u)^2/(2 cs2^2)
+ *                - phi u^2 / (2 cs2)]      (i != 0)
+ *   geq_0 = phi - sum_{i != 0} geq_i.
+ * Reading: u is the physical (half-force corrected) velocity.               */
+void orc_geq(int lattice, double phi, double mu_phi, double Gamma, const double *u, double *geq)
+{
+    int Q = lattice_Q(lattice);
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    double rest = 0.0;
+    for (int i = 1; i < Q; ++i) {
+        int c[3];
+        direction(i, c);
+        double cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+        geq[i] = weight_lat(lattice, i) * (Gamma * mu_phi / CS2 + phi * cu / CS2
+                                          + phi * cu * cu / (2.0 * CS2 * CS2)
+                                          - phi * uu / (2.0 * CS2));
+        rest += geq[i];
+    }
+    geq[0] = phi - rest;
+}
+
+/* ------------------------------------------------------------------------- */
+/* KBC entropic collision.                                                   */
+/* ------------------------------------------------------------------------- */
+
+/* Dual basis of the D1Q3 raw moments: for populations over c = (0,+1,-1),
+ * f(c) = sum_k M_k b_k(c) with M_k = sum_c f(c) c^k, where
+ * b_0 = (1, 0, 0), b_1 = (0, 1/2, -1/2) and b_2 = (-1, 1/2, 1/2) on
+ * c = (0, +1, -1); sum_c b_k(c) c^m = [k == m] for k, m in {0, 1, 2}.  The
+ * D2Q9 / D3Q27 basis is the tensor product over the axes.                  */
+static double b0(int c) { return c == 0 ? 1.0 : 0.0; }
+static double b1(int c) { return 0.5 * c; }
+static double b2(int c) { return c == 0 ? -1.0 : 0.5; }
+
+/* Split the non-equilibrium part df = f - feq into the shear part ds, which
+ * carries exactly the deviatoric second-order moments of df, and the rest
+ * dh = df - ds.  Reading: the shear subspace s of the KBC scheme is spanned by
+ * the traceless second moments (normal-stress differences and off-diagonal
+ * stresses); the trace and all higher moments belong to h.                  */
+void orc_kbc_split(int lattice, const double *df, double *ds, double *dh)
+{
+    int Q = lattice_Q(lattice);
+    int D = lattice_D(lattice);
+    double M[3][3] = {{0}};
+    for (int i = 0; i < Q; ++i) {
+        int c[3];
+        direction(i, c);
+        for (int a = 0; a < 3; ++a)
+            for (int bb = 0; bb < 3; ++bb) M[a][bb] += df[i] * c[a] * c[bb];
+    }
+    double tr = 0.0;
+    for (int a = 0; a < D; ++a) tr += M[a][a];
+    double dev[3];
+    for (int a = 0; a < D; ++a) dev[a] = M[a][a] - tr / D;
+    for (int i = 0; i < Q; ++i) {
+        int c[3];
+        direction(i, c);
+        double s;
+        if (D == 2) {
+            s = dev[0] * b2(c[0]) * b0(c[1])
+              + dev[1] * b0(c[0]) * b2(c[1])
+              + M[0][1] * b1(c[0]) * b1(c[1]);
+        } else {
+            s = dev[0] * b2(c[0]) * b0(c[1]) * b0(c[2])
+              + dev[1] * b0(c[0]) * b2(c[1]) * b0(c[2])
+              + dev[2] * b0(c[0]) * b0(c[1]) * b2(c[2])
+              + M[0][1] * b1(c[0]) * b1(c[1]) * b0(c[2])
+              + M[0][2] * b1(c[0]) * b0(c[1]) * b1(c[2])
+              + M[1][2] * b0(c[0]) * b1(c[1]) * b1(c[2]);
+        }
+        ds[i] = s;
+        dh[i] = df[i] - s;
+    }
+}
+
+/* Stabiliser gamma of the KBC collision f* = f - beta (2 ds + gamma dh):
+ * the minimiser of the quadratic entropy estimate of the post-collision
+ * state, gamma = 1/beta - (2 - 1/beta) <ds|dh>/<dh|dh> with the entropic
+ * scalar product <X|Y> = sum_i X_i Y_i / feq_i.  Reading: gamma = 2 (the
+ * LBGK value) when <dh|dh> vanishes.                                        */
+double orc_kbc_gamma(int lattice, double beta, const double *feq, const double *ds, const double *dh)
+{
+    int Q = lattice_Q(lattice);
+    double sh = 0.0, hh = 0.0;
+    for (int i = 0; i < Q; ++i) {
+        sh += ds[i] * dh[i] / feq[i];
+        hh += dh[i] * dh[i] / feq[i];
+    }
+    if (!(hh > 1e-300)) return 2.0;
+    return 1.0 / beta - (2.0 - 1.0 / beta) * sh / hh;
+}
+
+/* One node: KBC collision of f about feq(rho, u = j/rho), then the
+ * exact-difference forcing term feq(rho, u + F/rho) - feq(rho, u).
+ * fstar and gamma are outputs.                                              */
+void orc_collide_node(int lattice, double beta, const double *f, const double *force,
+                      double *fstar, double *gamma_out)
+{
+    int Q = lattice_Q(lattice);
+    double rho = 0.0, j[3] = {0, 0, 0};
+    for (int i = 0; i < Q; ++i) {
+        int c[3];
+        direction(i, c);
+        rho += f[i];
+        j[0] += f[i] * c[0];
+        j[1] += f[i] * c[1];
+        j[2] += f[i] * c[2];
+    }
+    double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+    double du[3] = {force[0] / rho, force[1] / rho, force[2] / rho};
+    if (lattice == 0) { u[2] = 0.0; du[2] = 0.0; }
+    double feq[27], feq2[27], df[27], ds[27], dh[27];
+    orc_feq(lattice, rho, u, feq);
+    for (int i = 0; i < Q; ++i) df[i] = f[i] - feq[i];
+    orc_kbc_split(lattice, df, ds, dh);
+    double gamma = orc_kbc_gamma(lattice, beta, feq, ds, dh);
+    double u2[3] = {u[0] + du[0], u[1] + du[1], u[2] + du[2]};
+    orc_feq(lattice, rho, u2, feq2);
+    for (int i = 0; i < Q; ++i)
+        fstar[i] = f[i] - beta * (2.0 * ds[i] + gamma * dh[i]) + (feq2[i] - feq[i]);
+    if (gamma_out) *gamma_out = gamma;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Whole-lattice fields and the time step.                                   */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    double *rho, *phi, *j, *lap_rho, *lap_phi, *mu_rho, *mu_phi;
+    double *grad_rho, *grad_mu_phi, *force;
+} orc_work;
+
+static int work_alloc(orc_work *w, int64_t N)
+{
+    memset(w, 0, sizeof(*w));
+    w->rho = calloc(N, sizeof(double));
+    w->phi = calloc(N, sizeof(double));
+    w->j = calloc(3 * N, sizeof(double));
+    w->lap_rho = calloc(N, sizeof(double));
+    w->lap_phi = calloc(N, sizeof(double));
+    w->mu_rho = calloc(N, sizeof(double));
+    w->mu_phi = calloc(N, sizeof(double));
+    w->grad_rho = calloc(3 * N, sizeof(double));
+    w->grad_mu_phi = calloc(3 * N, sizeof(double));
+    w->force = calloc(3 * N, sizeof(double));
+    return (w->rho && w->phi && w->j && w->lap_rho && w->lap_phi && w->mu_rho && w->mu_phi
+            && w->grad_rho && w->grad_mu_phi && w->force) ? 0 : -1;
+}
+
+static void work_free(orc_work *w)
+{
+    free(w->rho); free(w->phi); free(w->j); free(w->lap_rho); free(w->lap_phi);
+    free(w->mu_rho); free(w->mu_phi); free(w->grad_rho);
+    free(w->grad_mu_phi); free(w->force);
+}
+
+/* Chemical potentials with their gradient parts (from the f_I rewrite):
+ *   mu_rho = bulk - 2 A lap(rho) - D lap(phi)
+ *   mu_phi = bulk - 2 B lap(phi) - D lap(rho).                              */
+static void chemical_potentials(const orc_params *p, orc_work *w)
+{
+    int64_t N = num_nodes(p);
+    double abd[3];
+    orc_gradient_coefficients(p, abd);
+    orc_laplacian(p, w->rho, w->lap_rho);
+    orc_laplacian(p, w->phi, w->lap_phi);
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n) {
+        double mb[2];
+        orc_mu_bulk(p, w->rho[n], w->phi[n], mb);
+        w->mu_rho[n] = mb[0] - 2.0 * abd[0] * w->lap_rho[n] - abd[2] * w->lap_phi[n];
+        w->mu_phi[n] = mb[1] - 2.0 * abd[1] * w->lap_phi[n] - abd[2] * w->lap_rho[n];
+    }
+}
+
+/* Thermodynamic force on the fluid.  The pressure tensor enters through
+ * div P = rho grad mu_rho + phi grad mu_phi (stated after Eq. (7)).  The
+ * lattice already carries the ideal pressure cs2 rho, whose chemical
+ * potential is cs2 ln rho, so the force added is
+ *   F = cs2 grad rho - div P = -rho grad(mu_rho - cs2 ln rho) - phi grad mu_phi.
+ * Reading: the gradient is taken of the excess potential mu_rho - cs2 ln rho
+ * (the form that stays bounded per unit mass where the gas is thin); the
+ * split cs2 grad rho - rho grad mu_rho is identical in the continuum.
+ * grad_rho holds the excess potential's gradient.                           */
+static void thermodynamic_force(const orc_params *p, orc_work *w)
+{
+    int64_t N = num_nodes(p);
+    double *excess = w->lap_rho;   /* reuse: the Laplacian is no longer needed */
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n) excess[n] = w->mu_rho[n] - CS2 * log(w->rho[n]);
+    orc_gradient(p, excess, w->grad_rho);
+    orc_gradient(p, w->mu_phi, w->grad_mu_phi);
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n)
+        for (int a = 0; a < 3; ++a)
+            w->force[a * N + n] = -w->rho[n] * w->grad_rho[a * N + n]
+                                  - w->phi[n] * w->grad_mu_phi[a * N + n];
+}
+
+/* Zeroth and first moments of the (post-streaming) populations. */
+static void moments(const orc_params *p, const double *f, const double *g, orc_work *w)
+{
+    int Q = lattice_Q(p->lattice);
+    int64_t N = num_nodes(p);
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n) {
+        double r = 0.0, ph = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            int c[3];
+            direction(i, c);
+            double fi = f[(int64_t)i * N + n];
+            r += fi;
+            jx += fi * c[0];
+            jy += fi * c[1];
+            jz += fi * c[2];
+            ph += g[(int64_t)i * N + n];
+        }
+        w->rho[n] = r;
+        w->phi[n] = ph;
+        w->j[n] = jx;
+        w->j[N + n] = jy;
+        w->j[2 * N + n] = jz;
+    }
+}
+
+/* Derived constants: tau = 3 nu + 1/2 (so nu = cs2 (tau - 1/2)),
+ * beta = 1/(2 tau), and Gamma = M / (tau_phi - 1/2) so that the phase-field
+ * BGK recovers the mobility M of Eq. (7).                                    */
+static double beta_of(const orc_params *p) { return 1.0 / (2.0 * (3.0 * p->nu + 0.5)); }
+static double gamma_cap_of(const orc_params *p) { return p->mobility / (p->tau_phi - 0.5); }
+
+/* Initial populations.  Reading: f = feq(rho0, u0) and
+ * g = geq(phi0, mu_phi(rho0, phi0), u0).  u0 may be NULL (zero velocity).   */
+int orc_init(const orc_params *p, const double *rho0, const double *phi0, const double *u0,
+             double *f, double *g)
+{
+    int Q = lattice_Q(p->lattice);
+    int64_t N = num_nodes(p);
+    orc_work w;
+    if (work_alloc(&w, N)) { work_free(&w); return -1; }
+    memcpy(w.rho, rho0, N * sizeof(double));
+    memcpy(w.phi, phi0, N * sizeof(double));
+    chemical_potentials(p, &w);
+    double Gam = gamma_cap_of(p);
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n) {
+        double u[3] = {0, 0, 0}, fe[27], ge[27];
+        if (u0) { u[0] = u0[n]; u[1] = u0[N + n]; if (p->lattice == 1) u[2] = u0[2 * N + n]; }
+        orc_feq(p->lattice, rho0[n], u, fe);
+        orc_geq(p->lattice, phi0[n], w.mu_phi[n], Gam, u, ge);
+        for (int i = 0; i < Q; ++i) {
+            f[(int64_t)i * N + n] = fe[i];
+            g[(int64_t)i * N + n] = ge[i];
+        }
+    }
+    work_free(&w);
+    return 0;
+}
+
+/* Advance the post-streaming populations f, g (layout [Q][N]) by nsteps time
+ * steps.  If diag is not NULL it receives, per step, the totals before the
+ * step {sum rho, sum phi, sum j (3), sum F (3)} and the collision's
+ * {min gamma, max gamma}: 10 doubles per step.                               */
+int orc_run(const orc_params *p, double *f, double *g, int64_t nsteps, double *diag)
+{
+    int Q = lattice_Q(p->lattice);
+    int64_t N = num_nodes(p);
+    orc_work w;
+    double *fs = malloc((size_t)Q * N * sizeof(double));
+    double *gs = malloc((size_t)Q * N * sizeof(double));
+    double *gam = malloc((size_t)N * sizeof(double));
+    if (work_alloc(&w, N) || !fs || !gs || !gam) {
+        work_free(&w); free(fs); free(gs); free(gam);
+        return -1;
+    }
+    const double beta = beta_of(p);
+    const double Gam = gamma_cap_of(p);
+    const double tau_phi = p->tau_phi;
+
+    for (int64_t step = 0; step < nsteps; ++step) {
+        /* 1. rho, j, phi of the post-streaming populations */
+        moments(p, f, g, &w);
+        /* 2-3. Laplacians and chemical potentials */
+        chemical_potentials(p, &w);
+        /* 4. gradients and the thermodynamic force */
+        thermodynamic_force(p, &w);
+        /* 5-9. collisions, node by node */
+#pragma omp parallel for schedule(static)
+        for (int64_t n = 0; n < N; ++n) {
+            double fn[27], gn[27], fo[27], ge[27], F[3], up[3];
+            for (int i = 0; i < Q; ++i) {
+                fn[i] = f[(int64_t)i * N + n];
+                gn[i] = g[(int64_t)i * N + n];
+            }
+            F[0] = w.force[n]; F[1] = w.force[N + n]; F[2] = w.force[2 * N + n];
+            if (p->lattice == 0) F[2] = 0.0;
+            orc_collide_node(p->lattice, beta, fn, F, fo, &gam[n]);
+            double r = w.rho[n];
+            for (int a = 0; a < 3; ++a) up[a] = (w.j[a * N + n] + 0.5 * F[a]) / r;
+            if (p->lattice == 0) up[2] = 0.0;
+            orc_geq(p->lattice, w.phi[n], w.mu_phi[n], Gam, up, ge);
+            for (int i = 0; i < Q; ++i) {
+                fs[(int64_t)i * N + n] = fo[i];
+                gs[(int64_t)i * N + n] = gn[i] - (gn[i] - ge[i]) / tau_phi;
+            }
+        }
+        if (diag) {
+            double s[10] = {0, 0, 0, 0, 0, 0, 0, 0, INFINITY, -INFINITY};
+            for (int64_t n = 0; n < N; ++n) {
+                s[0] += w.rho[n];
+                s[1] += w.phi[n];
+                for (int a = 0; a < 3; ++a) {
+                    s[2 + a] += w.j[a * N + n];
+                    s[5 + a] += w.force[a * N + n];
+                }
+                if (gam[n] < s[8]) s[8] = gam[n];
+                if (gam[n] > s[9]) s[9] = gam[n];
+            }
+            memcpy(diag + 10 * step, s, sizeof(s));
+        }
+        /* 10. streaming: f(x + c_i, t + 1) = f*(x, t) */
+#pragma omp parallel for schedule(static)
+        for (int64_t n = 0; n < N; ++n) {
+            for (int i = 0; i < Q; ++i) {
+                int c[3];
+                direction(i, c);
+                int64_t m = neighbour(p, n, c);
+                f[(int64_t)i * N + m] = fs[(int64_t)i * N + n];
+                g[(int64_t)i * N + m] = gs[(int64_t)i * N + n];
+            }
+        }
+    }
+    work_free(&w);
+    free(fs); free(gs); free(gam);
+    return 0;
+}
+
+/* Macroscopic fields of the state held in f, g (post-streaming).  Any output
+ * pointer may be NULL.  u is the physical velocity u + F/(2 rho) ([3][N]).   */
+int orc_fields(const orc_params *p, const double *f, const double *g,
+               double *rho, double *phi, double *u, double *c1, double *c2,
+               double *mu_rho, double *mu_phi, double *force)
+{
+    int64_t N = num_nodes(p);
+    orc_work w;
+    if (work_alloc(&w, N)) { work_free(&w); return -1; }
+    moments(p, f, g, &w);
+    chemical_potentials(p, &w);
+    thermodynamic_force(p, &w);
+    for (int64_t n = 0; n < N; ++n) {
+        if (rho) rho[n] = w.rho[n];
+        if (phi) phi[n] = w.phi[n];
+        if (mu_rho) mu_rho[n] = w.mu_rho[n];
+        if (mu_phi) mu_phi[n] = w.mu_phi[n];
+        if (c1 || c2) {
+            double a1, a2;
+            orc_concentrations(p, w.rho[n], w.phi[n], &a1, &a2);
+            if (c1) c1[n] = a1;
+            if (c2) c2[n] = a2;
+        }
+        for (int a = 0; a < 3; ++a) {
+            double F = (p->lattice == 0 && a == 2) ? 0.0 : w.force[a * N + n];
+            if (u) u[a * N + n] = (p->lattice == 0 && a == 2) ? 0.0 : (w.j[a * N + n] + 0.5 * F) / w.rho[n];
+            if (force) force[a * N + n] = F;
+        }
+    }
+    work_free(&w);
+    return 0;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

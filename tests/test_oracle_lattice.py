@@ -1,0 +1,160 @@
+"""Pins of the oracle's whole time step against what the continuum equations
+(5)-(7) and the free energy (1)-(3) fix: conservation, momentum bookkeeping,
+exact fixed points, the Navier-Stokes shear-wave decay rate, the linearised
+Cahn-Hilliard growth rate, reflection symmetry, the flat liquid-liquid tanh
+profile and the Maxwell coexistence densities.
+"""
+import numpy as np
+import pytest
+
+import synth
+from synth import workloads as W
+
+
+def lens_state(orc, lattice=0, n=32, ratio=10.0, kappa=0.045, seed=0):
+    if lattice == 0:
+        w = W.lens(n, n, radius=n / 6, ratio=ratio, kappa=kappa, seed=seed)
+        u = None
+    else:
+        w = W.collision_3d(n, radius=n / 6, ratio=ratio, v_rel=0.02, kappa2=kappa, kappa3=kappa, seed=seed)
+    p = orc.coexisting_params(w.ratio, **w.physics())
+    rho, phi, u = W.fields(w, p.rho_g, p.rho_l)
+    return p, orc.State(p, rho, phi, u if lattice else None)
+
+
+@pytest.mark.parametrize("lattice,n,ratio", [(0, 48, 10.0), (0, 48, 1000.0), (1, 16, 10.0), (1, 16, 1000.0)])
+def test_mass_conservation_and_momentum_bookkeeping(orc, lattice, n, ratio):
+    p, st = lens_state(orc, lattice, n, ratio)
+    steps = 200 if lattice == 0 else 40
+    d = st.run(steps, diag=True)
+    mass, phit, j, F = d[:, 0], d[:, 1], d[:, 2:5], d[:, 5:8]
+    assert np.abs(mass / mass[0] - 1).max() < 1e-13
+    assert np.abs(phit - phit[0]).max() < 1e-13 * np.abs(mass[0])
+    # sum_x j^{n+1} - sum_x j^n = sum_x F^n (the force is not a divergence discretely)
+    jump = j[1:] - j[:-1]
+    assert np.abs(jump - F[:-1]).max() < 1e-12 * mass[0]
+    assert np.isfinite(d).all()
+
+
+def test_uniform_states_are_fixed_points(orc):
+    for lattice, shape in ((0, (1, 8, 10)), (1, (4, 5, 6))):
+        p = orc.coexisting_params(10.0, lattice=lattice, nx=shape[2], ny=shape[1], nz=shape[0])
+        for phi0 in (p.chi, -p.chi):
+            rho = np.full(shape, p.rho_l)
+            phi = np.full(shape, phi0)
+            u = np.zeros((3,) + shape)
+            u[0] = 0.05
+            u[1] = -0.03
+            st = orc.State(p, rho, phi, u[:2] if lattice == 0 else u)
+            f0, g0 = st.f.copy(), st.g.copy()
+            st.run(5)
+            assert np.abs(st.f - f0).max() < 1e-14 and np.abs(st.g - g0).max() < 1e-14
+
+
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_shear_wave_decay_rate(orc, lattice):
+    """u_x = U sin(2 pi y / L) decays as exp(-nu k^2 t) with nu = (tau - 1/2)/3,
+    Navier-Stokes (Eq. 6) at uniform density."""
+    L = 64
+    shape = (1, L, 4) if lattice == 0 else (2, L, 2)
+    nu = 0.1
+    p = orc.coexisting_params(10.0, lattice=lattice, nx=shape[2], ny=shape[1], nz=shape[0], nu=nu)
+    y = np.arange(L)[None, :, None] * np.ones(shape)
+    k = 2 * np.pi / L
+    U = 1e-4
+    u = np.zeros((3,) + shape)
+    u[0] = U * np.sin(k * y)
+    st = orc.State(p, np.full(shape, p.rho_l), np.full(shape, p.chi), u if lattice else u[:2])
+    st.run(50)  # let the initial (equilibrium-start) layer decay
+    a0 = np.sum(st.fields()["u"][0] * np.sin(k * y))
+    t = 300
+    st.run(t)
+    a1 = np.sum(st.fields()["u"][0] * np.sin(k * y))
+    rate = -np.log(a1 / a0) / t
+    assert abs(rate / (nu * k ** 2) - 1) < 1e-3
+
+
+def test_linear_cahn_hilliard_growth(orc):
+    """phi = eps cos(kx) at rho = rho_l, phi0 = 0 (C1 = C2 = 1/2, the spinodal
+    point of the double wells): the linearised Eq. (7) gives
+    d phi_k/dt = M s(k) [mu_b'(0) - 2 B s(k)] phi_k with s(k) = 2cos k - 2 and
+    mu_b'(0) = -(lambda2 + lambda3)/(8 chi^2)."""
+    nx = 128
+    p = orc.coexisting_params(10.0, lattice=0, nx=nx, ny=1, nz=1, kappa2=0.3, kappa3=0.3,
+                              lambda2=0.9375, lambda3=0.9375, mobility=0.05, tau_phi=1.0)
+    A, Bc, D = orc.gradient_coefficients(p)
+    x = np.arange(nx)[None, None, :].astype(float)
+    for m in (1, 2):
+        k = 2 * np.pi * m / nx
+        eps = 1e-6
+        st = orc.State(p, np.full((1, 1, nx), p.rho_l), eps * np.cos(k * x))
+        t = 400
+        a0 = np.sum(st.fields()["phi"] * np.cos(k * x))
+        st.run(t)
+        a1 = np.sum(st.fields()["phi"] * np.cos(k * x))
+        s = 2 * np.cos(k) - 2
+        mub = -(p.lambda2 + p.lambda3) / (8 * p.chi ** 2)
+        want = p.mobility * s * (mub - 2 * Bc * s)
+        got = np.log(a1 / a0) / t
+        assert abs(got / want - 1) < 1e-2
+
+
+def test_reflection_symmetry(orc):
+    """Mirroring the initial fields in x mirrors the solution and flips u_x."""
+    p, st = lens_state(orc, 0, 32, 10.0)
+    w = W.lens(32, 32, radius=32 / 6, ratio=10.0, kappa=0.045)
+    rho, phi, _ = W.fields(w, p.rho_g, p.rho_l)
+    rho2, phi2 = rho[..., ::-1].copy(), phi[..., ::-1].copy()
+    st2 = orc.State(p, rho2, phi2)
+    st.run(60)
+    st2.run(60)
+    a, b = st.fields(), st2.fields()
+    assert np.abs(a["rho"][..., ::-1] - b["rho"]).max() < 1e-12
+    assert np.abs(a["phi"][..., ::-1] - b["phi"]).max() < 1e-12
+    assert np.abs(a["u"][0][..., ::-1] + b["u"][0]).max() < 1e-12
+    assert np.abs(a["u"][1][..., ::-1] - b["u"][1]).max() < 1e-12
+
+
+def test_flat_liquid_liquid_interface(orc):
+    """With lambda2/kappa2 = lambda3/kappa3 the liquid-liquid interface is
+    rho = rho_l and phi = chi tanh(x / W), W = 2 sqrt(kappa/lambda) (continuum).
+    Checked at lambda = kappa / 2 (W = 2.83 lattice units), a width the lattice
+    resolves; the paper's lambda = 3.125 kappa gives W = 1.13."""
+    nx = 128
+    kap, lam = 0.2, 0.1
+    p = orc.coexisting_params(10.0, lattice=0, nx=nx, ny=1, nz=1, kappa2=kap, kappa3=kap,
+                              lambda2=lam, lambda3=lam)
+    x = np.arange(nx, dtype=float)
+    W0 = 2 * np.sqrt(kap / lam)
+    phi0 = p.chi * np.tanh((x - nx / 4) / 3.0) * np.tanh((3 * nx / 4 - x) / 3.0)
+    st = orc.State(p, np.full((1, 1, nx), p.rho_l), phi0.reshape(1, 1, nx))
+    st.run(3000)
+    f = st.fields()
+    assert np.abs(f["rho"] - p.rho_l).max() / p.rho_l < 3e-3
+    # interface position near nx/4 by linear interpolation of the zero of phi
+    ph = f["phi"][0, 0]
+    i = int(np.argmin(np.abs(ph[: nx // 2])))
+    j = i if ph[i] * ph[i + 1] <= 0 else i - 1
+    x0 = j - ph[j] / (ph[j + 1] - ph[j])
+    sel = slice(nx // 8, 3 * nx // 8)
+    prof = p.chi * np.tanh((x[sel] - x0) / W0)
+    assert np.abs(ph[sel] - prof).max() / p.chi < 2e-2
+
+
+def test_flat_liquid_gas_coexistence(orc):
+    """Bulk densities of a flat liquid-gas slab approach the Maxwell densities,
+    and more closely as the interface widens (kappa1 up)."""
+    nx = 160
+    errs = []
+    for k1 in (0.003, 0.03):
+        p = orc.coexisting_params(10.0, lattice=0, nx=nx, ny=1, nz=1, kappa1=k1, kappa2=0.1,
+                                  kappa3=0.1, lambda2=0.3125, lambda3=0.3125)
+        x = np.arange(nx, dtype=float)
+        c1 = 0.5 * (np.tanh((x - nx / 4) / 3.0) - np.tanh((x - 3 * nx / 4) / 3.0))
+        st = orc.State(p, (p.rho_g + (p.rho_l - p.rho_g) * c1).reshape(1, 1, nx), (p.chi * c1).reshape(1, 1, nx))
+        st.run(5000)
+        f = st.fields()
+        errs.append((f["rho"][0, 0, 0] / p.rho_g - 1, f["rho"][0, 0, nx // 2] / p.rho_l - 1))
+        assert np.abs(f["u"]).max() < 1e-3
+    assert abs(errs[1][1]) < 1e-2 and abs(errs[1][0]) < 3e-2
+    assert abs(errs[1][0]) < abs(errs[0][0]) and abs(errs[1][1]) < abs(errs[0][1])
