@@ -1,0 +1,191 @@
+/*
+ * telbm.h -- C ABI of the MI355X library for the ternary free-energy entropic
+ * lattice Boltzmann update of Woehrwag, Semprebon, Mazloomi, Karlin and
+ * Kusumaatmaja, "Ternary free-energy entropic lattice Boltzmann model with
+ * high density ratio" (arXiv:1710.07486).
+ *
+ * The calls follow the paper's statement of the problem: fix the free energy
+ * (Eqs. 1-4), initialise the density rho, order parameter phi and velocity v
+ * of Eqs. (5)-(7), advance N time steps, read the fields back.
+ *
+ * Conventions
+ *  - Fields are arrays of doubles laid out [nz][ny][nx] with x fastest.
+ *    Vector fields are three such arrays back to back (x, y, z components).
+ *  - "on_device" != 0 means the pointer is a device pointer on the current
+ *    HIP device; otherwise it is host memory.  The library copies; it never
+ *    keeps a caller's field pointer.
+ *  - Device memory: the caller allocates one arena of telbm_required_bytes()
+ *    (e.g. a torch uint8 tensor) and lends it to telbm_create(); the library
+ *    never allocates or frees device memory itself and never frees the arena.
+ *  - Work is enqueued on the stream set by telbm_set_stream (default: the
+ *    null stream).  telbm_step is asynchronous; telbm_read, telbm_diagnostics
+ *    and telbm_sync synchronise that stream.
+ *  - Every call returns TELBM_OK or an error code; no C++ exception crosses
+ *    the ABI.  telbm_last_error gives a message for the last failed call on a
+ *    handle.  Handles are not thread-safe; distinct handles are independent.
+ */
+#ifndef TELBM_H
+#define TELBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define TELBM_OK 0
+#define TELBM_ERR_INVAL 1     /* bad argument or parameter; nothing was enqueued  */
+#define TELBM_ERR_UNSTABLE 2  /* non-finite value, rho <= 0 or |u_alpha| >= 1       */
+#define TELBM_ERR_DEVICE 3    /* a HIP runtime call failed                          */
+#define TELBM_ERR_NOMEM 4     /* arena smaller than telbm_required_bytes            */
+
+/* Lattices: the same velocity set carries the density and the phase-field
+ * populations. */
+#define TELBM_D2Q9 0
+#define TELBM_D3Q27 1
+
+/* Storage precision of the populations. */
+#define TELBM_FP64 0
+#define TELBM_FP32_MIXED 1  /* FP32 populations stored as deviations from w_i rho_ref;
+                               FP64 for the equation-of-state chemical potential and
+                               for the entropic stabiliser ratio                     */
+
+/* Fields that telbm_read can return. */
+#define TELBM_FIELD_RHO 0    /* density rho                                         */
+#define TELBM_FIELD_PHI 1    /* phase field phi                                     */
+#define TELBM_FIELD_UX 2     /* physical velocity (j + F/2)/rho, x component        */
+#define TELBM_FIELD_UY 3
+#define TELBM_FIELD_UZ 4
+#define TELBM_FIELD_C1 5     /* liquid-1 concentration C_l1                         */
+#define TELBM_FIELD_C2 6     /* liquid-2 concentration C_l2                         */
+#define TELBM_FIELD_MU_RHO 7 /* chemical potential mu_rho = dF/drho                 */
+#define TELBM_FIELD_MU_PHI 8 /* chemical potential mu_phi = dF/dphi                 */
+#define TELBM_FIELD_FX 9     /* thermodynamic force density, x component            */
+#define TELBM_FIELD_FY 10
+#define TELBM_FIELD_FZ 11
+
+/* Parameters (plain data, copied by telbm_create).
+ *  a, b, R, T          Carnahan-Starling equation of state, Eq. (4).
+ *  rho_g, rho_l        coexisting gas/liquid densities; both 0 means "solve the
+ *                      Maxwell construction at T" (text after Eq. 4).
+ *  lambda1..3          bulk free energy weights, Eq. (2).
+ *  kappa1..3           interfacial free energy weights, Eq. (3).
+ *  chi                 scale of the phase field phi (definition of C_l1, C_l2).
+ *  nu                  kinematic viscosity eta/rho (uniform; tau = 3 nu + 1/2).
+ *  mobility            M of the Cahn-Hilliard equation (7).
+ *  tau_phi             relaxation time of the phase-field populations (> 1/2).
+ *  rho_ref             FP32_MIXED reference density (0 means rho_l).
+ *  diag_every          conservation/health diagnostics every this many steps
+ *                      (0 disables).
+ * Validation: 0 < T < T_c, rho_l > rho_g > 0, nu > 0, tau_phi > 1/2, chi != 0,
+ * sizes >= 1 (nz == 1 for D2Q9), nx*ny*nz < 2^40.                           */
+typedef struct telbm_params {
+    int32_t lattice;
+    int32_t precision;
+    int32_t nx, ny, nz;
+    int32_t reserved0;
+    double a, b, R, T;
+    double rho_g, rho_l;
+    double lambda1, lambda2, lambda3;
+    double kappa1, kappa2, kappa3;
+    double chi;
+    double nu;
+    double mobility;
+    double tau_phi;
+    double rho_ref;
+    uint32_t diag_every;
+    uint32_t reserved1;
+} telbm_params;
+
+/* Diagnostics of the state before step `step` (the last diagnosed step):
+ * totals of rho, phi and momentum j = sum_i f_i c_i; max |u_phys|; min rho;
+ * min/max of the entropic stabiliser gamma of that step's collision; count
+ * of nodes with a non-finite rho, phi or velocity. */
+typedef struct telbm_diag {
+    int64_t step;
+    double mass;
+    double phi_total;
+    double mom[3];
+    double max_u;
+    double min_rho;
+    double gamma_min;
+    double gamma_max;
+    int64_t nonfinite;
+} telbm_diag;
+
+typedef struct telbm_solver telbm_solver;
+
+/* Version string of the library build. */
+const char *telbm_version(void);
+
+/* Critical temperature of the Carnahan-Starling EOS (dp/drho = d2p/drho2 = 0).
+ * Writes T_c; returns TELBM_ERR_INVAL for a, b, R not positive. */
+int telbm_critical_temperature(double a, double b, double R, double *T_c);
+
+/* Maxwell construction at temperature T (the common tangent stated after
+ * Eq. 4): coexisting densities and the constants C, Psi0 that make
+ * Psi(rho_g) = Psi(rho_l) = Psi0 with Psi'(rho_g) = Psi'(rho_l) = 0.
+ * Host only, stateless.  TELBM_ERR_INVAL if T is not in (0, T_c). */
+int telbm_coexistence(double a, double b, double R, double T,
+                      double *rho_g, double *rho_l, double *C, double *Psi0);
+
+/* Temperature whose Maxwell ratio rho_l/rho_g equals `ratio` (> 1). */
+int telbm_temperature_for_ratio(double a, double b, double R, double ratio, double *T);
+
+/* Bytes of device arena telbm_create needs for these parameters. */
+int telbm_required_bytes(const telbm_params *p, size_t *bytes);
+
+/* Create a solver.  `device_arena` (device pointer, >= required bytes, 256-byte
+ * aligned) is borrowed for the solver's lifetime.  The state is undefined
+ * until telbm_init_fields. */
+int telbm_create(const telbm_params *p, void *device_arena, size_t bytes, telbm_solver **out);
+
+/* Enqueue all further work of this solver on `stream` (a hipStream_t). */
+int telbm_set_stream(telbm_solver *s, void *stream);
+
+/* Initialise the populations at equilibrium with the given fields (the
+ * entropic equilibrium for rho, u and the phase-field equilibrium for phi,
+ * with mu_phi evaluated from rho and phi).  rho and phi are required; u may
+ * be NULL for zero velocity, else 2 (D2Q9) or 3 (D3Q27) component arrays.
+ * Returns TELBM_ERR_UNSTABLE (state unchanged) if any rho <= 0, any value is
+ * non-finite or any |u_alpha| >= 1.  Resets the step counter. */
+int telbm_init_fields(telbm_solver *s, const double *rho, const double *phi, const double *u,
+                      int on_device);
+
+/* Advance n >= 0 time steps (asynchronous).  A diagnosed unstable state is
+ * reported by the next synchronising call. */
+int telbm_step(telbm_solver *s, int64_t n);
+
+/* Read one field of the current state into `out` (nx*ny*nz doubles). */
+int telbm_read(telbm_solver *s, int field, double *out, int on_device);
+
+/* Latest diagnostics (runs a diagnostic pass of the current state if none has
+ * been taken since the last step).  Synchronises.  Returns TELBM_ERR_UNSTABLE
+ * (with `out` filled) if the state is unstable. */
+int telbm_diagnostics(telbm_solver *s, telbm_diag *out);
+
+/* Wait for the solver's stream; reports pending instability. */
+int telbm_sync(telbm_solver *s);
+
+/* Steps taken since telbm_init_fields. */
+int telbm_step_count(const telbm_solver *s, int64_t *steps);
+
+/* Kernel-level timing: run n steps recording a HIP event pair around each
+ * kernel launch, and return the mean duration in milliseconds of each kernel
+ * kind (ms[k] for k < *kinds; names via telbm_kernel_name).  Synchronises. */
+int telbm_time_kernels(telbm_solver *s, int64_t n, double *ms, int *kinds);
+const char *telbm_kernel_name(const telbm_solver *s, int kind);
+
+/* Algorithmic bytes moved per lattice update: read and write of every f and
+ * g population once (2 * 2Q * bytes per population). */
+double telbm_algorithmic_bytes_per_update(const telbm_solver *s);
+
+int telbm_destroy(telbm_solver *s);
+const char *telbm_last_error(const telbm_solver *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TELBM_H */

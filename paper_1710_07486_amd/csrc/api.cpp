@@ -1,0 +1,497 @@
+// api.cpp -- the C ABI of include/telbm.h: parameter validation, arena
+// layout, state machine of the time stepping, read-out and diagnostics.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/telbm.h"
+#include "kernels.hpp"
+#include "thermo.hpp"
+
+using namespace telbm;
+
+struct telbm_solver {
+    telbm_params p;
+    PhysConst k;
+    GridDims g;
+    int Q;
+    size_t pop_bytes;  // bytes of one population buffer
+    char* arena;
+    size_t arena_bytes;
+    void* pop[2];
+    double *rho, *phi, *mux, *mup, *partials, *diag_dev, *scratch;
+    unsigned long long* bad;
+    double* diag_host;  // pinned
+    hipStream_t stream;
+    int cur;             // pop[cur] holds the state
+    bool aux_valid;      // rho/phi/mux/mup belong to the current state
+    int64_t steps;
+    int64_t diag_step;   // step of the last diagnostics enqueued (-1: none)
+    bool diag_unread;
+    telbm_diag last;
+    std::string err;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+int fail(telbm_solver* s, int code, const std::string& msg) {
+    if (s) s->err = msg;
+    return code;
+}
+
+int hip_fail(telbm_solver* s, hipError_t e, const char* where) {
+    return fail(s, TELBM_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+struct Layout {
+    size_t pop, aux, partials, diag, bad, total;
+    size_t o_pop0, o_pop1, o_rho, o_phi, o_mux, o_mup, o_part, o_diag, o_bad;
+};
+
+Layout layout_of(const telbm_params& p) {
+    const int Q = p.lattice == TELBM_D2Q9 ? 9 : 27;
+    const int64_t N = (int64_t)p.nx * p.ny * p.nz;
+    const size_t s = p.precision == TELBM_FP32_MIXED ? 4 : 8;
+    GridDims g{p.nx, p.ny, p.nz, 0, N};
+    Layout L{};
+    L.pop = align_up((size_t)2 * Q * N * s);
+    L.aux = align_up((size_t)N * sizeof(double));
+    L.partials = align_up((size_t)collide_blocks(g) * kDiag * sizeof(double));
+    L.diag = align_up(16 * sizeof(double));
+    L.bad = align_up(sizeof(unsigned long long));
+    size_t o = 0;
+    L.o_pop0 = o; o += L.pop;
+    L.o_pop1 = o; o += L.pop;
+    L.o_rho = o; o += L.aux;
+    L.o_phi = o; o += L.aux;
+    L.o_mux = o; o += L.aux;
+    L.o_mup = o; o += L.aux;
+    L.o_part = o; o += L.partials;
+    L.o_diag = o; o += L.diag;
+    L.o_bad = o; o += L.bad;
+    L.total = o;
+    return L;
+}
+
+int validate(const telbm_params* p, std::string* why) {
+    if (!p) { *why = "null params"; return TELBM_ERR_INVAL; }
+    if (p->lattice != TELBM_D2Q9 && p->lattice != TELBM_D3Q27) { *why = "lattice must be D2Q9 or D3Q27"; return TELBM_ERR_INVAL; }
+    if (p->precision != TELBM_FP64 && p->precision != TELBM_FP32_MIXED) { *why = "unknown precision"; return TELBM_ERR_INVAL; }
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) { *why = "sizes must be >= 1"; return TELBM_ERR_INVAL; }
+    if (p->lattice == TELBM_D2Q9 && p->nz != 1) { *why = "D2Q9 needs nz == 1"; return TELBM_ERR_INVAL; }
+    const double N = (double)p->nx * p->ny * p->nz;
+    if (N >= 1099511627776.0) { *why = "lattice too large"; return TELBM_ERR_INVAL; }
+    double Tc;
+    if (!critical_point(p->a, p->b, p->R, &Tc, nullptr)) { *why = "a, b, R must be positive"; return TELBM_ERR_INVAL; }
+    if (!(p->T > 0.0 && p->T < Tc)) { *why = "T must lie in (0, T_c)"; return TELBM_ERR_INVAL; }
+    if (!(p->nu > 0.0) || !isfinite(p->nu)) { *why = "nu must be positive"; return TELBM_ERR_INVAL; }
+    if (!(p->tau_phi > 0.5) || !isfinite(p->tau_phi)) { *why = "tau_phi must exceed 1/2"; return TELBM_ERR_INVAL; }
+    if (!(p->chi != 0.0) || !isfinite(p->chi)) { *why = "chi must be non-zero"; return TELBM_ERR_INVAL; }
+    if (!(p->mobility >= 0.0)) { *why = "mobility must be non-negative"; return TELBM_ERR_INVAL; }
+    const bool given = p->rho_g != 0.0 || p->rho_l != 0.0;
+    if (given && !(p->rho_l > p->rho_g && p->rho_g > 0.0)) { *why = "need rho_l > rho_g > 0"; return TELBM_ERR_INVAL; }
+    const double vals[] = {p->lambda1, p->lambda2, p->lambda3, p->kappa1, p->kappa2, p->kappa3, p->rho_ref};
+    for (double v : vals)
+        if (!isfinite(v)) { *why = "non-finite free-energy parameter"; return TELBM_ERR_INVAL; }
+    return TELBM_OK;
+}
+
+// Derived constants of the free energy and the kinetics.
+PhysConst derive(const telbm_params& p, double rho_g, double rho_l, double C) {
+    PhysConst k{};
+    k.a = p.a;
+    k.b = p.b;
+    k.RT = p.R * p.T;
+    k.C = C;
+    k.half_lambda1 = 0.5 * p.lambda1;
+    k.lambda2 = p.lambda2;
+    k.lambda3 = p.lambda3;
+    k.rho_l = rho_l;
+    const double dlt = rho_g - rho_l;
+    k.inv_delta = 1.0 / dlt;
+    k.inv_2delta = 1.0 / (2.0 * dlt);
+    k.inv_chi = 1.0 / p.chi;
+    k.inv_2chi = 1.0 / (2.0 * p.chi);
+    const double A = 0.5 * p.kappa1 + (p.kappa2 + p.kappa3) / (8.0 * dlt * dlt);
+    const double B = (p.kappa2 + p.kappa3) / (8.0 * p.chi * p.chi);
+    const double D = (p.kappa3 - p.kappa2) / (4.0 * p.chi * dlt);
+    k.twoA = 2.0 * A;
+    k.twoB = 2.0 * B;
+    k.Dc = D;
+    const double tau = 3.0 * p.nu + 0.5;
+    k.beta = 1.0 / (2.0 * tau);
+    k.omega_phi = 1.0 / p.tau_phi;
+    k.Gamma = p.mobility / (p.tau_phi - 0.5);
+    k.rho_ref = p.precision == TELBM_FP32_MIXED ? (p.rho_ref != 0.0 ? p.rho_ref : rho_l) : 0.0;
+    return k;
+}
+
+StepArgs args_of(telbm_solver* s, bool forward) {
+    StepArgs a{};
+    a.g = s->g;
+    a.k = s->k;
+    a.src = s->pop[s->cur];
+    a.dst = forward ? s->pop[1 - s->cur] : s->pop[s->cur];
+    a.rho = s->rho;
+    a.phi = s->phi;
+    a.mux = s->mux;
+    a.mup = s->mup;
+    a.partials = s->partials;
+    a.diag_out = s->diag_dev;
+    a.diag = 0;
+    a.stream = s->stream;
+    return a;
+}
+
+// Bring the aux fields to the current state (moments + chemical potentials).
+int ensure_aux(telbm_solver* s) {
+    if (s->aux_valid) return TELBM_OK;
+    StepArgs a = args_of(s, false);
+    for (int part = 0; part < 2; ++part) {
+        hipError_t e = launch_part(s->p.lattice, s->p.precision, a, part);
+        if (e != hipSuccess) return hip_fail(s, e, "moment/chemical-potential launch");
+    }
+    s->aux_valid = true;
+    return TELBM_OK;
+}
+
+int consume_diag(telbm_solver* s) {
+    if (!s->diag_unread) return TELBM_OK;
+    hipError_t e = hipMemcpyAsync(s->diag_host, s->diag_dev, kDiag * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "diagnostics copy");
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "stream synchronise");
+    const double* d = s->diag_host;
+    telbm_diag& o = s->last;
+    o.step = s->diag_step;
+    o.mass = d[0];
+    o.phi_total = d[1];
+    o.mom[0] = d[2];
+    o.mom[1] = d[3];
+    o.mom[2] = d[4];
+    o.max_u = d[5];
+    o.min_rho = d[6];
+    o.gamma_min = d[7];
+    o.gamma_max = d[8];
+    o.nonfinite = (int64_t)d[9];
+    s->diag_unread = false;
+    return TELBM_OK;
+}
+
+bool unstable(const telbm_diag& d) {
+    return d.nonfinite > 0 || !(d.min_rho > 0.0) || !(d.max_u < 1.0) || !isfinite(d.mass);
+}
+
+// One time step.
+int one_step(telbm_solver* s, bool diag) {
+    int rc = ensure_aux(s);
+    if (rc) return rc;
+    StepArgs a = args_of(s, true);
+    a.diag = diag ? 1 : 0;
+    hipError_t e = launch_part(s->p.lattice, s->p.precision, a, 2);
+    if (e != hipSuccess) return hip_fail(s, e, "collision launch");
+    s->cur = 1 - s->cur;
+    s->aux_valid = false;
+    if (diag) {
+        s->diag_step = s->steps;
+        s->diag_unread = true;
+    }
+    s->steps += 1;
+    return TELBM_OK;
+}
+
+const char* kKernelNames[3] = {"moments", "chemical_potentials", "collide"};
+
+}  // namespace
+
+extern "C" {
+
+const char* telbm_version(void) { return "telbm 0.1 (gfx950)"; }
+
+int telbm_critical_temperature(double a, double b, double R, double* T_c) {
+    if (!T_c) return TELBM_ERR_INVAL;
+    return critical_point(a, b, R, T_c, nullptr) ? TELBM_OK : TELBM_ERR_INVAL;
+}
+
+int telbm_coexistence(double a, double b, double R, double T, double* rho_g, double* rho_l, double* C,
+                      double* Psi0) {
+    if (!rho_g || !rho_l) return TELBM_ERR_INVAL;
+    double c = 0, p0 = 0;
+    if (!maxwell(a, b, R, T, rho_g, rho_l, &c, &p0)) return TELBM_ERR_INVAL;
+    if (C) *C = c;
+    if (Psi0) *Psi0 = p0;
+    return TELBM_OK;
+}
+
+int telbm_temperature_for_ratio(double a, double b, double R, double ratio, double* T) {
+    if (!T) return TELBM_ERR_INVAL;
+    return temperature_for_ratio(a, b, R, ratio, T) ? TELBM_OK : TELBM_ERR_INVAL;
+}
+
+int telbm_required_bytes(const telbm_params* p, size_t* bytes) {
+    std::string why;
+    if (!bytes) return TELBM_ERR_INVAL;
+    int rc = validate(p, &why);
+    if (rc) return rc;
+    *bytes = layout_of(*p).total;
+    return TELBM_OK;
+}
+
+int telbm_create(const telbm_params* p, void* device_arena, size_t bytes, telbm_solver** out) {
+    if (!out) return TELBM_ERR_INVAL;
+    *out = nullptr;
+    std::string why;
+    int rc = validate(p, &why);
+    if (rc) return rc;
+    const Layout L = layout_of(*p);
+    if (!device_arena || ((uintptr_t)device_arena % kAlign) != 0) return TELBM_ERR_INVAL;
+    if (bytes < L.total) return TELBM_ERR_NOMEM;
+    double rg = p->rho_g, rl = p->rho_l, C = 0.0, psi0 = 0.0;
+    double mg, ml;
+    if (!maxwell(p->a, p->b, p->R, p->T, &mg, &ml, &C, &psi0)) return TELBM_ERR_INVAL;
+    if (rg == 0.0 && rl == 0.0) {
+        rg = mg;
+        rl = ml;
+    }
+    telbm_solver* s = new (std::nothrow) telbm_solver();
+    if (!s) return TELBM_ERR_NOMEM;
+    s->p = *p;
+    s->p.rho_g = rg;
+    s->p.rho_l = rl;
+    s->k = derive(*p, rg, rl, C);
+    s->Q = p->lattice == TELBM_D2Q9 ? 9 : 27;
+    s->g = GridDims{p->nx, p->ny, p->nz, 0, (int64_t)p->nx * p->ny * p->nz};
+    s->pop_bytes = L.pop;
+    s->arena = (char*)device_arena;
+    s->arena_bytes = bytes;
+    s->pop[0] = s->arena + L.o_pop0;
+    s->pop[1] = s->arena + L.o_pop1;
+    s->rho = (double*)(s->arena + L.o_rho);
+    s->phi = (double*)(s->arena + L.o_phi);
+    s->mux = (double*)(s->arena + L.o_mux);
+    s->mup = (double*)(s->arena + L.o_mup);
+    s->partials = (double*)(s->arena + L.o_part);
+    s->diag_dev = (double*)(s->arena + L.o_diag);
+    s->bad = (unsigned long long*)(s->arena + L.o_bad);
+    s->stream = nullptr;
+    s->cur = 0;
+    s->aux_valid = false;
+    s->steps = 0;
+    s->diag_step = -1;
+    s->diag_unread = false;
+    memset(&s->last, 0, sizeof(s->last));
+    s->last.step = -1;
+    hipError_t e = hipHostMalloc((void**)&s->diag_host, 16 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete s;
+        return TELBM_ERR_DEVICE;
+    }
+    *out = s;
+    return TELBM_OK;
+}
+
+int telbm_set_stream(telbm_solver* s, void* stream) {
+    if (!s) return TELBM_ERR_INVAL;
+    s->stream = (hipStream_t)stream;
+    return TELBM_OK;
+}
+
+int telbm_init_fields(telbm_solver* s, const double* rho, const double* phi, const double* u, int on_device) {
+    if (!s) return TELBM_ERR_INVAL;
+    if (!rho || !phi) return fail(s, TELBM_ERR_INVAL, "rho and phi are required");
+    const int64_t N = s->g.N;
+    const int D = s->p.lattice == TELBM_D2Q9 ? 2 : 3;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    // stage: rho, phi into the aux fields, u into the spare population buffer
+    double* u_dev = u ? (double*)s->pop[1 - s->cur] : nullptr;
+    hipError_t e = hipMemcpyAsync(s->rho, rho, N * sizeof(double), kind, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->phi, phi, N * sizeof(double), kind, s->stream);
+    if (e == hipSuccess && u) e = hipMemcpyAsync(u_dev, u, (size_t)D * N * sizeof(double), kind, s->stream);
+    if (e == hipSuccess) e = launch_check_init(s->g, D, s->rho, s->phi, u_dev, s->bad, s->stream);
+    unsigned long long bad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(s->diag_host, s->bad, sizeof(bad), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "init staging");
+    memcpy(&bad, s->diag_host, sizeof(bad));
+    s->aux_valid = false;
+    if (bad) return fail(s, TELBM_ERR_UNSTABLE, std::to_string(bad) + " nodes with rho <= 0, |u| >= 1 or non-finite values");
+    // mu_phi of the initial fields, then the equilibria into the state buffer
+    StepArgs a = args_of(s, false);
+    e = launch_part(s->p.lattice, s->p.precision, a, 1);
+    if (e == hipSuccess) e = launch_init(s->p.lattice, s->p.precision, a, u_dev);
+    if (e != hipSuccess) return hip_fail(s, e, "init launch");
+    s->steps = 0;
+    s->diag_step = -1;
+    s->diag_unread = false;
+    s->last.step = -1;
+    return TELBM_OK;
+}
+
+int telbm_step(telbm_solver* s, int64_t n) {
+    if (!s || n < 0) return TELBM_ERR_INVAL;
+    for (int64_t i = 0; i < n; ++i) {
+        const bool diag = s->p.diag_every > 0 && (s->steps % s->p.diag_every) == 0;
+        int rc = one_step(s, diag);
+        if (rc) return rc;
+    }
+    return TELBM_OK;
+}
+
+int telbm_sync(telbm_solver* s) {
+    if (!s) return TELBM_ERR_INVAL;
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "stream synchronise");
+    int rc = consume_diag(s);
+    if (rc) return rc;
+    if (s->last.step >= 0 && unstable(s->last)) return fail(s, TELBM_ERR_UNSTABLE, "unstable state detected");
+    return TELBM_OK;
+}
+
+int telbm_read(telbm_solver* s, int field, double* out, int on_device) {
+    if (!s || !out) return TELBM_ERR_INVAL;
+    if (field < 0 || field > kFieldFz) return fail(s, TELBM_ERR_INVAL, "unknown field");
+    int rc = ensure_aux(s);
+    if (rc) return rc;
+    StepArgs a = args_of(s, false);
+    double* dst = on_device ? out : (double*)s->pop[1 - s->cur];
+    hipError_t e = launch_macro(s->p.lattice, s->p.precision, a, field, dst);
+    if (e == hipSuccess && !on_device)
+        e = hipMemcpyAsync(out, dst, s->g.N * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "read");
+    return telbm_sync(s);
+}
+
+int telbm_diagnostics(telbm_solver* s, telbm_diag* out) {
+    if (!s || !out) return TELBM_ERR_INVAL;
+    if (s->diag_step != s->steps) {
+        // diagnostic pass over the current state: a collision into the spare
+        // buffer with the diagnostics on; the state itself is not advanced
+        int rc = ensure_aux(s);
+        if (rc) return rc;
+        StepArgs a = args_of(s, true);
+        a.diag = 1;
+        hipError_t e = launch_part(s->p.lattice, s->p.precision, a, 2);
+        if (e != hipSuccess) return hip_fail(s, e, "diagnostic launch");
+        s->diag_step = s->steps;
+        s->diag_unread = true;
+    }
+    int rc = telbm_sync(s);
+    *out = s->last;
+    return rc;
+}
+
+int telbm_step_count(const telbm_solver* s, int64_t* steps) {
+    if (!s || !steps) return TELBM_ERR_INVAL;
+    *steps = s->steps;
+    return TELBM_OK;
+}
+
+int telbm_time_kernels(telbm_solver* s, int64_t n, double* ms, int* kinds) {
+    if (!s || !ms || !kinds || n < 1) return TELBM_ERR_INVAL;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<int> kind;
+    ev.reserve(3 * n);
+    kind.reserve(3 * n);
+    // pre-create enough events
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool(3 * n);
+    for (auto& pr : pool) {
+        if (hipEventCreate(&pr.first) != hipSuccess || hipEventCreate(&pr.second) != hipSuccess)
+            return fail(s, TELBM_ERR_DEVICE, "event create");
+    }
+    int rc = TELBM_OK;
+    size_t used = 0;
+    for (int64_t i = 0; i < n && rc == TELBM_OK; ++i) {
+        // events for the (up to) three launches of this step
+        std::vector<std::pair<hipEvent_t, hipEvent_t>> step_ev(pool.begin() + used, pool.begin() + used + 3);
+        used += 3;
+        // the launches of one_step, each bracketed by its own event pair
+        StepArgs a = args_of(s, false);
+        if (!s->aux_valid) {
+            for (int part = 0; part < 2; ++part) {
+                hipEventRecord(step_ev[part].first, s->stream);
+                hipError_t e = launch_part(s->p.lattice, s->p.precision, a, part);
+                hipEventRecord(step_ev[part].second, s->stream);
+                if (e != hipSuccess) { rc = hip_fail(s, e, "timed launch"); break; }
+                ev.push_back(step_ev[part]);
+                kind.push_back(part);
+            }
+            s->aux_valid = true;
+        }
+        if (rc) break;
+        const bool diag = s->p.diag_every > 0 && (s->steps % s->p.diag_every) == 0;
+        StepArgs b = args_of(s, true);
+        b.diag = diag ? 1 : 0;
+        hipEventRecord(step_ev[2].first, s->stream);
+        hipError_t e = launch_part(s->p.lattice, s->p.precision, b, 2);
+        hipEventRecord(step_ev[2].second, s->stream);
+        if (e != hipSuccess) { rc = hip_fail(s, e, "timed launch"); break; }
+        ev.push_back(step_ev[2]);
+        kind.push_back(2);
+        s->cur = 1 - s->cur;
+        s->aux_valid = false;
+        if (diag) {
+            s->diag_step = s->steps;
+            s->diag_unread = true;
+        }
+        s->steps += 1;
+    }
+    if (rc == TELBM_OK) {
+        hipError_t e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) rc = hip_fail(s, e, "timed synchronise");
+    }
+    double sum[3] = {0, 0, 0};
+    int cnt[3] = {0, 0, 0};
+    if (rc == TELBM_OK) {
+        for (size_t i = 0; i < ev.size(); ++i) {
+            float t = 0.f;
+            hipEventElapsedTime(&t, ev[i].first, ev[i].second);
+            sum[kind[i]] += t;
+            cnt[kind[i]] += 1;
+        }
+        for (int k = 0; k < 3; ++k) ms[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
+        *kinds = 3;
+    }
+    for (auto& pr : pool) {
+        hipEventDestroy(pr.first);
+        hipEventDestroy(pr.second);
+    }
+    return rc;
+}
+
+const char* telbm_kernel_name(const telbm_solver* s, int kind) {
+    (void)s;
+    if (kind < 0 || kind > 2) return "";
+    return kKernelNames[kind];
+}
+
+double telbm_algorithmic_bytes_per_update(const telbm_solver* s) {
+    if (!s) return 0.0;
+    const double b = s->p.precision == TELBM_FP32_MIXED ? 4.0 : 8.0;
+    return 2.0 * 2.0 * s->Q * b;
+}
+
+int telbm_destroy(telbm_solver* s) {
+    if (!s) return TELBM_ERR_INVAL;
+    if (s->stream) hipStreamSynchronize(s->stream);
+    else hipDeviceSynchronize();
+    if (s->diag_host) hipHostFree(s->diag_host);
+    delete s;
+    return TELBM_OK;
+}
+
+const char* telbm_last_error(const telbm_solver* s) {
+    if (!s) return "null solver";
+    return s->err.c_str();
+}
+
+}  // extern "C"

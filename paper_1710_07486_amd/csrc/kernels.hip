@@ -1,0 +1,441 @@
+// kernels.hip -- HIP kernels (gfx950) of the ternary free-energy entropic LBM
+// time step (arXiv:1710.07486) and their host-side launchers.
+//
+// Layout in HBM (structure of arrays, x fastest):
+//   populations  pop[k][n], k = 0..Q-1 for f (offset form f_i - w_i rho_ref),
+//                k = Q..2Q-1 for g; n = (z ny + y) nx + x.  The buffer holds
+//                the post-collision values f*(x) of the previous step, so a
+//                step pulls f_i(x) = pop[i][x - c_i] (periodic).
+//   aux fields   rho[n], phi[n], mux[n] (= mu_rho - cs2 ln rho), mup[n] (mu_phi),
+//                all FP64.
+//
+// One step is three launches: node moments (pull-sum of both population sets),
+// chemical potentials (Laplacian stencils over rho, phi), and the fused
+// pull -> force -> KBC + exact-difference forcing -> phase-field BGK -> write.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+#include "lattice.hpp"
+
+namespace telbm {
+
+constexpr int BX = 64;   // threads along x: one wavefront spans 64 consecutive nodes
+constexpr int BY = 4;    // rows per workgroup
+constexpr int NXCD = 8;  // accelerator complex dies of the MI355X
+
+// Workgroups are dispatched to the eight XCDs round robin (block b runs on
+// XCD b mod 8).  Remap so that each XCD receives a contiguous range of tiles:
+// neighbouring tiles share halo lines in that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb / NXCD, r = nb % NXCD;
+    const int x = b % NXCD, k = b / NXCD;
+    return x * q + (x < r ? x : r) + k;
+}
+
+struct Tile {
+    int x, y, z;
+    bool in;
+};
+
+__device__ __forceinline__ Tile tile_coords(const GridDims& g) {
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + BY - 1) / BY;
+    const int bx = b % bxc;
+    const int rest = b / bxc;
+    const int by = rest % byc;
+    const int bz = rest / byc;
+    Tile t;
+    t.x = bx * BX + threadIdx.x;
+    t.y = by * BY + threadIdx.y;
+    t.z = bz;
+    t.in = (t.x < g.nx) && (t.y < g.ny) && (t.z < g.nz);
+    return t;
+}
+
+__device__ __forceinline__ int64_t node_of(const GridDims& g, const Tile& t) {
+    return ((int64_t)t.z * g.ny + t.y) * g.nx + t.x;
+}
+
+// ---------------------------------------------------------------------------
+// Moments: rho = sum_i f_i (+ rho_ref for the offset form), phi = sum_i g_i.
+// ---------------------------------------------------------------------------
+template <int L, typename T>
+__global__ __launch_bounds__(BX* BY) void k_moments(GridDims g, const T* __restrict__ pop,
+                                                    double* __restrict__ rho, double* __restrict__ phi,
+                                                    double rho_ref) {
+    using Lt = Lattice<L>;
+    constexpr int Q = Lt::Q;
+    const Tile t = tile_coords(g);
+    if (!t.in) return;
+    const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
+    const int64_t n = node_of(g, t);
+    double r = 0.0, p = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int64_t m = n + nbr_off<L>(nb, i, -1);
+        r += double(pop[(int64_t)i * g.N + m]);
+        p += double(pop[(int64_t)(Q + i) * g.N + m]);
+    }
+    rho[n] = r + rho_ref;
+    phi[n] = p;
+}
+
+// ---------------------------------------------------------------------------
+// Chemical potentials with lattice Laplacians
+//   lap psi(x) = 6 sum_i w_i [psi(x + c_i) - psi(x)].
+// ---------------------------------------------------------------------------
+template <int L>
+__global__ __launch_bounds__(BX* BY) void k_chempot(GridDims g, PhysConst k, const double* __restrict__ rho,
+                                                    const double* __restrict__ phi, double* __restrict__ mux,
+                                                    double* __restrict__ mup) {
+    using Lt = Lattice<L>;
+    constexpr int Q = Lt::Q;
+    const Tile t = tile_coords(g);
+    if (!t.in) return;
+    const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
+    const int64_t n = node_of(g, t);
+    const double r0 = rho[n], p0 = phi[n];
+    double lr = 0.0, lp = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int64_t m = n + nbr_off<L>(nb, i, +1);
+        lr += Lt::w[i] * (rho[m] - r0);
+        lp += Lt::w[i] * (phi[m] - p0);
+    }
+    double mx, mp;
+    chem_pot(k, r0, p0, 6.0 * lr, 6.0 * lp, &mx, &mp);
+    mux[n] = mx;
+    mup[n] = mp;
+}
+
+// Isotropic gradient grad psi(x) = 3 sum_i w_i c_i psi(x + c_i).
+template <int L>
+__device__ __forceinline__ void gradient2(const Nbr& nb, int64_t n, const double* __restrict__ a,
+                                          const double* __restrict__ b, double* ga, double* gb) {
+    using Lt = Lattice<L>;
+    constexpr int Q = Lt::Q;
+    ga[0] = ga[1] = ga[2] = 0.0;
+    gb[0] = gb[1] = gb[2] = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int64_t m = n + nbr_off<L>(nb, i, +1);
+        const double va = Lt::w[i] * a[m], vb = Lt::w[i] * b[m];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (Lt::c[i][d] > 0) {
+                ga[d] += va;
+                gb[d] += vb;
+            } else if (Lt::c[i][d] < 0) {
+                ga[d] -= va;
+                gb[d] -= vb;
+            }
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        ga[d] *= 3.0;
+        gb[d] *= 3.0;
+    }
+}
+
+// Block-level reduction of the health diagnostics into partials[block][kDiag].
+__device__ void diag_block_reduce(double* vals, double* __restrict__ out) {
+    // vals: 0 sum rho, 1 sum phi, 2-4 sum j, 5 max |u|, 6 min rho, 7 min gamma,
+    //       8 max gamma, 9 nonfinite count
+    __shared__ double red[BX * BY / 64][kDiag];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) vals[v] += __shfl_xor(vals[v], off);
+        vals[5] = fmax(vals[5], __shfl_xor(vals[5], off));
+        vals[6] = fmin(vals[6], __shfl_xor(vals[6], off));
+        vals[7] = fmin(vals[7], __shfl_xor(vals[7], off));
+        vals[8] = fmax(vals[8], __shfl_xor(vals[8], off));
+        vals[9] += __shfl_xor(vals[9], off);
+    }
+    const int lane = (threadIdx.y * BX + threadIdx.x) & 63;
+    const int wave = (threadIdx.y * BX + threadIdx.x) >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int v = 0; v < kDiag; ++v) red[wave][v] = vals[v];
+    }
+    __syncthreads();
+    if (wave == 0 && lane < kDiag) {
+        double acc = red[0][lane];
+        for (int w = 1; w < BX * BY / 64; ++w) {
+            const double x = red[w][lane];
+            if (lane == 5 || lane == 8) acc = fmax(acc, x);
+            else if (lane == 6 || lane == 7) acc = fmin(acc, x);
+            else acc += x;
+        }
+        out[(int64_t)xcd_remap(blockIdx.x, gridDim.x) * kDiag + lane] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The fused collision kernel: pull f, g; force from the excess potentials;
+// KBC with exact-difference forcing; phase-field BGK; write in place order.
+// ---------------------------------------------------------------------------
+template <int L, typename T>
+__global__ __launch_bounds__(BX* BY) void k_collide(GridDims g, PhysConst k, const T* __restrict__ src,
+                                                    T* __restrict__ dst, const double* __restrict__ rho,
+                                                    const double* __restrict__ phi,
+                                                    const double* __restrict__ mux,
+                                                    const double* __restrict__ mup,
+                                                    double* __restrict__ partials, int diag) {
+    using Lt = Lattice<L>;
+    using R = T;
+    constexpr int Q = Lt::Q;
+    const Tile t = tile_coords(g);
+    double dv[kDiag] = {0, 0, 0, 0, 0, 0, INFINITY, INFINITY, -INFINITY, 0};
+    if (t.in) {
+        const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
+        const int64_t n = node_of(g, t);
+        R f[Q];
+        R jx = 0, jy = 0, jz = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            f[i] = src[(int64_t)i * g.N + n + nbr_off<L>(nb, i, -1)];
+            if (Lt::c[i][0]) jx += Lt::c[i][0] > 0 ? f[i] : -f[i];
+            if (Lt::c[i][1]) jy += Lt::c[i][1] > 0 ? f[i] : -f[i];
+            if (Lt::c[i][2]) jz += Lt::c[i][2] > 0 ? f[i] : -f[i];
+        }
+        const double r = rho[n], p = phi[n];
+        double gx[3], gp[3];
+        gradient2<L>(nb, n, mux, mup, gx, gp);
+        double F[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) F[d] = -r * gx[d] - p * gp[d];
+        const double ir = 1.0 / r;
+        R u[3] = {R(double(jx) * ir), R(double(jy) * ir), R(double(jz) * ir)};
+        R du[3] = {R(F[0] * ir), R(F[1] * ir), R(F[2] * ir)};
+        if (Lt::D == 2) u[2] = du[2] = R(0);
+        const double gam = collide_f<L, R>(f, r, u, du, R(k.beta), R(k.rho_ref));
+#pragma unroll
+        for (int i = 0; i < Q; ++i) dst[(int64_t)i * g.N + n] = f[i];
+
+        R gg[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) gg[i] = src[(int64_t)(Q + i) * g.N + n + nbr_off<L>(nb, i, -1)];
+        R up[3] = {u[0] + R(0.5) * du[0], u[1] + R(0.5) * du[1], u[2] + R(0.5) * du[2]};
+        collide_g<L, R>(gg, R(p), R(mup[n]), up, R(k.Gamma), R(k.omega_phi));
+#pragma unroll
+        for (int i = 0; i < Q; ++i) dst[(int64_t)(Q + i) * g.N + n] = gg[i];
+
+        if (diag) {
+            const double ux = double(jx) * ir + 0.5 * F[0] * ir;
+            const double uy = double(jy) * ir + 0.5 * F[1] * ir;
+            const double uz = double(jz) * ir + 0.5 * F[2] * ir;
+            const double um = sqrt(ux * ux + uy * uy + uz * uz);
+            dv[0] = r;
+            dv[1] = p;
+            dv[2] = double(jx);
+            dv[3] = double(jy);
+            dv[4] = double(jz);
+            dv[5] = um;
+            dv[6] = r;
+            dv[7] = gam;
+            dv[8] = gam;
+            const bool bad = !(isfinite(r) && isfinite(p) && isfinite(um)) || !(r > 0.0);
+            dv[9] = bad ? 1.0 : 0.0;
+            if (bad) dv[5] = INFINITY;
+        }
+    }
+    if (diag) diag_block_reduce(dv, partials);
+}
+
+// Deterministic second pass over the block partials (one workgroup).
+__global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ partials, int nblocks,
+                                                    double* __restrict__ out) {
+    __shared__ double red[256][kDiag];
+    double acc[kDiag] = {0, 0, 0, 0, 0, 0, INFINITY, INFINITY, -INFINITY, 0};
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
+        const double* v = partials + (int64_t)b * kDiag;
+        for (int j = 0; j < kDiag; ++j) {
+            if (j == 5 || j == 8) acc[j] = fmax(acc[j], v[j]);
+            else if (j == 6 || j == 7) acc[j] = fmin(acc[j], v[j]);
+            else acc[j] += v[j];
+        }
+    }
+    for (int j = 0; j < kDiag; ++j) red[threadIdx.x][j] = acc[j];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            for (int j = 0; j < kDiag; ++j) {
+                const double a = red[threadIdx.x][j], b = red[threadIdx.x + s][j];
+                if (j == 5 || j == 8) red[threadIdx.x][j] = fmax(a, b);
+                else if (j == 6 || j == 7) red[threadIdx.x][j] = fmin(a, b);
+                else red[threadIdx.x][j] = a + b;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < kDiag) out[threadIdx.x] = red[0][threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation: equilibrium populations of (rho0, phi0, u0), written so that
+// the next pull sees them at their own node (pop[i][x - c_i] = f_i(x)).
+// ---------------------------------------------------------------------------
+template <int L, typename T>
+__global__ __launch_bounds__(BX* BY) void k_init(GridDims g, PhysConst k, const double* __restrict__ rho,
+                                                 const double* __restrict__ phi,
+                                                 const double* __restrict__ mup,
+                                                 const double* __restrict__ u0, T* __restrict__ pop) {
+    using Lt = Lattice<L>;
+    using R = T;
+    constexpr int Q = Lt::Q;
+    const Tile t = tile_coords(g);
+    if (!t.in) return;
+    const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
+    const int64_t n = node_of(g, t);
+    R u[3] = {R(0), R(0), R(0)};
+    if (u0) {
+        u[0] = R(u0[n]);
+        u[1] = R(u0[g.N + n]);
+        if (Lt::D == 3) u[2] = R(u0[2 * g.N + n]);
+    }
+    R fd[Q], gg[Q];
+    equilibria<L, R>(rho[n], R(phi[n]), R(mup[n]), u, R(k.Gamma), R(k.rho_ref), fd, gg);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int64_t m = n + nbr_off<L>(nb, i, -1);
+        pop[(int64_t)i * g.N + m] = fd[i];
+        pop[(int64_t)(Q + i) * g.N + m] = gg[i];
+    }
+}
+
+// Count of nodes whose initial values are unusable.
+__global__ void k_check_init(int64_t N, int D, const double* __restrict__ rho, const double* __restrict__ phi,
+                             const double* __restrict__ u0, unsigned long long* __restrict__ bad) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    bool b = !(isfinite(rho[n]) && rho[n] > 0.0 && isfinite(phi[n]));
+    if (u0) {
+        for (int d = 0; d < D; ++d) {
+            const double v = u0[(int64_t)d * N + n];
+            b = b || !(isfinite(v) && fabs(v) < 1.0);
+        }
+    }
+    if (b) atomicAdd(bad, 1ull);
+}
+
+// ---------------------------------------------------------------------------
+// Read-out of macroscopic fields of the current state.
+// ---------------------------------------------------------------------------
+template <int L, typename T>
+__global__ __launch_bounds__(BX* BY) void k_macro(GridDims g, PhysConst k, const T* __restrict__ pop,
+                                                  const double* __restrict__ rho,
+                                                  const double* __restrict__ phi,
+                                                  const double* __restrict__ mux,
+                                                  const double* __restrict__ mup, int field,
+                                                  double* __restrict__ out) {
+    using Lt = Lattice<L>;
+    constexpr int Q = Lt::Q;
+    const Tile t = tile_coords(g);
+    if (!t.in) return;
+    const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
+    const int64_t n = node_of(g, t);
+    const double r = rho[n], p = phi[n];
+    double v = 0.0;
+    if (field == kFieldRho) {
+        v = r;
+    } else if (field == kFieldPhi) {
+        v = p;
+    } else if (field == kFieldC1 || field == kFieldC2) {
+        const double cg = (r - k.rho_l) * k.inv_delta;
+        v = 0.5 * (1.0 + (field == kFieldC1 ? 1.0 : -1.0) * p * k.inv_chi - cg);
+    } else if (field == kFieldMuRho) {
+        v = mux[n] + (1.0 / 3.0) * log(r);
+    } else if (field == kFieldMuPhi) {
+        v = mup[n];
+    } else {
+        const int d = (field >= kFieldFx) ? field - kFieldFx : field - kFieldUx;
+        double gx[3], gp[3];
+        gradient2<L>(nb, n, mux, mup, gx, gp);
+        const double F = (Lt::D == 2 && d == 2) ? 0.0 : -r * gx[d] - p * gp[d];
+        if (field >= kFieldFx) {
+            v = F;
+        } else {
+            double j = 0.0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                if (Lt::c[i][d] == 0) continue;
+                const double fi = double(pop[(int64_t)i * g.N + n + nbr_off<L>(nb, i, -1)]);
+                j += Lt::c[i][d] > 0 ? fi : -fi;
+            }
+            v = (j + 0.5 * F) / r;
+        }
+    }
+    out[n] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+static inline unsigned grid_blocks(const GridDims& g) {
+    return (unsigned)(((g.nx + BX - 1) / BX) * ((g.ny + BY - 1) / BY) * g.nz);
+}
+
+unsigned collide_blocks(const GridDims& g) { return grid_blocks(g); }
+
+template <int L, typename T>
+static hipError_t launch_step_parts(const StepArgs& a, int part) {
+    const dim3 blk(BX, BY, 1);
+    const dim3 grd(grid_blocks(a.g), 1, 1);
+    if (part == 0) {
+        k_moments<L, T><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho, a.phi, a.k.rho_ref);
+    } else if (part == 1) {
+        k_chempot<L><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup);
+    } else {
+        k_collide<L, T><<<grd, blk, 0, a.stream>>>(a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho, a.phi, a.mux,
+                                                     a.mup, a.partials, a.diag);
+        if (a.diag) k_diag_final<<<1, 256, 0, a.stream>>>(a.partials, (int)grd.x, a.diag_out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_part(int lattice, int precision, const StepArgs& a, int part) {
+    if (lattice == kD2Q9)
+        return precision ? launch_step_parts<kD2Q9, float>(a, part) : launch_step_parts<kD2Q9, double>(a, part);
+    return precision ? launch_step_parts<kD3Q27, float>(a, part) : launch_step_parts<kD3Q27, double>(a, part);
+}
+
+template <int L, typename T>
+static hipError_t launch_init_t(const StepArgs& a, const double* u0) {
+    k_init<L, T><<<grid_blocks(a.g), dim3(BX, BY, 1), 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mup, u0,
+                                                                     (T*)a.dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int lattice, int precision, const StepArgs& a, const double* u0) {
+    if (lattice == kD2Q9) return precision ? launch_init_t<kD2Q9, float>(a, u0) : launch_init_t<kD2Q9, double>(a, u0);
+    return precision ? launch_init_t<kD3Q27, float>(a, u0) : launch_init_t<kD3Q27, double>(a, u0);
+}
+
+hipError_t launch_check_init(const GridDims& g, int D, const double* rho, const double* phi, const double* u0,
+                             unsigned long long* bad, hipStream_t s) {
+    hipError_t e = hipMemsetAsync(bad, 0, sizeof(unsigned long long), s);
+    if (e != hipSuccess) return e;
+    const unsigned nb = (unsigned)((g.N + 255) / 256);
+    k_check_init<<<nb, 256, 0, s>>>(g.N, D, rho, phi, u0, bad);
+    return hipGetLastError();
+}
+
+template <int L, typename T>
+static hipError_t launch_macro_t(const StepArgs& a, int field, double* out) {
+    k_macro<L, T><<<grid_blocks(a.g), dim3(BX, BY, 1), 0, a.stream>>>(a.g, a.k, (const T*)a.src, a.rho, a.phi,
+                                                                      a.mux, a.mup, field, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_macro(int lattice, int precision, const StepArgs& a, int field, double* out) {
+    if (lattice == kD2Q9)
+        return precision ? launch_macro_t<kD2Q9, float>(a, field, out) : launch_macro_t<kD2Q9, double>(a, field, out);
+    return precision ? launch_macro_t<kD3Q27, float>(a, field, out) : launch_macro_t<kD3Q27, double>(a, field, out);
+}
+
+}  // namespace telbm

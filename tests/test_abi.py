@@ -1,0 +1,97 @@
+"""CPU checks of the C ABI library: it loads, exports every symbol that
+include/telbm.h declares, validates parameters before touching a device, and
+its host thermodynamics (an implementation independent of the oracle's)
+agree with the oracle.  No compute call is made here: no GPU is needed."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            names |= set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(telbm_\w+)\s*\(", text, re.M))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1710_07486_amd import _lib
+    return _lib.load()
+
+
+def test_header_declares_the_problem_calls():
+    names = declared_symbols()
+    for must in ("telbm_create", "telbm_init_fields", "telbm_step", "telbm_read", "telbm_diagnostics",
+                 "telbm_destroy", "telbm_coexistence", "telbm_required_bytes", "telbm_set_stream"):
+        assert must in names, must
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_symbols() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_python_prototypes_cover_header():
+    import importlib
+    from paper_1710_07486_amd import _lib
+    covered = set(_lib.PROTOTYPES)
+    for mod in ("batch", "surrogate"):
+        try:
+            covered |= set(importlib.import_module("paper_1710_07486_amd." + mod).PROTOTYPES)
+        except ImportError:
+            pass
+    assert set(declared_symbols()) <= covered, set(declared_symbols()) - covered
+
+
+def test_library_thermodynamics_match_oracle(orc):
+    import paper_1710_07486_amd as T
+    Tc_l = T.critical_temperature()
+    Tc_o, _ = orc.critical_temperature()
+    assert abs(Tc_l / Tc_o - 1) < 1e-12
+    for tr in (0.45, 0.485, 0.6, 0.8, 0.95):
+        rg, rl, C, p0 = T.coexistence(tr * Tc_o)
+        og, ol, oC, op0 = orc.maxwell(tr * Tc_o)
+        assert abs(rg / og - 1) < 1e-9 and abs(rl / ol - 1) < 1e-11
+        assert abs(C - oC) < 1e-11 and abs(p0 - op0) < 1e-12
+    for ratio in (10.0, 150.0, 1000.0):
+        assert abs(T.temperature_for_ratio(ratio) / orc.temperature_for_ratio(ratio)[0] - 1) < 1e-11
+
+
+def test_parameter_validation_without_device(orc):
+    import paper_1710_07486_amd as T
+    from paper_1710_07486_amd import _lib
+    T0 = orc.temperature_for_ratio(10.0)[0]
+    good = T.Params(nx=16, ny=16, T=T0)
+    assert T.required_bytes(good) >= 2 * 18 * 256 * 8
+    bad = [dict(T=0.5), dict(T=-1.0), dict(nz=2), dict(nx=0), dict(nu=0.0), dict(tau_phi=0.5),
+           dict(chi=0.0), dict(lattice=7), dict(precision=3), dict(rho_g=2.0, rho_l=1.0),
+           dict(mobility=-1.0)]
+    for kw in bad:
+        p = T.Params(nx=16, ny=16, T=T0)
+        for k, v in kw.items():
+            setattr(p, k, v)
+        with pytest.raises(T.TelbmError) as e:
+            T.required_bytes(p)
+        assert e.value.code == _lib.ERR_INVAL, kw
+    # the arena of the mixed-precision form is about half
+    big = T.Params(nx=256, ny=256, T=T0)
+    mixed = T.Params(nx=256, ny=256, T=T0, precision=T.FP32_MIXED)
+    assert T.required_bytes(mixed) < 0.7 * T.required_bytes(big)
+    p3 = T.Params(lattice=T.D3Q27, nx=8, ny=8, nz=8, T=T0)
+    assert T.required_bytes(p3) >= 2 * 54 * 512 * 8
+
+
+def test_null_arguments_are_rejected(lib):
+    from paper_1710_07486_amd import _lib
+    assert lib.telbm_step(None, 1) == _lib.ERR_INVAL
+    assert lib.telbm_read(None, 0, None, 0) == _lib.ERR_INVAL
+    assert lib.telbm_destroy(None) == _lib.ERR_INVAL
+    assert lib.telbm_required_bytes(None, None) == _lib.ERR_INVAL
+    assert lib.telbm_coexistence(0.037, 0.2, 1.0, 1.0, None, None, None, None) == _lib.ERR_INVAL
