@@ -25,11 +25,13 @@ struct telbm_solver {
     char* arena;
     size_t arena_bytes;
     void* pop[2];
-    double *rho, *phi, *mux, *mup, *partials, *diag_dev, *scratch;
+    double* rhob[2];     // densities: the current state's reference and the computed one
+    double *phi, *mux, *mup, *partials, *diag_dev;
     unsigned long long* bad;
     double* diag_host;  // pinned
     hipStream_t stream;
     int cur;             // pop[cur] holds the state
+    int ref;             // FP32 form: the state's f values are relative to rhob[ref]
     bool aux_valid;      // rho/phi/mux/mup belong to the current state
     int64_t steps;
     int64_t diag_step;   // step of the last diagnostics enqueued (-1: none)
@@ -54,7 +56,7 @@ int hip_fail(telbm_solver* s, hipError_t e, const char* where) {
 
 struct Layout {
     size_t pop, aux, partials, diag, bad, total;
-    size_t o_pop0, o_pop1, o_rho, o_phi, o_mux, o_mup, o_part, o_diag, o_bad;
+    size_t o_pop0, o_pop1, o_rho0, o_rho1, o_phi, o_mux, o_mup, o_part, o_diag, o_bad;
 };
 
 Layout layout_of(const telbm_params& p) {
@@ -71,7 +73,8 @@ Layout layout_of(const telbm_params& p) {
     size_t o = 0;
     L.o_pop0 = o; o += L.pop;
     L.o_pop1 = o; o += L.pop;
-    L.o_rho = o; o += L.aux;
+    L.o_rho0 = o; o += L.aux;
+    L.o_rho1 = o; o += L.aux;
     L.o_phi = o; o += L.aux;
     L.o_mux = o; o += L.aux;
     L.o_mup = o; o += L.aux;
@@ -131,9 +134,13 @@ PhysConst derive(const telbm_params& p, double rho_g, double rho_l, double C) {
     k.beta = 1.0 / (2.0 * tau);
     k.omega_phi = 1.0 / p.tau_phi;
     k.Gamma = p.mobility / (p.tau_phi - 0.5);
-    k.rho_ref = p.precision == TELBM_FP32_MIXED ? (p.rho_ref != 0.0 ? p.rho_ref : rho_l) : 0.0;
     return k;
 }
+
+bool mixed(const telbm_solver* s) { return s->p.precision == TELBM_FP32_MIXED; }
+
+// Density field that the moment kernel fills for the current state.
+double* density_out(telbm_solver* s) { return mixed(s) ? s->rhob[1 - s->ref] : s->rhob[0]; }
 
 StepArgs args_of(telbm_solver* s, bool forward) {
     StepArgs a{};
@@ -141,7 +148,8 @@ StepArgs args_of(telbm_solver* s, bool forward) {
     a.k = s->k;
     a.src = s->pop[s->cur];
     a.dst = forward ? s->pop[1 - s->cur] : s->pop[s->cur];
-    a.rho = s->rho;
+    a.rho_ref = mixed(s) ? s->rhob[s->ref] : nullptr;
+    a.rho = density_out(s);
     a.phi = s->phi;
     a.mux = s->mux;
     a.mup = s->mup;
@@ -152,12 +160,30 @@ StepArgs args_of(telbm_solver* s, bool forward) {
     return a;
 }
 
+// Optional per-launch event timing (telbm_time_kernels).
+struct Timing {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+    size_t used = 0;
+    std::vector<int> kind;
+};
+
+hipError_t timed_launch(telbm_solver* s, const StepArgs& a, int part, Timing* t) {
+    if (!t) return launch_part(s->p.lattice, s->p.precision, a, part);
+    if (t->used >= t->pool.size()) return hipErrorInvalidValue;
+    auto& ev = t->pool[t->used++];
+    hipError_t e = hipEventRecord(ev.first, s->stream);
+    if (e == hipSuccess) e = launch_part(s->p.lattice, s->p.precision, a, part);
+    if (e == hipSuccess) e = hipEventRecord(ev.second, s->stream);
+    t->kind.push_back(part);
+    return e;
+}
+
 // Bring the aux fields to the current state (moments + chemical potentials).
-int ensure_aux(telbm_solver* s) {
+int ensure_aux(telbm_solver* s, Timing* t = nullptr) {
     if (s->aux_valid) return TELBM_OK;
     StepArgs a = args_of(s, false);
     for (int part = 0; part < 2; ++part) {
-        hipError_t e = launch_part(s->p.lattice, s->p.precision, a, part);
+        hipError_t e = timed_launch(s, a, part, t);
         if (e != hipSuccess) return hip_fail(s, e, "moment/chemical-potential launch");
     }
     s->aux_valid = true;
@@ -192,14 +218,15 @@ bool unstable(const telbm_diag& d) {
 }
 
 // One time step.
-int one_step(telbm_solver* s, bool diag) {
-    int rc = ensure_aux(s);
+int one_step(telbm_solver* s, bool diag, Timing* t = nullptr) {
+    int rc = ensure_aux(s, t);
     if (rc) return rc;
     StepArgs a = args_of(s, true);
     a.diag = diag ? 1 : 0;
-    hipError_t e = launch_part(s->p.lattice, s->p.precision, a, 2);
+    hipError_t e = timed_launch(s, a, 2, t);
     if (e != hipSuccess) return hip_fail(s, e, "collision launch");
     s->cur = 1 - s->cur;
+    if (mixed(s)) s->ref = 1 - s->ref;  // the new state is relative to the density just used
     s->aux_valid = false;
     if (diag) {
         s->diag_step = s->steps;
@@ -275,7 +302,8 @@ int telbm_create(const telbm_params* p, void* device_arena, size_t bytes, telbm_
     s->arena_bytes = bytes;
     s->pop[0] = s->arena + L.o_pop0;
     s->pop[1] = s->arena + L.o_pop1;
-    s->rho = (double*)(s->arena + L.o_rho);
+    s->rhob[0] = (double*)(s->arena + L.o_rho0);
+    s->rhob[1] = (double*)(s->arena + L.o_rho1);
     s->phi = (double*)(s->arena + L.o_phi);
     s->mux = (double*)(s->arena + L.o_mux);
     s->mup = (double*)(s->arena + L.o_mup);
@@ -284,6 +312,7 @@ int telbm_create(const telbm_params* p, void* device_arena, size_t bytes, telbm_
     s->bad = (unsigned long long*)(s->arena + L.o_bad);
     s->stream = nullptr;
     s->cur = 0;
+    s->ref = 0;
     s->aux_valid = false;
     s->steps = 0;
     s->diag_step = -1;
@@ -313,10 +342,11 @@ int telbm_init_fields(telbm_solver* s, const double* rho, const double* phi, con
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     // stage: rho, phi into the aux fields, u into the spare population buffer
     double* u_dev = u ? (double*)s->pop[1 - s->cur] : nullptr;
-    hipError_t e = hipMemcpyAsync(s->rho, rho, N * sizeof(double), kind, s->stream);
+    double* rho_dev = density_out(s);
+    hipError_t e = hipMemcpyAsync(rho_dev, rho, N * sizeof(double), kind, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s->phi, phi, N * sizeof(double), kind, s->stream);
     if (e == hipSuccess && u) e = hipMemcpyAsync(u_dev, u, (size_t)D * N * sizeof(double), kind, s->stream);
-    if (e == hipSuccess) e = launch_check_init(s->g, D, s->rho, s->phi, u_dev, s->bad, s->stream);
+    if (e == hipSuccess) e = launch_check_init(s->g, D, rho_dev, s->phi, u_dev, s->bad, s->stream);
     unsigned long long bad = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(s->diag_host, s->bad, sizeof(bad), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -329,6 +359,8 @@ int telbm_init_fields(telbm_solver* s, const double* rho, const double* phi, con
     e = launch_part(s->p.lattice, s->p.precision, a, 1);
     if (e == hipSuccess) e = launch_init(s->p.lattice, s->p.precision, a, u_dev);
     if (e != hipSuccess) return hip_fail(s, e, "init launch");
+    // FP32 form: the initial populations are relative to the initial density
+    if (mixed(s)) s->ref = 1 - s->ref;
     s->steps = 0;
     s->diag_step = -1;
     s->diag_unread = false;
@@ -398,72 +430,38 @@ int telbm_step_count(const telbm_solver* s, int64_t* steps) {
 
 int telbm_time_kernels(telbm_solver* s, int64_t n, double* ms, int* kinds) {
     if (!s || !ms || !kinds || n < 1) return TELBM_ERR_INVAL;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
-    std::vector<int> kind;
-    ev.reserve(3 * n);
-    kind.reserve(3 * n);
-    // pre-create enough events
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool(3 * n);
-    for (auto& pr : pool) {
-        if (hipEventCreate(&pr.first) != hipSuccess || hipEventCreate(&pr.second) != hipSuccess)
-            return fail(s, TELBM_ERR_DEVICE, "event create");
-    }
+    Timing t;
+    t.pool.resize(3 * n);
     int rc = TELBM_OK;
-    size_t used = 0;
+    size_t made = 0;
+    for (auto& pr : t.pool) {
+        if (hipEventCreate(&pr.first) != hipSuccess) { rc = fail(s, TELBM_ERR_DEVICE, "event create"); break; }
+        if (hipEventCreate(&pr.second) != hipSuccess) { (void)hipEventDestroy(pr.first); rc = fail(s, TELBM_ERR_DEVICE, "event create"); break; }
+        ++made;
+    }
     for (int64_t i = 0; i < n && rc == TELBM_OK; ++i) {
-        // events for the (up to) three launches of this step
-        std::vector<std::pair<hipEvent_t, hipEvent_t>> step_ev(pool.begin() + used, pool.begin() + used + 3);
-        used += 3;
-        // the launches of one_step, each bracketed by its own event pair
-        StepArgs a = args_of(s, false);
-        if (!s->aux_valid) {
-            for (int part = 0; part < 2; ++part) {
-                hipEventRecord(step_ev[part].first, s->stream);
-                hipError_t e = launch_part(s->p.lattice, s->p.precision, a, part);
-                hipEventRecord(step_ev[part].second, s->stream);
-                if (e != hipSuccess) { rc = hip_fail(s, e, "timed launch"); break; }
-                ev.push_back(step_ev[part]);
-                kind.push_back(part);
-            }
-            s->aux_valid = true;
-        }
-        if (rc) break;
         const bool diag = s->p.diag_every > 0 && (s->steps % s->p.diag_every) == 0;
-        StepArgs b = args_of(s, true);
-        b.diag = diag ? 1 : 0;
-        hipEventRecord(step_ev[2].first, s->stream);
-        hipError_t e = launch_part(s->p.lattice, s->p.precision, b, 2);
-        hipEventRecord(step_ev[2].second, s->stream);
-        if (e != hipSuccess) { rc = hip_fail(s, e, "timed launch"); break; }
-        ev.push_back(step_ev[2]);
-        kind.push_back(2);
-        s->cur = 1 - s->cur;
-        s->aux_valid = false;
-        if (diag) {
-            s->diag_step = s->steps;
-            s->diag_unread = true;
-        }
-        s->steps += 1;
+        rc = one_step(s, diag, &t);
     }
     if (rc == TELBM_OK) {
         hipError_t e = hipStreamSynchronize(s->stream);
         if (e != hipSuccess) rc = hip_fail(s, e, "timed synchronise");
     }
-    double sum[3] = {0, 0, 0};
-    int cnt[3] = {0, 0, 0};
     if (rc == TELBM_OK) {
-        for (size_t i = 0; i < ev.size(); ++i) {
-            float t = 0.f;
-            hipEventElapsedTime(&t, ev[i].first, ev[i].second);
-            sum[kind[i]] += t;
-            cnt[kind[i]] += 1;
+        double sum[3] = {0, 0, 0};
+        int cnt[3] = {0, 0, 0};
+        for (size_t i = 0; i < t.used; ++i) {
+            float ms1 = 0.f;
+            if (hipEventElapsedTime(&ms1, t.pool[i].first, t.pool[i].second) != hipSuccess) continue;
+            sum[t.kind[i]] += ms1;
+            cnt[t.kind[i]] += 1;
         }
         for (int k = 0; k < 3; ++k) ms[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
         *kinds = 3;
     }
-    for (auto& pr : pool) {
-        hipEventDestroy(pr.first);
-        hipEventDestroy(pr.second);
+    for (size_t i = 0; i < made; ++i) {
+        (void)hipEventDestroy(t.pool[i].first);
+        (void)hipEventDestroy(t.pool[i].second);
     }
     return rc;
 }
@@ -482,9 +480,9 @@ double telbm_algorithmic_bytes_per_update(const telbm_solver* s) {
 
 int telbm_destroy(telbm_solver* s) {
     if (!s) return TELBM_ERR_INVAL;
-    if (s->stream) hipStreamSynchronize(s->stream);
-    else hipDeviceSynchronize();
-    if (s->diag_host) hipHostFree(s->diag_host);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    else (void)hipDeviceSynchronize();
+    if (s->diag_host) (void)hipHostFree(s->diag_host);
     delete s;
     return TELBM_OK;
 }

@@ -2,10 +2,15 @@
 // time step (arXiv:1710.07486) and their host-side launchers.
 //
 // Layout in HBM (structure of arrays, x fastest):
-//   populations  pop[k][n], k = 0..Q-1 for f (offset form f_i - w_i rho_ref),
-//                k = Q..2Q-1 for g; n = (z ny + y) nx + x.  The buffer holds
-//                the post-collision values f*(x) of the previous step, so a
-//                step pulls f_i(x) = pop[i][x - c_i] (periodic).
+//   populations  pop[k][n], k = 0..Q-1 for f, k = Q..2Q-1 for g;
+//                n = (z ny + y) nx + x.  The buffer holds the post-collision
+//                values f*(x) of the previous step, so a step pulls
+//                f_i(x) = pop[i][x - c_i] (periodic).  FP64: absolute values.
+//                FP32: f is stored as the deviation f*_i(x) - w_i rho(x) from
+//                the writing node's own density (a collision invariant), and
+//                rebuilt on the pull from the FP64 densities of the previous
+//                state, so the stored number keeps FP32 relative precision in
+//                the dilute gas as well as in the liquid.
 //   aux fields   rho[n], phi[n], mux[n] (= mu_rho - cs2 ln rho), mup[n] (mu_phi),
 //                all FP64.
 //
@@ -59,13 +64,24 @@ __device__ __forceinline__ int64_t node_of(const GridDims& g, const Tile& t) {
     return ((int64_t)t.z * g.ny + t.y) * g.nx + t.x;
 }
 
+// FP32 populations are deviations from w_i times the writer's density.
+template <typename T>
+struct Deviation {
+    static constexpr bool on = false;
+};
+template <>
+struct Deviation<float> {
+    static constexpr bool on = true;
+};
+
 // ---------------------------------------------------------------------------
-// Moments: rho = sum_i f_i (+ rho_ref for the offset form), phi = sum_i g_i.
+// Moments: rho = sum_i f_i, phi = sum_i g_i (FP64 accumulation).  rho_ref is
+// the density field the stored f values are relative to (FP32 form only).
 // ---------------------------------------------------------------------------
 template <int L, typename T>
 __global__ __launch_bounds__(BX* BY) void k_moments(GridDims g, const T* __restrict__ pop,
-                                                    double* __restrict__ rho, double* __restrict__ phi,
-                                                    double rho_ref) {
+                                                    const double* __restrict__ rho_ref,
+                                                    double* __restrict__ rho, double* __restrict__ phi) {
     using Lt = Lattice<L>;
     constexpr int Q = Lt::Q;
     const Tile t = tile_coords(g);
@@ -76,10 +92,12 @@ __global__ __launch_bounds__(BX* BY) void k_moments(GridDims g, const T* __restr
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int64_t m = n + nbr_off<L>(nb, i, -1);
-        r += double(pop[(int64_t)i * g.N + m]);
+        double fi = double(pop[(int64_t)i * g.N + m]);
+        if (Deviation<T>::on) fi += Lt::w[i] * rho_ref[m];
+        r += fi;
         p += double(pop[(int64_t)(Q + i) * g.N + m]);
     }
-    rho[n] = r + rho_ref;
+    rho[n] = r;
     phi[n] = p;
 }
 
@@ -181,7 +199,8 @@ __device__ void diag_block_reduce(double* vals, double* __restrict__ out) {
 // ---------------------------------------------------------------------------
 template <int L, typename T>
 __global__ __launch_bounds__(BX* BY) void k_collide(GridDims g, PhysConst k, const T* __restrict__ src,
-                                                    T* __restrict__ dst, const double* __restrict__ rho,
+                                                    T* __restrict__ dst, const double* __restrict__ rho_ref,
+                                                    const double* __restrict__ rho,
                                                     const double* __restrict__ phi,
                                                     const double* __restrict__ mux,
                                                     const double* __restrict__ mup,
@@ -194,16 +213,19 @@ __global__ __launch_bounds__(BX* BY) void k_collide(GridDims g, PhysConst k, con
     if (t.in) {
         const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
         const int64_t n = node_of(g, t);
+        const double r = rho[n], p = phi[n];
+        // f in offset form about this node's density in the FP32 form
         R f[Q];
         R jx = 0, jy = 0, jz = 0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            f[i] = src[(int64_t)i * g.N + n + nbr_off<L>(nb, i, -1)];
+            const int64_t m = n + nbr_off<L>(nb, i, -1);
+            f[i] = src[(int64_t)i * g.N + m];
+            if (Deviation<T>::on) f[i] += R(Lt::w[i] * (rho_ref[m] - r));
             if (Lt::c[i][0]) jx += Lt::c[i][0] > 0 ? f[i] : -f[i];
             if (Lt::c[i][1]) jy += Lt::c[i][1] > 0 ? f[i] : -f[i];
             if (Lt::c[i][2]) jz += Lt::c[i][2] > 0 ? f[i] : -f[i];
         }
-        const double r = rho[n], p = phi[n];
         double gx[3], gp[3];
         gradient2<L>(nb, n, mux, mup, gx, gp);
         double F[3];
@@ -213,7 +235,7 @@ __global__ __launch_bounds__(BX* BY) void k_collide(GridDims g, PhysConst k, con
         R u[3] = {R(double(jx) * ir), R(double(jy) * ir), R(double(jz) * ir)};
         R du[3] = {R(F[0] * ir), R(F[1] * ir), R(F[2] * ir)};
         if (Lt::D == 2) u[2] = du[2] = R(0);
-        const double gam = collide_f<L, R>(f, r, u, du, R(k.beta), R(k.rho_ref));
+        const double gam = collide_f<L, R>(f, r, u, du, R(k.beta), Deviation<T>::on ? r : 0.0);
 #pragma unroll
         for (int i = 0; i < Q; ++i) dst[(int64_t)i * g.N + n] = f[i];
 
@@ -299,11 +321,15 @@ __global__ __launch_bounds__(BX* BY) void k_init(GridDims g, PhysConst k, const 
         if (Lt::D == 3) u[2] = R(u0[2 * g.N + n]);
     }
     R fd[Q], gg[Q];
-    equilibria<L, R>(rho[n], R(phi[n]), R(mup[n]), u, R(k.Gamma), R(k.rho_ref), fd, gg);
+    const double r = rho[n];
+    equilibria<L, R>(r, R(phi[n]), R(mup[n]), u, R(k.Gamma), Deviation<T>::on ? r : 0.0, fd, gg);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int64_t m = n + nbr_off<L>(nb, i, -1);
-        pop[(int64_t)i * g.N + m] = fd[i];
+        // FP32: the value stored at m is relative to the density held for m
+        R v = fd[i];
+        if (Deviation<T>::on) v += R(Lt::w[i] * (r - rho[m]));
+        pop[(int64_t)i * g.N + m] = v;
         pop[(int64_t)(Q + i) * g.N + m] = gg[i];
     }
 }
@@ -328,6 +354,7 @@ __global__ void k_check_init(int64_t N, int D, const double* __restrict__ rho, c
 // ---------------------------------------------------------------------------
 template <int L, typename T>
 __global__ __launch_bounds__(BX* BY) void k_macro(GridDims g, PhysConst k, const T* __restrict__ pop,
+                                                  const double* __restrict__ rho_ref,
                                                   const double* __restrict__ rho,
                                                   const double* __restrict__ phi,
                                                   const double* __restrict__ mux,
@@ -364,7 +391,9 @@ __global__ __launch_bounds__(BX* BY) void k_macro(GridDims g, PhysConst k, const
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 if (Lt::c[i][d] == 0) continue;
-                const double fi = double(pop[(int64_t)i * g.N + n + nbr_off<L>(nb, i, -1)]);
+                const int64_t m = n + nbr_off<L>(nb, i, -1);
+                double fi = double(pop[(int64_t)i * g.N + m]);
+                if (Deviation<T>::on) fi += Lt::w[i] * rho_ref[m];
                 j += Lt::c[i][d] > 0 ? fi : -fi;
             }
             v = (j + 0.5 * F) / r;
@@ -387,12 +416,12 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
     const dim3 blk(BX, BY, 1);
     const dim3 grd(grid_blocks(a.g), 1, 1);
     if (part == 0) {
-        k_moments<L, T><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho, a.phi, a.k.rho_ref);
+        k_moments<L, T><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
     } else if (part == 1) {
         k_chempot<L><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup);
     } else {
-        k_collide<L, T><<<grd, blk, 0, a.stream>>>(a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho, a.phi, a.mux,
-                                                     a.mup, a.partials, a.diag);
+        k_collide<L, T><<<grd, blk, 0, a.stream>>>(a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref, a.rho,
+                                                     a.phi, a.mux, a.mup, a.partials, a.diag);
         if (a.diag) k_diag_final<<<1, 256, 0, a.stream>>>(a.partials, (int)grd.x, a.diag_out);
     }
     return hipGetLastError();
@@ -427,8 +456,8 @@ hipError_t launch_check_init(const GridDims& g, int D, const double* rho, const 
 
 template <int L, typename T>
 static hipError_t launch_macro_t(const StepArgs& a, int field, double* out) {
-    k_macro<L, T><<<grid_blocks(a.g), dim3(BX, BY, 1), 0, a.stream>>>(a.g, a.k, (const T*)a.src, a.rho, a.phi,
-                                                                      a.mux, a.mup, field, out);
+    k_macro<L, T><<<grid_blocks(a.g), dim3(BX, BY, 1), 0, a.stream>>>(a.g, a.k, (const T*)a.src, a.rho_ref,
+                                                                      a.rho, a.phi, a.mux, a.mup, field, out);
     return hipGetLastError();
 }
 

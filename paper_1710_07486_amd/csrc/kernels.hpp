@@ -26,6 +26,7 @@ struct StepArgs {
     PhysConst k;
     const void* src;     // populations holding the current state
     void* dst;           // populations receiving the next state
+    const double* rho_ref;  // density the stored f values are relative to (FP32 form)
     double *rho, *phi, *mux, *mup;
     double* partials;    // per-block diagnostic partials
     double* diag_out;    // final diagnostics (kDiag doubles)

@@ -63,7 +63,6 @@ struct PhysConst {
     double beta;                  // 1 / (2 tau), tau = 3 nu + 1/2
     double omega_phi;             // 1 / tau_phi
     double Gamma;                 // M / (tau_phi - 1/2)
-    double rho_ref;               // storage offset of the f populations (0 in FP64)
 };
 
 // Periodic neighbour offsets of one node: off[d][k] is the element offset of
@@ -155,8 +154,9 @@ __device__ __forceinline__ R eq_inv(const AxisEq<R>* ax, int i) {
 
 // ---------------------------------------------------------------------------
 // One collision of the density populations.  fd[i] holds f_i - w_i rho_ref
-// (rho_ref = 0 in FP64) and is overwritten with the post-collision value in
-// the same offset form.  u = j / rho, du = F / rho.
+// and is overwritten with the post-collision value in the same offset form
+// (rho_ref = 0 for absolute populations; the node's own density for the
+// FP32 deviation storage).  u = j / rho, du = F / rho.
 //
 // KBC: df = f - feq; the shear part ds carries exactly the traceless second
 // moments of df (normal-stress differences and off-diagonal stresses), the
@@ -167,12 +167,12 @@ __device__ __forceinline__ R eq_inv(const AxisEq<R>* ax, int i) {
 // ---------------------------------------------------------------------------
 template <int L, typename R>
 __device__ __forceinline__ double collide_f(R* fd, double rho_d, const R* u, const R* du, R beta,
-                                            R rho_ref) {
+                                            double rho_ref) {
     using Lt = Lattice<L>;
     constexpr int Q = Lt::Q;
     constexpr int D = Lt::D;
     const R rho = R(rho_d);
-    const R drho = R(rho_d - double(rho_ref));  // rho - rho_ref, exact in FP64 before rounding
+    const R drho = R(rho_d - rho_ref);  // rho - rho_ref, formed in FP64 before rounding
 
     AxisEq<R> ax[3], ax2[3];
 #pragma unroll
@@ -277,10 +277,10 @@ __device__ __forceinline__ void collide_g(R* g, R phi, R mu_phi, const R* u, R G
     }
 }
 
-// Equilibrium populations for initialisation (offset form for f).
+// Equilibrium populations for initialisation, f in offset form about rho_ref.
 template <int L, typename R>
 __device__ __forceinline__ void equilibria(double rho_d, R phi, R mu_phi, const R* u, R Gamma,
-                                           R rho_ref, R* fd, R* g) {
+                                           double rho_ref, R* fd, R* g) {
     using Lt = Lattice<L>;
     constexpr int Q = Lt::Q;
     AxisEq<R> ax[3];
@@ -288,7 +288,7 @@ __device__ __forceinline__ void equilibria(double rho_d, R phi, R mu_phi, const 
     for (int a = 0; a < Lt::D; ++a) ax[a] = axis_eq<R>(u[a], false);
     if (Lt::D == 2) ax[2].e[0] = ax[2].e[1] = ax[2].e[2] = R(0);
     const R rho = R(rho_d);
-    const R drho = R(rho_d - double(rho_ref));
+    const R drho = R(rho_d - rho_ref);
 #pragma unroll
     for (int i = 0; i < Q; ++i) fd[i] = R(Lt::w[i]) * (drho + rho * eq_excess<L, R>(ax, i));
     for (int i = 0; i < Q; ++i) g[i] = R(0);

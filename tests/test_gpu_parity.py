@@ -132,7 +132,7 @@ def test_init_rejects_bad_fields(orc):
             elif bad == "nan":
                 p[0, 5, 5] = np.nan
             else:
-                uu[0, 1, 1] = 1.0
+                uu[0, 0, 1, 1] = 1.0
             with pytest.raises(T.TelbmError) as e:
                 s.init_fields(r, p, uu)
             assert e.value.code == 2  # TELBM_ERR_UNSTABLE
@@ -153,18 +153,21 @@ def test_diagnostics_and_device_read(orc):
     with T.Solver(pl) as s:
         s.init_fields(torch.from_numpy(rho).cuda(), torch.from_numpy(phi).cuda())
         s.step(41)
+        s.sync()
+        # telbm_diagnostics reports the current state (before step 41)
+        d_next = st.run(1, diag=True)
+        st.steps -= 1
         d = s.diagnostics()
-        assert d["step"] == 40
-        ref = d_or[40]
+        assert d["step"] == 41
+        ref = d_next[0]
         assert abs(d["mass"] / ref[0] - 1) < 1e-13
         assert abs(d["phi_total"] - ref[1]) < 1e-11 * abs(ref[0])
         assert np.abs(np.array(d["mom"]) - ref[2:5]).max() < 1e-10
         assert d["nonfinite"] == 0 and d["min_rho"] > 0
         assert 1.0 < d["gamma_min"] <= d["gamma_max"] < 3.0
-        st.run(0)
         rd = s.read("rho", device=True)
         assert rd.is_cuda
-        assert abs(float(rd.sum()) - st.fields()["rho"].sum()) < 1e-9 * abs(ref[0])
+        assert abs(float(rd.sum()) - ref[0]) < 1e-9 * abs(ref[0])
 
 
 def _window(arr, center, r):
@@ -210,7 +213,10 @@ def test_full_size_sampled(orc, case):
         cz = int(c[2]) if nz > 1 else 0
         pts.append((cz, int(c[1]), int(c[0])))
         pts.append((cz, int(c[1]), int(c[0] + d["radius"])))
+    # absolute tolerances: FP64 1e-10 of the field scale; FP32 storage 1e-5 of it
+    scale = {"rho": po.rho_l, "phi": po.chi, "ux": 0.05, "uy": 0.05}
     tol = FP64_TOL if precision == 0 else 1e-5
+    worst = {k: 0.0 for k in scale}
     for (z, y, x) in pts:
         wz = 1 if nz == 1 else 2 * r + 1
         sub = orc.Params(**{**po.__dict__, "nx": 2 * r + 1, "ny": 2 * r + 1, "nz": wz})
@@ -222,7 +228,7 @@ def test_full_size_sampled(orc, case):
         f = st.fields()
         cz = 0 if nz == 1 else r
         for name, ref in (("rho", f["rho"]), ("phi", f["phi"]), ("ux", f["u"][0]), ("uy", f["u"][1])):
-            want = ref[cz, r, r]
-            got = g[name][z, y, x]
-            scale = {"rho": po.rho_l, "phi": po.chi, "ux": 0.05, "uy": 0.05}[name]
-            assert abs(got - want) <= tol * scale, (case, (z, y, x), name, got, want)
+            worst[name] = max(worst[name], abs(g[name][z, y, x] - ref[cz, r, r]) / scale[name])
+    print("sampled max error / scale", case, worst, flush=True)
+    for name, v in worst.items():
+        assert v <= tol, (case, name, v)
