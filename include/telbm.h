@@ -48,9 +48,11 @@ extern "C" {
 
 /* Storage precision of the populations. */
 #define TELBM_FP64 0
-#define TELBM_FP32_MIXED 1  /* FP32 populations stored as deviations from w_i rho_ref;
-                               FP64 for the equation-of-state chemical potential and
-                               for the entropic stabiliser ratio                     */
+#define TELBM_FP32_MIXED 1  /* FP32 populations: each f value is stored as its deviation
+                               f_i - w_i rho_ref with rho_ref the FP64 density of the node
+                               that wrote it; FP64 for the densities, the equation-of-
+                               state chemical potential and the entropic stabiliser
+                               ratio                                                 */
 
 /* Fields that telbm_read can return. */
 #define TELBM_FIELD_RHO 0    /* density rho                                         */
@@ -76,7 +78,7 @@ extern "C" {
  *  nu                  kinematic viscosity eta/rho (uniform; tau = 3 nu + 1/2).
  *  mobility            M of the Cahn-Hilliard equation (7).
  *  tau_phi             relaxation time of the phase-field populations (> 1/2).
- *  rho_ref             FP32_MIXED reference density (0 means rho_l).
+ *  rho_ref             reserved (the FP32 form takes each writer's own density).
  *  diag_every          conservation/health diagnostics every this many steps
  *                      (0 disables).
  * Validation: 0 < T < T_c, rho_l > rho_g > 0, nu > 0, tau_phi > 1/2, chi != 0,
@@ -184,6 +186,53 @@ double telbm_algorithmic_bytes_per_update(const telbm_solver *s);
 
 int telbm_destroy(telbm_solver *s);
 const char *telbm_last_error(const telbm_solver *s);
+
+
+/* ------------------------------------------------------------------------- */
+/* Batched form: many lattices of uneven size and parameters advanced        */
+/* together.  All instances share lattice and precision; each has its own    */
+/* sizes, temperature, free-energy and transport parameters.  Each phase of  */
+/* a step is one persistent launch over a work list of (instance, tile)      */
+/* items; runs of an even number of steps are replayed from captured HIP     */
+/* graphs.  Diagnostics are not collected in this form.                     */
+/* ------------------------------------------------------------------------- */
+typedef struct telbm_batch telbm_batch;
+
+/* Arena bytes for `count` instances with parameters p[0..count-1]. */
+int telbm_batch_required_bytes(const telbm_params *p, int count, size_t *bytes);
+
+/* Create a batch in a borrowed, 256-byte aligned device arena. */
+int telbm_batch_create(const telbm_params *p, int count, void *device_arena, size_t bytes,
+                       telbm_batch **out);
+
+int telbm_batch_set_stream(telbm_batch *b, void *stream);
+
+/* Number of compiled tile shapes and the shape (threads along x, y) of one. */
+int telbm_batch_tile_variants(int *count);
+int telbm_batch_tile_shape(int variant, int *bx, int *by);
+
+/* Select the tile shape and the persistent grid size (workgroups per compute
+ * unit, 1..64).  Synchronises the stream and drops captured graphs. */
+int telbm_batch_set_tiles(telbm_batch *b, int variant, int wg_per_cu);
+
+/* Steps per captured graph (even; 0 disables graphs).  Default 10. */
+int telbm_batch_set_graph_steps(telbm_batch *b, int steps_per_graph);
+
+/* Initialise instance idx (same semantics as telbm_init_fields).  Every
+ * instance must be initialised before the first telbm_batch_step. */
+int telbm_batch_init_fields(telbm_batch *b, int idx, const double *rho, const double *phi,
+                            const double *u, int on_device);
+
+/* Advance all instances n steps (asynchronous). */
+int telbm_batch_step(telbm_batch *b, int64_t n);
+
+/* Read one field of instance idx (synchronises). */
+int telbm_batch_read(telbm_batch *b, int idx, int field, double *out, int on_device);
+
+int telbm_batch_sync(telbm_batch *b);
+int telbm_batch_step_count(const telbm_batch *b, int64_t *steps);
+int telbm_batch_destroy(telbm_batch *b);
+const char *telbm_batch_last_error(const telbm_batch *b);
 
 #ifdef __cplusplus
 }

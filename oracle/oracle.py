@@ -323,6 +323,19 @@ class State:
         return out
 
 
+def discrete_coexistence(p: Params, steps: int = 20000, n: int = 256, width: float = 2.0):
+    """(rho_g, rho_l) of a relaxed flat slab of liquid 1 in gas with p's free
+    energy on p's lattice: the discretised model's own coexistence densities."""
+    import dataclasses
+    q = dataclasses.replace(p, nx=n, ny=1, nz=1)
+    x = np.arange(n, dtype=np.float64)
+    c1 = 0.5 * (np.tanh((x - n / 4) / width) - np.tanh((x - 3 * n / 4) / width))
+    st = State(q, (p.rho_g + (p.rho_l - p.rho_g) * c1).reshape(1, 1, n), (q.chi * c1).reshape(1, 1, n))
+    st.run(steps)
+    r = st.fields()["rho"]
+    return float(r[0, 0, 0]), float(r[0, 0, n // 2])
+
+
 def num_threads() -> int:
     return lib().orc_num_threads()
 

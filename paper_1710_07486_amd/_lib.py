@@ -75,6 +75,10 @@ def load():
     """Load the in-tree HIP library; raises if it has not been built."""
     global _lib
     if _lib is None:
+        # torch brings its own HIP runtime (same soname as /opt/rocm's); load it
+        # first so that libtelbm binds to that one and the process holds a
+        # single HIP runtime
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1710_07486_amd.build`")
         L = ctypes.CDLL(LIB_PATH)

@@ -1,0 +1,34 @@
+"""Coexisting densities of the discretised model.
+
+The lattice model's bulk densities on either side of a flat liquid-gas
+interface differ from the Maxwell construction of the continuum EOS (by a
+few per cent at density ratio 10 and a factor of ~3 in the gas at ratio
+1000, shrinking as the interface widens).  Starting drops at the model's own
+coexistence densities avoids the strong pressure waves that a Maxwell start
+launches (in 3D they focus at the drop centre).  The densities are measured
+by relaxing a periodic 1D slab of liquid 1 in gas with the library itself.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .solver import Params, Solver
+
+
+def discrete_coexistence(p: Params, steps: int = 20000, n: int = 256, width: float = 2.0):
+    """(rho_g, rho_l) of a relaxed flat slab with p's free energy, on p's lattice."""
+    import dataclasses
+    q = dataclasses.replace(p, nx=n, ny=1, nz=1, diag_every=0)
+    from .solver import coexistence
+    rg, rl, _, _ = coexistence(p.T, p.a, p.b, p.R)
+    if p.rho_g and p.rho_l:
+        rg, rl = p.rho_g, p.rho_l
+    x = np.arange(n, dtype=np.float64)
+    c1 = 0.5 * (np.tanh((x - n / 4) / width) - np.tanh((x - 3 * n / 4) / width))
+    rho = (rg + (rl - rg) * c1).reshape(1, 1, n)
+    phi = (q.chi * c1).reshape(1, 1, n)
+    with Solver(q) as s:
+        s.init_fields(rho, phi)
+        s.step(steps)
+        r = s.read("rho", check=False)
+    return float(r[0, 0, 0]), float(r[0, 0, n // 2])

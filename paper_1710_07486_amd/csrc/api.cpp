@@ -28,7 +28,7 @@ struct telbm_solver {
     double* rhob[2];     // densities: the current state's reference and the computed one
     double *phi, *mux, *mup, *partials, *diag_dev;
     unsigned long long* bad;
-    double* diag_host;  // pinned
+    double diag_host[16];  // host copy of the diagnostics (pageable; 80 bytes)
     hipStream_t stream;
     int cur;             // pop[cur] holds the state
     int ref;             // FP32 form: the state's f values are relative to rhob[ref]
@@ -132,6 +132,7 @@ PhysConst derive(const telbm_params& p, double rho_g, double rho_l, double C) {
     k.Dc = D;
     const double tau = 3.0 * p.nu + 0.5;
     k.beta = 1.0 / (2.0 * tau);
+    k.inv_beta = 2.0 * tau;
     k.omega_phi = 1.0 / p.tau_phi;
     k.Gamma = p.mobility / (p.tau_phi - 0.5);
     return k;
@@ -319,11 +320,6 @@ int telbm_create(const telbm_params* p, void* device_arena, size_t bytes, telbm_
     s->diag_unread = false;
     memset(&s->last, 0, sizeof(s->last));
     s->last.step = -1;
-    hipError_t e = hipHostMalloc((void**)&s->diag_host, 16 * sizeof(double), hipHostMallocDefault);
-    if (e != hipSuccess) {
-        delete s;
-        return TELBM_ERR_DEVICE;
-    }
     *out = s;
     return TELBM_OK;
 }
@@ -482,7 +478,6 @@ int telbm_destroy(telbm_solver* s) {
     if (!s) return TELBM_ERR_INVAL;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     else (void)hipDeviceSynchronize();
-    if (s->diag_host) (void)hipHostFree(s->diag_host);
     delete s;
     return TELBM_OK;
 }

@@ -24,6 +24,7 @@
 
 #include "kernels.hpp"
 #include "lattice.hpp"
+#include "node_ops.hpp"
 
 namespace telbm {
 
@@ -64,101 +65,6 @@ __device__ __forceinline__ int64_t node_of(const GridDims& g, const Tile& t) {
     return ((int64_t)t.z * g.ny + t.y) * g.nx + t.x;
 }
 
-// FP32 populations are deviations from w_i times the writer's density.
-template <typename T>
-struct Deviation {
-    static constexpr bool on = false;
-};
-template <>
-struct Deviation<float> {
-    static constexpr bool on = true;
-};
-
-// ---------------------------------------------------------------------------
-// Moments: rho = sum_i f_i, phi = sum_i g_i (FP64 accumulation).  rho_ref is
-// the density field the stored f values are relative to (FP32 form only).
-// ---------------------------------------------------------------------------
-template <int L, typename T>
-__global__ __launch_bounds__(BX* BY) void k_moments(GridDims g, const T* __restrict__ pop,
-                                                    const double* __restrict__ rho_ref,
-                                                    double* __restrict__ rho, double* __restrict__ phi) {
-    using Lt = Lattice<L>;
-    constexpr int Q = Lt::Q;
-    const Tile t = tile_coords(g);
-    if (!t.in) return;
-    const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
-    const int64_t n = node_of(g, t);
-    double r = 0.0, p = 0.0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int64_t m = n + nbr_off<L>(nb, i, -1);
-        double fi = double(pop[(int64_t)i * g.N + m]);
-        if (Deviation<T>::on) fi += Lt::w[i] * rho_ref[m];
-        r += fi;
-        p += double(pop[(int64_t)(Q + i) * g.N + m]);
-    }
-    rho[n] = r;
-    phi[n] = p;
-}
-
-// ---------------------------------------------------------------------------
-// Chemical potentials with lattice Laplacians
-//   lap psi(x) = 6 sum_i w_i [psi(x + c_i) - psi(x)].
-// ---------------------------------------------------------------------------
-template <int L>
-__global__ __launch_bounds__(BX* BY) void k_chempot(GridDims g, PhysConst k, const double* __restrict__ rho,
-                                                    const double* __restrict__ phi, double* __restrict__ mux,
-                                                    double* __restrict__ mup) {
-    using Lt = Lattice<L>;
-    constexpr int Q = Lt::Q;
-    const Tile t = tile_coords(g);
-    if (!t.in) return;
-    const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
-    const int64_t n = node_of(g, t);
-    const double r0 = rho[n], p0 = phi[n];
-    double lr = 0.0, lp = 0.0;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const int64_t m = n + nbr_off<L>(nb, i, +1);
-        lr += Lt::w[i] * (rho[m] - r0);
-        lp += Lt::w[i] * (phi[m] - p0);
-    }
-    double mx, mp;
-    chem_pot(k, r0, p0, 6.0 * lr, 6.0 * lp, &mx, &mp);
-    mux[n] = mx;
-    mup[n] = mp;
-}
-
-// Isotropic gradient grad psi(x) = 3 sum_i w_i c_i psi(x + c_i).
-template <int L>
-__device__ __forceinline__ void gradient2(const Nbr& nb, int64_t n, const double* __restrict__ a,
-                                          const double* __restrict__ b, double* ga, double* gb) {
-    using Lt = Lattice<L>;
-    constexpr int Q = Lt::Q;
-    ga[0] = ga[1] = ga[2] = 0.0;
-    gb[0] = gb[1] = gb[2] = 0.0;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const int64_t m = n + nbr_off<L>(nb, i, +1);
-        const double va = Lt::w[i] * a[m], vb = Lt::w[i] * b[m];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            if (Lt::c[i][d] > 0) {
-                ga[d] += va;
-                gb[d] += vb;
-            } else if (Lt::c[i][d] < 0) {
-                ga[d] -= va;
-                gb[d] -= vb;
-            }
-        }
-    }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        ga[d] *= 3.0;
-        gb[d] *= 3.0;
-    }
-}
-
 // Block-level reduction of the health diagnostics into partials[block][kDiag].
 __device__ void diag_block_reduce(double* vals, double* __restrict__ out) {
     // vals: 0 sum rho, 1 sum phi, 2-4 sum j, 5 max |u|, 6 min rho, 7 min gamma,
@@ -194,78 +100,39 @@ __device__ void diag_block_reduce(double* vals, double* __restrict__ out) {
 }
 
 // ---------------------------------------------------------------------------
-// The fused collision kernel: pull f, g; force from the excess potentials;
-// KBC with exact-difference forcing; phase-field BGK; write in place order.
+// Kernels of the three phases over one lattice (one node per thread).
 // ---------------------------------------------------------------------------
 template <int L, typename T>
-__global__ __launch_bounds__(BX* BY) void k_collide(GridDims g, PhysConst k, const T* __restrict__ src,
+__global__ __launch_bounds__(BX* BY) void k_moments(GridDims g, const T* __restrict__ pop,
+                                                    const double* __restrict__ rho_ref,
+                                                    double* __restrict__ rho, double* __restrict__ phi) {
+    const Tile t = tile_coords(g);
+    if (t.in) node_moments<L, T>(g, pop, rho_ref, rho, phi, t.x, t.y, t.z);
+}
+
+template <int L>
+__global__ __launch_bounds__(BX* BY) void k_chempot(GridDims g, PhysConst k, const double* __restrict__ rho,
+                                                    const double* __restrict__ phi, double* __restrict__ mux,
+                                                    double* __restrict__ mup) {
+    const Tile t = tile_coords(g);
+    if (t.in) node_chempot<L>(g, k, rho, phi, mux, mup, t.x, t.y, t.z);
+}
+
+template <int L, typename T>
+__global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(2))) void k_collide(GridDims g, PhysConst k, const T* __restrict__ src,
                                                     T* __restrict__ dst, const double* __restrict__ rho_ref,
                                                     const double* __restrict__ rho,
                                                     const double* __restrict__ phi,
                                                     const double* __restrict__ mux,
                                                     const double* __restrict__ mup,
                                                     double* __restrict__ partials, int diag) {
-    using Lt = Lattice<L>;
-    using R = T;
-    constexpr int Q = Lt::Q;
-    const Tile t = tile_coords(g);
+    // the block's tile of BX x BY nodes, two lanes per node
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + BY - 1) / BY;
+    const int bx = b % bxc, rest = b / bxc, by = rest % byc, bz = rest / byc;
     double dv[kDiag] = {0, 0, 0, 0, 0, 0, INFINITY, INFINITY, -INFINITY, 0};
-    if (t.in) {
-        const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
-        const int64_t n = node_of(g, t);
-        const double r = rho[n], p = phi[n];
-        // f in offset form about this node's density in the FP32 form
-        R f[Q];
-        R jx = 0, jy = 0, jz = 0;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const int64_t m = n + nbr_off<L>(nb, i, -1);
-            f[i] = src[(int64_t)i * g.N + m];
-            if (Deviation<T>::on) f[i] += R(Lt::w[i] * (rho_ref[m] - r));
-            if (Lt::c[i][0]) jx += Lt::c[i][0] > 0 ? f[i] : -f[i];
-            if (Lt::c[i][1]) jy += Lt::c[i][1] > 0 ? f[i] : -f[i];
-            if (Lt::c[i][2]) jz += Lt::c[i][2] > 0 ? f[i] : -f[i];
-        }
-        double gx[3], gp[3];
-        gradient2<L>(nb, n, mux, mup, gx, gp);
-        double F[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) F[d] = -r * gx[d] - p * gp[d];
-        const double ir = 1.0 / r;
-        R u[3] = {R(double(jx) * ir), R(double(jy) * ir), R(double(jz) * ir)};
-        R du[3] = {R(F[0] * ir), R(F[1] * ir), R(F[2] * ir)};
-        if (Lt::D == 2) u[2] = du[2] = R(0);
-        const double gam = collide_f<L, R>(f, r, u, du, R(k.beta), Deviation<T>::on ? r : 0.0);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) dst[(int64_t)i * g.N + n] = f[i];
-
-        R gg[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) gg[i] = src[(int64_t)(Q + i) * g.N + n + nbr_off<L>(nb, i, -1)];
-        R up[3] = {u[0] + R(0.5) * du[0], u[1] + R(0.5) * du[1], u[2] + R(0.5) * du[2]};
-        collide_g<L, R>(gg, R(p), R(mup[n]), up, R(k.Gamma), R(k.omega_phi));
-#pragma unroll
-        for (int i = 0; i < Q; ++i) dst[(int64_t)(Q + i) * g.N + n] = gg[i];
-
-        if (diag) {
-            const double ux = double(jx) * ir + 0.5 * F[0] * ir;
-            const double uy = double(jy) * ir + 0.5 * F[1] * ir;
-            const double uz = double(jz) * ir + 0.5 * F[2] * ir;
-            const double um = sqrt(ux * ux + uy * uy + uz * uz);
-            dv[0] = r;
-            dv[1] = p;
-            dv[2] = double(jx);
-            dv[3] = double(jy);
-            dv[4] = double(jz);
-            dv[5] = um;
-            dv[6] = r;
-            dv[7] = gam;
-            dv[8] = gam;
-            const bool bad = !(isfinite(r) && isfinite(p) && isfinite(um)) || !(r > 0.0);
-            dv[9] = bad ? 1.0 : 0.0;
-            if (bad) dv[5] = INFINITY;
-        }
-    }
+    tile_collide_pair<L, T, BX * BY>(g, k, src, dst, rho_ref, rho, phi, mux, mup, bx * BX, by * BY, bz, BX, BY,
+                                     threadIdx.y * BX + threadIdx.x, diag != 0, dv);
     if (diag) diag_block_reduce(dv, partials);
 }
 

@@ -14,7 +14,9 @@ namespace telbm {
 constexpr int kD2Q9 = 0;
 constexpr int kD3Q27 = 1;
 
-// Velocity sets in the conventional order: rest, faces, edges, corners.
+// Velocity sets: rest first, then opposite pairs (2p-1, 2p) = (c, -c) for
+// p = 1..(Q-1)/2, ordered faces, edges, corners.  The pair order lets half a
+// wavefront handle each direction's opposite (see node_ops.hpp).
 template <int L>
 struct Lattice;
 
@@ -22,8 +24,8 @@ template <>
 struct Lattice<kD2Q9> {
     static constexpr int D = 2;
     static constexpr int Q = 9;
-    static constexpr int c[9][3] = {{0, 0, 0},  {1, 0, 0},  {0, 1, 0},   {-1, 0, 0}, {0, -1, 0},
-                                    {1, 1, 0},  {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+    static constexpr int c[9][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+                                    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
     static constexpr double w[9] = {4.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9, 1.0 / 9,
                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 };
@@ -61,6 +63,7 @@ struct PhysConst {
     double twoA, twoB, Dc;
     // kinetics
     double beta;                  // 1 / (2 tau), tau = 3 nu + 1/2
+    double inv_beta;              // 2 tau
     double omega_phi;             // 1 / tau_phi
     double Gamma;                 // M / (tau_phi - 1/2)
 };
@@ -107,20 +110,38 @@ struct AxisEq {
     R inv[3];    // 1 / factor for c = 0, +1, -1
 };
 
+// Reciprocals without the full IEEE division sequence: the hardware estimate,
+// refined by Newton steps to full precision in FP64 (one step suffices for
+// FP32, whose estimate is accurate to about one ulp).
+__device__ __forceinline__ double fast_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = r * (2.0 - x * r);
+    r = r * (2.0 - x * r);
+    return r;
+}
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// S - 1 = sqrt(1 + 3u^2) - 1.  FP32: 3u^2/(1 + S), free of cancellation, so
+// that the equilibrium's deviation from w_i rho keeps its relative precision
+// for the deviation storage.  FP64: S - 1 directly; its absolute error is
+// one ulp of 1, the rounding the factor (1 + e) carries anyway.
+__device__ __forceinline__ double s_minus_1(double u2, double S) { return S - 1.0; }
+__device__ __forceinline__ float s_minus_1(float u2, float S) { return 3.0f * u2 * fast_rcp(1.0f + S); }
+
 template <typename R>
 __device__ __forceinline__ AxisEq<R> axis_eq(R u, bool want_inv) {
     AxisEq<R> a;
     const R u2 = u * u;
     const R S = sqrt(R(1) + R(3) * u2);
-    const R sm1 = R(3) * u2 / (R(1) + S);  // S - 1
+    const R sm1 = s_minus_1(u2, S);
     a.e[0] = -sm1;
     a.e[1] = R(2) * sm1 + R(3) * u;
     a.e[2] = R(2) * sm1 - R(3) * u;
     if (want_inv) {
-        // (2S-1+3u)(2S-1-3u) = 5 + 3u^2 - 4S; one division for the three reciprocals
+        // (2S-1+3u)(2S-1-3u) = 5 + 3u^2 - 4S; one reciprocal for the three
         const R twoms = R(1) - sm1;                  // 2 - S
         const R prod = R(5) + R(3) * u2 - R(4) * S;  // > 0 for |u| < 1
-        const R inv = R(1) / (twoms * prod);
+        const R inv = fast_rcp(twoms * prod);
         a.inv[0] = R(1.5) * prod * inv;
         a.inv[1] = R(6) * (R(1) + R(2) * sm1 - R(3) * u) * twoms * inv;
         a.inv[2] = R(6) * (R(1) + R(2) * sm1 + R(3) * u) * twoms * inv;
@@ -153,21 +174,26 @@ __device__ __forceinline__ R eq_inv(const AxisEq<R>* ax, int i) {
 }
 
 // ---------------------------------------------------------------------------
-// One collision of the density populations.  fd[i] holds f_i - w_i rho_ref
-// and is overwritten with the post-collision value in the same offset form
-// (rho_ref = 0 for absolute populations; the node's own density for the
-// FP32 deviation storage).  u = j / rho, du = F / rho.
+// One collision of the density populations, streamed: the Q populations are
+// not held in registers across the passes; `load(i)` re-reads f_i (offset
+// form f_i - w_i rho_ref) and `store(i, v)` writes the post-collision value in
+// the same form.  u = j / rho, du = F / rho; P holds the raw second moments
+// sum_i fd_i c_ia c_ib (xx, yy, zz, xy, xz, yz) of the offset-form f.
 //
 // KBC: df = f - feq; the shear part ds carries exactly the traceless second
 // moments of df (normal-stress differences and off-diagonal stresses), the
 // rest dh = df - ds.  gamma = 1/beta - (2 - 1/beta) <ds|dh>/<dh|dh> with
 // <X|Y> = sum X_i Y_i / feq_i, and gamma = 2 when <dh|dh> = 0.
 // f* = f - beta (2 ds + gamma dh) + feq(rho, u + du) - feq(rho, u).
-// The two scalar products and their ratio are accumulated in FP64.
+// The second moments of the product-form equilibrium are closed forms,
+// rho (2 S_a - 1)/3 on the diagonal and rho u_a u_b off it, so df's moments
+// need no pass over feq.  The scalar products and their ratio are FP64.
+// `fence()` separates the passes so that their reloads stay reloads.
 // ---------------------------------------------------------------------------
-template <int L, typename R>
-__device__ __forceinline__ double collide_f(R* fd, double rho_d, const R* u, const R* du, R beta,
-                                            double rho_ref) {
+template <int L, typename R, class Load, class Store, class Fence>
+__device__ __forceinline__ double collide_f(Load load, Store store, Fence fence, const double* P,
+                                            double rho_d, double inv_rho_d, const R* u, const R* du, R beta,
+                                            double inv_beta, double rho_ref) {
     using Lt = Lattice<L>;
     constexpr int Q = Lt::Q;
     constexpr int D = Lt::D;
@@ -185,73 +211,65 @@ __device__ __forceinline__ double collide_f(R* fd, double rho_d, const R* u, con
         ax[2].inv[0] = ax[2].inv[1] = ax[2].inv[2] = R(1);
         ax2[2] = ax[2];
     }
-
-    // non-equilibrium part df = f - feq (kept in fd) and its second moments
-    R mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const R w = R(Lt::w[i]);
-        const R feq_off = w * (drho + rho * eq_excess<L, R>(ax, i));  // feq_i - w_i rho_ref
-        const R df = fd[i] - feq_off;
-        fd[i] = df;
-        const int cx = Lt::c[i][0], cy = Lt::c[i][1], cz = Lt::c[i][2];
-        if (cx) mxx += df;
-        if (cy) myy += df;
-        if (cz) mzz += df;
-        if (cx * cy) mxy += (cx * cy > 0) ? df : -df;
-        if (cx * cz) mxz += (cx * cz > 0) ? df : -df;
-        if (cy * cz) myz += (cy * cz > 0) ? df : -df;
+    // second moments of df = (offset f) - (offset feq); the offset w_i rho_ref
+    // is isotropic (cs2 rho_ref delta_ab) and drops out of the traceless part
+    double m[6];
+    for (int a = 0; a < 3; ++a) {
+        const double sm1 = a < D ? double(-ax[a].e[0]) : 0.0;  // S_a - 1
+        m[a] = P[a] - (2.0 * rho_d * sm1 + (rho_d - rho_ref)) * (1.0 / 3.0);
     }
-    // traceless diagonal parts
+    m[3] = P[3] - rho_d * double(u[0]) * double(u[1]);
+    m[4] = P[4] - rho_d * double(u[0]) * double(u[2]);
+    m[5] = P[5] - rho_d * double(u[1]) * double(u[2]);
     R dxx, dyy, dzz;
     if (D == 2) {
-        dxx = R(0.5) * (mxx - myy);
+        dxx = R(0.5 * (m[0] - m[1]));
         dyy = -dxx;
         dzz = 0;
     } else {
-        const R tr = (mxx + myy + mzz) * R(1.0 / 3.0);
-        dxx = mxx - tr;
-        dyy = myy - tr;
-        dzz = mzz - tr;
+        const double tr = (m[0] + m[1] + m[2]) * (1.0 / 3.0);
+        dxx = R(m[0] - tr);
+        dyy = R(m[1] - tr);
+        dzz = R(m[2] - tr);
     }
+    const R mxy = R(m[3]), mxz = R(m[4]), myz = R(m[5]);
     // shear part: ds_i = sum_pq M_pq b_p(c_ix) b_q(c_iy) b_r(c_iz) over the
-    // second-order (deviatoric) moments, with the D1Q3 dual basis
-    // b0 = [c == 0], b1 = c/2, b2 = (c == 0 ? -1 : 1/2).
+    // traceless second moments, with the D1Q3 dual basis b0 = [c == 0],
+    // b1 = c/2, b2 = (c == 0 ? -1 : 1/2); only the nonzero terms are formed.
     auto shear = [&](int i) -> R {
         const int cx = Lt::c[i][0], cy = Lt::c[i][1], cz = Lt::c[i][2];
-        const R b2x = cx ? R(0.5) : R(-1), b2y = cy ? R(0.5) : R(-1), b2z = cz ? R(0.5) : R(-1);
-        const R b0x = cx ? R(0) : R(1), b0y = cy ? R(0) : R(1), b0z = cz ? R(0) : R(1);
-        R s = dxx * b2x * b0y * b0z + dyy * b0x * b2y * b0z;
-        if (D == 3) s += dzz * b0x * b0y * b2z;
-        s += mxy * R(0.25 * cx * cy) * b0z;
-        if (D == 3) {
-            s += mxz * R(0.25 * cx * cz) * b0y;
-            s += myz * R(0.25 * cy * cz) * b0x;
+        const int nz = (cx != 0) + (cy != 0) + (cz != 0);
+        if (nz == 1) return R(0.5) * (cx ? dxx : (cy ? dyy : dzz));
+        if (nz == 2) {
+            if (!cz) return R(0.25 * cx * cy) * mxy;
+            if (!cy) return R(0.25 * cx * cz) * mxz;
+            return R(0.25 * cy * cz) * myz;
         }
-        return s;
+        if (nz == 0) return -(dxx + dyy + dzz);  // zero up to rounding (traceless)
+        return R(0);
     };
-    const R inv_rho = R(1) / rho;
+    auto feq_off = [&](int i) -> R { return R(Lt::w[i]) * (drho + rho * eq_excess<L, R>(ax, i)); };
+    const R inv_rho = R(inv_rho_d);
     double sh = 0.0, hh = 0.0;
+    fence();
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const R s = shear(i);
-        const R dh = fd[i] - s;
+        const R dh = load(i) - feq_off(i) - s;
         const double ifeq = double(inv_rho * eq_inv<L, R>(ax, i));
         sh += double(s) * double(dh) * ifeq;
         hh += double(dh) * double(dh) * ifeq;
     }
-    const double binv = 1.0 / double(beta);
-    const double gamma = (hh > 1e-300) ? (binv - (2.0 - binv) * sh / hh) : 2.0;
+    const double gamma = (hh > 1e-300) ? (inv_beta - (2.0 - inv_beta) * sh / hh) : 2.0;
     const R g = R(gamma);
+    // f* = (1 - 2 beta) ds + (1 - beta gamma) dh + feq(u + du)  (offset form)
+    const R cs = R(1) - R(2) * beta, ch = R(1) - beta * g;
+    fence();
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const R w = R(Lt::w[i]);
-        const R ex = eq_excess<L, R>(ax, i);
-        const R feq_off = w * (drho + rho * ex);
         const R s = shear(i);
-        const R dh = fd[i] - s;
-        const R edm = w * rho * (eq_excess<L, R>(ax2, i) - ex);
-        fd[i] = feq_off + fd[i] - beta * (R(2) * s + g * dh) + edm;
+        const R dh = load(i) - feq_off(i) - s;
+        store(i, cs * s + ch * dh + R(Lt::w[i]) * (drho + rho * eq_excess<L, R>(ax2, i)));
     }
     return gamma;
 }

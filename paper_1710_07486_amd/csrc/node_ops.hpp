@@ -1,0 +1,501 @@
+// node_ops.hpp -- the per-node bodies of the three phases of a time step,
+// shared by the single-lattice kernels (kernels.hip) and the batched
+// persistent kernels (batch.hip).  Each body handles the node (x, y, z) of
+// one periodic lattice described by GridDims / PhysConst and raw pointers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+#include "lattice.hpp"
+
+namespace telbm {
+
+// FP32 populations are deviations from w_i times the writer's density; FP64
+// populations are absolute.
+template <typename T>
+struct Deviation {
+    static constexpr bool on = false;
+};
+template <>
+struct Deviation<float> {
+    static constexpr bool on = true;
+};
+
+__device__ __forceinline__ int64_t node_index(const GridDims& g, int x, int y, int z) {
+    return ((int64_t)z * g.ny + y) * g.nx + x;
+}
+
+// Phase 1: rho = sum_i f_i, phi = sum_i g_i of the pulled populations, FP64
+// accumulation.  rho_ref: densities the stored f values are relative to.
+template <int L, typename T>
+__device__ __forceinline__ void node_moments(const GridDims& g, const T* __restrict__ pop,
+                                             const double* __restrict__ rho_ref, double* __restrict__ rho,
+                                             double* __restrict__ phi, int x, int y, int z) {
+    using Lt = Lattice<L>;
+    constexpr int Q = Lt::Q;
+    const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
+    const int64_t n = node_index(g, x, y, z);
+    double r = 0.0, p = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int64_t m = n + nbr_off<L>(nb, i, -1);
+        double fi = double(pop[(int64_t)i * g.N + m]);
+        if (Deviation<T>::on) fi += Lt::w[i] * rho_ref[m];
+        r += fi;
+        p += double(pop[(int64_t)(Q + i) * g.N + m]);
+    }
+    rho[n] = r;
+    phi[n] = p;
+}
+
+// Phase 2: chemical potentials with the lattice Laplacians
+// lap psi(x) = 6 sum_i w_i [psi(x + c_i) - psi(x)].
+template <int L>
+__device__ __forceinline__ void node_chempot(const GridDims& g, const PhysConst& k, const double* __restrict__ rho,
+                                             const double* __restrict__ phi, double* __restrict__ mux,
+                                             double* __restrict__ mup, int x, int y, int z) {
+    using Lt = Lattice<L>;
+    constexpr int Q = Lt::Q;
+    const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
+    const int64_t n = node_index(g, x, y, z);
+    const double r0 = rho[n], p0 = phi[n];
+    double lr = 0.0, lp = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int64_t m = n + nbr_off<L>(nb, i, +1);
+        lr += Lt::w[i] * (rho[m] - r0);
+        lp += Lt::w[i] * (phi[m] - p0);
+    }
+    double mx, mp;
+    chem_pot(k, r0, p0, 6.0 * lr, 6.0 * lp, &mx, &mp);
+    mux[n] = mx;
+    mup[n] = mp;
+}
+
+// Isotropic gradient grad psi(x) = 3 sum_i w_i c_i psi(x + c_i) of two fields.
+template <int L>
+__device__ __forceinline__ void gradient2(const Nbr& nb, int64_t n, const double* __restrict__ a,
+                                          const double* __restrict__ b, double* ga, double* gb) {
+    using Lt = Lattice<L>;
+    constexpr int Q = Lt::Q;
+    ga[0] = ga[1] = ga[2] = 0.0;
+    gb[0] = gb[1] = gb[2] = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int64_t m = n + nbr_off<L>(nb, i, +1);
+        const double va = Lt::w[i] * a[m], vb = Lt::w[i] * b[m];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (Lt::c[i][d] > 0) {
+                ga[d] += va;
+                gb[d] += vb;
+            } else if (Lt::c[i][d] < 0) {
+                ga[d] -= va;
+                gb[d] -= vb;
+            }
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        ga[d] *= 3.0;
+        gb[d] *= 3.0;
+    }
+}
+
+// Compiler fence between the sub-phases of the collision kernel: memory
+// operations are not moved across it, so the loads of one sub-phase are not
+// hoisted into the live range of the previous one.
+__device__ __forceinline__ void phase_fence() { asm volatile("" ::: "memory"); }
+
+// 32-bit periodic neighbour offsets (node counts below 2^31 per lattice): the
+// pulls then address a uniform per-direction base plus a 32-bit lane offset.
+struct Nbr32 {
+    int32_t ox[3], oy[3], oz[3];
+};
+
+__device__ __forceinline__ Nbr32 make_nbr32(int x, int y, int z, int nx, int ny, int nz) {
+    Nbr32 n;
+    const int32_t sy = nx, sz = nx * ny;
+    n.ox[1] = 0;
+    n.ox[0] = x == 0 ? nx - 1 : -1;
+    n.ox[2] = x == nx - 1 ? -(nx - 1) : 1;
+    n.oy[1] = 0;
+    n.oy[0] = (y == 0 ? ny - 1 : -1) * sy;
+    n.oy[2] = (y == ny - 1 ? -(ny - 1) : 1) * sy;
+    n.oz[1] = 0;
+    n.oz[0] = (z == 0 ? nz - 1 : -1) * sz;
+    n.oz[2] = (z == nz - 1 ? -(nz - 1) : 1) * sz;
+    return n;
+}
+
+template <int L>
+__device__ __forceinline__ uint32_t nbr32(const Nbr32& nb, uint32_t n, int i, int sign) {
+    using Lt = Lattice<L>;
+    return n + nb.ox[1 + sign * Lt::c[i][0]] + nb.oy[1 + sign * Lt::c[i][1]] + nb.oz[1 + sign * Lt::c[i][2]];
+}
+
+// Element m of the array at `base`, addressed as a uniform base plus a 32-bit
+// byte offset (the host guarantees every per-direction slice is < 4 GiB), so
+// that the load takes its base from scalar registers.
+template <typename T>
+__device__ __forceinline__ T ld(const T* __restrict__ base, uint32_t m) {
+    return *(const T*)((const char*)base + (uint32_t)(m * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void st(T* __restrict__ base, uint32_t m, T v) {
+    *(T*)((char*)base + (uint32_t)(m * (uint32_t)sizeof(T))) = v;
+}
+
+// Phase 3: pull f, g; force from the excess potentials; KBC with
+// exact-difference forcing; phase-field BGK; write the node's own slots.
+// If diag, dv receives {rho, phi, j (3), |u_phys|, rho, gamma, gamma, bad}.
+// The three sub-phases (stencil, f, g) are kept apart by scheduling barriers
+// so that their loads do not all become live at once.
+template <int L, typename T>
+__device__ __forceinline__ void node_collide(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
+                                             T* __restrict__ dst, const double* __restrict__ rho_ref,
+                                             const double* __restrict__ rho, const double* __restrict__ phi,
+                                             const double* __restrict__ mux, const double* __restrict__ mup,
+                                             int x, int y, int z, bool diag, double* dv) {
+    using Lt = Lattice<L>;
+    using R = T;
+    constexpr int Q = Lt::Q;
+    const Nbr32 nb = make_nbr32(x, y, z, g.nx, g.ny, g.nz);
+    const uint32_t n = (uint32_t)node_index(g, x, y, z);
+    const double r = ld(rho, n), p = ld(phi, n);
+
+    // force from the isotropic gradients of the two potentials
+    double gx[3] = {0, 0, 0}, gp[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const uint32_t m = nbr32<L>(nb, n, i, +1);
+        const double va = Lt::w[i] * ld(mux, m), vb = Lt::w[i] * ld(mup, m);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (Lt::c[i][d] > 0) {
+                gx[d] += va;
+                gp[d] += vb;
+            } else if (Lt::c[i][d] < 0) {
+                gx[d] -= va;
+                gp[d] -= vb;
+            }
+        }
+    }
+    double F[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) F[d] = -r * 3.0 * gx[d] - p * 3.0 * gp[d];
+    phase_fence();
+
+    // pass A: pull f (offset form about this node's density in the FP32
+    // form); momentum and raw second moments
+    auto load = [&](int i) -> R {
+        const uint32_t m = nbr32<L>(nb, n, i, -1);
+        R v = ld(src + (size_t)i * g.N, m);
+        if (Deviation<T>::on) v += R(Lt::w[i] * (ld(rho_ref, m) - r));
+        return v;
+    };
+    R jx = 0, jy = 0, jz = 0;
+    double P[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const R fi = load(i);
+        const int cx = Lt::c[i][0], cy = Lt::c[i][1], cz = Lt::c[i][2];
+        if (cx) jx += cx > 0 ? fi : -fi;
+        if (cy) jy += cy > 0 ? fi : -fi;
+        if (cz) jz += cz > 0 ? fi : -fi;
+        const double fd = double(fi);
+        if (cx) P[0] += fd;
+        if (cy) P[1] += fd;
+        if (cz) P[2] += fd;
+        if (cx * cy) P[3] += cx * cy > 0 ? fd : -fd;
+        if (cx * cz) P[4] += cx * cz > 0 ? fd : -fd;
+        if (cy * cz) P[5] += cy * cz > 0 ? fd : -fd;
+    }
+    const double ir = 1.0 / r;
+    R u[3] = {R(double(jx) * ir), R(double(jy) * ir), R(double(jz) * ir)};
+    R du[3] = {R(F[0] * ir), R(F[1] * ir), R(F[2] * ir)};
+    if (Lt::D == 2) u[2] = du[2] = R(0);
+    // passes B and C re-pull f instead of keeping it in registers
+    auto store = [&](int i, R v) { st(dst + (size_t)i * g.N, n, v); };
+    const double gam = collide_f<L, R>(load, store, phase_fence, P, r, ir, u, du, R(k.beta), k.inv_beta,
+                                       Deviation<T>::on ? r : 0.0);
+    phase_fence();
+
+    R gg[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) gg[i] = ld(src + (size_t)(Q + i) * g.N, nbr32<L>(nb, n, i, -1));
+    R up[3] = {u[0] + R(0.5) * du[0], u[1] + R(0.5) * du[1], u[2] + R(0.5) * du[2]};
+    collide_g<L, R>(gg, R(p), R(ld(mup, n)), up, R(k.Gamma), R(k.omega_phi));
+#pragma unroll
+    for (int i = 0; i < Q; ++i) st(dst + (size_t)(Q + i) * g.N, n, gg[i]);
+
+    if (diag) {
+        const double ux = double(jx) * ir + 0.5 * F[0] * ir;
+        const double uy = double(jy) * ir + 0.5 * F[1] * ir;
+        const double uz = double(jz) * ir + 0.5 * F[2] * ir;
+        const double um = sqrt(ux * ux + uy * uy + uz * uz);
+        const bool bad = !(isfinite(r) && isfinite(p) && isfinite(um)) || !(r > 0.0);
+        dv[0] = r;
+        dv[1] = p;
+        dv[2] = double(jx);
+        dv[3] = double(jy);
+        dv[4] = double(jz);
+        dv[5] = bad ? INFINITY : um;
+        dv[6] = r;
+        dv[7] = gam;
+        dv[8] = gam;
+        dv[9] = bad ? 1.0 : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Collision with the work of one node split over two lanes l and l ^ 32 of a
+// wavefront.  The directions come in opposite pairs (2p-1, 2p) = (c, -c);
+// side A (lanes 0-31) takes c_{2p-1} and the rest population, side B (lanes
+// 32-63) takes c_{2p}.  Side B works in the mirrored frame x -> -x: the
+// entropic factors satisfy psi_-(u) = psi_+(-u) and the phase-field
+// equilibrium is even in (c, u) -> (-c, -u), so side B runs the same
+// instructions with u -> -u on the opposite populations.  Odd partial sums
+// (momentum, gradients) combine as A - B, even ones (second moments, the
+// entropic scalar products) as A + B, each with one cross-half exchange.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double xhalf(double v) { return __shfl_xor(v, 32); }
+__device__ __forceinline__ float xhalf(float v) { return __shfl_xor(v, 32); }
+
+template <int L, typename T>
+__device__ __forceinline__ void node_collide_pair(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
+                                                  T* __restrict__ dst, const double* __restrict__ rho_ref,
+                                                  const double* __restrict__ rho, const double* __restrict__ phi,
+                                                  const double* __restrict__ mux, const double* __restrict__ mup,
+                                                  int x, int y, int z, int side, bool diag, double* dv) {
+    using Lt = Lattice<L>;
+    using R = T;
+    constexpr int Q = Lt::Q;
+    constexpr int NP = (Q - 1) / 2;
+    constexpr int D = Lt::D;
+    const bool B = side != 0;
+    Nbr32 nb = make_nbr32(x, y, z, g.nx, g.ny, g.nz);
+    if (B) {  // this side's frame is mirrored: +c here is -c on the lattice
+        int32_t t;
+        t = nb.ox[0]; nb.ox[0] = nb.ox[2]; nb.ox[2] = t;
+        t = nb.oy[0]; nb.oy[0] = nb.oy[2]; nb.oy[2] = t;
+        t = nb.oz[0]; nb.oz[0] = nb.oz[2]; nb.oz[2] = t;
+    }
+    const uint32_t n = (uint32_t)node_index(g, x, y, z);
+    const uint32_t soff = B ? (uint32_t)g.N : 0u;  // side B addresses direction 2p, the next array
+    const double r = ld(rho, n), p = ld(phi, n);
+
+    // gradients of the two potentials (frame components)
+    double gx[3] = {0, 0, 0}, gp[3] = {0, 0, 0};
+#pragma unroll
+    for (int q = 1; q <= NP; ++q) {
+        const int i = 2 * q - 1;
+        const uint32_t m = nbr32<L>(nb, n, i, +1);
+        const double va = Lt::w[i] * ld(mux, m), vb = Lt::w[i] * ld(mup, m);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (Lt::c[i][d] > 0) {
+                gx[d] += va;
+                gp[d] += vb;
+            } else if (Lt::c[i][d] < 0) {
+                gx[d] -= va;
+                gp[d] -= vb;
+            }
+        }
+    }
+    double F[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double ga = 3.0 * (gx[d] - xhalf(gx[d]));
+        const double gb = 3.0 * (gp[d] - xhalf(gp[d]));
+        F[d] = -r * ga - p * gb;
+    }
+    phase_fence();
+
+    // pull f: side A directions 2p-1 at x - c, side B directions 2p at x + c
+    R f[NP];
+    R f0 = ld(src, n);
+    if (Deviation<T>::on) f0 += R(Lt::w[0] * (ld(rho_ref, n) - r));
+    R jx = 0, jy = 0, jz = 0;
+    double P[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int q = 1; q <= NP; ++q) {
+        const int i = 2 * q - 1;
+        const uint32_t m = nbr32<L>(nb, n, i, -1);
+        R v = ld(src + (size_t)i * g.N, soff + m);
+        if (Deviation<T>::on) v += R(Lt::w[i] * (ld(rho_ref, m) - r));
+        f[q - 1] = v;
+        const int cx = Lt::c[i][0], cy = Lt::c[i][1], cz = Lt::c[i][2];
+        if (cx) jx += cx > 0 ? v : -v;
+        if (cy) jy += cy > 0 ? v : -v;
+        if (cz) jz += cz > 0 ? v : -v;
+        const double fd = double(v);
+        if (cx) P[0] += fd;
+        if (cy) P[1] += fd;
+        if (cz) P[2] += fd;
+        if (cx * cy) P[3] += cx * cy > 0 ? fd : -fd;
+        if (cx * cz) P[4] += cx * cz > 0 ? fd : -fd;
+        if (cy * cz) P[5] += cy * cz > 0 ? fd : -fd;
+    }
+    jx = jx - xhalf(jx);
+    jy = jy - xhalf(jy);
+    jz = jz - xhalf(jz);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) P[a] += xhalf(P[a]);
+    const double ir = 1.0 / r;
+    R u[3] = {R(double(jx) * ir), R(double(jy) * ir), R(double(jz) * ir)};
+    R du[3] = {R(F[0] * ir), R(F[1] * ir), R(F[2] * ir)};
+    if (D == 2) u[2] = du[2] = R(0);
+
+    // KBC with exact-difference forcing (see collide_f in lattice.hpp)
+    const R rr = R(r);
+    const double rho_off = Deviation<T>::on ? r : 0.0;
+    const R drho = R(r - rho_off);
+    AxisEq<R> ax[3], ax2[3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        ax[a] = axis_eq<R>(u[a], true);
+        ax2[a] = axis_eq<R>(u[a] + du[a], false);
+    }
+    if (D == 2) {
+        ax[2].e[0] = ax[2].e[1] = ax[2].e[2] = R(0);
+        ax[2].inv[0] = ax[2].inv[1] = ax[2].inv[2] = R(1);
+        ax2[2] = ax[2];
+    }
+    double mm[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double sm1 = a < D ? double(-ax[a].e[0]) : 0.0;  // S_a - 1
+        mm[a] = P[a] - (2.0 * r * sm1 + (r - rho_off)) * (1.0 / 3.0);
+    }
+    mm[3] = P[3] - r * double(u[0]) * double(u[1]);
+    mm[4] = P[4] - r * double(u[0]) * double(u[2]);
+    mm[5] = P[5] - r * double(u[1]) * double(u[2]);
+    R dxx, dyy, dzz;
+    if (D == 2) {
+        dxx = R(0.5 * (mm[0] - mm[1]));
+        dyy = -dxx;
+        dzz = 0;
+    } else {
+        const double tr = (mm[0] + mm[1] + mm[2]) * (1.0 / 3.0);
+        dxx = R(mm[0] - tr);
+        dyy = R(mm[1] - tr);
+        dzz = R(mm[2] - tr);
+    }
+    const R mxy = R(mm[3]), mxz = R(mm[4]), myz = R(mm[5]);
+    auto shear = [&](int i) -> R {
+        const int cx = Lt::c[i][0], cy = Lt::c[i][1], cz = Lt::c[i][2];
+        const int nzc = (cx != 0) + (cy != 0) + (cz != 0);
+        if (nzc == 1) return R(0.5) * (cx ? dxx : (cy ? dyy : dzz));
+        if (nzc == 2) {
+            if (!cz) return R(0.25 * cx * cy) * mxy;
+            if (!cy) return R(0.25 * cx * cz) * mxz;
+            return R(0.25 * cy * cz) * myz;
+        }
+        if (nzc == 0) return -(dxx + dyy + dzz);
+        return R(0);
+    };
+    const R inv_rho = R(ir);
+    double sh = 0.0, hh = 0.0;
+#pragma unroll
+    for (int q = 1; q <= NP; ++q) {
+        const int i = 2 * q - 1;
+        const R s = shear(i);
+        const R dh = f[q - 1] - R(Lt::w[i]) * (drho + rr * eq_excess<L, R>(ax, i)) - s;
+        f[q - 1] = dh;
+        const double ifeq = double(inv_rho * eq_inv<L, R>(ax, i));
+        sh += double(s) * double(dh) * ifeq;
+        hh += double(dh) * double(dh) * ifeq;
+    }
+    const R s0 = shear(0);
+    const R dh0 = f0 - R(Lt::w[0]) * (drho + rr * eq_excess<L, R>(ax, 0)) - s0;
+    if (!B) {
+        const double ifeq0 = double(inv_rho * eq_inv<L, R>(ax, 0));
+        sh += double(s0) * double(dh0) * ifeq0;
+        hh += double(dh0) * double(dh0) * ifeq0;
+    }
+    sh += xhalf(sh);
+    hh += xhalf(hh);
+    const double gam = (hh > 1e-300) ? (k.inv_beta - (2.0 - k.inv_beta) * sh / hh) : 2.0;
+    const R beta = R(k.beta);
+    const R cs = R(1) - R(2) * beta, ch = R(1) - beta * R(gam);
+#pragma unroll
+    for (int q = 1; q <= NP; ++q) {
+        const int i = 2 * q - 1;
+        const R v = cs * shear(i) + ch * f[q - 1] + R(Lt::w[i]) * (drho + rr * eq_excess<L, R>(ax2, i));
+        st(dst + (size_t)i * g.N, soff + n, v);
+    }
+    if (!B) st(dst, n, cs * s0 + ch * dh0 + R(Lt::w[0]) * (drho + rr * eq_excess<L, R>(ax2, 0)));
+    phase_fence();
+
+    // phase-field BGK on the same split (geq is even in (c, u) -> (-c, -u))
+    R up[3] = {u[0] + R(0.5) * du[0], u[1] + R(0.5) * du[1], u[2] + R(0.5) * du[2]};
+    const R ph = R(p), om = R(k.omega_phi);
+    const R uu = up[0] * up[0] + up[1] * up[1] + up[2] * up[2];
+    const R base = R(3) * R(k.Gamma) * R(ld(mup, n)) - R(1.5) * ph * uu;
+#pragma unroll
+    for (int q = 1; q <= NP; ++q) {
+        const int i = 2 * q - 1;
+        const R gi = ld(src + (size_t)(Q + i) * g.N, soff + nbr32<L>(nb, n, i, -1));
+        const R cu = R(Lt::c[i][0]) * up[0] + R(Lt::c[i][1]) * up[1] + R(Lt::c[i][2]) * up[2];
+        const R geq = R(Lt::w[i]) * (base + R(3) * ph * cu + R(4.5) * ph * cu * cu);
+        st(dst + (size_t)(Q + i) * g.N, soff + n, gi + om * (geq - gi));
+    }
+    if (!B) {
+        const R g0 = ld(src + (size_t)Q * g.N, n);
+        const R geq0 = ph - R(1.0 - Lt::w[0]) * base - R(1.5) * ph * uu;
+        st(dst + (size_t)Q * g.N, n, g0 + om * (geq0 - g0));
+    }
+
+    if (diag && !B) {
+        const double ux = double(jx) * ir + 0.5 * F[0] * ir;
+        const double uy = double(jy) * ir + 0.5 * F[1] * ir;
+        const double uz = double(jz) * ir + 0.5 * F[2] * ir;
+        const double um = sqrt(ux * ux + uy * uy + uz * uz);
+        const bool bad = !(isfinite(r) && isfinite(p) && isfinite(um)) || !(r > 0.0);
+        dv[0] = r;
+        dv[1] = p;
+        dv[2] = double(jx);
+        dv[3] = double(jy);
+        dv[4] = double(jz);
+        dv[5] = bad ? INFINITY : um;
+        dv[6] = r;
+        dv[7] = gam;
+        dv[8] = gam;
+        dv[9] = bad ? 1.0 : 0.0;
+    }
+}
+
+// All nodes of a tile of TW x TH nodes at (x0, y0, z), processed by a block
+// of NT threads with the two sides of each node on lanes l and l ^ 32.
+template <int L, typename T, int NT>
+__device__ __forceinline__ void tile_collide_pair(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
+                                                  T* __restrict__ dst, const double* __restrict__ rho_ref,
+                                                  const double* __restrict__ rho, const double* __restrict__ phi,
+                                                  const double* __restrict__ mux, const double* __restrict__ mup,
+                                                  int x0, int y0, int z, int TW, int TH, int tid, bool diag,
+                                                  double* dv) {
+    const int lane = tid & 63, wave = tid >> 6;
+    const int side = lane >> 5;
+    for (int base = 0; base < TW * TH; base += NT / 2) {
+        const int kk = base + wave * 32 + (lane & 31);
+        const int x = x0 + kk % TW, y = y0 + kk / TW;
+        if (kk < TW * TH && x < g.nx && y < g.ny && z < g.nz) {
+            double d1[kDiag] = {0, 0, 0, 0, 0, 0, INFINITY, INFINITY, -INFINITY, 0};
+            node_collide_pair<L, T>(g, k, src, dst, rho_ref, rho, phi, mux, mup, x, y, z, side, diag, d1);
+            if (diag) {
+                for (int v = 0; v < 5; ++v) dv[v] += d1[v];
+                dv[5] = fmax(dv[5], d1[5]);
+                dv[6] = fmin(dv[6], d1[6]);
+                dv[7] = fmin(dv[7], d1[7]);
+                dv[8] = fmax(dv[8], d1[8]);
+                dv[9] += d1[9];
+            }
+        }
+    }
+}
+
+}  // namespace telbm

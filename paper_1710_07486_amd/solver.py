@@ -168,16 +168,20 @@ class Solver:
     def sync(self):
         _check(self.L.telbm_sync(self.h), self.h)
 
-    def read(self, field: str, device: bool = False):
-        """One field of the current state: numpy (host) or a torch CUDA tensor."""
+    def read(self, field: str, device: bool = False, check: bool = True):
+        """One field of the current state: numpy (host) or a torch CUDA tensor.
+        With check=False a diagnosed instability does not raise (the field is
+        still returned)."""
         import torch
         code = FIELDS[field]
         if device:
             out = torch.empty(self.p.shape, dtype=torch.float64, device=self.device)
-            _check(self.L.telbm_read(self.h, code, ctypes.c_void_p(out.data_ptr()), 1), self.h)
-            return out
-        out = np.empty(self.p.shape, dtype=np.float64)
-        _check(self.L.telbm_read(self.h, code, out.ctypes.data_as(ctypes.c_void_p), 0), self.h)
+            rc = self.L.telbm_read(self.h, code, ctypes.c_void_p(out.data_ptr()), 1)
+        else:
+            out = np.empty(self.p.shape, dtype=np.float64)
+            rc = self.L.telbm_read(self.h, code, out.ctypes.data_as(ctypes.c_void_p), 0)
+        if check or rc != _lib.ERR_UNSTABLE:
+            _check(rc, self.h)
         return out
 
     def fields(self):

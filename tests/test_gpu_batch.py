@@ -1,0 +1,119 @@
+"""GPU checks of the batched form: uneven instances advanced together must
+match each instance run alone (bit for bit: the node arithmetic is shared),
+for every tile shape and grid size and across graph replays; one instance is
+checked against the FP64 oracle; the FP32 form against the FP64 form."""
+import numpy as np
+import pytest
+
+from synth import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+SIZES = [(48, 40), (64, 64), (37, 50), (100, 30), (70, 71)]
+
+
+def instances(orc, precision=0, sizes=SIZES):
+    import paper_1710_07486_amd as T
+    out = []
+    rng = np.random.default_rng(5)
+    for k, (nx, ny) in enumerate(sizes):
+        ratio = float(rng.uniform(100, 1000))
+        kap = float(rng.uniform(0.05, 0.2))
+        wl = W.lens(nx, ny, radius=min(nx, ny) / 6, ratio=ratio, kappa=kap, seed=100 + k)
+        v = float(rng.uniform(0.0, 0.04))
+        wl.drops[0]["velocity"] = (v / 2, 0.0, 0.0)
+        wl.drops[1]["velocity"] = (-v / 2, 0.0, 0.0)
+        po = orc.coexisting_params(wl.ratio, **wl.physics())
+        rho, phi, u = W.fields(wl, po.rho_g, po.rho_l)
+        pl = T.Params(lattice=0, precision=precision, nx=nx, ny=ny, nz=1, T=po.T, rho_g=po.rho_g, rho_l=po.rho_l,
+                      lambda1=po.lambda1, lambda2=po.lambda2, lambda3=po.lambda3, kappa1=po.kappa1,
+                      kappa2=po.kappa2, kappa3=po.kappa3, chi=po.chi, nu=po.nu, mobility=po.mobility,
+                      tau_phi=po.tau_phi)
+        out.append((po, pl, rho, phi, u))
+    return out
+
+
+def run_single(pl, rho, phi, u, steps):
+    import paper_1710_07486_amd as T
+    with T.Solver(pl) as s:
+        s.init_fields(rho, phi, u)
+        s.step(steps)
+        return {k: s.read(k) for k in ("rho", "phi", "ux", "uy")}
+
+
+def test_batch_matches_single_bitwise(orc):
+    from paper_1710_07486_amd.batch import Batch
+    inst = instances(orc)
+    steps = 24  # two graph replays of 10 steps plus 4 eager steps
+    say("batch of", len(inst), "vs single solvers")
+    singles = [run_single(pl, r, p, u, steps) for (_, pl, r, p, u) in inst]
+    with Batch([pl for (_, pl, *_r) in inst]) as b:
+        for i, (_, pl, r, p, u) in enumerate(inst):
+            b.init_fields(i, r, p, u)
+        b.step(steps)
+        assert b.steps == steps
+        for i in range(len(inst)):
+            for k in ("rho", "phi", "ux", "uy"):
+                got = b.read(i, k)
+                assert np.array_equal(got, singles[i][k]), (i, k, np.abs(got - singles[i][k]).max())
+
+
+def test_batch_tile_shapes_agree(orc):
+    from paper_1710_07486_amd.batch import Batch, tile_variants
+    inst = instances(orc, sizes=SIZES[:3])
+    ref = None
+    for v, shape in enumerate(tile_variants()):
+        for wg in (1, 3):
+            say("tile variant", v, shape, "wg/cu", wg)
+            with Batch([pl for (_, pl, *_r) in inst]) as b:
+                b.set_tiles(v, wg)
+                for i, (_, pl, r, p, u) in enumerate(inst):
+                    b.init_fields(i, r, p, u)
+                b.step(12)
+                res = [b.read(i, "rho") for i in range(len(inst))]
+            if ref is None:
+                ref = res
+            for a, c in zip(res, ref):
+                assert np.array_equal(a, c)
+
+
+def test_batch_instance_vs_oracle(orc):
+    from paper_1710_07486_amd.batch import Batch
+    inst = instances(orc)
+    steps = 40
+    say("batch instance 3 vs oracle")
+    po, pl, r, p, u = inst[3]
+    st = orc.State(po, r, p, u[:2])
+    st.run(steps)
+    ref = st.fields()
+    with Batch([x[1] for x in inst]) as b:
+        for i, (_, pl_, r_, p_, u_) in enumerate(inst):
+            b.init_fields(i, r_, p_, u_)
+        b.step(steps)
+        got = b.read(3, "rho")
+        gphi = b.read(3, "phi")
+    assert np.abs(got - ref["rho"]).max() / np.abs(ref["rho"]).max() < 1e-10
+    assert np.abs(gphi - ref["phi"]).max() / np.abs(ref["phi"]).max() < 1e-10
+
+
+def test_batch_fp32_mixed_vs_fp64(orc):
+    from paper_1710_07486_amd.batch import Batch
+    i64 = instances(orc, 0)
+    i32 = instances(orc, 1)
+    steps = 60
+    say("batch FP32-mixed vs FP64")
+    out = {}
+    for tag, inst in (("64", i64), ("32", i32)):
+        with Batch([x[1] for x in inst]) as b:
+            for i, (_, pl, r, p, u) in enumerate(inst):
+                b.init_fields(i, r, p, u)
+            b.step(steps)
+            out[tag] = [b.read(i, "rho") for i in range(len(inst))]
+    errs = [float(np.abs(a - c).max() / np.abs(c).max()) for a, c in zip(out["32"], out["64"])]
+    print("per-instance relative density error", errs, flush=True)
+    assert max(errs) < 1e-5

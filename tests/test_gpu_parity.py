@@ -232,3 +232,33 @@ def test_full_size_sampled(orc, case):
     print("sampled max error / scale", case, worst, flush=True)
     for name, v in worst.items():
         assert v <= tol, (case, name, v)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_3d_collision_stays_finite_and_conserves_mass(orc, precision):
+    """The D3Q27 256^3 ratio-1000 collision started at the model's own
+    coexistence densities (oracle 1D relaxation): 300 steps on the GPU stay
+    finite with bounded velocities, and total mass is conserved (FP64 to 1e-12
+    relative; the FP32 storage form to 1e-7)."""
+    import paper_1710_07486_amd as T
+    wl = W.collision_3d(256, radius=32, ratio=1000.0, v_rel=0.04, kappa2=0.1, kappa3=0.1)
+    po = orc.coexisting_params(wl.ratio, **wl.physics())
+    pd = orc.Params(**{**po.__dict__, "lattice": 1})
+    rg, rl = orc.discrete_coexistence(pd, steps=6000, n=128)
+    say("3D 256^3 discrete start", precision, rg, rl)
+    rho, phi, u = W.fields(wl, rg, rl)
+    nz, ny, nx = wl.shape
+    pl = T.Params(lattice=1, precision=precision, nx=nx, ny=ny, nz=nz, T=po.T, rho_g=po.rho_g, rho_l=po.rho_l,
+                  lambda1=po.lambda1, lambda2=po.lambda2, lambda3=po.lambda3, kappa1=po.kappa1,
+                  kappa2=po.kappa2, kappa3=po.kappa3, chi=po.chi, nu=po.nu, mobility=po.mobility,
+                  tau_phi=po.tau_phi, diag_every=50)
+    with T.Solver(pl) as s:
+        s.init_fields(rho, phi, u)
+        d0 = s.diagnostics()
+        for _ in range(6):
+            s.step(50)
+            d = s.diagnostics()
+            assert d["nonfinite"] == 0 and d["max_u"] < 0.3 and d["min_rho"] > 0
+        tol = 1e-12 if precision == 0 else 1e-7
+        print("mass drift", d["mass"] / d0["mass"] - 1, "max_u", d["max_u"], flush=True)
+        assert abs(d["mass"] / d0["mass"] - 1) < tol
