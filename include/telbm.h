@@ -234,6 +234,79 @@ int telbm_batch_step_count(const telbm_batch *b, int64_t *steps);
 int telbm_batch_destroy(telbm_batch *b);
 const char *telbm_batch_last_error(const telbm_batch *b);
 
+/* ------------------------------------------------------------------------- */
+/* Learned form: kernels of a convolutional surrogate (3x3 filters, circular  */
+/* padding) on NHWC BF16 activations (uint16 storage) with FP32 accumulation */
+/* on the matrix cores.  Channel counts must be 32 or 64 (fields with fewer  */
+/* channels are stored zero-padded to 32).  Weights: FP32 masters            */
+/* w[tap][ci][co] (tap = 3 (dy+1) + (dx+1)), packed to BF16 by               */
+/* telbm_conv_pack_weights.  All pointers are device pointers; work is       */
+/* enqueued on `stream`.  The training loop lives in the caller.             */
+/* The paper has no learned part: these calls serve a surrogate that maps a  */
+/* state (the density and the two liquid concentrations of Sec. 2) to the   */
+/* state a fixed number of steps later.  Errors: TELBM_ERR_INVAL for a NULL  */
+/* required pointer, a non-positive size or an unsupported channel count;   */
+/* TELBM_ERR_NOMEM for a missing or short workspace; TELBM_ERR_DEVICE when a */
+/* launch fails.  Buffers are owned by the caller; nothing is allocated.     */
+/* ------------------------------------------------------------------------- */
+
+/* Pack w (FP32, 9*cin*cout) into the forward layout wf[co][tap*cin + ci] and
+ * the data-gradient layout wd[ci][tap*cout + co] with taps flipped (BF16). */
+int telbm_conv_pack_weights(const float *w, int cin, int cout, void *wf_bf16, void *wd_bf16, void *stream);
+
+/* y[p][co] = act(bias[co] + sum_{tap,ci} x[p + off(tap)][ci] w[tap][ci][co]) over
+ * an n x h x w periodic grid; act = ReLU if relu != 0.  Writes y_bf16 and/or
+ * y_f32 (either may be NULL, not both). */
+int telbm_conv_forward(const void *x, int n, int h, int w, int cin, const void *wf_bf16, const float *bias,
+                       int cout, int relu, void *y_bf16, float *y_f32, void *stream);
+
+/* Gradients of telbm_conv_forward given dy (BF16, n*h*w*cout):
+ * dx (BF16, optional) = sum_t dy[p - off(t)] w[t]^T, multiplied by
+ * (x_relu_mask > 0) when a mask (the ReLU output that fed this layer) is
+ * given; dw (FP32, optional) = sum_p x[p + off(t)] dy[p]^T; db (FP32,
+ * optional) = sum_p dy[p].  dw and db need a workspace of
+ * telbm_conv_workspace_bytes; the reductions are deterministic. */
+int telbm_conv_backward(const void *x, const void *dy, int n, int h, int w, int cin, int cout,
+                        const void *wd_bf16, const void *x_relu_mask, void *dx_bf16, float *dw, float *db,
+                        void *workspace, size_t workspace_bytes, void *stream);
+int telbm_conv_workspace_bytes(int n, int h, int w, int cin, int cout, size_t *bytes);
+
+/* Residual head and loss over `pixels` x `channels` (first `valid` used):
+ * pred = x + y; with a target, dy = 2 (pred - target)/(pixels*valid) (BF16)
+ * and per-block partial sums of (pred - target)^2 into loss_partials
+ * (*nblocks of them).  pred (FP32) is optional. */
+int telbm_residual_mse(const void *x, const float *y, const void *target, int64_t pixels, int channels,
+                       int valid, void *dy_bf16, float *pred, float *loss_partials, int *nblocks, void *stream);
+
+/* Network input from a state (FP64 rho, phi and optionally the velocity
+ * ux, uy; `pixels` values each): BF16 NHWC with 32 channels, channel 0 =
+ * (rho - rho_g)/(rho_l - rho_g), channel 1 = C1 = (ch0 + phi/chi)/2,
+ * channel 2 = C2 = (ch0 - phi/chi)/2 (the concentrations of Sec. 2 with
+ * C_g = 1 - ch0), channels 3, 4 = u_scale ux, u_scale uy (zero when ux or uy
+ * is NULL), channels 5..31 zero. */
+int telbm_surrogate_encode(const double *rho, const double *phi, const double *ux, const double *uy,
+                           int64_t pixels, double rho_g, double rho_l, double chi, double u_scale, void *x_bf16,
+                           void *stream);
+
+/* State from the network output y (FP32 NHWC, 32 channels, first five
+ * used) and the exact input state (n images of h x w; ux_in, uy_in may be
+ * NULL for a state at rest): the encoded input plus y (residual head),
+ * clamped to rho >= rho_g/2 and |phi| <= chi, then projected so that each
+ * image's totals of rho, phi and rho u equal the input's (the quantities
+ * the method conserves): the rho and phi defects are added in proportion to
+ * w = |grad ch0| + |grad(phi/chi)| + 1e-3, the momentum defect by a uniform
+ * velocity shift.  Writes rho, phi, ux, uy (FP64, n*h*w each); needs
+ * telbm_surrogate_decode_workspace_bytes of workspace. */
+int telbm_surrogate_decode(const float *y, const double *rho_in, const double *phi_in, const double *ux_in,
+                           const double *uy_in, int n, int h, int w, double rho_g, double rho_l, double chi,
+                           double u_scale, double *rho_out, double *phi_out, double *ux_out, double *uy_out,
+                           void *workspace, size_t workspace_bytes, void *stream);
+int telbm_surrogate_decode_workspace_bytes(int n, int h, int w, size_t *bytes);
+
+/* One Adam step (Kingma and Ba 2015) on n FP32 weights at step t >= 1. */
+int telbm_adam_step(float *w, const float *g, float *m, float *v, int64_t n, float lr, float beta1,
+                    float beta2, float eps, int64_t t, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

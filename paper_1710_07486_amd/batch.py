@@ -143,6 +143,13 @@ class Batch:
         self._check(self.L.telbm_batch_read(self.h, int(idx), FIELDS[field], out.ctypes.data_as(ctypes.c_void_p), 0))
         return out
 
+    def read_device(self, idx: int, field: str, out):
+        """One field of instance idx into a float64 CUDA tensor of its size."""
+        p = self.params[idx]
+        assert out.is_cuda and out.dtype.itemsize == 8 and out.numel() == p.nodes and out.is_contiguous()
+        self._check(self.L.telbm_batch_read(self.h, int(idx), FIELDS[field], ctypes.c_void_p(out.data_ptr()), 1))
+        return out
+
     @property
     def steps(self) -> int:
         n = ctypes.c_int64()

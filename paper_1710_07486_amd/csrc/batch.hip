@@ -68,7 +68,7 @@ __global__ __launch_bounds__(TBX* TBY) void kb_phase(const InstDesc* __restrict_
         if (PHASE == 2) {
             // two lanes per node (uniform control flow for the lane exchange)
             double dv[kDiag];
-            tile_collide_pair<L, T, TBX * TBY>(d.g, d.k, (const T*)d.pop[cur], (T*)d.pop[1 - cur], rho_ref, rho,
+            tile_collide<L, T, TBX * TBY>(d.g, d.k, (const T*)d.pop[cur], (T*)d.pop[1 - cur], rho_ref, rho,
                                                d.phi, d.mux, d.mup, bx * TBX, by * TBY, bz, TBX, TBY,
                                                threadIdx.y * TBX + threadIdx.x, false, dv);
             continue;

@@ -119,7 +119,7 @@ __global__ __launch_bounds__(BX* BY) void k_chempot(GridDims g, PhysConst k, con
 }
 
 template <int L, typename T>
-__global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(2))) void k_collide(GridDims g, PhysConst k, const T* __restrict__ src,
+__global__ __launch_bounds__(BX* BY) void k_collide(GridDims g, PhysConst k, const T* __restrict__ src,
                                                     T* __restrict__ dst, const double* __restrict__ rho_ref,
                                                     const double* __restrict__ rho,
                                                     const double* __restrict__ phi,
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(2))) voi
     const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + BY - 1) / BY;
     const int bx = b % bxc, rest = b / bxc, by = rest % byc, bz = rest / byc;
     double dv[kDiag] = {0, 0, 0, 0, 0, 0, INFINITY, INFINITY, -INFINITY, 0};
-    tile_collide_pair<L, T, BX * BY>(g, k, src, dst, rho_ref, rho, phi, mux, mup, bx * BX, by * BY, bz, BX, BY,
+    tile_collide<L, T, BX * BY>(g, k, src, dst, rho_ref, rho, phi, mux, mup, bx * BX, by * BY, bz, BX, BY,
                                      threadIdx.y * BX + threadIdx.x, diag != 0, dv);
     if (diag) diag_block_reduce(dv, partials);
 }

@@ -174,26 +174,23 @@ __device__ __forceinline__ R eq_inv(const AxisEq<R>* ax, int i) {
 }
 
 // ---------------------------------------------------------------------------
-// One collision of the density populations, streamed: the Q populations are
-// not held in registers across the passes; `load(i)` re-reads f_i (offset
-// form f_i - w_i rho_ref) and `store(i, v)` writes the post-collision value in
-// the same form.  u = j / rho, du = F / rho; P holds the raw second moments
-// sum_i fd_i c_ia c_ib (xx, yy, zz, xy, xz, yz) of the offset-form f.
+// One collision of the density populations held in registers.  fd[i] holds
+// f_i - w_i rho_ref and is overwritten with the post-collision value in the
+// same offset form (rho_ref = 0 for absolute populations; the node's own
+// density for the FP32 deviation storage).  u = j / rho, du = F / rho.
 //
 // KBC: df = f - feq; the shear part ds carries exactly the traceless second
 // moments of df (normal-stress differences and off-diagonal stresses), the
 // rest dh = df - ds.  gamma = 1/beta - (2 - 1/beta) <ds|dh>/<dh|dh> with
 // <X|Y> = sum X_i Y_i / feq_i, and gamma = 2 when <dh|dh> = 0.
-// f* = f - beta (2 ds + gamma dh) + feq(rho, u + du) - feq(rho, u).
-// The second moments of the product-form equilibrium are closed forms,
-// rho (2 S_a - 1)/3 on the diagonal and rho u_a u_b off it, so df's moments
-// need no pass over feq.  The scalar products and their ratio are FP64.
-// `fence()` separates the passes so that their reloads stay reloads.
+// f* = f - beta (2 ds + gamma dh) + feq(rho, u + du) - feq(rho, u)
+//    = (1 - 2 beta) ds + (1 - beta gamma) dh + feq(rho, u + du)   (offset form).
+// The two scalar products and their ratio are accumulated in FP64.  The
+// array holds df, then dh, so that one array is live through the passes.
 // ---------------------------------------------------------------------------
-template <int L, typename R, class Load, class Store, class Fence>
-__device__ __forceinline__ double collide_f(Load load, Store store, Fence fence, const double* P,
-                                            double rho_d, double inv_rho_d, const R* u, const R* du, R beta,
-                                            double inv_beta, double rho_ref) {
+template <int L, typename R>
+__device__ __forceinline__ double collide_f(R* fd, double rho_d, double inv_rho_d, const R* u, const R* du,
+                                            R beta, double inv_beta, double rho_ref) {
     using Lt = Lattice<L>;
     constexpr int Q = Lt::Q;
     constexpr int D = Lt::D;
@@ -211,66 +208,63 @@ __device__ __forceinline__ double collide_f(Load load, Store store, Fence fence,
         ax[2].inv[0] = ax[2].inv[1] = ax[2].inv[2] = R(1);
         ax2[2] = ax[2];
     }
-    // second moments of df = (offset f) - (offset feq); the offset w_i rho_ref
-    // is isotropic (cs2 rho_ref delta_ab) and drops out of the traceless part
-    double m[6];
-    for (int a = 0; a < 3; ++a) {
-        const double sm1 = a < D ? double(-ax[a].e[0]) : 0.0;  // S_a - 1
-        m[a] = P[a] - (2.0 * rho_d * sm1 + (rho_d - rho_ref)) * (1.0 / 3.0);
+    // non-equilibrium part df = f - feq (kept in fd) and its second moments
+    R mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const R df = fd[i] - R(Lt::w[i]) * (drho + rho * eq_excess<L, R>(ax, i));
+        fd[i] = df;
+        const int cx = Lt::c[i][0], cy = Lt::c[i][1], cz = Lt::c[i][2];
+        if (cx) mxx += df;
+        if (cy) myy += df;
+        if (cz) mzz += df;
+        if (cx * cy) mxy += (cx * cy > 0) ? df : -df;
+        if (cx * cz) mxz += (cx * cz > 0) ? df : -df;
+        if (cy * cz) myz += (cy * cz > 0) ? df : -df;
     }
-    m[3] = P[3] - rho_d * double(u[0]) * double(u[1]);
-    m[4] = P[4] - rho_d * double(u[0]) * double(u[2]);
-    m[5] = P[5] - rho_d * double(u[1]) * double(u[2]);
     R dxx, dyy, dzz;
     if (D == 2) {
-        dxx = R(0.5 * (m[0] - m[1]));
+        dxx = R(0.5) * (mxx - myy);
         dyy = -dxx;
         dzz = 0;
     } else {
-        const double tr = (m[0] + m[1] + m[2]) * (1.0 / 3.0);
-        dxx = R(m[0] - tr);
-        dyy = R(m[1] - tr);
-        dzz = R(m[2] - tr);
+        const R tr = (mxx + myy + mzz) * R(1.0 / 3.0);
+        dxx = mxx - tr;
+        dyy = myy - tr;
+        dzz = mzz - tr;
     }
-    const R mxy = R(m[3]), mxz = R(m[4]), myz = R(m[5]);
     // shear part: ds_i = sum_pq M_pq b_p(c_ix) b_q(c_iy) b_r(c_iz) over the
     // traceless second moments, with the D1Q3 dual basis b0 = [c == 0],
     // b1 = c/2, b2 = (c == 0 ? -1 : 1/2); only the nonzero terms are formed.
     auto shear = [&](int i) -> R {
         const int cx = Lt::c[i][0], cy = Lt::c[i][1], cz = Lt::c[i][2];
-        const int nz = (cx != 0) + (cy != 0) + (cz != 0);
-        if (nz == 1) return R(0.5) * (cx ? dxx : (cy ? dyy : dzz));
-        if (nz == 2) {
+        const int nzc = (cx != 0) + (cy != 0) + (cz != 0);
+        if (nzc == 1) return R(0.5) * (cx ? dxx : (cy ? dyy : dzz));
+        if (nzc == 2) {
             if (!cz) return R(0.25 * cx * cy) * mxy;
             if (!cy) return R(0.25 * cx * cz) * mxz;
             return R(0.25 * cy * cz) * myz;
         }
-        if (nz == 0) return -(dxx + dyy + dzz);  // zero up to rounding (traceless)
+        if (nzc == 0) return -(dxx + dyy + dzz);  // zero up to rounding (traceless)
         return R(0);
     };
-    auto feq_off = [&](int i) -> R { return R(Lt::w[i]) * (drho + rho * eq_excess<L, R>(ax, i)); };
     const R inv_rho = R(inv_rho_d);
     double sh = 0.0, hh = 0.0;
-    fence();
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const R s = shear(i);
-        const R dh = load(i) - feq_off(i) - s;
+        const R dh = fd[i] - s;
+        fd[i] = dh;
         const double ifeq = double(inv_rho * eq_inv<L, R>(ax, i));
         sh += double(s) * double(dh) * ifeq;
         hh += double(dh) * double(dh) * ifeq;
     }
     const double gamma = (hh > 1e-300) ? (inv_beta - (2.0 - inv_beta) * sh / hh) : 2.0;
     const R g = R(gamma);
-    // f* = (1 - 2 beta) ds + (1 - beta gamma) dh + feq(u + du)  (offset form)
     const R cs = R(1) - R(2) * beta, ch = R(1) - beta * g;
-    fence();
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const R s = shear(i);
-        const R dh = load(i) - feq_off(i) - s;
-        store(i, cs * s + ch * dh + R(Lt::w[i]) * (drho + rho * eq_excess<L, R>(ax2, i)));
-    }
+    for (int i = 0; i < Q; ++i)
+        fd[i] = cs * shear(i) + ch * fd[i] + R(Lt::w[i]) * (drho + rho * eq_excess<L, R>(ax2, i));
     return gamma;
 }
 

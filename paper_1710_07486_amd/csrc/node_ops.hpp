@@ -189,39 +189,26 @@ __device__ __forceinline__ void node_collide(const GridDims& g, const PhysConst&
     for (int d = 0; d < 3; ++d) F[d] = -r * 3.0 * gx[d] - p * 3.0 * gp[d];
     phase_fence();
 
-    // pass A: pull f (offset form about this node's density in the FP32
-    // form); momentum and raw second moments
-    auto load = [&](int i) -> R {
+    // pull f (offset form about this node's density in the FP32 form)
+    R f[Q];
+    R jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
         const uint32_t m = nbr32<L>(nb, n, i, -1);
         R v = ld(src + (size_t)i * g.N, m);
         if (Deviation<T>::on) v += R(Lt::w[i] * (ld(rho_ref, m) - r));
-        return v;
-    };
-    R jx = 0, jy = 0, jz = 0;
-    double P[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const R fi = load(i);
-        const int cx = Lt::c[i][0], cy = Lt::c[i][1], cz = Lt::c[i][2];
-        if (cx) jx += cx > 0 ? fi : -fi;
-        if (cy) jy += cy > 0 ? fi : -fi;
-        if (cz) jz += cz > 0 ? fi : -fi;
-        const double fd = double(fi);
-        if (cx) P[0] += fd;
-        if (cy) P[1] += fd;
-        if (cz) P[2] += fd;
-        if (cx * cy) P[3] += cx * cy > 0 ? fd : -fd;
-        if (cx * cz) P[4] += cx * cz > 0 ? fd : -fd;
-        if (cy * cz) P[5] += cy * cz > 0 ? fd : -fd;
+        f[i] = v;
+        if (Lt::c[i][0]) jx += Lt::c[i][0] > 0 ? v : -v;
+        if (Lt::c[i][1]) jy += Lt::c[i][1] > 0 ? v : -v;
+        if (Lt::c[i][2]) jz += Lt::c[i][2] > 0 ? v : -v;
     }
     const double ir = 1.0 / r;
     R u[3] = {R(double(jx) * ir), R(double(jy) * ir), R(double(jz) * ir)};
     R du[3] = {R(F[0] * ir), R(F[1] * ir), R(F[2] * ir)};
     if (Lt::D == 2) u[2] = du[2] = R(0);
-    // passes B and C re-pull f instead of keeping it in registers
-    auto store = [&](int i, R v) { st(dst + (size_t)i * g.N, n, v); };
-    const double gam = collide_f<L, R>(load, store, phase_fence, P, r, ir, u, du, R(k.beta), k.inv_beta,
-                                       Deviation<T>::on ? r : 0.0);
+    const double gam = collide_f<L, R>(f, r, ir, u, du, R(k.beta), k.inv_beta, Deviation<T>::on ? r : 0.0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) st(dst + (size_t)i * g.N, n, f[i]);
     phase_fence();
 
     R gg[Q];
@@ -495,6 +482,34 @@ __device__ __forceinline__ void tile_collide_pair(const GridDims& g, const PhysC
                 dv[9] += d1[9];
             }
         }
+    }
+}
+
+// Whether the collision of this lattice and storage type runs two lanes per
+// node (pair split) or one: the split halves the per-lane registers but
+// repeats the per-node square roots and reciprocals on both halves, which pays
+// off where registers limit occupancy most (D3Q27 with FP32 storage).
+template <int L, typename T>
+struct UsePairs {
+    static constexpr bool value = (L == kD3Q27) && Deviation<T>::on;
+};
+
+// All nodes of a tile of TW x TH nodes at (x0, y0, z) with the block's NT
+// threads, in the collision form UsePairs selects.
+template <int L, typename T, int NT>
+__device__ __forceinline__ void tile_collide(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
+                                             T* __restrict__ dst, const double* __restrict__ rho_ref,
+                                             const double* __restrict__ rho, const double* __restrict__ phi,
+                                             const double* __restrict__ mux, const double* __restrict__ mup,
+                                             int x0, int y0, int z, int TW, int TH, int tid, bool diag, double* dv) {
+    if (UsePairs<L, T>::value) {
+        tile_collide_pair<L, T, NT>(g, k, src, dst, rho_ref, rho, phi, mux, mup, x0, y0, z, TW, TH, tid, diag, dv);
+        return;
+    }
+    for (int kk = tid; kk < TW * TH; kk += NT) {
+        const int x = x0 + kk % TW, y = y0 + kk / TW;
+        if (x < g.nx && y < g.ny && z < g.nz)
+            node_collide<L, T>(g, k, src, dst, rho_ref, rho, phi, mux, mup, x, y, z, diag, dv);
     }
 }
 

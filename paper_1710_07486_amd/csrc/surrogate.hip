@@ -1,0 +1,585 @@
+// surrogate.hip -- kernels of the learned form: a stack of 3x3 convolutions
+// with circular padding on NHWC BF16 activations, FP32 accumulation on the
+// gfx950 matrix cores (v_mfma_f32_16x16x32_bf16), for forward, data gradient
+// and weight gradient, plus weight packing, bias gradient, the residual MSE
+// loss and an Adam step on FP32 master weights.
+//
+// Channel counts are multiples of 32 (the 3-channel fields are stored padded
+// to 32 zero channels), so every K chunk of 32 lies inside one filter tap.
+//
+// MFMA 16x16x32 operand layout (lane l of 64): A row l % 16, B column l % 16,
+// both with K = 8 (l / 16) + [0, 8); C holds rows 4 (l / 16) + [0, 4) of
+// column l % 16.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "../../include/telbm.h"
+
+namespace telbm {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+// round to nearest even (finite inputs)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+
+union Pack8 {
+    uint4 v;
+    bf16x8 b;
+    uint16_t h[8];
+};
+
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// ---------------------------------------------------------------------------
+// Implicit-GEMM convolution: out[p][co] = sum_{tap, ci} in[p + s*off(tap)][ci]
+// * Wp[co][tap*CIN + ci] (+ bias, ReLU), off(tap) = (tap/3 - 1, tap%3 - 1);
+// s = +1 for the forward pass and for the data gradient (which runs on the
+// flipped, transposed weights).  Optional mask: out *= (mask[p][co] > 0)
+// (derivative of the ReLU that produced the layer input).  Each wavefront
+// computes 32 pixels (two M tiles) of one image row segment x COUT channels.
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wp,
+                                              const float* __restrict__ bias, const uint16_t* __restrict__ mask,
+                                              uint16_t* __restrict__ out_bf, float* __restrict__ out_f32, int N,
+                                              int H, int W, int sgn, int relu) {
+    constexpr int NT = COUT / 16;
+    constexpr int KC = CIN / 32;  // K chunks per tap
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * (blockDim.x >> 6)) + (threadIdx.x >> 6);
+    const int64_t P = (int64_t)N * H * W;
+    const int64_t p0 = (int64_t)wave * 32;
+    if (p0 >= P) return;
+    const int r16 = lane & 15, kg = lane >> 4;
+    // the two pixels this lane feeds as A rows
+    int64_t pa[2];
+    int hh[2], ww[2], nn[2];
+    for (int mt = 0; mt < 2; ++mt) {
+        pa[mt] = p0 + mt * 16 + r16;
+        const int64_t pc = pa[mt] < P ? pa[mt] : P - 1;
+        nn[mt] = (int)(pc / ((int64_t)H * W));
+        const int rem = (int)(pc % ((int64_t)H * W));
+        hh[mt] = rem / W;
+        ww[mt] = rem % W;
+    }
+    f32x4 acc[2][NT];
+    for (int mt = 0; mt < 2; ++mt)
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dh = sgn * (tap / 3 - 1), dw = sgn * (tap % 3 - 1);
+        int64_t src[2];
+        for (int mt = 0; mt < 2; ++mt)
+            src[mt] = (((int64_t)nn[mt] * H + wrap(hh[mt] + dh, H)) * W + wrap(ww[mt] + dw, W)) * CIN;
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+            const int ci = kc * 32 + kg * 8;
+            Pack8 a[2], b[NT];
+            for (int mt = 0; mt < 2; ++mt) a[mt].v = *(const uint4*)(in + src[mt] + ci);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                b[nt].v = *(const uint4*)(wp + (int64_t)(nt * 16 + r16) * (9 * CIN) + tap * CIN + ci);
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt].b, b[nt].b, acc[mt][nt], 0, 0, 0);
+        }
+    }
+    // epilogue: lane holds rows (pixels) 4 kg + j of column (channel) r16
+    for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t p = p0 + mt * 16 + kg * 4 + j;
+            if (p >= P) continue;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int co = nt * 16 + r16;
+                float v = acc[mt][nt][j];
+                if (bias) v += bias[co];
+                if (relu) v = v > 0.f ? v : 0.f;
+                if (mask && !(bf2f(mask[p * COUT + co]) > 0.f)) v = 0.f;
+                if (out_bf) out_bf[p * COUT + co] = f2bf(v);
+                if (out_f32) out_f32[p * COUT + co] = v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: dW[tap][ci][co] = sum_p in[p + off(tap)][ci] * dy[p][co].
+// Each wavefront walks a contiguous range of pixels in slabs of 32, stages
+// the slab's in (shifted by the tap) and dy transposed in its LDS region,
+// and accumulates the CIN x COUT tile of one tap on the matrix cores; the
+// wave's partial sum goes to part[wave][tap][ci][co] (reduced separately, in
+// a fixed order).
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__ in, const uint16_t* __restrict__ dy,
+                                                    float* __restrict__ part, int N, int H, int W,
+                                                    int waves_per_tap) {
+    constexpr int MT = CIN / 16, NT = COUT / 16;
+    __shared__ uint16_t lds[4][(CIN + COUT) * 32];  // per wave: inT[CIN][32], dyT[COUT][32]
+    const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
+    const int wave = blockIdx.x * 4 + wl;
+    const int tap = wave / waves_per_tap, wt = wave % waves_per_tap;
+    if (tap >= 9) return;
+    const int dh = tap / 3 - 1, dw = tap % 3 - 1;
+    uint16_t* inT = lds[wl];
+    uint16_t* dyT = lds[wl] + CIN * 32;
+    const int64_t P = (int64_t)N * H * W;
+    const int64_t nslab = (P + 31) / 32;
+    const int64_t s0 = nslab * wt / waves_per_tap, s1 = nslab * (wt + 1) / waves_per_tap;
+    const int r16 = lane & 15, kg = lane >> 4;
+    f32x4 acc[MT][NT];
+    for (int a = 0; a < MT; ++a)
+        for (int b = 0; b < NT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t sl = s0; sl < s1; ++sl) {
+        // stage: 32 pixels x (CIN + COUT) channels, 8 channels per lane-load
+        constexpr int VIN = CIN / 8, VDY = COUT / 8;
+        for (int t = lane; t < 32 * (VIN + VDY); t += 64) {
+            const int px = t % 32, v = t / 32;
+            const int64_t p = sl * 32 + px;
+            Pack8 d;
+            d.v = uint4{0u, 0u, 0u, 0u};
+            if (p < P) {
+                if (v < VIN) {
+                    const int n = (int)(p / ((int64_t)H * W));
+                    const int rem = (int)(p % ((int64_t)H * W));
+                    const int h = wrap(rem / W + dh, H), w = wrap(rem % W + dw, W);
+                    d.v = *(const uint4*)(in + (((int64_t)n * H + h) * W + w) * CIN + v * 8);
+                } else {
+                    d.v = *(const uint4*)(dy + p * COUT + (v - VIN) * 8);
+                }
+            }
+            uint16_t* dst = v < VIN ? inT + (v * 8) * 32 + px : dyT + ((v - VIN) * 8) * 32 + px;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) dst[j * 32] = d.h[j];
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        // A = in^T (ci rows x 32 pixels), B = dy (32 pixels x co columns)
+        Pack8 a[MT], b[NT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) a[mt].v = *(const uint4*)(inT + (mt * 16 + r16) * 32 + kg * 8);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) b[nt].v = *(const uint4*)(dyT + (nt * 16 + r16) * 32 + kg * 8);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt].b, b[nt].b, acc[mt][nt], 0, 0, 0);
+        __builtin_amdgcn_wave_barrier();
+    }
+    float* out = part + ((int64_t)wt * 9 + tap) * CIN * COUT;
+    for (int mt = 0; mt < MT; ++mt)
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) out[(mt * 16 + kg * 4 + j) * COUT + nt * 16 + r16] = acc[mt][nt][j];
+}
+
+// Sum of the per-wave partials in a fixed order: dw[e] = sum_w part[w][e].
+__global__ void k_reduce_parts(const float* __restrict__ part, int nparts, int64_t n, float* __restrict__ dw) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float s = 0.f;
+    for (int w = 0; w < nparts; ++w) s += part[(int64_t)w * n + e];
+    dw[e] = s;
+}
+
+// Bias gradient partials: per block sums over a range of pixels, per channel.
+__global__ void k_bias_grad(const uint16_t* __restrict__ dy, int64_t P, int C, float* __restrict__ part) {
+    // block b handles pixels [b*chunk, (b+1)*chunk); thread t < C sums channel t
+    const int64_t chunk = (P + gridDim.x - 1) / gridDim.x;
+    const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = p0 + chunk < P ? p0 + chunk : P;
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        float s = 0.f;
+        for (int64_t p = p0; p < p1; ++p) s += bf2f(dy[p * C + c]);
+        part[(int64_t)blockIdx.x * C + c] = s;
+    }
+}
+
+// Pack FP32 master weights w[tap][ci][co] into the forward layout
+// wf[co][tap*CIN + ci] and the data-gradient layout wd[ci][tap'*COUT + co]
+// = w[8 - tap'][ci][co] (flipped taps), both BF16.
+__global__ void k_pack_weights(const float* __restrict__ w, int cin, int cout, uint16_t* __restrict__ wf,
+                               uint16_t* __restrict__ wd) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = 9 * cin * cout;
+    if (e >= n) return;
+    const int co = e % cout, ci = (e / cout) % cin, tap = e / (cout * cin);
+    const uint16_t v = f2bf(w[e]);
+    wf[(int64_t)co * 9 * cin + tap * cin + ci] = v;
+    wd[(int64_t)ci * 9 * cout + (8 - tap) * cout + co] = v;
+}
+
+// Residual head and loss: pred = x + y (first `valid` channels), diff =
+// pred - target; writes dy = 2 diff / count (BF16, zero on padding channels),
+// pred (FP32, optional) and per-block partial sums of diff^2.
+__global__ void k_residual_mse(const uint16_t* __restrict__ x, const float* __restrict__ y,
+                               const uint16_t* __restrict__ target, int64_t P, int C, int valid, float scale,
+                               uint16_t* __restrict__ dy, float* __restrict__ pred, float* __restrict__ part) {
+    __shared__ float red[256];
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float l = 0.f;
+    if (e < P * C) {
+        const int c = (int)(e % C);
+        float g = 0.f;
+        const float pr = bf2f(x[e]) + y[e];
+        if (c < valid) {
+            if (target) {
+                const float d = pr - bf2f(target[e]);
+                l = d * d;
+                g = 2.f * d * scale;
+            }
+            if (pred) pred[e] = pr;
+        } else if (pred) {
+            pred[e] = 0.f;
+        }
+        if (dy) dy[e] = f2bf(g);
+    }
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && part) part[blockIdx.x] = red[0];
+}
+
+// Adam (Kingma and Ba, 2015) on FP32 master weights.
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const float gi = g[e];
+    const float mi = b1 * m[e] + (1.f - b1) * gi;
+    const float vi = b2 * v[e] + (1.f - b2) * gi * gi;
+    m[e] = mi;
+    v[e] = vi;
+    w[e] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Encoding of a state for the network: channel 0 is the scaled density
+// rho^ = (rho - rho_g)/(rho_l - rho_g), channels 1 and 2 are the liquid
+// concentrations C1 = (rho^ + phi/chi)/2 and C2 = (rho^ - phi/chi)/2,
+// channels 3 and 4 the velocity times u_scale (zero without a velocity);
+// channels 5..31 are zero.  One thread per pixel, 64 bytes out.
+__global__ void k_encode(const double* __restrict__ rho, const double* __restrict__ phi,
+                         const double* __restrict__ ux, const double* __restrict__ uy, int64_t P, double rho_g,
+                         double inv_drho, double inv_chi, double u_scale, uint16_t* __restrict__ x) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const double s = (rho[p] - rho_g) * inv_drho, q = phi[p] * inv_chi;
+    Pack8 v[4];
+    for (int k = 0; k < 4; ++k) v[k].v = uint4{0u, 0u, 0u, 0u};
+    v[0].h[0] = f2bf((float)s);
+    v[0].h[1] = f2bf((float)(0.5 * (s + q)));
+    v[0].h[2] = f2bf((float)(0.5 * (s - q)));
+    if (ux) v[0].h[3] = f2bf((float)(ux[p] * u_scale));
+    if (uy) v[0].h[4] = f2bf((float)(uy[p] * u_scale));
+    uint4* o = (uint4*)(x + p * 32);
+    for (int k = 0; k < 4; ++k) o[k] = v[k].v;
+}
+
+// Decoding.  The prediction is the exact input plus the network output y
+// (residual head): rho^ = rho^_in + y0, C1 = C1_in + y1, C2 = C2_in + y2,
+// u = u_in + y3,4 / u_scale; rho^ is clamped so that rho >= rho_g/2 and
+// phi/chi = C1 - C2 to [-1, 1].  The first pass writes these values, the
+// interface weight w = |grad rho^| + |grad(phi/chi)| + floor (central
+// differences, periodic) and per-block partial sums; the second pass adds
+// the mass and phase defects in proportion to w and shifts the velocity
+// uniformly so that the totals of rho, phi and rho u equal the input's.
+// Blocks never straddle images.
+constexpr int kDecSums = 11;  // rho_in, phi_in, rho, phi, w, (rho u)_in x,y, rho u x,y, w u x,y
+
+struct DecodeArgs {
+    const float* y;
+    const double *rho_in, *phi_in, *ux_in, *uy_in;
+    double *rho_out, *phi_out, *ux_out, *uy_out, *wgt, *part;
+    int H, W, bpi;
+    double rho_g, drho, chi, smin, inv_uscale;
+};
+
+__device__ __forceinline__ void decode_px(const DecodeArgs& a, int64_t p, double& s, double& q) {
+    const double s_in = (a.rho_in[p] - a.rho_g) / a.drho, q_in = a.phi_in[p] / a.chi;
+    const float* y = a.y + p * 32;
+    s = s_in + (double)y[0];
+    const double c1 = 0.5 * (s_in + q_in) + (double)y[1], c2 = 0.5 * (s_in - q_in) + (double)y[2];
+    q = c1 - c2;
+    s = s < a.smin ? a.smin : s;
+    q = q > 1.0 ? 1.0 : (q < -1.0 ? -1.0 : q);
+}
+
+__global__ void k_decode_stats(DecodeArgs a) {
+    __shared__ double red[kDecSums][256];
+    const int img = blockIdx.x / a.bpi, b = blockIdx.x % a.bpi;
+    const int64_t HW = (int64_t)a.H * a.W, base = img * HW;
+    const int64_t chunk = (HW + a.bpi - 1) / a.bpi;
+    const int64_t l0 = (int64_t)b * chunk, l1 = l0 + chunk < HW ? l0 + chunk : HW;
+    double acc[kDecSums];
+    for (int k = 0; k < kDecSums; ++k) acc[k] = 0.0;
+    for (int64_t l = l0 + threadIdx.x; l < l1; l += blockDim.x) {
+        const int h = (int)(l / a.W), w = (int)(l % a.W);
+        const int64_t p = base + l;
+        double s, q, sx0, qx0, sx1, qx1, sy0, qy0, sy1, qy1;
+        decode_px(a, p, s, q);
+        decode_px(a, base + (int64_t)h * a.W + wrap(w - 1, a.W), sx0, qx0);
+        decode_px(a, base + (int64_t)h * a.W + wrap(w + 1, a.W), sx1, qx1);
+        decode_px(a, base + (int64_t)wrap(h - 1, a.H) * a.W + w, sy0, qy0);
+        decode_px(a, base + (int64_t)wrap(h + 1, a.H) * a.W + w, sy1, qy1);
+        const double gs = sqrt(0.25 * ((sx1 - sx0) * (sx1 - sx0) + (sy1 - sy0) * (sy1 - sy0)));
+        const double gq = sqrt(0.25 * ((qx1 - qx0) * (qx1 - qx0) + (qy1 - qy0) * (qy1 - qy0)));
+        const double wt = gs + gq + 1e-3;
+        const double r = a.rho_g + a.drho * s, f = a.chi * q;
+        const double uxi = a.ux_in ? a.ux_in[p] : 0.0, uyi = a.uy_in ? a.uy_in[p] : 0.0;
+        const double uxo = uxi + (double)a.y[p * 32 + 3] * a.inv_uscale;
+        const double uyo = uyi + (double)a.y[p * 32 + 4] * a.inv_uscale;
+        a.rho_out[p] = r;
+        a.phi_out[p] = f;
+        a.ux_out[p] = uxo;
+        a.uy_out[p] = uyo;
+        a.wgt[p] = wt;
+        const double ri = a.rho_in[p];
+        acc[0] += ri;
+        acc[1] += a.phi_in[p];
+        acc[2] += r;
+        acc[3] += f;
+        acc[4] += wt;
+        acc[5] += ri * uxi;
+        acc[6] += ri * uyi;
+        acc[7] += r * uxo;
+        acc[8] += r * uyo;
+        acc[9] += wt * uxo;
+        acc[10] += wt * uyo;
+    }
+    for (int k = 0; k < kDecSums; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int k = 0; k < kDecSums; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < kDecSums) a.part[(int64_t)blockIdx.x * kDecSums + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Second pass.  With c_rho = (M_in - M)/W_sum the new density is rho + c_rho
+// w, so its momentum is sum rho u + c_rho sum w u; the uniform shift du then
+// restores the input momentum: du = (J_in - that) / M_in.
+__global__ void k_decode_apply(DecodeArgs a) {
+    const int img = blockIdx.x / a.bpi, b = blockIdx.x % a.bpi;
+    double t[kDecSums];
+    for (int c = 0; c < kDecSums; ++c) t[c] = 0.0;
+    for (int k = 0; k < a.bpi; ++k)
+        for (int c = 0; c < kDecSums; ++c) t[c] += a.part[((int64_t)img * a.bpi + k) * kDecSums + c];
+    const double cr = (t[0] - t[2]) / t[4], cf = (t[1] - t[3]) / t[4];
+    const double dux = (t[5] - (t[7] + cr * t[9])) / t[0], duy = (t[6] - (t[8] + cr * t[10])) / t[0];
+    const int64_t HW = (int64_t)a.H * a.W, base = img * HW;
+    const int64_t chunk = (HW + a.bpi - 1) / a.bpi;
+    const int64_t l0 = (int64_t)b * chunk, l1 = l0 + chunk < HW ? l0 + chunk : HW;
+    for (int64_t l = l0 + threadIdx.x; l < l1; l += blockDim.x) {
+        const int64_t p = base + l;
+        const double wt = a.wgt[p];
+        a.rho_out[p] += cr * wt;
+        a.phi_out[p] += cf * wt;
+        a.ux_out[p] += dux;
+        a.uy_out[p] += duy;
+    }
+}
+
+template <int CIN, int COUT>
+static hipError_t conv_t(const uint16_t* in, const uint16_t* wp, const float* bias, const uint16_t* mask,
+                         uint16_t* out_bf, float* out_f32, int N, int H, int W, int sgn, int relu, hipStream_t st) {
+    const int64_t P = (int64_t)N * H * W;
+    const int64_t waves = (P + 31) / 32;
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    k_conv<CIN, COUT><<<blocks, 256, 0, st>>>(in, wp, bias, mask, out_bf, out_f32, N, H, W, sgn, relu);
+    return hipGetLastError();
+}
+
+static hipError_t conv_dispatch(int cin, int cout, const uint16_t* in, const uint16_t* wp, const float* bias,
+                                const uint16_t* mask, uint16_t* out_bf, float* out_f32, int N, int H, int W, int sgn,
+                                int relu, hipStream_t st) {
+    if (cin == 32 && cout == 64) return conv_t<32, 64>(in, wp, bias, mask, out_bf, out_f32, N, H, W, sgn, relu, st);
+    if (cin == 64 && cout == 64) return conv_t<64, 64>(in, wp, bias, mask, out_bf, out_f32, N, H, W, sgn, relu, st);
+    if (cin == 64 && cout == 32) return conv_t<64, 32>(in, wp, bias, mask, out_bf, out_f32, N, H, W, sgn, relu, st);
+    if (cin == 32 && cout == 32) return conv_t<32, 32>(in, wp, bias, mask, out_bf, out_f32, N, H, W, sgn, relu, st);
+    return hipErrorInvalidValue;
+}
+
+static hipError_t wgrad_dispatch(int cin, int cout, const uint16_t* in, const uint16_t* dy, float* part, int N,
+                                 int H, int W, int wpt, hipStream_t st) {
+    const unsigned blocks = (unsigned)((9 * wpt + 3) / 4);
+    if (cin == 32 && cout == 64) k_conv_wgrad<32, 64><<<blocks, 256, 0, st>>>(in, dy, part, N, H, W, wpt);
+    else if (cin == 64 && cout == 64) k_conv_wgrad<64, 64><<<blocks, 256, 0, st>>>(in, dy, part, N, H, W, wpt);
+    else if (cin == 64 && cout == 32) k_conv_wgrad<64, 32><<<blocks, 256, 0, st>>>(in, dy, part, N, H, W, wpt);
+    else if (cin == 32 && cout == 32) k_conv_wgrad<32, 32><<<blocks, 256, 0, st>>>(in, dy, part, N, H, W, wpt);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace telbm
+
+using namespace telbm;
+
+namespace {
+bool conv_shape_ok(int cin, int cout) {
+    return (cin == 32 || cin == 64) && (cout == 32 || cout == 64);
+}
+}  // namespace
+
+extern "C" {
+
+int telbm_conv_pack_weights(const float* w, int cin, int cout, void* wf_bf16, void* wd_bf16, void* stream) {
+    if (!w || !wf_bf16 || !wd_bf16 || !conv_shape_ok(cin, cout)) return TELBM_ERR_INVAL;
+    const int n = 9 * cin * cout;
+    k_pack_weights<<<(n + 255) / 256, 256, 0, (hipStream_t)stream>>>(w, cin, cout, (uint16_t*)wf_bf16,
+                                                                     (uint16_t*)wd_bf16);
+    return hipGetLastError() == hipSuccess ? TELBM_OK : TELBM_ERR_DEVICE;
+}
+
+int telbm_conv_forward(const void* x, int n, int h, int w, int cin, const void* wf_bf16, const float* bias,
+                       int cout, int relu, void* y_bf16, float* y_f32, void* stream) {
+    if (!x || !wf_bf16 || (!y_bf16 && !y_f32) || n < 1 || h < 1 || w < 1 || !conv_shape_ok(cin, cout))
+        return TELBM_ERR_INVAL;
+    hipError_t e = conv_dispatch(cin, cout, (const uint16_t*)x, (const uint16_t*)wf_bf16, bias, nullptr,
+                                 (uint16_t*)y_bf16, y_f32, n, h, w, +1, relu, (hipStream_t)stream);
+    return e == hipSuccess ? TELBM_OK : TELBM_ERR_DEVICE;
+}
+
+int telbm_conv_backward(const void* x, const void* dy, int n, int h, int w, int cin, int cout, const void* wd_bf16,
+                        const void* x_relu_mask, void* dx_bf16, float* dw, float* db, void* workspace,
+                        size_t workspace_bytes, void* stream) {
+    if (!x || !dy || n < 1 || h < 1 || w < 1 || !conv_shape_ok(cin, cout)) return TELBM_ERR_INVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (dx_bf16) {
+        if (!wd_bf16) return TELBM_ERR_INVAL;
+        // dx[q] = sum_t dy[q - off(t)] w[t] = sum_t' dy[q + off(t')] w[8 - t']: a
+        // forward convolution of dy with the flipped, transposed weights
+        hipError_t e = conv_dispatch(cout, cin, (const uint16_t*)dy, (const uint16_t*)wd_bf16, nullptr,
+                                     (const uint16_t*)x_relu_mask, (uint16_t*)dx_bf16, nullptr, n, h, w, +1, 0, st);
+        if (e != hipSuccess) return TELBM_ERR_DEVICE;
+    }
+    if (dw || db) {
+        const int64_t P = (int64_t)n * h * w;
+        const int64_t slabs = (P + 31) / 32;
+        int wpt = (int)(slabs < 256 ? slabs : 256);
+        if (wpt < 1) wpt = 1;
+        const size_t need = (size_t)wpt * 9 * cin * cout * sizeof(float);
+        const int bblocks = 512;
+        const size_t need_b = (size_t)bblocks * cout * sizeof(float);
+        if (!workspace || workspace_bytes < (need > need_b ? need : need_b)) return TELBM_ERR_NOMEM;
+        if (dw) {
+            hipError_t e = wgrad_dispatch(cin, cout, (const uint16_t*)x, (const uint16_t*)dy, (float*)workspace, n, h,
+                                          w, wpt, st);
+            if (e != hipSuccess) return TELBM_ERR_DEVICE;
+            const int64_t ne = 9LL * cin * cout;
+            k_reduce_parts<<<(unsigned)((ne + 255) / 256), 256, 0, st>>>((const float*)workspace, wpt, ne, dw);
+            if (hipGetLastError() != hipSuccess) return TELBM_ERR_DEVICE;
+        }
+        if (db) {
+            k_bias_grad<<<bblocks, 64, 0, st>>>((const uint16_t*)dy, P, cout, (float*)workspace);
+            k_reduce_parts<<<(cout + 255) / 256, 256, 0, st>>>((const float*)workspace, bblocks, cout, db);
+            if (hipGetLastError() != hipSuccess) return TELBM_ERR_DEVICE;
+        }
+    }
+    return TELBM_OK;
+}
+
+int telbm_conv_workspace_bytes(int n, int h, int w, int cin, int cout, size_t* bytes) {
+    if (!bytes || n < 1 || h < 1 || w < 1 || !conv_shape_ok(cin, cout)) return TELBM_ERR_INVAL;
+    const int64_t slabs = ((int64_t)n * h * w + 31) / 32;
+    const int64_t wpt = slabs < 256 ? slabs : 256;
+    const size_t a = (size_t)wpt * 9 * cin * cout * sizeof(float);
+    const size_t b = (size_t)512 * cout * sizeof(float);
+    *bytes = a > b ? a : b;
+    return TELBM_OK;
+}
+
+int telbm_residual_mse(const void* x, const float* y, const void* target, int64_t pixels, int channels, int valid,
+                       void* dy_bf16, float* pred, float* loss_partials, int* nblocks, void* stream) {
+    if (!x || !y || pixels < 1 || channels < 1 || valid < 1 || valid > channels || !nblocks) return TELBM_ERR_INVAL;
+    const int64_t ne = pixels * channels;
+    const unsigned blocks = (unsigned)((ne + 255) / 256);
+    *nblocks = (int)blocks;
+    const float scale = 1.0f / (float)(pixels * valid);
+    k_residual_mse<<<blocks, 256, 0, (hipStream_t)stream>>>((const uint16_t*)x, y, (const uint16_t*)target, pixels,
+                                                            channels, valid, scale, (uint16_t*)dy_bf16, pred,
+                                                            loss_partials);
+    return hipGetLastError() == hipSuccess ? TELBM_OK : TELBM_ERR_DEVICE;
+}
+
+int telbm_surrogate_encode(const double* rho, const double* phi, const double* ux, const double* uy,
+                           int64_t pixels, double rho_g, double rho_l, double chi, double u_scale, void* x_bf16,
+                           void* stream) {
+    if (!rho || !phi || !x_bf16 || pixels < 1 || !(rho_l > rho_g) || !(chi > 0.0) || !(u_scale > 0.0))
+        return TELBM_ERR_INVAL;
+    k_encode<<<(unsigned)((pixels + 255) / 256), 256, 0, (hipStream_t)stream>>>(
+        rho, phi, ux, uy, pixels, rho_g, 1.0 / (rho_l - rho_g), 1.0 / chi, u_scale, (uint16_t*)x_bf16);
+    return hipGetLastError() == hipSuccess ? TELBM_OK : TELBM_ERR_DEVICE;
+}
+
+static int decode_blocks_per_image(int h, int w) {
+    const int64_t hw = (int64_t)h * w;
+    const int64_t b = (hw + 1023) / 1024;
+    return (int)(b < 1 ? 1 : (b > 256 ? 256 : b));
+}
+
+int telbm_surrogate_decode_workspace_bytes(int n, int h, int w, size_t* bytes) {
+    if (!bytes || n < 1 || h < 3 || w < 3) return TELBM_ERR_INVAL;
+    *bytes = ((size_t)n * h * w + (size_t)n * decode_blocks_per_image(h, w) * kDecSums) * sizeof(double);
+    return TELBM_OK;
+}
+
+int telbm_surrogate_decode(const float* y, const double* rho_in, const double* phi_in, const double* ux_in,
+                           const double* uy_in, int n, int h, int w, double rho_g, double rho_l, double chi,
+                           double u_scale, double* rho_out, double* phi_out, double* ux_out, double* uy_out,
+                           void* workspace, size_t workspace_bytes, void* stream) {
+    size_t need = 0;
+    if (!y || !rho_in || !phi_in || !rho_out || !phi_out || !ux_out || !uy_out || !(rho_l > rho_g) ||
+        !(chi > 0.0) || !(u_scale > 0.0) || telbm_surrogate_decode_workspace_bytes(n, h, w, &need) != TELBM_OK)
+        return TELBM_ERR_INVAL;
+    if (!workspace || workspace_bytes < need) return TELBM_ERR_NOMEM;
+    DecodeArgs a;
+    a.y = y;
+    a.rho_in = rho_in;
+    a.phi_in = phi_in;
+    a.ux_in = ux_in;
+    a.uy_in = uy_in;
+    a.rho_out = rho_out;
+    a.phi_out = phi_out;
+    a.ux_out = ux_out;
+    a.uy_out = uy_out;
+    a.wgt = (double*)workspace;
+    a.part = (double*)workspace + (size_t)n * h * w;
+    a.H = h;
+    a.W = w;
+    a.bpi = decode_blocks_per_image(h, w);
+    a.rho_g = rho_g;
+    a.drho = rho_l - rho_g;
+    a.chi = chi;
+    a.smin = -0.5 * rho_g / (rho_l - rho_g);  // keeps rho >= rho_g / 2
+    a.inv_uscale = 1.0 / u_scale;
+    const unsigned blocks = (unsigned)(n * a.bpi);
+    k_decode_stats<<<blocks, 256, 0, (hipStream_t)stream>>>(a);
+    k_decode_apply<<<blocks, 256, 0, (hipStream_t)stream>>>(a);
+    return hipGetLastError() == hipSuccess ? TELBM_OK : TELBM_ERR_DEVICE;
+}
+
+int telbm_adam_step(float* w, const float* g, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
+                    float eps, int64_t t, void* stream) {
+    if (!w || !g || !m || !v || n < 1 || t < 1) return TELBM_ERR_INVAL;
+    const float c1 = 1.f - powf(beta1, (float)t), c2 = 1.f - powf(beta2, (float)t);
+    k_adam<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(w, g, m, v, n, lr, beta1, beta2, eps, c1,
+                                                                         c2);
+    return hipGetLastError() == hipSuccess ? TELBM_OK : TELBM_ERR_DEVICE;
+}
+
+}  // extern "C"
