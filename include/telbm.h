@@ -254,19 +254,21 @@ const char *telbm_batch_last_error(const telbm_batch *b);
  * the data-gradient layout wd[ci][tap*cout + co] with taps flipped (BF16). */
 int telbm_conv_pack_weights(const float *w, int cin, int cout, void *wf_bf16, void *wd_bf16, void *stream);
 
-/* y[p][co] = act(bias[co] + sum_{tap,ci} x[p + off(tap)][ci] w[tap][ci][co]) over
- * an n x h x w periodic grid; act = ReLU if relu != 0.  Writes y_bf16 and/or
- * y_f32 (either may be NULL, not both). */
+/* y[p][co] = act(bias[co] + sum_{tap,ci} x[p + d off(tap)][ci] w[tap][ci][co])
+ * over an n x h x w periodic grid, off(tap) = (tap/3 - 1, tap%3 - 1) in
+ * (row, column), dilation d = `dilation` >= 1; act = ReLU if relu != 0.
+ * bias may be NULL.  Writes y_bf16 and/or y_f32 (either may be NULL, not
+ * both). */
 int telbm_conv_forward(const void *x, int n, int h, int w, int cin, const void *wf_bf16, const float *bias,
-                       int cout, int relu, void *y_bf16, float *y_f32, void *stream);
+                       int cout, int dilation, int relu, void *y_bf16, float *y_f32, void *stream);
 
-/* Gradients of telbm_conv_forward given dy (BF16, n*h*w*cout):
- * dx (BF16, optional) = sum_t dy[p - off(t)] w[t]^T, multiplied by
- * (x_relu_mask > 0) when a mask (the ReLU output that fed this layer) is
- * given; dw (FP32, optional) = sum_p x[p + off(t)] dy[p]^T; db (FP32,
- * optional) = sum_p dy[p].  dw and db need a workspace of
+/* Gradients of the linear part of telbm_conv_forward given dy (BF16,
+ * n*h*w*cout): dx (BF16, optional) = sum_t dy[p - d off(t)] w[t]^T,
+ * multiplied by (x_relu_mask > 0) when a mask (the ReLU output that fed
+ * this layer) is given; dw (FP32, optional) = sum_p x[p + d off(t)] dy[p]^T;
+ * db (FP32, optional) = sum_p dy[p].  dw and db need a workspace of
  * telbm_conv_workspace_bytes; the reductions are deterministic. */
-int telbm_conv_backward(const void *x, const void *dy, int n, int h, int w, int cin, int cout,
+int telbm_conv_backward(const void *x, const void *dy, int n, int h, int w, int cin, int cout, int dilation,
                         const void *wd_bf16, const void *x_relu_mask, void *dx_bf16, float *dw, float *db,
                         void *workspace, size_t workspace_bytes, void *stream);
 int telbm_conv_workspace_bytes(int n, int h, int w, int cin, int cout, size_t *bytes);
@@ -291,10 +293,10 @@ int telbm_surrogate_encode(const double *rho, const double *phi, const double *u
 /* State from the network output y (FP32 NHWC, 32 channels, first five
  * used) and the exact input state (n images of h x w; ux_in, uy_in may be
  * NULL for a state at rest): the encoded input plus y (residual head),
- * clamped to rho >= rho_g/2 and |phi| <= chi, then projected so that each
+ * clamped to rho >= rho_g/2 and |phi| <= 1.1 chi, then projected so that each
  * image's totals of rho, phi and rho u equal the input's (the quantities
  * the method conserves): the rho and phi defects are added in proportion to
- * w = |grad ch0| + |grad(phi/chi)| + 1e-3, the momentum defect by a uniform
+ * w = |grad ch0| + |grad(phi/chi)| + 1e-6, the momentum defect by a uniform
  * velocity shift.  Writes rho, phi, ux, uy (FP64, n*h*w each); needs
  * telbm_surrogate_decode_workspace_bytes of workspace. */
 int telbm_surrogate_decode(const float *y, const double *rho_in, const double *phi_in, const double *ux_in,

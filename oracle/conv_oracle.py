@@ -3,9 +3,9 @@
 TEST INFRASTRUCTURE ONLY (tests, smoke check, benchmark CPU leg).
 
 A layer maps an image batch x[n, h, w, ci] on a periodic grid to
-    y[n, h, w, co] = b[co] + sum_{t, ci} x[n, h + dy_t, w + dx_t, ci] * W[t, ci, co]
-with the nine taps t = 3 (dy + 1) + (dx + 1), dy, dx in {-1, 0, 1}
-(circular padding), optionally followed by a ReLU.  The gradients below are
+    y[n, h, w, co] = b[co] + sum_{t, ci} x[n, h + d dy_t, w + d dx_t, ci] * W[t, ci, co]
+with the nine taps t = 3 (dy + 1) + (dx + 1), dy, dx in {-1, 0, 1}, the
+dilation d >= 1 (circular padding), optionally followed by a ReLU.  The gradients below are
 the adjoints of that definition; they are pinned against central finite
 differences of `conv_forward` in tests/test_conv_oracle.py.
 """
@@ -19,12 +19,12 @@ def shifted(x, dy, dx):
     return np.roll(x, shift=(-dy, -dx), axis=(1, 2))
 
 
-def conv_forward(x, W, b=None, relu=False):
+def conv_forward(x, W, b=None, relu=False, dil=1):
     x = np.asarray(x, dtype=np.float64)
     W = np.asarray(W, dtype=np.float64)
     y = np.zeros(x.shape[:3] + (W.shape[2],))
     for t, (dy, dx) in enumerate(OFFSETS):
-        y += shifted(x, dy, dx) @ W[t]
+        y += shifted(x, dil * dy, dil * dx) @ W[t]
     if b is not None:
         y += np.asarray(b, dtype=np.float64)
     if relu:
@@ -32,7 +32,7 @@ def conv_forward(x, W, b=None, relu=False):
     return y
 
 
-def conv_backward(x, W, dy_out):
+def conv_backward(x, W, dy_out, dil=1):
     """Gradients of the linear part: (dx, dW, db) for upstream gradient dy_out."""
     x = np.asarray(x, dtype=np.float64)
     W = np.asarray(W, dtype=np.float64)
@@ -40,6 +40,7 @@ def conv_backward(x, W, dy_out):
     dx = np.zeros_like(x)
     dW = np.zeros_like(W)
     for t, (dy, dxo) in enumerate(OFFSETS):
+        dy, dxo = dil * dy, dil * dxo
         # y[p] gets x[p + off] W[t]  =>  x[q] receives g[q - off] W[t]^T
         dx += shifted(g @ W[t].T, -dy, -dxo)
         xs = shifted(x, dy, dxo)

@@ -36,10 +36,16 @@ union Pack8 {
 };
 
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+// periodic index for any offset (dilated taps may exceed the grid size)
+__device__ __forceinline__ int wrapn(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
 
 // ---------------------------------------------------------------------------
-// Implicit-GEMM convolution: out[p][co] = sum_{tap, ci} in[p + s*off(tap)][ci]
-// * Wp[co][tap*CIN + ci] (+ bias, ReLU), off(tap) = (tap/3 - 1, tap%3 - 1);
+// Implicit-GEMM convolution: out[p][co] = sum_{tap, ci} in[p + s*d*off(tap)][ci]
+// * Wp[co][tap*CIN + ci] (+ bias, ReLU), off(tap) = (tap/3 - 1, tap%3 - 1),
+// dilation d >= 1;
 // s = +1 for the forward pass and for the data gradient (which runs on the
 // flipped, transposed weights).  Optional mask: out *= (mask[p][co] > 0)
 // (derivative of the ReLU that produced the layer input).  Each wavefront
@@ -49,7 +55,7 @@ template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wp,
                                               const float* __restrict__ bias, const uint16_t* __restrict__ mask,
                                               uint16_t* __restrict__ out_bf, float* __restrict__ out_f32, int N,
-                                              int H, int W, int sgn, int relu) {
+                                              int H, int W, int sgn, int dil, int relu) {
     constexpr int NT = COUT / 16;
     constexpr int KC = CIN / 32;  // K chunks per tap
     const int lane = threadIdx.x & 63;
@@ -73,10 +79,10 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
     for (int mt = 0; mt < 2; ++mt)
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int tap = 0; tap < 9; ++tap) {
-        const int dh = sgn * (tap / 3 - 1), dw = sgn * (tap % 3 - 1);
+        const int dh = sgn * dil * (tap / 3 - 1), dw = sgn * dil * (tap % 3 - 1);
         int64_t src[2];
         for (int mt = 0; mt < 2; ++mt)
-            src[mt] = (((int64_t)nn[mt] * H + wrap(hh[mt] + dh, H)) * W + wrap(ww[mt] + dw, W)) * CIN;
+            src[mt] = (((int64_t)nn[mt] * H + wrapn(hh[mt] + dh, H)) * W + wrapn(ww[mt] + dw, W)) * CIN;
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
             const int ci = kc * 32 + kg * 8;
@@ -113,7 +119,7 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradient: dW[tap][ci][co] = sum_p in[p + off(tap)][ci] * dy[p][co].
+// Weight gradient: dW[tap][ci][co] = sum_p in[p + d*off(tap)][ci] * dy[p][co].
 // Each wavefront walks a contiguous range of pixels in slabs of 32, stages
 // the slab's in (shifted by the tap) and dy transposed in its LDS region,
 // and accumulates the CIN x COUT tile of one tap on the matrix cores; the
@@ -122,7 +128,7 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
 // ---------------------------------------------------------------------------
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__ in, const uint16_t* __restrict__ dy,
-                                                    float* __restrict__ part, int N, int H, int W,
+                                                    float* __restrict__ part, int N, int H, int W, int dil,
                                                     int waves_per_tap) {
     constexpr int MT = CIN / 16, NT = COUT / 16;
     __shared__ uint16_t lds[4][(CIN + COUT) * 32];  // per wave: inT[CIN][32], dyT[COUT][32]
@@ -130,7 +136,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__
     const int wave = blockIdx.x * 4 + wl;
     const int tap = wave / waves_per_tap, wt = wave % waves_per_tap;
     if (tap >= 9) return;
-    const int dh = tap / 3 - 1, dw = tap % 3 - 1;
+    const int dh = dil * (tap / 3 - 1), dw = dil * (tap % 3 - 1);
     uint16_t* inT = lds[wl];
     uint16_t* dyT = lds[wl] + CIN * 32;
     const int64_t P = (int64_t)N * H * W;
@@ -152,7 +158,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__
                 if (v < VIN) {
                     const int n = (int)(p / ((int64_t)H * W));
                     const int rem = (int)(p % ((int64_t)H * W));
-                    const int h = wrap(rem / W + dh, H), w = wrap(rem % W + dw, W);
+                    const int h = wrapn(rem / W + dh, H), w = wrapn(rem % W + dw, W);
                     d.v = *(const uint4*)(in + (((int64_t)n * H + h) * W + w) * CIN + v * 8);
                 } else {
                     d.v = *(const uint4*)(dy + p * COUT + (v - VIN) * 8);
@@ -292,9 +298,12 @@ __global__ void k_encode(const double* __restrict__ rho, const double* __restric
 // Decoding.  The prediction is the exact input plus the network output y
 // (residual head): rho^ = rho^_in + y0, C1 = C1_in + y1, C2 = C2_in + y2,
 // u = u_in + y3,4 / u_scale; rho^ is clamped so that rho >= rho_g/2 and
-// phi/chi = C1 - C2 to [-1, 1].  The first pass writes these values, the
-// interface weight w = |grad rho^| + |grad(phi/chi)| + floor (central
-// differences, periodic) and per-block partial sums; the second pass adds
+// phi/chi = C1 - C2 to [-1.1, 1.1] (a clamp at +-1 would cut the positive
+// half of the bulk noise and leave a biased phase defect for the projection;
+// the double well pulls slight excursions back).  The first pass writes these values, the
+// interface weight w = |grad rho^| + |grad(phi/chi)| + 1e-6 (central
+// differences, periodic; the small floor keeps a featureless image defined
+// while putting the defects on the interfaces, not into the bulk phases) and per-block partial sums; the second pass adds
 // the mass and phase defects in proportion to w and shifts the velocity
 // uniformly so that the totals of rho, phi and rho u equal the input's.
 // Blocks never straddle images.
@@ -315,7 +324,7 @@ __device__ __forceinline__ void decode_px(const DecodeArgs& a, int64_t p, double
     const double c1 = 0.5 * (s_in + q_in) + (double)y[1], c2 = 0.5 * (s_in - q_in) + (double)y[2];
     q = c1 - c2;
     s = s < a.smin ? a.smin : s;
-    q = q > 1.0 ? 1.0 : (q < -1.0 ? -1.0 : q);
+    q = q > 1.1 ? 1.1 : (q < -1.1 ? -1.1 : q);
 }
 
 __global__ void k_decode_stats(DecodeArgs a) {
@@ -337,7 +346,7 @@ __global__ void k_decode_stats(DecodeArgs a) {
         decode_px(a, base + (int64_t)wrap(h + 1, a.H) * a.W + w, sy1, qy1);
         const double gs = sqrt(0.25 * ((sx1 - sx0) * (sx1 - sx0) + (sy1 - sy0) * (sy1 - sy0)));
         const double gq = sqrt(0.25 * ((qx1 - qx0) * (qx1 - qx0) + (qy1 - qy0) * (qy1 - qy0)));
-        const double wt = gs + gq + 1e-3;
+        const double wt = gs + gq + 1e-6;
         const double r = a.rho_g + a.drho * s, f = a.chi * q;
         const double uxi = a.ux_in ? a.ux_in[p] : 0.0, uyi = a.uy_in ? a.uy_in[p] : 0.0;
         const double uxo = uxi + (double)a.y[p * 32 + 3] * a.inv_uscale;
@@ -396,31 +405,35 @@ __global__ void k_decode_apply(DecodeArgs a) {
 
 template <int CIN, int COUT>
 static hipError_t conv_t(const uint16_t* in, const uint16_t* wp, const float* bias, const uint16_t* mask,
-                         uint16_t* out_bf, float* out_f32, int N, int H, int W, int sgn, int relu, hipStream_t st) {
+                         uint16_t* out_bf, float* out_f32, int N, int H, int W, int sgn, int dil, int relu,
+                         hipStream_t st) {
     const int64_t P = (int64_t)N * H * W;
     const int64_t waves = (P + 31) / 32;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
-    k_conv<CIN, COUT><<<blocks, 256, 0, st>>>(in, wp, bias, mask, out_bf, out_f32, N, H, W, sgn, relu);
+    k_conv<CIN, COUT><<<blocks, 256, 0, st>>>(in, wp, bias, mask, out_bf, out_f32, N, H, W, sgn, dil, relu);
     return hipGetLastError();
 }
 
 static hipError_t conv_dispatch(int cin, int cout, const uint16_t* in, const uint16_t* wp, const float* bias,
                                 const uint16_t* mask, uint16_t* out_bf, float* out_f32, int N, int H, int W, int sgn,
-                                int relu, hipStream_t st) {
-    if (cin == 32 && cout == 64) return conv_t<32, 64>(in, wp, bias, mask, out_bf, out_f32, N, H, W, sgn, relu, st);
-    if (cin == 64 && cout == 64) return conv_t<64, 64>(in, wp, bias, mask, out_bf, out_f32, N, H, W, sgn, relu, st);
-    if (cin == 64 && cout == 32) return conv_t<64, 32>(in, wp, bias, mask, out_bf, out_f32, N, H, W, sgn, relu, st);
-    if (cin == 32 && cout == 32) return conv_t<32, 32>(in, wp, bias, mask, out_bf, out_f32, N, H, W, sgn, relu, st);
+                                int dil, int relu, hipStream_t st) {
+#define TELBM_CONV(CI, CO) \
+    if (cin == CI && cout == CO) return conv_t<CI, CO>(in, wp, bias, mask, out_bf, out_f32, N, H, W, sgn, dil, relu, st);
+    TELBM_CONV(32, 64)
+    TELBM_CONV(64, 64)
+    TELBM_CONV(64, 32)
+    TELBM_CONV(32, 32)
+#undef TELBM_CONV
     return hipErrorInvalidValue;
 }
 
 static hipError_t wgrad_dispatch(int cin, int cout, const uint16_t* in, const uint16_t* dy, float* part, int N,
-                                 int H, int W, int wpt, hipStream_t st) {
+                                 int H, int W, int dil, int wpt, hipStream_t st) {
     const unsigned blocks = (unsigned)((9 * wpt + 3) / 4);
-    if (cin == 32 && cout == 64) k_conv_wgrad<32, 64><<<blocks, 256, 0, st>>>(in, dy, part, N, H, W, wpt);
-    else if (cin == 64 && cout == 64) k_conv_wgrad<64, 64><<<blocks, 256, 0, st>>>(in, dy, part, N, H, W, wpt);
-    else if (cin == 64 && cout == 32) k_conv_wgrad<64, 32><<<blocks, 256, 0, st>>>(in, dy, part, N, H, W, wpt);
-    else if (cin == 32 && cout == 32) k_conv_wgrad<32, 32><<<blocks, 256, 0, st>>>(in, dy, part, N, H, W, wpt);
+    if (cin == 32 && cout == 64) k_conv_wgrad<32, 64><<<blocks, 256, 0, st>>>(in, dy, part, N, H, W, dil, wpt);
+    else if (cin == 64 && cout == 64) k_conv_wgrad<64, 64><<<blocks, 256, 0, st>>>(in, dy, part, N, H, W, dil, wpt);
+    else if (cin == 64 && cout == 32) k_conv_wgrad<64, 32><<<blocks, 256, 0, st>>>(in, dy, part, N, H, W, dil, wpt);
+    else if (cin == 32 && cout == 32) k_conv_wgrad<32, 32><<<blocks, 256, 0, st>>>(in, dy, part, N, H, W, dil, wpt);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -446,25 +459,27 @@ int telbm_conv_pack_weights(const float* w, int cin, int cout, void* wf_bf16, vo
 }
 
 int telbm_conv_forward(const void* x, int n, int h, int w, int cin, const void* wf_bf16, const float* bias,
-                       int cout, int relu, void* y_bf16, float* y_f32, void* stream) {
-    if (!x || !wf_bf16 || (!y_bf16 && !y_f32) || n < 1 || h < 1 || w < 1 || !conv_shape_ok(cin, cout))
+                       int cout, int dilation, int relu, void* y_bf16, float* y_f32, void* stream) {
+    if (!x || !wf_bf16 || (!y_bf16 && !y_f32) || n < 1 || h < 1 || w < 1 || dilation < 1 ||
+        !conv_shape_ok(cin, cout))
         return TELBM_ERR_INVAL;
     hipError_t e = conv_dispatch(cin, cout, (const uint16_t*)x, (const uint16_t*)wf_bf16, bias, nullptr,
-                                 (uint16_t*)y_bf16, y_f32, n, h, w, +1, relu, (hipStream_t)stream);
+                                 (uint16_t*)y_bf16, y_f32, n, h, w, +1, dilation, relu, (hipStream_t)stream);
     return e == hipSuccess ? TELBM_OK : TELBM_ERR_DEVICE;
 }
 
-int telbm_conv_backward(const void* x, const void* dy, int n, int h, int w, int cin, int cout, const void* wd_bf16,
-                        const void* x_relu_mask, void* dx_bf16, float* dw, float* db, void* workspace,
-                        size_t workspace_bytes, void* stream) {
-    if (!x || !dy || n < 1 || h < 1 || w < 1 || !conv_shape_ok(cin, cout)) return TELBM_ERR_INVAL;
+int telbm_conv_backward(const void* x, const void* dy, int n, int h, int w, int cin, int cout, int dilation,
+                        const void* wd_bf16, const void* x_relu_mask, void* dx_bf16, float* dw, float* db,
+                        void* workspace, size_t workspace_bytes, void* stream) {
+    if (!x || !dy || n < 1 || h < 1 || w < 1 || dilation < 1 || !conv_shape_ok(cin, cout)) return TELBM_ERR_INVAL;
     hipStream_t st = (hipStream_t)stream;
     if (dx_bf16) {
         if (!wd_bf16) return TELBM_ERR_INVAL;
-        // dx[q] = sum_t dy[q - off(t)] w[t] = sum_t' dy[q + off(t')] w[8 - t']: a
-        // forward convolution of dy with the flipped, transposed weights
+        // dx[q] = sum_t dy[q - d off(t)] w[t] = sum_t' dy[q + d off(t')] w[8 - t']:
+        // a forward convolution of dy with the flipped, transposed weights
         hipError_t e = conv_dispatch(cout, cin, (const uint16_t*)dy, (const uint16_t*)wd_bf16, nullptr,
-                                     (const uint16_t*)x_relu_mask, (uint16_t*)dx_bf16, nullptr, n, h, w, +1, 0, st);
+                                     (const uint16_t*)x_relu_mask, (uint16_t*)dx_bf16, nullptr, n, h, w, +1,
+                                     dilation, 0, st);
         if (e != hipSuccess) return TELBM_ERR_DEVICE;
     }
     if (dw || db) {
@@ -478,7 +493,7 @@ int telbm_conv_backward(const void* x, const void* dy, int n, int h, int w, int 
         if (!workspace || workspace_bytes < (need > need_b ? need : need_b)) return TELBM_ERR_NOMEM;
         if (dw) {
             hipError_t e = wgrad_dispatch(cin, cout, (const uint16_t*)x, (const uint16_t*)dy, (float*)workspace, n, h,
-                                          w, wpt, st);
+                                          w, dilation, wpt, st);
             if (e != hipSuccess) return TELBM_ERR_DEVICE;
             const int64_t ne = 9LL * cin * cout;
             k_reduce_parts<<<(unsigned)((ne + 255) / 256), 256, 0, st>>>((const float*)workspace, wpt, ne, dw);

@@ -1,21 +1,26 @@
-"""Equilibrium detector used to judge a run.
+"""Equilibrium detectors used to judge a run.
 
-The observables are the interface measures L_k = sum_x |grad s_k| of the
-scaled density s_0 = (rho - rho_g)/(rho_l - rho_g) and of the two liquid
-concentrations s_1 = C1, s_2 = C2 (central differences, periodic): in two
-dimensions they are the lengths of the liquid-gas outline and of each
-liquid's outline.  Relaxation to the equilibrium lens (or engulfed drop)
-lowers them toward their final values.  They do not change when the whole
-structure drifts, which it does slowly through the periodic box, so a
-pointwise field difference is no test of settling.  The velocity is no test
-either: near the triple points the spurious currents stay at O(1e-3) in
-lattice units at a density ratio of 10.
+The observables are shape measures: for the scaled density s_0 = (rho -
+rho_g)/(rho_l - rho_g) and the two liquid concentrations s_1 = C1, s_2 =
+C2, L_k = sum_x |grad r(s_k)| with the indicator ramp r(v) = clip((v -
+1/4)/(1/2), 0, 1) (central differences, periodic).  In two dimensions L_0 is
+the length of the liquid-gas outline and L_1, L_2 those of each liquid's
+outline.  The ramp is flat in the bulk phases, so the measures see the
+shapes and not the slow drift of the bulk densities toward the curved-
+interface coexistence values; and they do not change when the whole
+structure drifts through the periodic box, which it does slowly.  The
+velocity is no test either: near the triple points the spurious currents
+stay at O(1e-3) in lattice units at a density ratio of 10.
 
-The detector fires when every L_k changes by less than `tol` (relative)
-over each of `patience` consecutive windows of steps (capillary waves make
-a single quiet window a poor sign); the steps counted are those at the end
-of the first quiet window.  Analysis only; the state is read back through
-the library.
+Two detectors:
+  - online (run_to_equilibrium): fires when every L_k changes by less than
+    `tol` (relative) over each of `patience` consecutive windows of steps
+    (capillary waves make a single quiet window a poor sign);
+  - judged (settle_step): given a run's trajectory of measures and the
+    equilibrium measures of a long plain reference run, the first step from
+    which every L_k stays within `tol` (relative) of its equilibrium value
+    until the end of the trajectory.
+Analysis only; the state is read back through the library.
 """
 from __future__ import annotations
 
@@ -33,7 +38,12 @@ class Detector:
     patience: int = 2
 
 
+def _ramp(v: np.ndarray) -> np.ndarray:
+    return np.clip((v - 0.25) / 0.5, 0.0, 1.0)
+
+
 def _grad_norm_sum(s: np.ndarray) -> float:
+    s = _ramp(s)
     g2 = np.zeros_like(s)
     for ax in range(s.ndim):
         if s.shape[ax] > 1:
@@ -75,3 +85,28 @@ def run_to_equilibrium(solver, rho_g: float, rho_l: float, chi: float = 5.0, det
             return steps - det.window * (det.patience - 1), hist
         prev = cur
     return det.max_steps + det.window, hist
+
+
+def trajectory(solver, steps: int, window: int, rho_g: float, rho_l: float, chi: float = 5.0) -> np.ndarray:
+    """Interface measures at t = 0, window, 2 window, ..., steps (rows)."""
+    out = [measures_of(solver, rho_g, rho_l, chi)]
+    for _ in range(steps // window):
+        solver.step(window)
+        out.append(measures_of(solver, rho_g, rho_l, chi))
+    return np.array(out)
+
+
+def distance(traj: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """Per-row largest relative distance of the measures to `ref`."""
+    return np.max(np.abs(traj - ref[None, :]) / np.maximum(np.abs(ref[None, :]), 1e-30), axis=1)
+
+
+def settle_step(traj: np.ndarray, ref: np.ndarray, tol: float, window: int) -> int:
+    """First step from which the trajectory stays within tol of ref; -1 if
+    it never settles (its last point is outside)."""
+    d = distance(traj, ref)
+    outside = np.nonzero(d >= tol)[0]
+    if outside.size == 0:
+        return 0
+    k = int(outside[-1]) + 1
+    return -1 if k >= len(d) else k * window

@@ -30,8 +30,8 @@ _vp, _i, _i64, _sz, _f, _d = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, cty
                               ctypes.c_double)
 PROTOTYPES = {
     "telbm_conv_pack_weights": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
-    "telbm_conv_forward": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _i, _i, _vp, _vp, _vp]),
-    "telbm_conv_backward": (_i, [_vp, _vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "telbm_conv_forward": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _i, _i, _i, _vp, _vp, _vp]),
+    "telbm_conv_backward": (_i, [_vp, _vp, _i, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "telbm_conv_workspace_bytes": (_i, [_i, _i, _i, _i, _i, ctypes.POINTER(_sz)]),
     "telbm_residual_mse": (_i, [_vp, _vp, _vp, _i64, _i, _i, _vp, _vp, _vp, ctypes.POINTER(_i), _vp]),
     "telbm_adam_step": (_i, [_vp, _vp, _vp, _vp, _i64, _f, _f, _f, _f, _i64, _vp]),
@@ -45,6 +45,9 @@ CH = 32          # stored channels at the network's ends
 VALID = 5        # encoded channels: scaled density, C1, C2, scaled ux, uy
 U_SCALE = 10.0   # velocity scale of the encoding (lattice velocities are O(1e-2))
 LAYERS = [(32, 64), (64, 64), (64, 64), (64, 64), (64, 64), (64, 32)]
+# dilations of the six 3x3 layers: a receptive field of +-18 nodes, about
+# the distance an interface moves over the 2000-step horizon
+DILATIONS = (1, 2, 4, 8, 2, 1)
 
 
 def _load():
@@ -84,9 +87,9 @@ def pack_weights(w, cin, cout, wf, wd, stream):
     _ck(_load().telbm_conv_pack_weights(_p(w), cin, cout, _p(wf), _p(wd), _vp(stream.cuda_stream)), "pack")
 
 
-def conv_forward(x, n, h, w, cin, wf, bias, cout, relu, y_bf16=None, y_f32=None, stream=None):
-    _ck(_load().telbm_conv_forward(_p(x), n, h, w, cin, _p(wf), _p(bias), cout, int(relu), _p(y_bf16), _p(y_f32),
-                                   _vp(stream.cuda_stream)), "conv forward")
+def conv_forward(x, n, h, w, cin, wf, bias, cout, relu, y_bf16=None, y_f32=None, stream=None, dil=1):
+    _ck(_load().telbm_conv_forward(_p(x), n, h, w, cin, _p(wf), _p(bias), cout, dil, int(relu), _p(y_bf16),
+                                   _p(y_f32), _vp(stream.cuda_stream)), "conv forward")
 
 
 def conv_workspace_bytes(n, h, w, cin, cout) -> int:
@@ -95,9 +98,9 @@ def conv_workspace_bytes(n, h, w, cin, cout) -> int:
     return b.value
 
 
-def conv_backward(x, dy, n, h, w, cin, cout, wd, mask, dx, dw, db, ws, stream):
-    _ck(_load().telbm_conv_backward(_p(x), _p(dy), n, h, w, cin, cout, _p(wd), _p(mask), _p(dx), _p(dw), _p(db),
-                                    _p(ws), ws.numel() if ws is not None else 0, _vp(stream.cuda_stream)),
+def conv_backward(x, dy, n, h, w, cin, cout, wd, mask, dx, dw, db, ws, stream, dil=1):
+    _ck(_load().telbm_conv_backward(_p(x), _p(dy), n, h, w, cin, cout, dil, _p(wd), _p(mask), _p(dx), _p(dw),
+                                    _p(db), _p(ws), ws.numel() if ws is not None else 0, _vp(stream.cuda_stream)),
         "conv backward")
 
 
@@ -141,12 +144,15 @@ def decode(y, rho_in, phi_in, ux_in, uy_in, n, h, w, rho_g, rho_l, chi, rho_out,
 class Network:
     """Six-layer 3x3 convolutional surrogate with Adam on FP32 masters."""
 
-    def __init__(self, seed: int = 0, device: str = "cuda", stream=None, out_scale: float = 0.1):
+    def __init__(self, seed: int = 0, device: str = "cuda", stream=None, out_scale: float = 0.1,
+                 dilations: Sequence[int] = DILATIONS):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the surrogate needs a GPU: no HIP device is visible")
         _load()
         self.device = torch.device(device)
+        self.dilations = tuple(int(d) for d in dilations)
+        assert len(self.dilations) == len(LAYERS) and min(self.dilations) >= 1
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         g = torch.Generator().manual_seed(seed)
         self.w, self.b, self.wf, self.wd = [], [], [], []
@@ -176,7 +182,7 @@ class Network:
             pack_weights(self.w[k], ci, co, self.wf[k], self.wd[k], self.stream)
 
     def state_dict(self) -> dict:
-        d = {"t": np.array(self.t)}
+        d = {"t": np.array(self.t), "dilations": np.array(self.dilations)}
         for k in range(len(LAYERS)):
             d[f"w{k}"] = self.w[k].cpu().numpy()
             d[f"b{k}"] = self.b[k].cpu().numpy()
@@ -188,6 +194,8 @@ class Network:
             self.w[k].copy_(torch.as_tensor(d[f"w{k}"]))
             self.b[k].copy_(torch.as_tensor(d[f"b{k}"]))
         self.t = int(d["t"])
+        if "dilations" in d:
+            self.dilations = tuple(int(v) for v in d["dilations"])
         self.pack()
 
     # -- buffers ----------------------------------------------------------------
@@ -216,12 +224,14 @@ class Network:
         inp = x
         last = len(LAYERS) - 1
         for k, (ci, co) in enumerate(LAYERS):
+            d = self.dilations[k]
             if k < last:
                 conv_forward(inp, n, h, w, ci, self.wf[k], self.b[k], co, 1, y_bf16=self.a[k + 1],
-                             stream=self.stream)
+                             stream=self.stream, dil=d)
                 inp = self.a[k + 1]
             else:
-                conv_forward(inp, n, h, w, ci, self.wf[k], self.b[k], co, 0, y_f32=self.y, stream=self.stream)
+                conv_forward(inp, n, h, w, ci, self.wf[k], self.b[k], co, 0, y_f32=self.y, stream=self.stream,
+                             dil=d)
         return self.y
 
     def loss_and_grad(self, x, target, n, h, w):
@@ -236,7 +246,7 @@ class Network:
             dx = None if k == 0 else self.dy[k - 1]
             mask = None if k == 0 else self.a[k]
             conv_backward(inp, self.dy[k], n, h, w, ci, co, self.wd[k], mask, dx, self.gw[k], self.gb[k], self.ws,
-                          self.stream)
+                          self.stream, dil=self.dilations[k])
         return self.loss_part[:nb]
 
     def adam(self, lr: float):
@@ -308,15 +318,42 @@ def drops_for_seed(fam: Family, seed: int):
     return [{"center": c1, "radius": R1, "liquid": 1}, {"center": c2, "radius": R2, "liquid": 2}]
 
 
-def family_params(fam: Family, rho_g: float, rho_l: float, T: float, precision: int = 0):
+@dataclasses.dataclass
+class Physics:
+    """Thermodynamic state of a family: the EOS temperature and the Maxwell
+    densities that parametrise the free energy (the solver's rho_g, rho_l),
+    and the lattice model's own coexisting densities, measured on a flat
+    slab, that start the drops and scale the network's density channel.
+    (Starting at the Maxwell densities sets off a slow global drift of the
+    bulk densities that would mask the shape relaxation.)"""
+    T: float
+    rho_g: float
+    rho_l: float
+    ic_g: float
+    ic_l: float
+    chi: float = 5.0
+
+
+def physics(fam: Family, calibrate_steps: int = 20000) -> Physics:
+    from .calibrate import discrete_coexistence
+    from .solver import coexistence, temperature_for_ratio
+    T = temperature_for_ratio(fam.ratio)
+    rg, rl, _, _ = coexistence(T)
+    p = family_params(fam, Physics(T, rg, rl, rg, rl))
+    ig, il = discrete_coexistence(p, steps=calibrate_steps)
+    return Physics(T, rg, rl, ig, il)
+
+
+def family_params(fam: Family, ph: Physics, precision: int = 0):
     from .solver import Params
-    return Params(lattice=0, precision=precision, nx=fam.n, ny=fam.n, nz=1, T=T, rho_g=rho_g, rho_l=rho_l,
-                  kappa2=fam.kappa2, kappa3=fam.kappa3, lambda2=3.125 * fam.kappa2, lambda3=3.125 * fam.kappa3)
+    return Params(lattice=0, precision=precision, nx=fam.n, ny=fam.n, nz=1, T=ph.T, rho_g=ph.rho_g,
+                  rho_l=ph.rho_l, chi=ph.chi, kappa2=fam.kappa2, kappa3=fam.kappa3, lambda2=3.125 * fam.kappa2,
+                  lambda3=3.125 * fam.kappa3)
 
 
-def initial_fields(fam: Family, seed: int, rho_g: float, rho_l: float, chi: float = 5.0):
+def initial_fields(fam: Family, seed: int, ph: Physics):
     from synth.fields import two_drop_fields
-    rho, phi, _ = two_drop_fields((1, fam.n, fam.n), drops_for_seed(fam, seed), rho_g, rho_l, chi, seed)
+    rho, phi, _ = two_drop_fields((1, fam.n, fam.n), drops_for_seed(fam, seed), ph.ic_g, ph.ic_l, ph.chi, seed)
     return rho[0], phi[0]
 
 
@@ -333,8 +370,8 @@ class Dataset:
         return self.X[i:j], self.Y[i:j]
 
 
-def generate(fam: Family, seeds: Sequence[int], rho_g: float, rho_l: float, T: float, precision: int = 0,
-             chunk: int = 64, stream=None, order_seed: int = 0) -> Dataset:
+def generate(fam: Family, seeds: Sequence[int], ph: Physics, precision: int = 0, chunk: int = 64, stream=None,
+             order_seed: int = 0) -> Dataset:
     """Run each seed's configuration (from rest) for fam.jumps * fam.horizon
     steps with the batched solver, snapshotting every fam.horizon steps, and
     encode the consecutive pairs.  Pairs are stored in a seeded order so
@@ -347,16 +384,15 @@ def generate(fam: Family, seeds: Sequence[int], rho_g: float, rho_l: float, T: f
     X = torch.empty((S * J, n * n * CH), dtype=torch.int16, device="cuda")
     Y = torch.empty((S * J, n * n * CH), dtype=torch.int16, device="cuda")
     slot = np.random.default_rng(order_seed).permutation(S * J)
-    chi = 5.0
     names = ("rho", "phi", "ux", "uy")
     for c0 in range(0, S, chunk):
         part = list(seeds[c0:c0 + chunk])
         m = len(part)
-        params = [family_params(fam, rho_g, rho_l, T, precision) for _ in part]
+        params = [family_params(fam, ph, precision) for _ in part]
         with Batch(params, stream=stream) as B:
             prev = torch.zeros((4, m, n, n), dtype=torch.float64, device="cuda")
             for k, s in enumerate(part):
-                r, f = initial_fields(fam, s, rho_g, rho_l, chi)
+                r, f = initial_fields(fam, s, ph)
                 B.init_fields(k, r, f)
                 prev[0, k].copy_(torch.from_numpy(r))
                 prev[1, k].copy_(torch.from_numpy(f))
@@ -369,10 +405,10 @@ def generate(fam: Family, seeds: Sequence[int], rho_g: float, rho_l: float, T: f
                     for c, name in enumerate(names):
                         B.read_device(k, name, cur[c, k])
                 if j == 0:
-                    encode(prev[0], prev[1], None, None, rho_g, rho_l, chi, xe, stream)
+                    encode(prev[0], prev[1], None, None, ph.ic_g, ph.ic_l, ph.chi, xe, stream)
                 else:
-                    encode(prev[0], prev[1], prev[2], prev[3], rho_g, rho_l, chi, xe, stream)
-                encode(cur[0], cur[1], cur[2], cur[3], rho_g, rho_l, chi, ye, stream)
+                    encode(prev[0], prev[1], prev[2], prev[3], ph.ic_g, ph.ic_l, ph.chi, xe, stream)
+                encode(cur[0], cur[1], cur[2], cur[3], ph.ic_g, ph.ic_l, ph.chi, ye, stream)
                 idx = torch.as_tensor(slot[[(c0 + k) * J + j for k in range(m)]], device="cuda")
                 X.index_copy_(0, idx, xe)
                 Y.index_copy_(0, idx, ye)
@@ -437,7 +473,7 @@ def _bf16_to_f64(t):
     return (t.to(torch.int32).bitwise_and(0xFFFF).bitwise_left_shift(16)).view(torch.float32).double()
 
 
-def jump(net: Network, rho, phi, rho_g: float, rho_l: float, chi: float = 5.0, ux=None, uy=None):
+def jump(net: Network, rho, phi, ph: Physics, ux=None, uy=None):
     """Surrogate state from a start state (float64 device tensors (h, w) or
     (n, h, w); no velocity means at rest): encode, forward, decode with the
     conservation projection.  Returns (rho, phi, ux, uy)."""
@@ -451,13 +487,13 @@ def jump(net: Network, rho, phi, rho_g: float, rho_l: float, chi: float = 5.0, u
     ux = ux.contiguous() if ux is not None else None
     uy = uy.contiguous() if uy is not None else None
     x = torch.empty(m * h * w * CH, dtype=torch.int16, device=rho.device)
-    encode(rho, phi, ux, uy, rho_g, rho_l, chi, x, net.stream)
+    encode(rho, phi, ux, uy, ph.ic_g, ph.ic_l, ph.chi, x, net.stream)
     y = net.forward(x, m, h, w)
     out = torch.empty((4, m, h, w), dtype=torch.float64, device=rho.device)
     # the workspace stays referenced until the next jump: the decode kernels
     # run asynchronously on the network's stream
-    net._decode_ws = decode(y, rho, phi, ux, uy, m, h, w, rho_g, rho_l, chi, out[0], out[1], out[2], out[3],
-                            net.stream)
+    net._decode_ws = decode(y, rho, phi, ux, uy, m, h, w, ph.ic_g, ph.ic_l, ph.chi, out[0], out[1], out[2],
+                            out[3], net.stream)
     net._decode_in = x
     return out[0], out[1], out[2], out[3]
 
@@ -471,7 +507,7 @@ def check_state(rho, phi, rho_in, phi_in, rho_g: float, chi: float, rtol: float 
     res = {
         "finite": bool(torch.isfinite(rho).all() and torch.isfinite(phi).all()),
         "rho_positive": bool((rho > 0.25 * rho_g).all()),
-        "phi_bounded": bool((phi.abs() <= 1.05 * chi).all()),
+        "phi_bounded": bool((phi.abs() <= 1.25 * chi).all()),
         "mass_rel_err": abs(m - m_in) / abs(m_in),
         "phi_abs_err": abs(f - f_in) / max(1.0, float(phi_in.abs().sum())),
     }
@@ -480,49 +516,98 @@ def check_state(rho, phi, rho_in, phi_in, rho_g: float, chi: float, rtol: float 
     return res
 
 
-def compare_to_plain(net: Network, fam: Family, seed: int, rho_g: float, rho_l: float, T: float, det=None,
-                     chi: float = 5.0, jumps: int = 1, log=None) -> dict:
-    """Steps to the detector's equilibrium for one configuration: the plain
-    solver from t = 0, and the solver continued from `jumps` chained
-    surrogate jumps (which stand for jumps * fam.horizon steps).  If the jump fails its admission
-    checks, or the continued run turns unstable, the plain run is the result
-    (fallback).  Also returns the final interface measures of both runs."""
+def lead(d_plain: np.ndarray, d_surr: np.ndarray, window: int, horizon: int) -> float:
+    """How far ahead of the plain run the surrogate-started run is, in LBM
+    steps, averaged over its first 2 horizon / window windows: for each of
+    its states, the first time at which the plain run's running-minimum
+    distance to equilibrium has come down to the same value, minus the
+    surrogate run's own LBM steps.  A perfect jump leads by `horizon`."""
+    env = np.minimum.accumulate(d_plain)
+    t_plain = np.arange(len(env)) * window
+    out = []
+    for j in range(1, min(len(d_surr), 2 * horizon // window + 1)):
+        k = np.nonzero(env <= d_surr[j])[0]
+        t_eff = t_plain[k[0]] if k.size else t_plain[-1]
+        out.append(t_eff - j * window)
+    return float(np.mean(out)) if out else 0.0
+
+
+def compare_to_plain(net: Network, fam: Family, seed: int, ph: Physics, ref_steps: int, window: int = 500,
+                     tol: float = 1e-2, jumps: int = 1, between: int = 200, log=None) -> dict:
+    """Steps to equilibrium for one configuration, judged by the plain solver.
+
+    The plain solver runs ref_steps from t = 0; the mean interface measures
+    of its last four windows are the equilibrium reference.  The surrogate
+    run starts from `jumps` chained jumps (standing for jumps * fam.horizon
+    steps), with `between` LBM steps after each jump but the last (they
+    return the state to the solver's manifold before the next jump), and
+    runs ref_steps - jumps * fam.horizon LBM steps in all.  Each run's
+    count is the first step from which its measures stay within tol of the
+    reference (equilibrium.settle_step).  If the jumped state fails its
+    admission checks, or the continued run turns unstable, the plain run is
+    the result (fallback).  Also returns the final bulk densities and
+    totals of both runs."""
     import torch
     from ._lib import TelbmError
-    from .equilibrium import Detector, measures_of, run_to_equilibrium
+    from .equilibrium import distance, settle_step, trajectory
     from .solver import Solver
-    det = det or Detector()
-    p = family_params(fam, rho_g, rho_l, T)
-    r, f = initial_fields(fam, seed, rho_g, rho_l, chi)
+    p = family_params(fam, ph)
+    r, f = initial_fields(fam, seed, ph)
+    rho_g, rho_l, chi = ph.ic_g, ph.ic_l, ph.chi
     out = {"seed": seed, "horizon": fam.horizon, "jumps": jumps}
+
+    def finals(s):
+        rho = s.read("rho")
+        sc = (rho - rho_g) / (rho_l - rho_g)
+        return {"mass": float(rho.sum()), "phi_total": float(s.read("phi").sum()),
+                "rho_gas": float(np.median(rho[sc < 0.1])), "rho_liquid": float(np.median(rho[sc > 0.9]))}
+
     with Solver(p) as s:
         s.init_fields(r, f)
-        out["plain_steps"], out["plain_hist"] = run_to_equilibrium(s, rho_g, rho_l, chi, det)
-        out["plain_measures"] = measures_of(s, rho_g, rho_l, chi)
-        out["plain_mass"] = s.diagnostics()["mass"]
+        tp = trajectory(s, ref_steps, window, rho_g, rho_l, chi)
+        out["plain_final"] = finals(s)
+    ref = tp[-4:].mean(axis=0)
+    out["reference"] = ref
+    out["plain_distance"] = distance(tp, ref)
+    out["plain_steps"] = settle_step(tp, ref, tol, window)
     rt, ft = torch.from_numpy(r).cuda(), torch.from_numpy(f).cuda()
-    ro, po, ux, uy = jump(net, rt, ft, rho_g, rho_l, chi)
-    for _ in range(jumps - 1):
-        ro, po, ux, uy = jump(net, ro, po, rho_g, rho_l, chi, ux, uy)
-    torch.cuda.synchronize()
-    chk = check_state(ro, po, rt, ft, rho_g, chi)
-    out["checks"] = chk
-    out["fallback"] = not chk["ok"]
-    if chk["ok"]:
-        try:
-            with Solver(p) as s:
+    out["fallback"] = False
+    lbm = 0
+    try:
+        with Solver(p) as s:
+            ro, po, ux, uy = jump(net, rt, ft, ph)
+            for k in range(jumps):
+                torch.cuda.synchronize()
+                chk = check_state(ro, po, rt, ft, rho_g, chi)
+                out["checks"] = chk
+                if not chk["ok"]:
+                    out["fallback"] = True
+                    break
                 u = torch.stack([ux[0], uy[0], torch.zeros_like(ux[0])])
                 s.init_fields(ro[0], po[0], u)
-                out["surrogate_steps"], out["surrogate_hist"] = run_to_equilibrium(s, rho_g, rho_l, chi, det)
-                out["surrogate_measures"] = measures_of(s, rho_g, rho_l, chi)
-                out["surrogate_mass"] = s.diagnostics()["mass"]
-        except TelbmError:
-            out["fallback"] = True
+                if k == jumps - 1:
+                    break
+                s.step(between)
+                lbm += between
+                cur = [s.read(name, device=True) for name in ("rho", "phi", "ux", "uy")]
+                ro, po, ux, uy = jump(net, *[c.reshape(fam.n, fam.n) for c in cur[:2]], ph,
+                                      *[c.reshape(fam.n, fam.n) for c in cur[2:]])
+            if not out["fallback"]:
+                ts = trajectory(s, ref_steps - jumps * fam.horizon - lbm, window, rho_g, rho_l, chi)
+                out["surrogate_final"] = finals(s)
+                out["surrogate_distance"] = distance(ts, ref)
+                k = settle_step(ts, ref, tol, window)
+                out["surrogate_steps"] = k + lbm if k >= 0 else -1
+    except TelbmError:
+        out["fallback"] = True
     if out["fallback"]:
         out["surrogate_steps"] = out["plain_steps"]
-        out["surrogate_measures"] = out["plain_measures"]
-    out["gain_steps"] = out["plain_steps"] - out["surrogate_steps"]
+        out["surrogate_final"] = out["plain_final"]
+    if "surrogate_distance" in out:
+        out["lead_steps"] = lead(out["plain_distance"], out["surrogate_distance"], window, fam.horizon)
+    ok = out["plain_steps"] >= 0 and out["surrogate_steps"] >= 0
+    out["gain_steps"] = out["plain_steps"] - out["surrogate_steps"] if ok else None
     if log:
-        log(f"seed {seed}: plain {out['plain_steps']} steps, surrogate jump + {out['surrogate_steps']} steps"
+        log(f"seed {seed}: plain {out['plain_steps']} steps, {jumps} jump(s) + {out['surrogate_steps']} steps"
             f"{' (fallback)' if out['fallback'] else ''}")
     return out

@@ -26,6 +26,30 @@ def test_identity_filter_and_bias():
     assert np.allclose(C.conv_forward(x, W2)[:, :, -1], x[:, :, 0])
 
 
+def dense_conv_loops(x, K):
+    """Plain periodic convolution with a (2r+1) x (2r+1) kernel K[a, b, ci, co]
+    (a, b index offsets -r..r), summed by explicit loops."""
+    n, h, w, ci = x.shape
+    r = (K.shape[0] - 1) // 2
+    y = np.zeros((n, h, w, K.shape[3]))
+    for i in range(h):
+        for j in range(w):
+            for a in range(2 * r + 1):
+                for b in range(2 * r + 1):
+                    y[:, i, j] += x[:, (i + a - r) % h, (j + b - r) % w] @ K[a, b]
+    return y
+
+
+@pytest.mark.parametrize("dil", [1, 2, 3, 5])
+def test_dilated_conv_is_zero_stuffed_dense_conv(dil):
+    x = rand((2, 7, 9, 2), 10 + dil)
+    W = rand((9, 2, 3), 20 + dil)
+    K = np.zeros((2 * dil + 1, 2 * dil + 1, 2, 3))
+    for t in range(9):
+        K[dil * (t // 3), dil * (t % 3)] = W[t]
+    assert np.allclose(C.conv_forward(x, W, dil=dil), dense_conv_loops(x, K))
+
+
 def test_translation_equivariance():
     x = rand((1, 7, 9, 3), 1)
     W = rand((9, 3, 5), 2)
@@ -34,19 +58,19 @@ def test_translation_equivariance():
     assert np.allclose(np.roll(y, (2, -3), axis=(1, 2)), ys)
 
 
-@pytest.mark.parametrize("relu", [False, True])
-def test_backward_matches_finite_differences(relu):
+@pytest.mark.parametrize("relu,dil", [(False, 1), (True, 1), (True, 2), (False, 3)])
+def test_backward_matches_finite_differences(relu, dil):
     x = rand((2, 4, 5, 3), 3)
     W = rand((9, 3, 2), 4)
     b = rand((2,), 5)
     g = rand((2, 4, 5, 2), 6)
 
     def loss(x_, W_, b_):
-        return float(np.sum(C.conv_forward(x_, W_, b_, relu) * g))
+        return float(np.sum(C.conv_forward(x_, W_, b_, relu, dil) * g))
 
-    y_lin = C.conv_forward(x, W, b)
+    y_lin = C.conv_forward(x, W, b, dil=dil)
     gl = g * (y_lin > 0) if relu else g
-    dx, dW, db = C.conv_backward(x, W, gl)
+    dx, dW, db = C.conv_backward(x, W, gl, dil)
     h = 1e-6
     rng = np.random.default_rng(7)
     for _ in range(12):

@@ -41,8 +41,9 @@ def rel_err(a, b, scale):
 
 
 @pytest.mark.parametrize("cin,cout", SHAPES)
-@pytest.mark.parametrize("dims", [(1, 4, 8), (2, 5, 37), (1, 16, 19)])
-def test_conv_forward_matches_oracle(env, cin, cout, dims):
+@pytest.mark.parametrize("dims,dil", [((1, 4, 8), 1), ((2, 5, 37), 1), ((1, 16, 19), 1), ((2, 5, 37), 2),
+                                      ((1, 16, 19), 8), ((1, 3, 4), 5)])
+def test_conv_forward_matches_oracle(env, cin, cout, dims, dil):
     torch, S, st = env
     n, h, w = dims
     rng = np.random.default_rng(cin * 100 + cout + h)
@@ -58,12 +59,12 @@ def test_conv_forward_matches_oracle(env, cin, cout, dims):
     br = b.astype(np.float32).astype(np.float64)
     y32 = torch.empty(n * h * w * cout, dtype=torch.float32, device="cuda")
     ybf = torch.empty(n * h * w * cout, dtype=torch.int16, device="cuda")
-    S.conv_forward(x_t, n, h, w, cin, wf, bt, cout, 0, y_f32=y32, stream=st)
-    S.conv_forward(x_t, n, h, w, cin, wf, bt, cout, 1, y_bf16=ybf, stream=st)
+    S.conv_forward(x_t, n, h, w, cin, wf, bt, cout, 0, y_f32=y32, stream=st, dil=dil)
+    S.conv_forward(x_t, n, h, w, cin, wf, bt, cout, 1, y_bf16=ybf, stream=st, dil=dil)
     torch.cuda.synchronize()
-    ref = C.conv_forward(x, Wr, br)
+    ref = C.conv_forward(x, Wr, br, dil=dil)
     # FP32 accumulation of 9*cin exact BF16 products
-    scale = C.conv_forward(np.abs(x), np.abs(Wr), np.abs(br)) + 1e-30
+    scale = C.conv_forward(np.abs(x), np.abs(Wr), np.abs(br), dil=dil) + 1e-30
     assert rel_err(y32.cpu().numpy().reshape(ref.shape), ref, scale) < 1e-5
     got = from_bf16(ybf, ref.shape)
     relu = np.maximum(ref, 0.0)
@@ -71,8 +72,9 @@ def test_conv_forward_matches_oracle(env, cin, cout, dims):
 
 
 @pytest.mark.parametrize("cin,cout", SHAPES)
-@pytest.mark.parametrize("dims", [(1, 4, 8), (2, 5, 37), (3, 33, 40)])
-def test_conv_backward_matches_oracle(env, cin, cout, dims):
+@pytest.mark.parametrize("dims,dil", [((1, 4, 8), 1), ((2, 5, 37), 1), ((3, 33, 40), 1), ((2, 5, 37), 3),
+                                      ((3, 33, 40), 8)])
+def test_conv_backward_matches_oracle(env, cin, cout, dims, dil):
     torch, S, st = env
     n, h, w = dims
     rng = np.random.default_rng(7 * cin + cout + w)
@@ -89,11 +91,11 @@ def test_conv_backward_matches_oracle(env, cin, cout, dims):
     dw = torch.empty(9 * cin * cout, dtype=torch.float32, device="cuda")
     db = torch.empty(cout, dtype=torch.float32, device="cuda")
     ws = torch.empty(S.conv_workspace_bytes(n, h, w, cin, cout), dtype=torch.uint8, device="cuda")
-    S.conv_backward(x_t, g_t, n, h, w, cin, cout, wd, x_t, dx, dw, db, ws, st)
+    S.conv_backward(x_t, g_t, n, h, w, cin, cout, wd, x_t, dx, dw, db, ws, st, dil=dil)
     torch.cuda.synchronize()
-    rdx, rdw, rdb = C.conv_backward(x, Wr, g)
+    rdx, rdw, rdb = C.conv_backward(x, Wr, g, dil)
     rdx = rdx * (x > 0)
-    sdx, sdw, _ = C.conv_backward(np.abs(x), np.abs(Wr), np.abs(g))
+    sdx, sdw, _ = C.conv_backward(np.abs(x), np.abs(Wr), np.abs(g), dil)
     got = from_bf16(dx, x.shape)
     assert np.all(np.abs(got - rdx) <= 2.0 ** -8 * np.abs(rdx) + 1e-5 * sdx + 1e-30)
     assert rel_err(dw.cpu().numpy().reshape(rdw.shape), rdw, sdw + 1e-30) < 3e-5
@@ -216,13 +218,13 @@ def test_encode_and_conserving_decode(env):
     assert abs((R * UX).sum()) < 1e-10 * (R * np.abs(UX)).sum()
 
 
-def oracle_network(S, x, weights, biases, target):
+def oracle_network(S, x, weights, biases, target, dils):
     """FP64 forward/backward of the whole network with BF16 rounding at the
     same points as the device path (weights, activations, loss gradient)."""
     L = len(S.LAYERS)
     acts = [x]
     for k in range(L):
-        z = C.conv_forward(acts[-1], weights[k], biases[k])
+        z = C.conv_forward(acts[-1], weights[k], biases[k], dil=dils[k])
         if k < L - 1:
             acts.append(C.bf16_round(np.maximum(z, 0.0)))
         else:
@@ -235,7 +237,7 @@ def oracle_network(S, x, weights, biases, target):
     g = C.bf16_round(g)
     gw, gb = [None] * L, [None] * L
     for k in range(L - 1, -1, -1):
-        dx, gw[k], gb[k] = C.conv_backward(acts[k], weights[k], g)
+        dx, gw[k], gb[k] = C.conv_backward(acts[k], weights[k], g, dils[k])
         if k:
             g = C.bf16_round(dx * (acts[k] > 0))
     return loss, gw, gb
@@ -261,7 +263,7 @@ def test_network_gradient_matches_oracle(env):
     torch.cuda.synchronize()
     Ws = [C.bf16_round(wk.cpu().numpy().astype(np.float64)) for wk in net.w]
     Bs = [bk.cpu().numpy().astype(np.float64) for bk in net.b]
-    loss, gw, gb = oracle_network(S, x, Ws, Bs, tg)
+    loss, gw, gb = oracle_network(S, x, Ws, Bs, tg, net.dilations)
     assert abs(part.double().sum().item() - loss) < 2e-2 * loss
     for k in range(len(S.LAYERS)):
         gk = net.gw[k].cpu().numpy().astype(np.float64)
