@@ -22,6 +22,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, TFLOP/s
+
+# HBM bytes per launch of the D2Q9 1024x1024 FP64 collide kernel from two
+# rocprofv3 counter passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, scales from a
+# 1 GiB copy in the same runs; profiles/collide_d2q9_1024_fp64_traffic.md),
+# valid only for the kernel sources whose hash is recorded with it.
+COLLIDE_TRAFFIC = {"bytes_per_launch": 341020837, "sources_sha256_16": "b3dbef857f656b46"}
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp", "node_ops.hpp", "lattice.hpp"):
+        with open(os.path.join(ROOT, "paper_1710_07486_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def log(*a):
@@ -38,18 +54,20 @@ def library_params(T, wl, precision):
                      nu=ph["nu"], mobility=ph["mobility"], tau_phi=ph["tau_phi"])
 
 
-def measure(wl, precision, steps, warmup, fields=None):
+def measure(wl, precision, steps, warmup, fields=None, coex=None):
     """Whole-step MLUPS with HIP events on the solver's stream, and the mean
     duration of each kernel kind.  Drops start at the discretised model's own
-    coexistence densities (a 1D slab relaxed by the library)."""
+    coexistence densities (a 1D slab relaxed by the library, unless `coex`
+    gives them)."""
     import torch
     import paper_1710_07486_amd as T_
     from paper_1710_07486_amd.calibrate import discrete_coexistence
     from synth import workloads as W
     T = T_.temperature_for_ratio(wl.ratio)
     p = library_params(T, wl, precision)
+    rg = rl = None
     if fields is None:
-        rg, rl = discrete_coexistence(library_params(T, wl, T_.FP64))
+        rg, rl = coex if coex else discrete_coexistence(library_params(T, wl, T_.FP64))
         log("discrete coexistence densities", rg, rl)
         fields = W.fields(wl, rg, rl)
     rho, phi, u = fields
@@ -69,7 +87,7 @@ def measure(wl, precision, steps, warmup, fields=None):
     kern = s.time_kernels(max(3, min(steps, 20)))
     d = s.diagnostics(check=False)
     out = {"mlups": wl.nodes * steps / (ms * 1e-3) / 1e6, "ms_per_step": ms / steps, "kernels_ms": kern,
-           "bytes_per_update": s.algorithmic_bytes_per_update(), "diag": d}
+           "bytes_per_update": s.algorithmic_bytes_per_update(), "diag": d, "coex": [rg, rl]}
     out["rho"] = s.read("rho", check=False)
     s.close()
     del s
@@ -97,6 +115,65 @@ def cpu_baseline(wl, budget_s=15.0):
             "sample": f"{wl.name}: {n} time steps of the full lattice (FP64 oracle, OpenMP)"}
 
 
+def surrogate_throughput(n=256, batch=8, reps=10):
+    """Training-step and forward throughput of the convolutional surrogate
+    (six 3x3 layers, BF16 on the matrix cores) at the family's image size,
+    timed with HIP events on the network's stream, and the mean duration of
+    its dominant kernel (the 64->64 forward convolution, 4 of 6 layers)."""
+    import torch
+    from paper_1710_07486_amd import surrogate as S
+    net = S.Network(seed=0)
+    x = torch.zeros(batch * n * n * S.CH, dtype=torch.int16, device="cuda")
+    y = torch.zeros_like(x)
+    st = net.stream
+    for _ in range(3):
+        net.train_step(x, y, batch, n, n, 1e-5)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(reps):
+        net.train_step(x, y, batch, n, n, 1e-5)
+    e1.record(st)
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1) / reps
+    e0.record(st)
+    for _ in range(reps):
+        net.forward(x, batch, n, n)
+    e1.record(st)
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / reps
+    a = net.a[1]
+    out = net.a[2]
+    e0.record(st)
+    for _ in range(reps):
+        S.conv_forward(a, batch, n, n, 64, net.wf[1], net.b[1], 64, 1, y_bf16=out, stream=st, dil=2)
+    e1.record(st)
+    torch.cuda.synchronize()
+    conv_ms = e0.elapsed_time(e1) / reps
+    px = batch * n * n
+    fl_fwd = S.flops_per_pixel(padded=True) * px
+    conv_tf = 2 * 9 * 64 * 64 * px / (conv_ms * 1e-3) / 1e12
+    return {"image": f"{n}x{n}", "batch": batch, "train_step_ms": round(train_ms, 3),
+            "train_tflops": round(3 * fl_fwd / (train_ms * 1e-3) / 1e12, 1),
+            "forward_ms": round(fwd_ms, 3), "forward_tflops": round(fl_fwd / (fwd_ms * 1e-3) / 1e12, 1),
+            "roofline": {"bound": "mfma", "kernel": "conv 64->64 forward (bf16)", "achieved": round(conv_tf, 1),
+                         "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(conv_tf / BF16_PEAK_TFLOPS, 4),
+                         "kernel_ms": round(conv_ms, 4)}}
+
+
+def copy_probe(nbytes=1 << 30):
+    """A plain device copy of known size (read nbytes, write nbytes): its
+    FETCH_SIZE / WRITE_SIZE counters calibrate the byte counts read for the
+    solver's kernels in the same profiled run."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("copy probe", nbytes, "bytes")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,10 +181,24 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the D3Q27 256^3 measurement")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed measurement")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate throughput measurement")
+    ap.add_argument("--coex2d", type=float, nargs=2, metavar=("RHO_G", "RHO_L"),
+                    help="coexistence densities of the 2D workload (skips their calibration run)")
+    ap.add_argument("--coex3d", type=float, nargs=2, metavar=("RHO_G", "RHO_L"),
+                    help="coexistence densities of the 3D workload (skips their calibration run)")
+    ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB device copy first (counter scale)")
+    ap.add_argument("--coex-cache", default=None,
+                    help="JSON file of calibrated coexistence densities: read if present, else written")
     args = ap.parse_args()
+    cache = {}
+    if args.coex_cache and os.path.exists(args.coex_cache):
+        with open(args.coex_cache) as fh:
+            cache = json.load(fh)
+        args.coex2d = args.coex2d or cache.get("2d")
+        args.coex3d = args.coex3d or cache.get("3d")
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the lattice would shard by slabs, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -115,16 +206,18 @@ def main():
     from synth import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.copy_probe:
+        copy_probe()
     wl = W.drops_2d(1024, ratio=1000.0, seed=0)
     log("workload", wl.name, "steps", args.steps, "warmup", args.warmup)
-    r64, fields = measure(wl, T_.FP64, args.steps, args.warmup)
+    r64, fields = measure(wl, T_.FP64, args.steps, args.warmup, coex=args.coex2d)
+    cache["2d"] = r64["coex"]
     log("fp64", {k: v for k, v in r64.items() if k != "rho"})
-    r32, _ = measure(wl, T_.FP32_MIXED, args.steps, args.warmup, fields)
-    log("fp32-mixed", {k: v for k, v in r32.items() if k != "rho"})
-    rel_rho = float(np.abs(r32["rho"] - r64["rho"]).max() / np.abs(r64["rho"]).max())
 
     kern = r64["kernels_ms"]
     dom = max(kern, key=kern.get)
+    traffic = (COLLIDE_TRAFFIC["bytes_per_launch"]
+               if kernel_sources_hash() == COLLIDE_TRAFFIC["sources_sha256_16"] else None)
     achieved = r64["bytes_per_update"] * wl.nodes / (kern["collide"] * 1e-3) / 1e9
     result = {
         "metric": "ternary ELBM MLUPS & % HBM roofline; FP32-mixed vs FP64 at stated error",
@@ -142,20 +235,27 @@ def main():
         "config": {"workload": wl.name, "lattice": "D2Q9", "nx": 1024, "ny": 1024, "density_ratio": 1000,
                    "precision": "fp64", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes_per_launch": int(r64["bytes_per_update"] * wl.nodes),
                      "kernel": "collide", "kernels_ms": {k: round(v, 5) for k, v in kern.items()},
                      "dominant": dom},
-        "fp32_mixed": {"value": round(r32["mlups"], 2), "unit": "MLUPS",
-                       "speedup_vs_fp64": round(r32["mlups"] / r64["mlups"], 3),
-                       "rel_density_error_vs_fp64": rel_rho,
-                       "kernels_ms": {k: round(v, 5) for k, v in r32["kernels_ms"].items()}},
         "whole_step_hbm_frac": round(r64["mlups"] * 1e6 * r64["bytes_per_update"] / (HBM_PEAK_GBS * 1e9), 4),
     }
+    if not args.no_fp32:
+        r32, _ = measure(wl, T_.FP32_MIXED, args.steps, args.warmup, fields)
+        log("fp32-mixed", {k: v for k, v in r32.items() if k != "rho"})
+        rel_rho = float(np.abs(r32["rho"] - r64["rho"]).max() / np.abs(r64["rho"]).max())
+        result["fp32_mixed"] = {"value": round(r32["mlups"], 2), "unit": "MLUPS",
+                                "speedup_vs_fp64": round(r32["mlups"] / r64["mlups"], 3),
+                                "rel_density_error_vs_fp64": rel_rho,
+                                "kernels_ms": {k: round(v, 5) for k, v in r32["kernels_ms"].items()}}
     if not args.no_3d:
         wl3 = W.collision_3d(256, radius=32, ratio=1000.0, v_rel=0.04, kappa2=0.1, kappa3=0.1)
         s3 = max(10, args.steps // 4)
         log("workload", wl3.name, "steps", s3)
-        r3, f3 = measure(wl3, T_.FP64, s3, 5)
+        r3, f3 = measure(wl3, T_.FP64, s3, 5, coex=args.coex3d)
+        cache["3d"] = r3["coex"]
         r3m, _ = measure(wl3, T_.FP32_MIXED, s3, 5, f3)
         k3 = r3["kernels_ms"]
         result["d3q27_256"] = {
@@ -166,6 +266,12 @@ def main():
             "fp32_mixed_kernels_ms": {k: round(v, 5) for k, v in r3m["kernels_ms"].items()},
             "rel_density_error_mixed_vs_fp64": float(np.abs(r3m["rho"] - r3["rho"]).max() / np.abs(r3["rho"]).max()),
         }
+    if args.coex_cache and not os.path.exists(args.coex_cache):
+        with open(args.coex_cache, "w") as fh:
+            json.dump(cache, fh)
+    if not args.no_surrogate:
+        log("surrogate throughput")
+        result["surrogate"] = surrogate_throughput()
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(wl)
