@@ -112,6 +112,9 @@ def lib():
         L.orc_concentrations.argtypes = [P, d, d, vp, vp]
         L.orc_gradient_coefficients.argtypes = [P, vp]
         L.orc_mu_bulk.argtypes = [P, d, d, vp]
+        for name in ("orc_f_bulk", "orc_bulk_pressure"):
+            getattr(L, name).argtypes = [P, d, d]
+            getattr(L, name).restype = d
         L.orc_laplacian.argtypes = [P, vp, vp]
         L.orc_gradient.argtypes = [P, vp, vp]
         L.orc_feq.argtypes = [ctypes.c_int, d, vp, vp]
@@ -218,6 +221,16 @@ def mu_bulk(p: Params, rho, phi):
     out = np.zeros(2)
     lib().orc_mu_bulk(ctypes.byref(p.c_struct()), rho, phi, _ptr(out))
     return tuple(out)
+
+
+def f_bulk(p: Params, rho, phi):
+    """Bulk free-energy density of Eq. (2) (Psi0 = Psi(rho_g))."""
+    return lib().orc_f_bulk(ctypes.byref(p.c_struct()), float(rho), float(phi))
+
+
+def bulk_pressure(p: Params, rho, phi):
+    """rho mu_rho + phi mu_phi - f_B of a uniform state."""
+    return lib().orc_bulk_pressure(ctypes.byref(p.c_struct()), float(rho), float(phi))
 
 
 def laplacian(p: Params, psi: np.ndarray) -> np.ndarray:

@@ -306,6 +306,28 @@ void orc_mu_bulk(const orc_params *p, double rho, double phi, double *out)
     out[1] = (p->lambda2 * w1v - p->lambda3 * w2v) / (2.0 * p->chi);
 }
 
+/* Bulk free-energy density f_B of Eq. (2):
+ *   (lambda1/2)(Psi(rho) - Psi0) + (lambda2/2) C1^2 (1-C1)^2 + (lambda3/2) C2^2 (1-C2)^2
+ * with Psi0 = Psi(rho_g) (Reading: the constant only shifts the energy).    */
+double orc_f_bulk(const orc_params *p, double rho, double phi)
+{
+    double c1, c2;
+    orc_concentrations(p, rho, phi, &c1, &c2);
+    double psi = orc_psi_eos(p->a, p->b, p->R, p->T, p->C, rho);
+    double psi0 = orc_psi_eos(p->a, p->b, p->R, p->T, p->C, p->rho_g);
+    double d1 = c1 * (1.0 - c1), d2 = c2 * (1.0 - c2);
+    return 0.5 * p->lambda1 * (psi - psi0) + 0.5 * p->lambda2 * d1 * d1 + 0.5 * p->lambda3 * d2 * d2;
+}
+
+/* Thermodynamic pressure of a uniform state, rho mu_rho + phi mu_phi - f_B
+ * (the bulk part of the pressure tensor stated after Eq. (7)).              */
+double orc_bulk_pressure(const orc_params *p, double rho, double phi)
+{
+    double mu[2];
+    orc_mu_bulk(p, rho, phi, mu);
+    return rho * mu[0] + phi * mu[1] - orc_f_bulk(p, rho, phi);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Lattice stencils (Reading: the isotropic stencils with the lattice        */
 /* weights; the paper does not state its discretisation).                    */

@@ -158,3 +158,65 @@ def test_flat_liquid_gas_coexistence(orc):
         assert np.abs(f["u"]).max() < 1e-3
     assert abs(errs[1][1]) < 1e-2 and abs(errs[1][0]) < 3e-2
     assert abs(errs[1][0]) < abs(errs[0][0]) and abs(errs[1][1]) < abs(errs[0][1])
+
+
+def test_laplace_law_scaling(orc):
+    """Laplace's law on small 2D drops (the paper's Laplace tests): the
+    pressure jump across a relaxed circular drop of liquid 1 in gas, taken
+    relative to the jump across a flat interface (with interfaces 2-3 nodes
+    wide the bulk pressures on either side of a flat interface differ by a
+    discretisation offset), falls as 1/R, and so does the shift of the
+    chemical potential above its flat-interface value (Gibbs-Thomson):
+    R dp and R dmu agree across radii.  Bulk pressures from the oracle's
+    rho mu_rho + phi mu_phi - f_B, pinned by test_bulk_pressure_*."""
+    import dataclasses
+    base = orc.coexisting_params(10.0, lattice=0, nx=80, ny=80, nz=1, kappa2=0.045, kappa3=0.045,
+                                 lambda2=3.125 * 0.045, lambda3=3.125 * 0.045)
+    rg, rl = orc.discrete_coexistence(base, steps=10000, n=128)
+    q = dataclasses.replace(base, nx=128, ny=1, nz=1)
+    x = np.arange(128.0)
+    c1 = 0.5 * (np.tanh((x - 32) / 2.0) - np.tanh((x - 96) / 2.0))
+    st = orc.State(q, (rg + (rl - rg) * c1).reshape(1, 1, 128), (q.chi * c1).reshape(1, 1, 128))
+    st.run(10000)
+    f = st.fields()
+    dp_flat = (orc.bulk_pressure(q, f["rho"][0, 0, 64], f["phi"][0, 0, 64])
+               - orc.bulk_pressure(q, f["rho"][0, 0, 0], f["phi"][0, 0, 0]))
+    mu_flat = f["mu_rho"][0, 0, 0]
+    N = 80
+    yy, xx = np.mgrid[0:N, 0:N]
+    rr = np.sqrt((xx - N / 2) ** 2 + (yy - N / 2) ** 2)
+    Rdp, Rdmu = [], []
+    for R in (12, 16, 22):
+        c = 0.5 * (1 - np.tanh((rr - R) / 2.0))
+        s = orc.State(base, (rg + (rl - rg) * c).reshape(1, N, N), (base.chi * c).reshape(1, N, N))
+        s.run(10000)
+        fl = s.fields()
+        c0 = N // 2
+        ri, pi = fl["rho"][0, c0 - 1:c0 + 2, c0 - 1:c0 + 2].mean(), fl["phi"][0, c0 - 1:c0 + 2, c0 - 1:c0 + 2].mean()
+        ro, po = fl["rho"][0, 0:3, 0:3].mean(), fl["phi"][0, 0:3, 0:3].mean()
+        dp = orc.bulk_pressure(base, ri, pi) - orc.bulk_pressure(base, ro, po) - dp_flat
+        reff = np.sqrt(((fl["rho"][0] - ro) / (ri - ro)).sum() / np.pi)
+        assert abs(reff - R) < 2.0
+        Rdp.append(dp * reff)
+        Rdmu.append((fl["mu_rho"][0, 0, 0] - mu_flat) * reff)
+    Rdp, Rdmu = np.array(Rdp), np.array(Rdmu)
+    assert np.all(Rdp > 0) and np.all(Rdmu > 0)
+    # a 1/R^2 or R-independent jump would spread these by a factor ~1.8
+    assert Rdp.max() / Rdp.min() < 1.2, Rdp
+    assert Rdmu.max() / Rdmu.min() < 1.15, Rdmu
+
+
+def test_bulk_pressure_definition(orc):
+    """f_B's derivatives are the bulk chemical potentials, and at the Maxwell
+    densities of pure phases the bulk pressures of gas and liquid 1 are equal
+    (equal-area rule of the EOS part; the double wells vanish there)."""
+    p = orc.coexisting_params(10.0, lattice=0, nx=4, ny=4, nz=1)
+    for rho, phi in ((0.8, 0.3), (3.0, -2.0), (5.0, 4.5)):
+        h = 1e-6
+        dr = (orc.f_bulk(p, rho + h, phi) - orc.f_bulk(p, rho - h, phi)) / (2 * h)
+        dq = (orc.f_bulk(p, rho, phi + h) - orc.f_bulk(p, rho, phi - h)) / (2 * h)
+        mr, mq = orc.mu_bulk(p, rho, phi)
+        assert abs(dr - mr) < 1e-7 and abs(dq - mq) < 1e-7
+    pg = orc.bulk_pressure(p, p.rho_g, 0.0)
+    pl = orc.bulk_pressure(p, p.rho_l, p.chi)
+    assert abs(pl - pg) < 1e-10 * max(1.0, abs(pg))
