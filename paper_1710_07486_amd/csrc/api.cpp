@@ -33,6 +33,7 @@ struct telbm_solver {
     int cur;             // pop[cur] holds the state
     int ref;             // FP32 form: the state's f values are relative to rhob[ref]
     bool aux_valid;      // rho/phi/mux/mup belong to the current state
+    bool dens_valid;     // rho/phi belong to the current state
     int64_t steps;
     int64_t diag_step;   // step of the last diagnostics enqueued (-1: none)
     bool diag_unread;
@@ -175,18 +176,28 @@ hipError_t timed_launch(telbm_solver* s, const StepArgs& a, int part, Timing* t)
     hipError_t e = hipEventRecord(ev.first, s->stream);
     if (e == hipSuccess) e = launch_part(s->p.lattice, s->p.precision, a, part);
     if (e == hipSuccess) e = hipEventRecord(ev.second, s->stream);
-    t->kind.push_back(part);
+    t->kind.push_back(part == 3 ? 2 : part);  // the fused 2D launch counts as the collision
     return e;
+}
+
+// Bring the densities (moments) to the current state.
+int ensure_dens(telbm_solver* s, Timing* t = nullptr) {
+    if (s->dens_valid) return TELBM_OK;
+    StepArgs a = args_of(s, false);
+    hipError_t e = timed_launch(s, a, 0, t);
+    if (e != hipSuccess) return hip_fail(s, e, "moment launch");
+    s->dens_valid = true;
+    return TELBM_OK;
 }
 
 // Bring the aux fields to the current state (moments + chemical potentials).
 int ensure_aux(telbm_solver* s, Timing* t = nullptr) {
     if (s->aux_valid) return TELBM_OK;
+    int rc = ensure_dens(s, t);
+    if (rc) return rc;
     StepArgs a = args_of(s, false);
-    for (int part = 0; part < 2; ++part) {
-        hipError_t e = timed_launch(s, a, part, t);
-        if (e != hipSuccess) return hip_fail(s, e, "moment/chemical-potential launch");
-    }
+    hipError_t e = timed_launch(s, a, 1, t);
+    if (e != hipSuccess) return hip_fail(s, e, "chemical-potential launch");
     s->aux_valid = true;
     return TELBM_OK;
 }
@@ -219,16 +230,19 @@ bool unstable(const telbm_diag& d) {
 }
 
 // One time step.
+// On D2Q9 the chemical potentials are computed inside the collision launch.
 int one_step(telbm_solver* s, bool diag, Timing* t = nullptr) {
-    int rc = ensure_aux(s, t);
+    const bool fused = s->p.lattice == TELBM_D2Q9;
+    int rc = fused ? ensure_dens(s, t) : ensure_aux(s, t);
     if (rc) return rc;
     StepArgs a = args_of(s, true);
     a.diag = diag ? 1 : 0;
-    hipError_t e = timed_launch(s, a, 2, t);
+    hipError_t e = timed_launch(s, a, fused ? 3 : 2, t);
     if (e != hipSuccess) return hip_fail(s, e, "collision launch");
     s->cur = 1 - s->cur;
     if (mixed(s)) s->ref = 1 - s->ref;  // the new state is relative to the density just used
     s->aux_valid = false;
+    s->dens_valid = false;
     if (diag) {
         s->diag_step = s->steps;
         s->diag_unread = true;
@@ -315,6 +329,7 @@ int telbm_create(const telbm_params* p, void* device_arena, size_t bytes, telbm_
     s->cur = 0;
     s->ref = 0;
     s->aux_valid = false;
+    s->dens_valid = false;
     s->steps = 0;
     s->diag_step = -1;
     s->diag_unread = false;
@@ -349,6 +364,7 @@ int telbm_init_fields(telbm_solver* s, const double* rho, const double* phi, con
     if (e != hipSuccess) return hip_fail(s, e, "init staging");
     memcpy(&bad, s->diag_host, sizeof(bad));
     s->aux_valid = false;
+    s->dens_valid = false;
     if (bad) return fail(s, TELBM_ERR_UNSTABLE, std::to_string(bad) + " nodes with rho <= 0, |u| >= 1 or non-finite values");
     // mu_phi of the initial fields, then the equilibria into the state buffer
     StepArgs a = args_of(s, false);

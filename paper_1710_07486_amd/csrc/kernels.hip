@@ -16,7 +16,8 @@
 //
 // One step is three launches: node moments (pull-sum of both population sets),
 // chemical potentials (Laplacian stencils over rho, phi), and the fused
-// pull -> force -> KBC + exact-difference forcing -> phase-field BGK -> write.
+// pull -> force -> KBC + exact-difference forcing -> phase-field BGK -> write;
+// on D2Q9 the last two are one launch (k_collide_fused2).
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -65,11 +66,13 @@ __device__ __forceinline__ int64_t node_of(const GridDims& g, const Tile& t) {
     return ((int64_t)t.z * g.ny + t.y) * g.nx + t.x;
 }
 
-// Block-level reduction of the health diagnostics into partials[block][kDiag].
+// Block-level reduction of the health diagnostics into partials[block][kDiag]
+// (NT threads per block, threadIdx.y rows of BX).
+template <int NT = BX * BY>
 __device__ void diag_block_reduce(double* vals, double* __restrict__ out) {
     // vals: 0 sum rho, 1 sum phi, 2-4 sum j, 5 max |u|, 6 min rho, 7 min gamma,
     //       8 max gamma, 9 nonfinite count
-    __shared__ double red[BX * BY / 64][kDiag];
+    __shared__ double red[NT / 64][kDiag];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
 #pragma unroll
@@ -89,7 +92,7 @@ __device__ void diag_block_reduce(double* vals, double* __restrict__ out) {
     __syncthreads();
     if (wave == 0 && lane < kDiag) {
         double acc = red[0][lane];
-        for (int w = 1; w < BX * BY / 64; ++w) {
+        for (int w = 1; w < NT / 64; ++w) {
             const double x = red[w][lane];
             if (lane == 5 || lane == 8) acc = fmax(acc, x);
             else if (lane == 6 || lane == 7) acc = fmin(acc, x);
@@ -134,6 +137,89 @@ __global__ __launch_bounds__(BX* BY) void k_collide(GridDims g, PhysConst k, con
     tile_collide<L, T, BX * BY>(g, k, src, dst, rho_ref, rho, phi, mux, mup, bx * BX, by * BY, bz, BX, BY,
                                      threadIdx.y * BX + threadIdx.x, diag != 0, dv);
     if (diag) diag_block_reduce(dv, partials);
+}
+
+// ---------------------------------------------------------------------------
+// Fused chemical potentials and collision of the 2D lattice.  The block
+// stages the densities and phase field of its BX x FBY tile with a halo of two
+// nodes in LDS, computes the chemical potentials of the tile with a halo of
+// one node there (the same arithmetic, term for term, as k_chempot), and runs
+// the collision of its nodes with the force from those LDS potentials: one
+// launch and no potential fields in HBM per step.  (On D3Q27 the potential
+// halo of a 64 x 4 tile is 4.6 times the tile, so the 3D step keeps its
+// separate stencil pass.)  The tile is 64 x 8 so that the potential halo
+// adds 29 % to the tile's potential work rather than 55 % at 64 x 4.
+// ---------------------------------------------------------------------------
+constexpr int FBY = 8;                      // rows per workgroup of the fused step
+constexpr int FHX = BX + 4, FHY = FBY + 4;  // density tile with a halo of 2
+constexpr int FMX = BX + 2, FMY = FBY + 2;  // potential tile with a halo of 1
+
+__device__ __forceinline__ int wrap_any(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+struct LdsAux2 {
+    const double* sr;
+    const double* sp;
+    const double* smx;
+    const double* smp;
+    int lx, ly;  // the node's position in the tile
+    __device__ __forceinline__ double rho0(uint32_t) const { return sr[(ly + 2) * FHX + lx + 2]; }
+    __device__ __forceinline__ double phi0(uint32_t) const { return sp[(ly + 2) * FHX + lx + 2]; }
+    __device__ __forceinline__ double mup0(uint32_t) const { return smp[(ly + 1) * FMX + lx + 1]; }
+    template <int L>
+    __device__ __forceinline__ void nbr_mu(const Nbr32&, uint32_t, int i, double& a, double& b) const {
+        const int o = (ly + 1 + Lattice<L>::c[i][1]) * FMX + lx + 1 + Lattice<L>::c[i][0];
+        a = smx[o];
+        b = smp[o];
+    }
+};
+
+template <typename T>
+__global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysConst k, const T* __restrict__ src,
+                                                           T* __restrict__ dst, const double* __restrict__ rho_ref,
+                                                           const double* __restrict__ rho,
+                                                           const double* __restrict__ phi,
+                                                           double* __restrict__ partials, int diag) {
+    using Lt = Lattice<kD2Q9>;
+    __shared__ double sr[FHX * FHY], sp[FHX * FHY], smx[FMX * FMY], smp[FMX * FMY];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + FBY - 1) / FBY;
+    const int bx = b % bxc, rest = b / bxc, by = rest % byc, bz = rest / byc;
+    const int x0 = bx * BX, y0 = by * FBY;
+    const int tid = threadIdx.y * BX + threadIdx.x;
+    const int64_t zoff = (int64_t)bz * g.nx * g.ny;
+    for (int e = tid; e < FHX * FHY; e += BX * FBY) {
+        const int hx = e % FHX, hy = e / FHX;
+        const int64_t n = zoff + (int64_t)wrap_any(y0 - 2 + hy, g.ny) * g.nx + wrap_any(x0 - 2 + hx, g.nx);
+        sr[e] = rho[n];
+        sp[e] = phi[n];
+    }
+    __syncthreads();
+    for (int e = tid; e < FMX * FMY; e += BX * FBY) {
+        const int c = (e / FMX + 1) * FHX + e % FMX + 1;
+        const double r0 = sr[c], p0 = sp[c];
+        double lr = 0.0, lp = 0.0;
+#pragma unroll
+        for (int i = 1; i < Lt::Q; ++i) {
+            const int o = c + Lt::c[i][1] * FHX + Lt::c[i][0];
+            lr += Lt::w[i] * (sr[o] - r0);
+            lp += Lt::w[i] * (sp[o] - p0);
+        }
+        double mx, mp;
+        chem_pot(k, r0, p0, 6.0 * lr, 6.0 * lp, &mx, &mp);
+        smx[e] = mx;
+        smp[e] = mp;
+    }
+    __syncthreads();
+    double dv[kDiag] = {0, 0, 0, 0, 0, 0, INFINITY, INFINITY, -INFINITY, 0};
+    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
+    if (x < g.nx && y < g.ny) {
+        const LdsAux2 aux{sr, sp, smx, smp, (int)threadIdx.x, (int)threadIdx.y};
+        node_collide_aux<kD2Q9, T>(g, k, src, dst, rho_ref, aux, x, y, bz, diag != 0, dv);
+    }
+    if (diag) diag_block_reduce<BX * FBY>(dv, partials);
 }
 
 // Deterministic second pass over the block partials (one workgroup).
@@ -286,10 +372,16 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
         k_moments<L, T><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
     } else if (part == 1) {
         k_chempot<L><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup);
-    } else {
+    } else if (part == 2) {
         k_collide<L, T><<<grd, blk, 0, a.stream>>>(a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref, a.rho,
                                                      a.phi, a.mux, a.mup, a.partials, a.diag);
         if (a.diag) k_diag_final<<<1, 256, 0, a.stream>>>(a.partials, (int)grd.x, a.diag_out);
+    } else {
+        if (L != kD2Q9) return hipErrorInvalidValue;
+        const unsigned fb = (unsigned)(((a.g.nx + BX - 1) / BX) * ((a.g.ny + FBY - 1) / FBY) * a.g.nz);
+        k_collide_fused2<T><<<fb, dim3(BX, FBY, 1), 0, a.stream>>>(a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref,
+                                                                   a.rho, a.phi, a.partials, a.diag);
+        if (a.diag) k_diag_final<<<1, 256, 0, a.stream>>>(a.partials, (int)fb, a.diag_out);
     }
     return hipGetLastError();
 }

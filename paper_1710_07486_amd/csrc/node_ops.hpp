@@ -149,30 +149,48 @@ __device__ __forceinline__ void st(T* __restrict__ base, uint32_t m, T v) {
     *(T*)((char*)base + (uint32_t)(m * (uint32_t)sizeof(T))) = v;
 }
 
+// Where the collision reads its node's density, phase field and mu_phi, and
+// the potentials of its neighbours for the force: the aux fields in global
+// memory (GlobalAux) or a workgroup's LDS tile (the fused 2D step).
+struct GlobalAux {
+    const double* __restrict__ rho;
+    const double* __restrict__ phi;
+    const double* __restrict__ mux;
+    const double* __restrict__ mup;
+    __device__ __forceinline__ double rho0(uint32_t n) const { return ld(rho, n); }
+    __device__ __forceinline__ double phi0(uint32_t n) const { return ld(phi, n); }
+    __device__ __forceinline__ double mup0(uint32_t n) const { return ld(mup, n); }
+    template <int L>
+    __device__ __forceinline__ void nbr_mu(const Nbr32& nb, uint32_t n, int i, double& a, double& b) const {
+        const uint32_t m = nbr32<L>(nb, n, i, +1);
+        a = ld(mux, m);
+        b = ld(mup, m);
+    }
+};
+
 // Phase 3: pull f, g; force from the excess potentials; KBC with
 // exact-difference forcing; phase-field BGK; write the node's own slots.
 // If diag, dv receives {rho, phi, j (3), |u_phys|, rho, gamma, gamma, bad}.
 // The three sub-phases (stencil, f, g) are kept apart by scheduling barriers
 // so that their loads do not all become live at once.
-template <int L, typename T>
-__device__ __forceinline__ void node_collide(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
-                                             T* __restrict__ dst, const double* __restrict__ rho_ref,
-                                             const double* __restrict__ rho, const double* __restrict__ phi,
-                                             const double* __restrict__ mux, const double* __restrict__ mup,
-                                             int x, int y, int z, bool diag, double* dv) {
+template <int L, typename T, typename AUX>
+__device__ __forceinline__ void node_collide_aux(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
+                                                 T* __restrict__ dst, const double* __restrict__ rho_ref,
+                                                 const AUX& aux, int x, int y, int z, bool diag, double* dv) {
     using Lt = Lattice<L>;
     using R = T;
     constexpr int Q = Lt::Q;
     const Nbr32 nb = make_nbr32(x, y, z, g.nx, g.ny, g.nz);
     const uint32_t n = (uint32_t)node_index(g, x, y, z);
-    const double r = ld(rho, n), p = ld(phi, n);
+    const double r = aux.rho0(n), p = aux.phi0(n);
 
     // force from the isotropic gradients of the two potentials
     double gx[3] = {0, 0, 0}, gp[3] = {0, 0, 0};
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        const uint32_t m = nbr32<L>(nb, n, i, +1);
-        const double va = Lt::w[i] * ld(mux, m), vb = Lt::w[i] * ld(mup, m);
+        double ma, mb;
+        aux.template nbr_mu<L>(nb, n, i, ma, mb);
+        const double va = Lt::w[i] * ma, vb = Lt::w[i] * mb;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             if (Lt::c[i][d] > 0) {
@@ -215,7 +233,7 @@ __device__ __forceinline__ void node_collide(const GridDims& g, const PhysConst&
 #pragma unroll
     for (int i = 0; i < Q; ++i) gg[i] = ld(src + (size_t)(Q + i) * g.N, nbr32<L>(nb, n, i, -1));
     R up[3] = {u[0] + R(0.5) * du[0], u[1] + R(0.5) * du[1], u[2] + R(0.5) * du[2]};
-    collide_g<L, R>(gg, R(p), R(ld(mup, n)), up, R(k.Gamma), R(k.omega_phi));
+    collide_g<L, R>(gg, R(p), R(aux.mup0(n)), up, R(k.Gamma), R(k.omega_phi));
 #pragma unroll
     for (int i = 0; i < Q; ++i) st(dst + (size_t)(Q + i) * g.N, n, gg[i]);
 
@@ -236,6 +254,16 @@ __device__ __forceinline__ void node_collide(const GridDims& g, const PhysConst&
         dv[8] = gam;
         dv[9] = bad ? 1.0 : 0.0;
     }
+}
+
+template <int L, typename T>
+__device__ __forceinline__ void node_collide(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
+                                             T* __restrict__ dst, const double* __restrict__ rho_ref,
+                                             const double* __restrict__ rho, const double* __restrict__ phi,
+                                             const double* __restrict__ mux, const double* __restrict__ mup,
+                                             int x, int y, int z, bool diag, double* dv) {
+    const GlobalAux aux{rho, phi, mux, mup};
+    node_collide_aux<L, T>(g, k, src, dst, rho_ref, aux, x, y, z, diag, dv);
 }
 
 // ---------------------------------------------------------------------------

@@ -45,74 +45,88 @@ __device__ __forceinline__ int wrapn(int v, int n) {
 // ---------------------------------------------------------------------------
 // Implicit-GEMM convolution: out[p][co] = sum_{tap, ci} in[p + s*d*off(tap)][ci]
 // * Wp[co][tap*CIN + ci] (+ bias, ReLU), off(tap) = (tap/3 - 1, tap%3 - 1),
-// dilation d >= 1;
-// s = +1 for the forward pass and for the data gradient (which runs on the
-// flipped, transposed weights).  Optional mask: out *= (mask[p][co] > 0)
-// (derivative of the ReLU that produced the layer input).  Each wavefront
-// computes 32 pixels (two M tiles) of one image row segment x COUT channels.
+// dilation d >= 1; s = +1 for the forward pass and for the data gradient
+// (which runs on the flipped, transposed weights).  Optional mask: out *=
+// (mask[p][co] > 0) (derivative of the ReLU that produced the layer input).
+// The weights are staged once per workgroup in LDS; each wavefront computes
+// four M tiles (64 pixels) x all COUT channels, so each B fragment read from
+// LDS feeds four matrix instructions, and persistent workgroups walk 256-pixel
+// chunks so the weights are fetched from L2 once per workgroup.  LDS rows are
+// padded by 16 bytes so the 16 rows a fragment read touches fall in different
+// banks.
 // ---------------------------------------------------------------------------
 template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wp,
-                                              const float* __restrict__ bias, const uint16_t* __restrict__ mask,
-                                              uint16_t* __restrict__ out_bf, float* __restrict__ out_f32, int N,
-                                              int H, int W, int sgn, int dil, int relu) {
-    constexpr int NT = COUT / 16;
-    constexpr int KC = CIN / 32;  // K chunks per tap
-    const int lane = threadIdx.x & 63;
-    const int wave = (blockIdx.x * (blockDim.x >> 6)) + (threadIdx.x >> 6);
-    const int64_t P = (int64_t)N * H * W;
-    const int64_t p0 = (int64_t)wave * 32;
-    if (p0 >= P) return;
+__global__ __launch_bounds__(256) void k_conv_lds(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wp,
+                                                  const float* __restrict__ bias, const uint16_t* __restrict__ mask,
+                                                  uint16_t* __restrict__ out_bf, float* __restrict__ out_f32, int N,
+                                                  int H, int W, int sgn, int dil, int relu) {
+    constexpr int MT = 4, NT = COUT / 16, KC = CIN / 32;
+    constexpr int KW = 9 * CIN;    // K extent of a weight row
+    constexpr int ROW = KW + 8;    // padded LDS row, bf16 elements
+    __shared__ __align__(16) uint16_t wl[COUT * ROW];
+    for (int e = threadIdx.x; e < COUT * (KW / 8); e += 256) {
+        const int r = e / (KW / 8), c8 = e % (KW / 8);
+        *(uint4*)(wl + r * ROW + c8 * 8) = *(const uint4*)(wp + (int64_t)r * KW + c8 * 8);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r16 = lane & 15, kg = lane >> 4;
-    // the two pixels this lane feeds as A rows
-    int64_t pa[2];
-    int hh[2], ww[2], nn[2];
-    for (int mt = 0; mt < 2; ++mt) {
-        pa[mt] = p0 + mt * 16 + r16;
-        const int64_t pc = pa[mt] < P ? pa[mt] : P - 1;
-        nn[mt] = (int)(pc / ((int64_t)H * W));
-        const int rem = (int)(pc % ((int64_t)H * W));
-        hh[mt] = rem / W;
-        ww[mt] = rem % W;
-    }
-    f32x4 acc[2][NT];
-    for (int mt = 0; mt < 2; ++mt)
-        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int tap = 0; tap < 9; ++tap) {
-        const int dh = sgn * dil * (tap / 3 - 1), dw = sgn * dil * (tap % 3 - 1);
-        int64_t src[2];
-        for (int mt = 0; mt < 2; ++mt)
-            src[mt] = (((int64_t)nn[mt] * H + wrapn(hh[mt] + dh, H)) * W + wrapn(ww[mt] + dw, W)) * CIN;
+    const int64_t P = (int64_t)N * H * W;
+    for (int64_t chunk = blockIdx.x; chunk * 256 < P; chunk += gridDim.x) {
+        const int64_t p0 = chunk * 256 + (int64_t)wv * 64;
+        if (p0 >= P) continue;
+        int hh[MT], ww[MT], nn[MT];
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-            const int ci = kc * 32 + kg * 8;
-            Pack8 a[2], b[NT];
-            for (int mt = 0; mt < 2; ++mt) a[mt].v = *(const uint4*)(in + src[mt] + ci);
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-                b[nt].v = *(const uint4*)(wp + (int64_t)(nt * 16 + r16) * (9 * CIN) + tap * CIN + ci);
-#pragma unroll
-            for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt].b, b[nt].b, acc[mt][nt], 0, 0, 0);
+        for (int mt = 0; mt < MT; ++mt) {
+            int64_t pc = p0 + mt * 16 + r16;
+            pc = pc < P ? pc : P - 1;
+            nn[mt] = (int)(pc / ((int64_t)H * W));
+            const int rem = (int)(pc % ((int64_t)H * W));
+            hh[mt] = rem / W;
+            ww[mt] = rem % W;
         }
-    }
-    // epilogue: lane holds rows (pixels) 4 kg + j of column (channel) r16
-    for (int mt = 0; mt < 2; ++mt) {
+        f32x4 acc[MT][NT];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t p = p0 + mt * 16 + kg * 4 + j;
-            if (p >= P) continue;
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const int co = nt * 16 + r16;
-                float v = acc[mt][nt][j];
-                if (bias) v += bias[co];
-                if (relu) v = v > 0.f ? v : 0.f;
-                if (mask && !(bf2f(mask[p * COUT + co]) > 0.f)) v = 0.f;
-                if (out_bf) out_bf[p * COUT + co] = f2bf(v);
-                if (out_f32) out_f32[p * COUT + co] = v;
+            for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dh = sgn * dil * (tap / 3 - 1), dw = sgn * dil * (tap % 3 - 1);
+            int64_t src[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                src[mt] = (((int64_t)nn[mt] * H + wrapn(hh[mt] + dh, H)) * W + wrapn(ww[mt] + dw, W)) * CIN;
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                const int ci = kc * 32 + kg * 8;
+                Pack8 a[MT], b[NT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) a[mt].v = *(const uint4*)(in + src[mt] + ci);
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) b[nt].v = *(const uint4*)(wl + (nt * 16 + r16) * ROW + tap * CIN + ci);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt].b, b[nt].b, acc[mt][nt], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t p = p0 + mt * 16 + kg * 4 + j;
+                if (p >= P) continue;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const int co = nt * 16 + r16;
+                    float v = acc[mt][nt][j];
+                    if (bias) v += bias[co];
+                    if (relu) v = v > 0.f ? v : 0.f;
+                    if (mask && !(bf2f(mask[p * COUT + co]) > 0.f)) v = 0.f;
+                    if (out_bf) out_bf[p * COUT + co] = f2bf(v);
+                    if (out_f32) out_f32[p * COUT + co] = v;
+                }
             }
         }
     }
@@ -131,7 +145,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__
                                                     float* __restrict__ part, int N, int H, int W, int dil,
                                                     int waves_per_tap) {
     constexpr int MT = CIN / 16, NT = COUT / 16;
-    __shared__ uint16_t lds[4][(CIN + COUT) * 32];  // per wave: inT[CIN][32], dyT[COUT][32]
+    __shared__ __align__(16) uint16_t lds[4][(CIN + COUT) * 32];  // per wave: inT[CIN][32], dyT[COUT][32]
     const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
     const int wave = blockIdx.x * 4 + wl;
     const int tap = wave / waves_per_tap, wt = wave % waves_per_tap;
@@ -190,24 +204,48 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__
             for (int j = 0; j < 4; ++j) out[(mt * 16 + kg * 4 + j) * COUT + nt * 16 + r16] = acc[mt][nt][j];
 }
 
-// Sum of the per-wave partials in a fixed order: dw[e] = sum_w part[w][e].
-__global__ void k_reduce_parts(const float* __restrict__ part, int nparts, int64_t n, float* __restrict__ dw) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
+// Sum of the partials in a fixed order: dw[e] = sum_w part[w][e].  A block of
+// 256 threads takes 64 elements; its four thread groups sum the partials
+// w = g, g + 4, ... and the four group sums are added in order.
+__global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ part, int nparts, int64_t n,
+                                                      float* __restrict__ dw) {
+    __shared__ float red[4][64];
+    const int el = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int64_t e = (int64_t)blockIdx.x * 64 + el;
     float s = 0.f;
-    for (int w = 0; w < nparts; ++w) s += part[(int64_t)w * n + e];
-    dw[e] = s;
+    if (e < n)
+        for (int w = grp; w < nparts; w += 4) s += part[(int64_t)w * n + e];
+    red[grp][el] = s;
+    __syncthreads();
+    if (grp == 0 && e < n) dw[e] = ((red[0][el] + red[1][el]) + red[2][el]) + red[3][el];
 }
 
-// Bias gradient partials: per block sums over a range of pixels, per channel.
-__global__ void k_bias_grad(const uint16_t* __restrict__ dy, int64_t P, int C, float* __restrict__ part) {
-    // block b handles pixels [b*chunk, (b+1)*chunk); thread t < C sums channel t
+// Bias gradient partials: block b sums the pixels [b chunk, (b+1) chunk) per
+// channel.  Thread t reads channels 8 (t % (C/8)) .. +8 of every
+// (2048 / C)-th pixel with one 16-byte load, so a pixel's C channels come
+// from C/8 consecutive lanes; the rows are combined in LDS in a fixed order.
+constexpr int kBiasBlocks = 1024;
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dy, int64_t P, int C,
+                                                   float* __restrict__ part) {
+    __shared__ float red[256 * 8];
+    const int groups = C / 8, rows = 256 / groups;
+    const int cg = threadIdx.x % groups, r = threadIdx.x / groups;
     const int64_t chunk = (P + gridDim.x - 1) / gridDim.x;
     const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = p0 + chunk < P ? p0 + chunk : P;
-    for (int c = threadIdx.x; c < C; c += blockDim.x) {
-        float s = 0.f;
-        for (int64_t p = p0; p < p1; ++p) s += bf2f(dy[p * C + c]);
-        part[(int64_t)blockIdx.x * C + c] = s;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int64_t p = p0 + r; p < p1; p += rows) {
+        Pack8 v;
+        v.v = *(const uint4*)(dy + p * C + cg * 8);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] += bf2f(v.h[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) red[r * C + cg * 8 + j] = acc[j];
+    __syncthreads();
+    if ((int)threadIdx.x < C) {
+        float t = red[threadIdx.x];
+        for (int k = 1; k < rows; ++k) t += red[k * C + threadIdx.x];
+        part[(int64_t)blockIdx.x * C + threadIdx.x] = t;
     }
 }
 
@@ -299,14 +337,15 @@ __global__ void k_encode(const double* __restrict__ rho, const double* __restric
 // (residual head): rho^ = rho^_in + y0, C1 = C1_in + y1, C2 = C2_in + y2,
 // u = u_in + y3,4 / u_scale; rho^ is clamped so that rho >= rho_g/2 and
 // phi/chi = C1 - C2 to [-1.1, 1.1] (a clamp at +-1 would cut the positive
-// half of the bulk noise and leave a biased phase defect for the projection;
-// the double well pulls slight excursions back).  The first pass writes these values, the
-// interface weight w = |grad rho^| + |grad(phi/chi)| + 1e-6 (central
-// differences, periodic; the small floor keeps a featureless image defined
-// while putting the defects on the interfaces, not into the bulk phases) and per-block partial sums; the second pass adds
-// the mass and phase defects in proportion to w and shifts the velocity
-// uniformly so that the totals of rho, phi and rho u equal the input's.
-// Blocks never straddle images.
+// half of the bulk noise and leave a biased phase defect for the
+// projection; the double well pulls slight excursions back).  The first pass
+// writes these values, the interface weight w = |grad rho^| + |grad(phi/chi)|
+// + 1e-6 (central differences, periodic; the small floor keeps a featureless
+// image defined while putting the defects on the interfaces, not into the
+// bulk phases) and per-block partial sums; the second pass adds the mass and
+// phase defects in proportion to w and shifts the velocity uniformly so that
+// the totals of rho, phi and rho u equal the input's.  Blocks never straddle
+// images.
 constexpr int kDecSums = 11;  // rho_in, phi_in, rho, phi, w, (rho u)_in x,y, rho u x,y, w u x,y
 
 struct DecodeArgs {
@@ -408,9 +447,10 @@ static hipError_t conv_t(const uint16_t* in, const uint16_t* wp, const float* bi
                          uint16_t* out_bf, float* out_f32, int N, int H, int W, int sgn, int dil, int relu,
                          hipStream_t st) {
     const int64_t P = (int64_t)N * H * W;
-    const int64_t waves = (P + 31) / 32;
-    const unsigned blocks = (unsigned)((waves + 3) / 4);
-    k_conv<CIN, COUT><<<blocks, 256, 0, st>>>(in, wp, bias, mask, out_bf, out_f32, N, H, W, sgn, dil, relu);
+    const int64_t chunks = (P + 255) / 256;
+    // persistent: two workgroups per CU (the weight stage is at most 75 KB)
+    const unsigned blocks = (unsigned)(chunks < 512 ? chunks : 512);
+    k_conv_lds<CIN, COUT><<<blocks, 256, 0, st>>>(in, wp, bias, mask, out_bf, out_f32, N, H, W, sgn, dil, relu);
     return hipGetLastError();
 }
 
@@ -445,6 +485,12 @@ using namespace telbm;
 namespace {
 bool conv_shape_ok(int cin, int cout) {
     return (cin == 32 || cin == 64) && (cout == 32 || cout == 64);
+}
+// Wavefronts per tap of the weight gradient (each walks a contiguous range of
+// 32-pixel slabs; their partials are summed afterwards in a fixed order).
+int wgrad_waves_per_tap(int64_t P) {
+    const int64_t slabs = (P + 31) / 32;
+    return (int)(slabs < 256 ? (slabs < 1 ? 1 : slabs) : 256);
 }
 }  // namespace
 
@@ -484,24 +530,21 @@ int telbm_conv_backward(const void* x, const void* dy, int n, int h, int w, int 
     }
     if (dw || db) {
         const int64_t P = (int64_t)n * h * w;
-        const int64_t slabs = (P + 31) / 32;
-        int wpt = (int)(slabs < 256 ? slabs : 256);
-        if (wpt < 1) wpt = 1;
+        const int wpt = wgrad_waves_per_tap(P);
         const size_t need = (size_t)wpt * 9 * cin * cout * sizeof(float);
-        const int bblocks = 512;
-        const size_t need_b = (size_t)bblocks * cout * sizeof(float);
+        const size_t need_b = (size_t)kBiasBlocks * cout * sizeof(float);
         if (!workspace || workspace_bytes < (need > need_b ? need : need_b)) return TELBM_ERR_NOMEM;
         if (dw) {
             hipError_t e = wgrad_dispatch(cin, cout, (const uint16_t*)x, (const uint16_t*)dy, (float*)workspace, n, h,
                                           w, dilation, wpt, st);
             if (e != hipSuccess) return TELBM_ERR_DEVICE;
             const int64_t ne = 9LL * cin * cout;
-            k_reduce_parts<<<(unsigned)((ne + 255) / 256), 256, 0, st>>>((const float*)workspace, wpt, ne, dw);
+            k_reduce_parts<<<(unsigned)((ne + 63) / 64), 256, 0, st>>>((const float*)workspace, wpt, ne, dw);
             if (hipGetLastError() != hipSuccess) return TELBM_ERR_DEVICE;
         }
         if (db) {
-            k_bias_grad<<<bblocks, 64, 0, st>>>((const uint16_t*)dy, P, cout, (float*)workspace);
-            k_reduce_parts<<<(cout + 255) / 256, 256, 0, st>>>((const float*)workspace, bblocks, cout, db);
+            k_bias_grad<<<kBiasBlocks, 256, 0, st>>>((const uint16_t*)dy, P, cout, (float*)workspace);
+            k_reduce_parts<<<(cout + 63) / 64, 256, 0, st>>>((const float*)workspace, kBiasBlocks, cout, db);
             if (hipGetLastError() != hipSuccess) return TELBM_ERR_DEVICE;
         }
     }
@@ -510,10 +553,9 @@ int telbm_conv_backward(const void* x, const void* dy, int n, int h, int w, int 
 
 int telbm_conv_workspace_bytes(int n, int h, int w, int cin, int cout, size_t* bytes) {
     if (!bytes || n < 1 || h < 1 || w < 1 || !conv_shape_ok(cin, cout)) return TELBM_ERR_INVAL;
-    const int64_t slabs = ((int64_t)n * h * w + 31) / 32;
-    const int64_t wpt = slabs < 256 ? slabs : 256;
+    const int64_t wpt = wgrad_waves_per_tap((int64_t)n * h * w);
     const size_t a = (size_t)wpt * 9 * cin * cout * sizeof(float);
-    const size_t b = (size_t)512 * cout * sizeof(float);
+    const size_t b = (size_t)kBiasBlocks * cout * sizeof(float);
     *bytes = a > b ? a : b;
     return TELBM_OK;
 }
