@@ -121,6 +121,68 @@ __global__ __launch_bounds__(BX* BY) void k_chempot(GridDims g, PhysConst k, con
     if (t.in) node_chempot<L>(g, k, rho, phi, mux, mup, t.x, t.y, t.z);
 }
 
+__device__ __forceinline__ int wrap_any(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Chemical potentials of D3Q27 along z-columns: the block walks CZ planes of
+// its BX x BY tile, holding three planes of rho and phi (with an x-y halo of
+// one node) in LDS and loading one new plane per step, so each plane is
+// fetched once per column instead of by every z-neighbour.  The Laplacian
+// terms are summed in the lattice order of node_chempot, so the potentials
+// are the same numbers.
+constexpr int CZ = 8;
+constexpr int CPX = BX + 2, CPY = BY + 2, CPN = CPX * CPY;
+
+__global__ __launch_bounds__(BX* BY) void k_chempot_col(GridDims g, PhysConst k, const double* __restrict__ rho,
+                                                        const double* __restrict__ phi, double* __restrict__ mux,
+                                                        double* __restrict__ mup) {
+    using Lt = Lattice<kD3Q27>;
+    __shared__ double sr[3][CPN], sp[3][CPN];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + BY - 1) / BY;
+    const int bx = b % bxc, rest = b / bxc, by = rest % byc, bzc = rest / byc;
+    const int x0 = bx * BX, y0 = by * BY, z0 = bzc * CZ;
+    const int tid = threadIdx.y * BX + threadIdx.x;
+    auto load_plane = [&](int slot, int z) {
+        const int64_t zo = (int64_t)wrap_any(z, g.nz) * g.ny;
+        for (int e = tid; e < CPN; e += BX * BY) {
+            const int64_t n = (zo + wrap_any(y0 - 1 + e / CPX, g.ny)) * g.nx + wrap_any(x0 - 1 + e % CPX, g.nx);
+            sr[slot][e] = rho[n];
+            sp[slot][e] = phi[n];
+        }
+    };
+    load_plane(0, z0 - 1);
+    load_plane(1, z0);
+    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
+    const int c = (threadIdx.y + 1) * CPX + threadIdx.x + 1;
+    for (int zz = 0; zz < CZ; ++zz) {
+        const int z = z0 + zz;
+        if (z >= g.nz) break;  // uniform over the block
+        load_plane((zz + 2) % 3, z + 1);
+        __syncthreads();
+        const int below = zz % 3, centre = (zz + 1) % 3, above = (zz + 2) % 3;
+        if (x < g.nx && y < g.ny) {
+            const double r0 = sr[centre][c], p0 = sp[centre][c];
+            double lr = 0.0, lp = 0.0;
+#pragma unroll
+            for (int i = 1; i < Lt::Q; ++i) {
+                const int sl = Lt::c[i][2] == 0 ? centre : (Lt::c[i][2] > 0 ? above : below);
+                const int o = c + Lt::c[i][1] * CPX + Lt::c[i][0];
+                lr += Lt::w[i] * (sr[sl][o] - r0);
+                lp += Lt::w[i] * (sp[sl][o] - p0);
+            }
+            double mx, mp;
+            chem_pot(k, r0, p0, 6.0 * lr, 6.0 * lp, &mx, &mp);
+            const int64_t n = ((int64_t)z * g.ny + y) * g.nx + x;
+            mux[n] = mx;
+            mup[n] = mp;
+        }
+        __syncthreads();  // the next plane overwrites the slot just read as `below`
+    }
+}
+
 template <int L, typename T>
 __global__ __launch_bounds__(BX* BY) void k_collide(GridDims g, PhysConst k, const T* __restrict__ src,
                                                     T* __restrict__ dst, const double* __restrict__ rho_ref,
@@ -153,11 +215,6 @@ __global__ __launch_bounds__(BX* BY) void k_collide(GridDims g, PhysConst k, con
 constexpr int FBY = 8;                      // rows per workgroup of the fused step
 constexpr int FHX = BX + 4, FHY = FBY + 4;  // density tile with a halo of 2
 constexpr int FMX = BX + 2, FMY = FBY + 2;  // potential tile with a halo of 1
-
-__device__ __forceinline__ int wrap_any(int v, int n) {
-    v %= n;
-    return v < 0 ? v + n : v;
-}
 
 struct LdsAux2 {
     const double* sr;
@@ -371,7 +428,12 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
     if (part == 0) {
         k_moments<L, T><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
     } else if (part == 1) {
-        k_chempot<L><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup);
+        if (L == kD3Q27) {
+            const unsigned cb = (unsigned)(((a.g.nx + BX - 1) / BX) * ((a.g.ny + BY - 1) / BY) * ((a.g.nz + CZ - 1) / CZ));
+            k_chempot_col<<<cb, blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup);
+        } else {
+            k_chempot<L><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup);
+        }
     } else if (part == 2) {
         k_collide<L, T><<<grd, blk, 0, a.stream>>>(a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref, a.rho,
                                                      a.phi, a.mux, a.mup, a.partials, a.diag);
