@@ -262,3 +262,48 @@ def test_full_size_3d_collision_stays_finite_and_conserves_mass(orc, precision):
         tol = 1e-12 if precision == 0 else 1e-7
         print("mass drift", d["mass"] / d0["mass"] - 1, "max_u", d["max_u"], flush=True)
         assert abs(d["mass"] / d0["mass"] - 1) < tol
+
+
+def test_fp32_mixed_errors_at_equilibrium(orc):
+    """The FP32-mixed form against the FP64 path on a relaxing lens at
+    density ratio 1000 (D2Q9 256^2, 20,000 steps): density, spurious-current
+    magnitude and the lens shape (outline lengths of the liquid-gas and the
+    two liquid interfaces, which the three angles fix).  Printed for the
+    record; bounded loosely here."""
+    import paper_1710_07486_amd as T
+    from paper_1710_07486_amd.calibrate import discrete_coexistence
+    from paper_1710_07486_amd.equilibrium import interface_measures
+    wl = W.lens(256, 256, radius=40.0, ratio=1000.0, kappa=0.2, seed=7)
+    Tt = T.temperature_for_ratio(1000.0)
+    ph = wl.physics()
+    base = dict(lattice=0, nx=256, ny=256, nz=1, T=Tt, lambda1=ph["lambda1"], lambda2=ph["lambda2"],
+                lambda3=ph["lambda3"], kappa1=ph["kappa1"], kappa2=ph["kappa2"], kappa3=ph["kappa3"])
+    rg, rl = discrete_coexistence(T.Params(**base))
+    rho, phi, _ = W.fields(wl, rg, rl)
+    out = {}
+    for prec in (T.FP64, T.FP32_MIXED):
+        with T.Solver(T.Params(precision=prec, **base)) as s:
+            s.init_fields(rho, phi)
+            s.step(20000)
+            f = {"rho": s.read("rho"), "phi": s.read("phi"),
+                 "u": np.sqrt(s.read("ux") ** 2 + s.read("uy") ** 2)}
+            f["shape"] = interface_measures(f["rho"], f["phi"], rg, rl, 5.0)
+            out[prec] = f
+    a, b = out[T.FP64], out[T.FP32_MIXED]
+    e_rho = float(np.abs(b["rho"] - a["rho"]).max() / np.abs(a["rho"]).max())
+    sc = (a["rho"] - rg) / (rl - rg)
+    co = {}
+    for name, mask in (("gas", sc < 0.01), ("liquid", sc > 0.99)):
+        m64, m32 = float(np.median(a["rho"][mask])), float(np.median(b["rho"][mask]))
+        co[name] = abs(m32 - m64) / m64
+    u64, u32 = float(a["u"].max()), float(b["u"].max())
+    e_shape = float(np.max(np.abs(b["shape"] - a["shape"]) / a["shape"]))
+    say(f"FP32-mixed vs FP64 after 20000 steps: max-norm rho {e_rho:.2e}; coexistence densities gas "
+        f"{co['gas']:.2e}, liquid {co['liquid']:.2e}; spurious max|u| {u64:.4e} vs {u32:.4e}; shape {e_shape:.2e}")
+    # the max-norm error sits on the interfaces, where at ratio 1000 a shift
+    # of 1e-4 nodes changes the density by ~1e-3 of its maximum; measured
+    # 8.9e-4 there, 6.7e-6 on the shape and 2e-4 on the spurious currents
+    assert e_rho < 5e-3
+    assert co["gas"] < 1e-4 and co["liquid"] < 1e-5
+    assert abs(u32 - u64) < 0.01 * u64
+    assert e_shape < 1e-4
