@@ -25,13 +25,23 @@ struct telbm_solver {
     char* arena;
     size_t arena_bytes;
     void* pop[2];
-    double* rhob[2];     // densities: the current state's reference and the computed one
-    double *phi, *mux, *mup, *partials, *diag_dev;
+    // Density slots.  rhob[dsl], phib[psl]: moments of the current state (when
+    // dens_valid; partial tile sums completed by inbox[isl] when dens_partial).
+    // FP32 form: the stored f values are relative to rhob[ref].  The fused
+    // D2Q9 step writes the next partial moments into free slots and the other
+    // inbox, and (FP32 form) the completed current densities, the next
+    // reference, into a fourth density slot.
+    double* rhob[4];
+    double* phib[2];
+    double* inbox[2];
+    double *mux, *mup, *partials, *diag_dev;
     unsigned long long* bad;
     double diag_host[16];  // host copy of the diagnostics (pageable; 80 bytes)
     hipStream_t stream;
     int cur;             // pop[cur] holds the state
     int ref;             // FP32 form: the state's f values are relative to rhob[ref]
+    int dsl, psl, isl;   // slots of the current moments and of their inbox
+    bool dens_partial;   // rhob[dsl] / phib[psl] hold tile sums to complete
     bool aux_valid;      // rho/phi/mux/mup belong to the current state
     bool dens_valid;     // rho/phi belong to the current state
     int64_t steps;
@@ -56,8 +66,9 @@ int hip_fail(telbm_solver* s, hipError_t e, const char* where) {
 }
 
 struct Layout {
-    size_t pop, aux, partials, diag, bad, total;
-    size_t o_pop0, o_pop1, o_rho0, o_rho1, o_phi, o_mux, o_mup, o_part, o_diag, o_bad;
+    size_t pop, aux, inbox, partials, diag, bad, total;
+    int n_rho, n_phi, n_inbox;
+    size_t o_pop0, o_pop1, o_rho[4], o_phi[2], o_inbox[2], o_mux, o_mup, o_part, o_diag, o_bad;
 };
 
 Layout layout_of(const telbm_params& p) {
@@ -68,15 +79,22 @@ Layout layout_of(const telbm_params& p) {
     Layout L{};
     L.pop = align_up((size_t)2 * Q * N * s);
     L.aux = align_up((size_t)N * sizeof(double));
+    // D2Q9 (fused step): current and next moments, FP32 form also the
+    // reference and next reference densities; two inboxes
+    const bool fz = p.lattice == TELBM_D2Q9;
+    L.n_rho = fz && p.precision == TELBM_FP32_MIXED ? 4 : 2;
+    L.n_phi = fz ? 2 : 1;
+    L.n_inbox = fz ? 2 : 0;
+    L.inbox = fz ? align_up(inbox_doubles(g) * sizeof(double)) : 0;
     L.partials = align_up((size_t)collide_blocks(g) * kDiag * sizeof(double));
     L.diag = align_up(16 * sizeof(double));
     L.bad = align_up(sizeof(unsigned long long));
     size_t o = 0;
     L.o_pop0 = o; o += L.pop;
     L.o_pop1 = o; o += L.pop;
-    L.o_rho0 = o; o += L.aux;
-    L.o_rho1 = o; o += L.aux;
-    L.o_phi = o; o += L.aux;
+    for (int i = 0; i < L.n_rho; ++i) { L.o_rho[i] = o; o += L.aux; }
+    for (int i = 0; i < L.n_phi; ++i) { L.o_phi[i] = o; o += L.aux; }
+    for (int i = 0; i < L.n_inbox; ++i) { L.o_inbox[i] = o; o += L.inbox; }
     L.o_mux = o; o += L.aux;
     L.o_mup = o; o += L.aux;
     L.o_part = o; o += L.partials;
@@ -140,9 +158,23 @@ PhysConst derive(const telbm_params& p, double rho_g, double rho_l, double C) {
 }
 
 bool mixed(const telbm_solver* s) { return s->p.precision == TELBM_FP32_MIXED; }
+bool fused(const telbm_solver* s) { return s->p.lattice == TELBM_D2Q9; }
+
+// A density slot other than `a`.
+int other_slot(const telbm_solver* s, int a) { return fused(s) && mixed(s) ? (a + 1) % 4 : 1 - a; }
+
+// Free density slots of the fused step: k = 0 receives the next partial
+// moments, k = 1 (FP32 form) the completed current densities.  Neither is the
+// current slot or the reference.
+int free_slot(const telbm_solver* s, int k) {
+    if (!mixed(s)) return 1 - s->dsl;
+    for (int i = 0; i < 4; ++i)
+        if (i != s->dsl && i != s->ref && k-- == 0) return i;
+    return -1;
+}
 
 // Density field that the moment kernel fills for the current state.
-double* density_out(telbm_solver* s) { return mixed(s) ? s->rhob[1 - s->ref] : s->rhob[0]; }
+double* density_out(telbm_solver* s) { return s->rhob[s->dsl]; }
 
 StepArgs args_of(telbm_solver* s, bool forward) {
     StepArgs a{};
@@ -152,7 +184,14 @@ StepArgs args_of(telbm_solver* s, bool forward) {
     a.dst = forward ? s->pop[1 - s->cur] : s->pop[s->cur];
     a.rho_ref = mixed(s) ? s->rhob[s->ref] : nullptr;
     a.rho = density_out(s);
-    a.phi = s->phi;
+    a.phi = s->phib[s->psl];
+    if (fused(s)) {
+        a.inbox_in = s->dens_partial ? s->inbox[s->isl] : nullptr;
+        a.rho_next = s->rhob[free_slot(s, 0)];
+        a.phi_next = s->phib[1 - s->psl];
+        a.inbox_out = s->inbox[1 - s->isl];
+        a.rho_final = mixed(s) ? s->rhob[free_slot(s, 1)] : nullptr;
+    }
     a.mux = s->mux;
     a.mup = s->mup;
     a.partials = s->partials;
@@ -176,17 +215,26 @@ hipError_t timed_launch(telbm_solver* s, const StepArgs& a, int part, Timing* t)
     hipError_t e = hipEventRecord(ev.first, s->stream);
     if (e == hipSuccess) e = launch_part(s->p.lattice, s->p.precision, a, part);
     if (e == hipSuccess) e = hipEventRecord(ev.second, s->stream);
-    t->kind.push_back(part == 3 ? 2 : part);  // the fused 2D launch counts as the collision
+    t->kind.push_back(part == 3 ? 2 : part == 4 ? 0 : part);  // fused 2D launch: collision; completion: moments
     return e;
 }
 
-// Bring the densities (moments) to the current state.
-int ensure_dens(telbm_solver* s, Timing* t = nullptr) {
-    if (s->dens_valid) return TELBM_OK;
+// Bring the densities (moments) to the current state; partial tile sums are
+// kept (the fused step completes them) unless `complete`.
+int ensure_dens(telbm_solver* s, Timing* t = nullptr, bool complete = true) {
+    if (s->dens_valid) {
+        if (!s->dens_partial || !complete) return TELBM_OK;
+        StepArgs a = args_of(s, false);
+        hipError_t e = timed_launch(s, a, 4, t);
+        if (e != hipSuccess) return hip_fail(s, e, "moment completion launch");
+        s->dens_partial = false;
+        return TELBM_OK;
+    }
     StepArgs a = args_of(s, false);
     hipError_t e = timed_launch(s, a, 0, t);
     if (e != hipSuccess) return hip_fail(s, e, "moment launch");
     s->dens_valid = true;
+    s->dens_partial = false;
     return TELBM_OK;
 }
 
@@ -230,19 +278,31 @@ bool unstable(const telbm_diag& d) {
 }
 
 // One time step.
-// On D2Q9 the chemical potentials are computed inside the collision launch.
+// On D2Q9 one launch computes the chemical potentials, the collision and the
+// next state's moments (as tile sums plus inbox entries, completed by the
+// next launch), so the moment pass runs only after initialisation.
 int one_step(telbm_solver* s, bool diag, Timing* t = nullptr) {
-    const bool fused = s->p.lattice == TELBM_D2Q9;
-    int rc = fused ? ensure_dens(s, t) : ensure_aux(s, t);
+    const bool fz = fused(s);
+    int rc = fz ? ensure_dens(s, t, false) : ensure_aux(s, t);
     if (rc) return rc;
     StepArgs a = args_of(s, true);
     a.diag = diag ? 1 : 0;
-    hipError_t e = timed_launch(s, a, fused ? 3 : 2, t);
+    hipError_t e = timed_launch(s, a, fz ? 3 : 2, t);
     if (e != hipSuccess) return hip_fail(s, e, "collision launch");
     s->cur = 1 - s->cur;
-    if (mixed(s)) s->ref = 1 - s->ref;  // the new state is relative to the density just used
+    if (fz) {
+        const int nxt = free_slot(s, 0), fin = free_slot(s, 1);
+        s->dsl = nxt;
+        s->psl = 1 - s->psl;
+        s->isl = 1 - s->isl;
+        s->dens_partial = true;
+        if (mixed(s)) s->ref = fin;  // the new state is relative to the completed densities
+    } else if (mixed(s)) {
+        s->ref = s->dsl;  // the new state is relative to the density just used
+        s->dsl = other_slot(s, s->dsl);
+    }
     s->aux_valid = false;
-    s->dens_valid = false;
+    s->dens_valid = fz;
     if (diag) {
         s->diag_step = s->steps;
         s->diag_unread = true;
@@ -251,7 +311,8 @@ int one_step(telbm_solver* s, bool diag, Timing* t = nullptr) {
     return TELBM_OK;
 }
 
-const char* kKernelNames[3] = {"moments", "chemical_potentials", "collide"};
+constexpr int kKinds = 3;
+const char* kKernelNames[kKinds] = {"moments", "chemical_potentials", "collide"};
 
 }  // namespace
 
@@ -317,9 +378,9 @@ int telbm_create(const telbm_params* p, void* device_arena, size_t bytes, telbm_
     s->arena_bytes = bytes;
     s->pop[0] = s->arena + L.o_pop0;
     s->pop[1] = s->arena + L.o_pop1;
-    s->rhob[0] = (double*)(s->arena + L.o_rho0);
-    s->rhob[1] = (double*)(s->arena + L.o_rho1);
-    s->phi = (double*)(s->arena + L.o_phi);
+    for (int i = 0; i < 4; ++i) s->rhob[i] = i < L.n_rho ? (double*)(s->arena + L.o_rho[i]) : nullptr;
+    for (int i = 0; i < 2; ++i) s->phib[i] = (double*)(s->arena + L.o_phi[i < L.n_phi ? i : 0]);
+    for (int i = 0; i < 2; ++i) s->inbox[i] = i < L.n_inbox ? (double*)(s->arena + L.o_inbox[i]) : nullptr;
     s->mux = (double*)(s->arena + L.o_mux);
     s->mup = (double*)(s->arena + L.o_mup);
     s->partials = (double*)(s->arena + L.o_part);
@@ -328,6 +389,10 @@ int telbm_create(const telbm_params* p, void* device_arena, size_t bytes, telbm_
     s->stream = nullptr;
     s->cur = 0;
     s->ref = 0;
+    s->dsl = mixed(s) ? 1 : 0;
+    s->psl = 0;
+    s->isl = 0;
+    s->dens_partial = false;
     s->aux_valid = false;
     s->dens_valid = false;
     s->steps = 0;
@@ -354,10 +419,11 @@ int telbm_init_fields(telbm_solver* s, const double* rho, const double* phi, con
     // stage: rho, phi into the aux fields, u into the spare population buffer
     double* u_dev = u ? (double*)s->pop[1 - s->cur] : nullptr;
     double* rho_dev = density_out(s);
+    double* phi_dev = s->phib[s->psl];
     hipError_t e = hipMemcpyAsync(rho_dev, rho, N * sizeof(double), kind, s->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(s->phi, phi, N * sizeof(double), kind, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(phi_dev, phi, N * sizeof(double), kind, s->stream);
     if (e == hipSuccess && u) e = hipMemcpyAsync(u_dev, u, (size_t)D * N * sizeof(double), kind, s->stream);
-    if (e == hipSuccess) e = launch_check_init(s->g, D, rho_dev, s->phi, u_dev, s->bad, s->stream);
+    if (e == hipSuccess) e = launch_check_init(s->g, D, rho_dev, phi_dev, u_dev, s->bad, s->stream);
     unsigned long long bad = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(s->diag_host, s->bad, sizeof(bad), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -365,6 +431,7 @@ int telbm_init_fields(telbm_solver* s, const double* rho, const double* phi, con
     memcpy(&bad, s->diag_host, sizeof(bad));
     s->aux_valid = false;
     s->dens_valid = false;
+    s->dens_partial = false;
     if (bad) return fail(s, TELBM_ERR_UNSTABLE, std::to_string(bad) + " nodes with rho <= 0, |u| >= 1 or non-finite values");
     // mu_phi of the initial fields, then the equilibria into the state buffer
     StepArgs a = args_of(s, false);
@@ -372,7 +439,10 @@ int telbm_init_fields(telbm_solver* s, const double* rho, const double* phi, con
     if (e == hipSuccess) e = launch_init(s->p.lattice, s->p.precision, a, u_dev);
     if (e != hipSuccess) return hip_fail(s, e, "init launch");
     // FP32 form: the initial populations are relative to the initial density
-    if (mixed(s)) s->ref = 1 - s->ref;
+    if (mixed(s)) {
+        s->ref = s->dsl;
+        s->dsl = other_slot(s, s->ref);
+    }
     s->steps = 0;
     s->diag_step = -1;
     s->diag_unread = false;
@@ -460,16 +530,16 @@ int telbm_time_kernels(telbm_solver* s, int64_t n, double* ms, int* kinds) {
         if (e != hipSuccess) rc = hip_fail(s, e, "timed synchronise");
     }
     if (rc == TELBM_OK) {
-        double sum[3] = {0, 0, 0};
-        int cnt[3] = {0, 0, 0};
+        double sum[kKinds] = {0, 0, 0};
+        int cnt[kKinds] = {0, 0, 0};
         for (size_t i = 0; i < t.used; ++i) {
             float ms1 = 0.f;
             if (hipEventElapsedTime(&ms1, t.pool[i].first, t.pool[i].second) != hipSuccess) continue;
             sum[t.kind[i]] += ms1;
             cnt[t.kind[i]] += 1;
         }
-        for (int k = 0; k < 3; ++k) ms[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
-        *kinds = 3;
+        for (int k = 0; k < kKinds; ++k) ms[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
+        *kinds = kKinds;
     }
     for (size_t i = 0; i < made; ++i) {
         (void)hipEventDestroy(t.pool[i].first);
@@ -480,7 +550,7 @@ int telbm_time_kernels(telbm_solver* s, int64_t n, double* ms, int* kinds) {
 
 const char* telbm_kernel_name(const telbm_solver* s, int kind) {
     (void)s;
-    if (kind < 0 || kind > 2) return "";
+    if (kind < 0 || kind >= kKinds) return "";
     return kKernelNames[kind];
 }
 

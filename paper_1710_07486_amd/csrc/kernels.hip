@@ -12,12 +12,14 @@
 //                state, so the stored number keeps FP32 relative precision in
 //                the dilute gas as well as in the liquid.
 //   aux fields   rho[n], phi[n], mux[n] (= mu_rho - cs2 ln rho), mup[n] (mu_phi),
-//                all FP64.
+//                all FP64.  D2Q9 also keeps per-tile inboxes of next-step
+//                moment sums (k_collide_fused2).
 //
-// One step is three launches: node moments (pull-sum of both population sets),
-// chemical potentials (Laplacian stencils over rho, phi), and the fused
-// pull -> force -> KBC + exact-difference forcing -> phase-field BGK -> write;
-// on D2Q9 the last two are one launch (k_collide_fused2).
+// D3Q27: one step is three launches: node moments (pull-sum of both population
+// sets), chemical potentials (Laplacian stencils over rho, phi), and the fused
+// pull -> force -> KBC + exact-difference forcing -> phase-field BGK -> write.
+// D2Q9: one launch per step (k_collide_fused2) that also leaves the next
+// step's moments; the moment pass runs only after initialisation.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -202,19 +204,131 @@ __global__ __launch_bounds__(BX* BY) void k_collide(GridDims g, PhysConst k, con
 }
 
 // ---------------------------------------------------------------------------
-// Fused chemical potentials and collision of the 2D lattice.  The block
-// stages the densities and phase field of its BX x FBY tile with a halo of two
-// nodes in LDS, computes the chemical potentials of the tile with a halo of
-// one node there (the same arithmetic, term for term, as k_chempot), and runs
-// the collision of its nodes with the force from those LDS potentials: one
-// launch and no potential fields in HBM per step.  (On D3Q27 the potential
-// halo of a 64 x 4 tile is 4.6 times the tile, so the 3D step keeps its
-// separate stencil pass.)  The tile is 64 x 8 so that the potential halo
-// adds 29 % to the tile's potential work rather than 55 % at 64 x 4.
+// Fused chemical potentials, collision and next-step densities of the 2D
+// lattice.  The block stages the densities and phase field of its BX x FBY
+// tile with a halo of two nodes in LDS, computes the chemical potentials of
+// the tile with a halo of one node there (the same arithmetic, term for term,
+// as k_chempot), and runs the collision of its nodes with the force from those
+// LDS potentials: no potential fields in HBM.  (On D3Q27 the potential halo of
+// a 64 x 4 tile is 4.6 times the tile, so the 3D step keeps its separate
+// stencil pass.)  The tile is 64 x 8 so that the potential halo adds 29 % to
+// the tile's potential work rather than 55 % at 64 x 4.
+//
+// The block also sums the moments of the next step, rho'(x) = sum_i f*_i(x -
+// c_i) and phi'(x) = sum_i g*_i(x - c_i), from its own post-collision values
+// (the values the pull of the next step reconstructs: in the FP32 form the
+// stored deviation plus w_i times the writer's density), over the sources
+// that lie in the tile: tile nodes receive these partial sums in rho_next /
+// phi_next, and the sums for the one-node ring around the tile go to the
+// inboxes of the tiles that own those ring nodes.  The next launch completes
+// each staged density with the inbox entries of its node, so a step is one
+// launch and the moment pass over all populations runs only after
+// initialisation.
+//
+// Within a wavefront (one tile row of 64 consecutive x) the three directions
+// of each row offset c_y are combined with lane shuffles, so a node leaves
+// three sums per field in LDS instead of nine values.
 // ---------------------------------------------------------------------------
 constexpr int FBY = 8;                      // rows per workgroup of the fused step
 constexpr int FHX = BX + 4, FHY = FBY + 4;  // density tile with a halo of 2
 constexpr int FMX = BX + 2, FMY = FBY + 2;  // potential tile with a halo of 1
+
+// Inbox of a tile: sums of next-step moments that neighbouring tiles hold for
+// its edge nodes, (rho, phi) pairs.  Slots: bottom row from the tile below,
+// top row from the tile above, left and right columns from the side tiles,
+// then the four corners from the diagonal tiles (bottom-left, bottom-right,
+// top-left, top-right).
+constexpr int IB_DOWN = 0, IB_UP = BX, IB_LEFT = 2 * BX, IB_RIGHT = 2 * BX + FBY, IB_CORNER = 2 * BX + 2 * FBY;
+constexpr int INBOX = IB_CORNER + 4;
+
+// Tile of a node and the node's place in it.
+struct TilePos {
+    int tile, lx, ly, W, H;
+};
+__device__ __forceinline__ TilePos tile_pos(const GridDims& g, int gx, int gy) {
+    const int bxc = (g.nx + BX - 1) / BX;
+    const int tbx = gx / BX, tby = gy / FBY;
+    TilePos t;
+    t.tile = tby * bxc + tbx;
+    t.lx = gx - tbx * BX;
+    t.ly = gy - tby * FBY;
+    t.W = min(BX, g.nx - tbx * BX);
+    t.H = min(FBY, g.ny - tby * FBY);
+    return t;
+}
+
+// Add the inbox entries of node (gx, gy) to its tile's partial sums (r, p),
+// in a fixed order.
+__device__ __forceinline__ void inbox_complete(const GridDims& g, const double* __restrict__ in, int gx, int gy,
+                                               double& r, double& p) {
+    const TilePos t = tile_pos(g, gx, gy);
+    const bool x0 = t.lx == 0, x1 = t.lx == t.W - 1, y0 = t.ly == 0, y1 = t.ly == t.H - 1;
+    if (!(x0 || x1 || y0 || y1)) return;
+    const double* b = in + (int64_t)t.tile * INBOX * 2;
+    auto add = [&](int slot) {
+        r += b[2 * slot];
+        p += b[2 * slot + 1];
+    };
+    if (y0) add(IB_DOWN + t.lx);
+    if (y1) add(IB_UP + t.lx);
+    if (x0) add(IB_LEFT + t.ly);
+    if (x1) add(IB_RIGHT + t.ly);
+    if (x0 && y0) add(IB_CORNER + 0);
+    if (x1 && y0) add(IB_CORNER + 1);
+    if (x0 && y1) add(IB_CORNER + 2);
+    if (x1 && y1) add(IB_CORNER + 3);
+}
+
+// The same completion with the entries loaded together: a node of a tile at
+// least two nodes wide and high has at most one entry from each of a vertical
+// side, a horizontal side and a corner, taken in the order of inbox_complete;
+// the three loads are issued unconditionally (a missing entry reads the
+// tile's first slot and is not added).  Narrower tiles use inbox_complete.
+__device__ __forceinline__ void inbox_complete_fast(const GridDims& g, const double* __restrict__ in, int gx,
+                                                    int gy, double& r, double& p) {
+    const TilePos t = tile_pos(g, gx, gy);
+    const bool x0 = t.lx == 0, x1 = t.lx == t.W - 1, y0 = t.ly == 0, y1 = t.ly == t.H - 1;
+    if (!(x0 || x1 || y0 || y1)) return;
+    if (t.W < 2 || t.H < 2) {
+        inbox_complete(g, in, gx, gy, r, p);
+        return;
+    }
+    const double2* b = reinterpret_cast<const double2*>(in) + (int64_t)t.tile * INBOX;
+    const bool hv = y0 || y1, hh = x0 || x1, hc = hv && hh;
+    const int sv = hv ? (y0 ? IB_DOWN : IB_UP) + t.lx : 0;
+    const int sh = hh ? (x0 ? IB_LEFT : IB_RIGHT) + t.ly : 0;
+    const int sc = hc ? IB_CORNER + (x1 ? 1 : 0) + (y1 ? 2 : 0) : 0;
+    const double2 v = b[sv], h = b[sh], c = b[sc];
+    if (hv) {
+        r += v.x;
+        p += v.y;
+    }
+    if (hh) {
+        r += h.x;
+        p += h.y;
+    }
+    if (hc) {
+        r += c.x;
+        p += c.y;
+    }
+}
+
+// Inbox slot (in the owning tile) that receives the ring position (ex, ey)
+// of a W x H tile at (x0, y0).  Returns the slot's index in the inbox array.
+__device__ __forceinline__ int64_t inbox_target(const GridDims& g, int x0, int y0, int W, int H, int ex, int ey) {
+    int tx = x0 + ex, ty = y0 + ey;
+    tx += tx < 0 ? g.nx : (tx >= g.nx ? -g.nx : 0);
+    ty += ty < 0 ? g.ny : (ty >= g.ny ? -g.ny : 0);
+    const TilePos t = tile_pos(g, tx, ty);
+    // where the sending tile lies as seen from the receiving node
+    const int dx = ex < 0 ? 1 : (ex >= W ? -1 : 0);
+    const int dy = ey < 0 ? 1 : (ey >= H ? -1 : 0);
+    int slot;
+    if (dx == 0) slot = (dy > 0 ? IB_UP : IB_DOWN) + t.lx;
+    else if (dy == 0) slot = (dx > 0 ? IB_RIGHT : IB_LEFT) + t.ly;
+    else slot = IB_CORNER + (dx > 0 ? 1 : 0) + (dy > 0 ? 2 : 0);
+    return (int64_t)t.tile * INBOX + slot;
+}
 
 struct LdsAux2 {
     const double* sr;
@@ -233,25 +347,94 @@ struct LdsAux2 {
     }
 };
 
+// Index of the D2Q9 direction (cx, cy), and the row offset of group ky
+// (0, +1, -1 for ky = 0, 1, 2).
+__host__ __device__ constexpr int d2q9_dir(int cx, int cy) {
+    for (int i = 0; i < 9; ++i)
+        if (Lattice<kD2Q9>::c[i][0] == cx && Lattice<kD2Q9>::c[i][1] == cy) return i;
+    return -1;
+}
+__host__ __device__ constexpr int row_offset(int ky) { return ky == 0 ? 0 : (ky == 1 ? 1 : -1); }
+static_assert(d2q9_dir(0, 0) >= 0 && d2q9_dir(1, 0) >= 0 && d2q9_dir(-1, 0) >= 0 && d2q9_dir(0, 1) >= 0 &&
+                  d2q9_dir(1, 1) >= 0 && d2q9_dir(-1, 1) >= 0 && d2q9_dir(0, -1) >= 0 && d2q9_dir(1, -1) >= 0 &&
+                  d2q9_dir(-1, -1) >= 0,
+              "every D2Q9 direction present");
+
+// Per-row partial sums of the next moments.  For row offset c_y (group ky,
+// c_y = row_offset(ky)) the node at lane l leaves
+//   S_ky(l) = v(0, c_y)(l) + v(+1, c_y)(l - 1) + v(-1, c_y)(l + 1)
+// (terms from lanes of the tile only) in sum[field][ky][ly][l], and the
+// values that leave the tile sideways, v(-1, c_y) of lane 0 and v(+1, c_y) of
+// the last lane, in side[field][0 / 1][ky][ly].
+struct NextSink {
+    double* sum;   // [2][3][FBY][BX]
+    double* side;  // [2][2][3][FBY]
+    int lx, ly, W;
+    __device__ __forceinline__ void put(int field, const double* v) {
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+            const int cy = row_offset(ky);
+            const double a = v[d2q9_dir(0, cy)], b = v[d2q9_dir(1, cy)], c = v[d2q9_dir(-1, cy)];
+            const double bl = __shfl_up(b, 1);
+            const double cr = __shfl_down(c, 1);
+            double t = a;
+            if (lx >= 1) t += bl;
+            if (lx + 1 < W) t += cr;
+            sum[((field * 3 + ky) * FBY + ly) * BX + lx] = t;
+            if (lx == 0) side[((field * 2 + 0) * 3 + ky) * FBY + ly] = c;
+            if (lx == W - 1) side[((field * 2 + 1) * 3 + ky) * FBY + ly] = b;
+        }
+    }
+    template <int L, typename R>
+    __device__ __forceinline__ void post_f(const R* f, double r) {
+        using Lt = Lattice<L>;
+        double v[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            v[i] = double(f[i]);
+            if (Deviation<R>::on) v[i] += Lt::w[i] * r;
+        }
+        put(0, v);
+    }
+    template <int L, typename R>
+    __device__ __forceinline__ void post_g(const R* gg) {
+        double v[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) v[i] = double(gg[i]);
+        put(1, v);
+    }
+};
+
 template <typename T>
 __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysConst k, const T* __restrict__ src,
                                                            T* __restrict__ dst, const double* __restrict__ rho_ref,
                                                            const double* __restrict__ rho,
                                                            const double* __restrict__ phi,
+                                                           const double* __restrict__ inbox_in,
+                                                           double* __restrict__ rho_next,
+                                                           double* __restrict__ phi_next,
+                                                           double* __restrict__ inbox_out,
+                                                           double* __restrict__ rho_final,
                                                            double* __restrict__ partials, int diag) {
     using Lt = Lattice<kD2Q9>;
     __shared__ double sr[FHX * FHY], sp[FHX * FHY], smx[FMX * FMY], smp[FMX * FMY];
+    __shared__ double nsum[2 * 3 * FBY * BX], nside[2 * 2 * 3 * FBY];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + FBY - 1) / FBY;
-    const int bx = b % bxc, rest = b / bxc, by = rest % byc, bz = rest / byc;
+    const int bxc = (g.nx + BX - 1) / BX;
+    const int bx = b % bxc, by = b / bxc;
     const int x0 = bx * BX, y0 = by * FBY;
+    const int W = min(BX, g.nx - x0), H = min(FBY, g.ny - y0);
     const int tid = threadIdx.y * BX + threadIdx.x;
-    const int64_t zoff = (int64_t)bz * g.nx * g.ny;
+    // densities of the tile and its halo; partial sums (inbox_in set) are
+    // completed with the inbox entries of their nodes
     for (int e = tid; e < FHX * FHY; e += BX * FBY) {
         const int hx = e % FHX, hy = e / FHX;
-        const int64_t n = zoff + (int64_t)wrap_any(y0 - 2 + hy, g.ny) * g.nx + wrap_any(x0 - 2 + hx, g.nx);
-        sr[e] = rho[n];
-        sp[e] = phi[n];
+        const int gx = wrap_any(x0 - 2 + hx, g.nx), gy = wrap_any(y0 - 2 + hy, g.ny);
+        const int64_t n = (int64_t)gy * g.nx + gx;
+        double r = rho[n], p = phi[n];
+        if (inbox_in) inbox_complete_fast(g, inbox_in, gx, gy, r, p);
+        sr[e] = r;
+        sp[e] = p;
     }
     __syncthreads();
     for (int e = tid; e < FMX * FMY; e += BX * FBY) {
@@ -271,12 +454,86 @@ __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysCons
     }
     __syncthreads();
     double dv[kDiag] = {0, 0, 0, 0, 0, 0, INFINITY, INFINITY, -INFINITY, 0};
-    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
-    if (x < g.nx && y < g.ny) {
-        const LdsAux2 aux{sr, sp, smx, smp, (int)threadIdx.x, (int)threadIdx.y};
-        node_collide_aux<kD2Q9, T>(g, k, src, dst, rho_ref, aux, x, y, bz, diag != 0, dv);
+    {
+        // every lane runs a collision (lanes past a ragged edge on the tile's
+        // last node, without stores) so that the sink's shuffles see whole rows
+        const int lx = min((int)threadIdx.x, W - 1), ly = min((int)threadIdx.y, H - 1);
+        const bool active = (int)threadIdx.x < W && (int)threadIdx.y < H;
+        const LdsAux2 aux{sr, sp, smx, smp, lx, ly};
+        if (rho_final && active) rho_final[(int64_t)(y0 + ly) * g.nx + x0 + lx] = aux.rho0(0);
+        NextSink sink{nsum, nside, (int)threadIdx.x, (int)threadIdx.y, W};
+        node_collide_sink<kD2Q9, T>(g, k, src, dst, rho_ref, aux, x0 + lx, y0 + ly, 0, diag != 0, dv, active,
+                                    sink);
     }
     if (diag) diag_block_reduce<BX * FBY>(dv, partials);
+    __syncthreads();
+    // next moments of the tile and its ring, from the sources in the tile
+    for (int e = tid; e < (BX + 2) * (FBY + 2); e += BX * FBY) {
+        const int ex = e % (BX + 2) - 1, ey = e / (BX + 2) - 1;
+        if (ex > W || ey > H) continue;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+            const int sy = ey - row_offset(ky);
+            if (sy < 0 || sy >= H) continue;
+            if (ex < 0) {
+                s0 += nside[((0 * 2 + 0) * 3 + ky) * FBY + sy];
+                s1 += nside[((1 * 2 + 0) * 3 + ky) * FBY + sy];
+            } else if (ex >= W) {
+                s0 += nside[((0 * 2 + 1) * 3 + ky) * FBY + sy];
+                s1 += nside[((1 * 2 + 1) * 3 + ky) * FBY + sy];
+            } else {
+                s0 += nsum[((0 * 3 + ky) * FBY + sy) * BX + ex];
+                s1 += nsum[((1 * 3 + ky) * FBY + sy) * BX + ex];
+            }
+        }
+        if (ex >= 0 && ex < W && ey >= 0 && ey < H) {
+            const int64_t n = (int64_t)(y0 + ey) * g.nx + x0 + ex;
+            rho_next[n] = s0;
+            phi_next[n] = s1;
+        } else {
+            const int64_t q = 2 * inbox_target(g, x0, y0, W, H, ex, ey);
+            inbox_out[q] = s0;
+            inbox_out[q + 1] = s1;
+        }
+    }
+}
+
+// Completes partial next-step moments in place with their inbox entries (the
+// edge nodes of every tile), before the densities are read outside the fused
+// step.  One workgroup per tile, one thread per edge node.
+constexpr int FIX_THREADS = 2 * BX + 2 * FBY;
+
+__global__ __launch_bounds__(FIX_THREADS) void k_dens_complete2(GridDims g, double* __restrict__ rho,
+                                                                double* __restrict__ phi,
+                                                                const double* __restrict__ inbox) {
+    const int b = blockIdx.x;
+    const int bxc = (g.nx + BX - 1) / BX;
+    const int x0 = (b % bxc) * BX, y0 = (b / bxc) * FBY;
+    const int W = min(BX, g.nx - x0), H = min(FBY, g.ny - y0);
+    const int nrow = H > 1 ? 2 * W : W;
+    const int ncol = H > 2 ? (W > 1 ? 2 : 1) * (H - 2) : 0;
+    const int t = threadIdx.x;
+    if (t >= nrow + ncol) return;
+    int lx, ly;
+    if (t < W) {
+        lx = t;
+        ly = 0;
+    } else if (t < nrow) {
+        lx = t - W;
+        ly = H - 1;
+    } else if (t - nrow < H - 2) {
+        lx = 0;
+        ly = 1 + (t - nrow);
+    } else {
+        lx = W - 1;
+        ly = 1 + (t - nrow - (H - 2));
+    }
+    const int64_t n = (int64_t)(y0 + ly) * g.nx + x0 + lx;
+    double r = rho[n], p = phi[n];
+    inbox_complete(g, inbox, x0 + lx, y0 + ly, r, p);
+    rho[n] = r;
+    phi[n] = p;
 }
 
 // Deterministic second pass over the block partials (one workgroup).
@@ -421,6 +678,10 @@ static inline unsigned grid_blocks(const GridDims& g) {
 
 unsigned collide_blocks(const GridDims& g) { return grid_blocks(g); }
 
+unsigned fused_tiles(const GridDims& g) { return (unsigned)(((g.nx + BX - 1) / BX) * ((g.ny + FBY - 1) / FBY)); }
+
+size_t inbox_doubles(const GridDims& g) { return (size_t)fused_tiles(g) * INBOX * 2; }
+
 template <int L, typename T>
 static hipError_t launch_step_parts(const StepArgs& a, int part) {
     const dim3 blk(BX, BY, 1);
@@ -438,12 +699,19 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
         k_collide<L, T><<<grd, blk, 0, a.stream>>>(a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref, a.rho,
                                                      a.phi, a.mux, a.mup, a.partials, a.diag);
         if (a.diag) k_diag_final<<<1, 256, 0, a.stream>>>(a.partials, (int)grd.x, a.diag_out);
-    } else {
-        if (L != kD2Q9) return hipErrorInvalidValue;
-        const unsigned fb = (unsigned)(((a.g.nx + BX - 1) / BX) * ((a.g.ny + FBY - 1) / FBY) * a.g.nz);
-        k_collide_fused2<T><<<fb, dim3(BX, FBY, 1), 0, a.stream>>>(a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref,
-                                                                   a.rho, a.phi, a.partials, a.diag);
+    } else if (part == 3) {
+        if (L != kD2Q9 || a.g.nz != 1 || !a.rho_next || !a.phi_next || !a.inbox_out) return hipErrorInvalidValue;
+        if (Deviation<T>::on != (a.rho_final != nullptr)) return hipErrorInvalidValue;
+        const unsigned fb = fused_tiles(a.g);
+        k_collide_fused2<T><<<fb, dim3(BX, FBY, 1), 0, a.stream>>>(
+            a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref, a.rho, a.phi, a.inbox_in, a.rho_next, a.phi_next,
+            a.inbox_out, a.rho_final, a.partials, a.diag);
         if (a.diag) k_diag_final<<<1, 256, 0, a.stream>>>(a.partials, (int)fb, a.diag_out);
+    } else if (part == 4) {
+        if (L != kD2Q9 || a.g.nz != 1 || !a.inbox_in) return hipErrorInvalidValue;
+        k_dens_complete2<<<fused_tiles(a.g), FIX_THREADS, 0, a.stream>>>(a.g, a.rho, a.phi, a.inbox_in);
+    } else {
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -28,6 +28,13 @@ struct StepArgs {
     void* dst;           // populations receiving the next state
     const double* rho_ref;  // density the stored f values are relative to (FP32 form)
     double *rho, *phi, *mux, *mup;
+    // D2Q9 fused step (part 3): rho / phi may be partial sums completed from
+    // inbox_in (null: complete); the step leaves the next state's partial
+    // moments in rho_next / phi_next and their inbox entries in inbox_out;
+    // FP32 form: the completed densities (the new reference) in rho_final.
+    // Part 4 completes rho / phi in place from inbox_in.
+    const double* inbox_in;
+    double *rho_next, *phi_next, *inbox_out, *rho_final;
     double* partials;    // per-block diagnostic partials
     double* diag_out;    // final diagnostics (kDiag doubles)
     int diag;
@@ -35,8 +42,12 @@ struct StepArgs {
 };
 
 unsigned collide_blocks(const GridDims& g);
+unsigned fused_tiles(const GridDims& g);        // D2Q9 tiles of the fused step
+size_t inbox_doubles(const GridDims& g);        // size of one inbox array
 
-// part 0: moments, 1: chemical potentials, 2: collision (+ diagnostics)
+// part 0: moments, 1: chemical potentials, 2: collision (+ diagnostics);
+// D2Q9 only: 3: fused potentials + collision + tile sums of the next moments,
+// 4: completion of partial moments at the tile edges
 hipError_t launch_part(int lattice, int precision, const StepArgs& a, int part);
 hipError_t launch_init(int lattice, int precision, const StepArgs& a, const double* u0);
 hipError_t launch_check_init(const GridDims& g, int D, const double* rho, const double* phi, const double* u0,

@@ -192,15 +192,27 @@ struct GlobalAux {
     }
 };
 
+// Receiver of a node's post-collision populations, called right after they
+// are stored (post_f with the node's density, post_g).  NoSink: none.
+struct NoSink {
+    template <int L, typename R>
+    __device__ __forceinline__ void post_f(const R*, double) {}
+    template <int L, typename R>
+    __device__ __forceinline__ void post_g(const R*) {}
+};
+
 // Phase 3: pull f, g; force from the excess potentials; KBC with
 // exact-difference forcing; phase-field BGK; write the node's own slots.
 // If diag, dv receives {rho, phi, j (3), |u_phys|, rho, gamma, gamma, bad}.
 // The three sub-phases (stencil, f, g) are kept apart by scheduling barriers
-// so that their loads do not all become live at once.
-template <int L, typename T, typename AUX>
-__device__ __forceinline__ void node_collide_aux(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
-                                                 T* __restrict__ dst, const double* __restrict__ rho_ref,
-                                                 const AUX& aux, int x, int y, int z, bool diag, double* dv) {
+// so that their loads do not all become live at once.  With active false the
+// node is computed but nothing is stored or reported (lanes past a ragged
+// edge that run on a clamped node so that the sink sees a full wavefront).
+template <int L, typename T, typename AUX, typename SINK>
+__device__ __forceinline__ void node_collide_sink(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
+                                                  T* __restrict__ dst, const double* __restrict__ rho_ref,
+                                                  const AUX& aux, int x, int y, int z, bool diag, double* dv,
+                                                  bool active, SINK& sink) {
     using Lt = Lattice<L>;
     using R = T;
     constexpr int Q = Lt::Q;
@@ -249,8 +261,11 @@ __device__ __forceinline__ void node_collide_aux(const GridDims& g, const PhysCo
     R du[3] = {R(F[0] * ir), R(F[1] * ir), R(F[2] * ir)};
     if (Lt::D == 2) u[2] = du[2] = R(0);
     const double gam = collide_f<L, R>(f, r, ir, u, du, R(k.beta), k.inv_beta, Deviation<T>::on ? r : 0.0);
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) st_pop<L>(dst + (size_t)i * g.N, n, f[i]);
+        for (int i = 0; i < Q; ++i) st_pop<L>(dst + (size_t)i * g.N, n, f[i]);
+    }
+    sink.template post_f<L, R>(f, r);
     phase_fence();
 
     R gg[Q];
@@ -258,10 +273,13 @@ __device__ __forceinline__ void node_collide_aux(const GridDims& g, const PhysCo
     for (int i = 0; i < Q; ++i) gg[i] = ld_pop<L>(src + (size_t)(Q + i) * g.N, nbr32<L>(nb, n, i, -1));
     R up[3] = {u[0] + R(0.5) * du[0], u[1] + R(0.5) * du[1], u[2] + R(0.5) * du[2]};
     collide_g<L, R>(gg, R(p), R(aux.mup0(n)), up, R(k.Gamma), R(k.omega_phi));
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) st_pop<L>(dst + (size_t)(Q + i) * g.N, n, gg[i]);
+        for (int i = 0; i < Q; ++i) st_pop<L>(dst + (size_t)(Q + i) * g.N, n, gg[i]);
+    }
+    sink.template post_g<L, R>(gg);
 
-    if (diag) {
+    if (diag && active) {
         const double ux = double(jx) * ir + 0.5 * F[0] * ir;
         const double uy = double(jy) * ir + 0.5 * F[1] * ir;
         const double uz = double(jz) * ir + 0.5 * F[2] * ir;
@@ -278,6 +296,14 @@ __device__ __forceinline__ void node_collide_aux(const GridDims& g, const PhysCo
         dv[8] = gam;
         dv[9] = bad ? 1.0 : 0.0;
     }
+}
+
+template <int L, typename T, typename AUX>
+__device__ __forceinline__ void node_collide_aux(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
+                                                 T* __restrict__ dst, const double* __restrict__ rho_ref,
+                                                 const AUX& aux, int x, int y, int z, bool diag, double* dv) {
+    NoSink none;
+    node_collide_sink<L, T>(g, k, src, dst, rho_ref, aux, x, y, z, diag, dv, true, none);
 }
 
 template <int L, typename T>
