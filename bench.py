@@ -24,12 +24,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, TFLOP/s
 
-# HBM bytes per launch of the D2Q9 1024x1024 FP64 collision kernel (chemical
-# potentials and collision in one launch) from two rocprofv3 counter passes
-# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, scales from a 1 GiB copy in the same
-# runs; profiles/collide_d2q9_1024_fp64_traffic.md), valid only for the kernel
-# sources whose hash is recorded with it.
-COLLIDE_TRAFFIC = {"bytes_per_launch": 320772713, "sources_sha256_16": "c210e4f71a65b90e"}
+# HBM bytes per launch of the D2Q9 1024x1024 FP64 step kernel (chemical
+# potentials, collision and next-step moments in one launch) from two rocprofv3
+# counter passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, scales from a 1 GiB copy
+# in the same runs; profiles/collide_d2q9_1024_fp64_traffic.md), valid only for
+# the kernel sources whose hash is recorded with it.
+COLLIDE_TRAFFIC = {"bytes_per_launch": 348412015, "sources_sha256_16": "54e0828843a6eb3e"}
 
 
 def kernel_sources_hash():
