@@ -34,6 +34,7 @@ struct telbm_solver {
     double* rhob[4];
     double* phib[2];
     double* inbox[2];
+    double *part3, *inbox3;  // D3Q27 FP64: partial next-step moments and their inbox
     double *mux, *mup, *partials, *diag_dev;
     unsigned long long* bad;
     double diag_host[16];  // host copy of the diagnostics (pageable; 80 bytes)
@@ -41,7 +42,8 @@ struct telbm_solver {
     int cur;             // pop[cur] holds the state
     int ref;             // FP32 form: the state's f values are relative to rhob[ref]
     int dsl, psl, isl;   // slots of the current moments and of their inbox
-    bool dens_partial;   // rhob[dsl] / phib[psl] hold tile sums to complete
+    bool dens_partial;   // D2Q9: rhob[dsl] / phib[psl] hold tile sums to complete;
+                         // D3Q27 FP64: part3 / inbox3 hold the current moments
     bool aux_valid;      // rho/phi/mux/mup belong to the current state
     bool dens_valid;     // rho/phi belong to the current state
     int64_t steps;
@@ -66,9 +68,9 @@ int hip_fail(telbm_solver* s, hipError_t e, const char* where) {
 }
 
 struct Layout {
-    size_t pop, aux, inbox, partials, diag, bad, total;
+    size_t pop, aux, inbox, part3, inbox3, partials, diag, bad, total;
     int n_rho, n_phi, n_inbox;
-    size_t o_pop0, o_pop1, o_rho[4], o_phi[2], o_inbox[2], o_mux, o_mup, o_part, o_diag, o_bad;
+    size_t o_pop0, o_pop1, o_rho[4], o_phi[2], o_inbox[2], o_part3, o_inbox3, o_mux, o_mup, o_part, o_diag, o_bad;
 };
 
 Layout layout_of(const telbm_params& p) {
@@ -86,6 +88,10 @@ Layout layout_of(const telbm_params& p) {
     L.n_phi = fz ? 2 : 1;
     L.n_inbox = fz ? 2 : 0;
     L.inbox = fz ? align_up(inbox_doubles(g) * sizeof(double)) : 0;
+    // D3Q27 FP64: three partial next-step moment pairs per node and their inboxes
+    const bool next3 = !fz && p.precision == TELBM_FP64;
+    L.part3 = next3 ? align_up((size_t)N * 3 * 2 * sizeof(double)) : 0;
+    L.inbox3 = next3 ? align_up(inbox3_doubles(g) * sizeof(double)) : 0;
     L.partials = align_up((size_t)collide_blocks(g) * kDiag * sizeof(double));
     L.diag = align_up(16 * sizeof(double));
     L.bad = align_up(sizeof(unsigned long long));
@@ -95,6 +101,8 @@ Layout layout_of(const telbm_params& p) {
     for (int i = 0; i < L.n_rho; ++i) { L.o_rho[i] = o; o += L.aux; }
     for (int i = 0; i < L.n_phi; ++i) { L.o_phi[i] = o; o += L.aux; }
     for (int i = 0; i < L.n_inbox; ++i) { L.o_inbox[i] = o; o += L.inbox; }
+    L.o_part3 = o; o += L.part3;
+    L.o_inbox3 = o; o += L.inbox3;
     L.o_mux = o; o += L.aux;
     L.o_mup = o; o += L.aux;
     L.o_part = o; o += L.partials;
@@ -159,6 +167,8 @@ PhysConst derive(const telbm_params& p, double rho_g, double rho_l, double C) {
 
 bool mixed(const telbm_solver* s) { return s->p.precision == TELBM_FP32_MIXED; }
 bool fused(const telbm_solver* s) { return s->p.lattice == TELBM_D2Q9; }
+// D3Q27 FP64: the collision leaves the next moments as partial sums
+bool next3(const telbm_solver* s) { return s->p.lattice == TELBM_D3Q27 && !mixed(s); }
 
 // A density slot other than `a`.
 int other_slot(const telbm_solver* s, int a) { return fused(s) && mixed(s) ? (a + 1) % 4 : 1 - a; }
@@ -194,6 +204,8 @@ StepArgs args_of(telbm_solver* s, bool forward) {
     }
     a.mux = s->mux;
     a.mup = s->mup;
+    a.part3 = s->part3;
+    a.inbox3 = s->inbox3;
     a.partials = s->partials;
     a.diag_out = s->diag_dev;
     a.diag = 0;
@@ -215,7 +227,9 @@ hipError_t timed_launch(telbm_solver* s, const StepArgs& a, int part, Timing* t)
     hipError_t e = hipEventRecord(ev.first, s->stream);
     if (e == hipSuccess) e = launch_part(s->p.lattice, s->p.precision, a, part);
     if (e == hipSuccess) e = hipEventRecord(ev.second, s->stream);
-    t->kind.push_back(part == 3 ? 2 : part == 4 ? 0 : part);  // fused 2D launch: collision; completion: moments
+    // fused 2D launch and the 3D collision with next sums: collision; 2D
+    // completion: moments; completing 3D potential pass: potentials
+    t->kind.push_back(part == 3 || part == 6 ? 2 : part == 4 ? 0 : part == 5 ? 1 : part);
     return e;
 }
 
@@ -224,10 +238,12 @@ hipError_t timed_launch(telbm_solver* s, const StepArgs& a, int part, Timing* t)
 int ensure_dens(telbm_solver* s, Timing* t = nullptr, bool complete = true) {
     if (s->dens_valid) {
         if (!s->dens_partial || !complete) return TELBM_OK;
+        // D3Q27: the completing pass also computes the chemical potentials
         StepArgs a = args_of(s, false);
-        hipError_t e = timed_launch(s, a, 4, t);
+        hipError_t e = timed_launch(s, a, fused(s) ? 4 : 5, t);
         if (e != hipSuccess) return hip_fail(s, e, "moment completion launch");
         s->dens_partial = false;
+        if (!fused(s)) s->aux_valid = true;
         return TELBM_OK;
     }
     StepArgs a = args_of(s, false);
@@ -243,6 +259,7 @@ int ensure_aux(telbm_solver* s, Timing* t = nullptr) {
     if (s->aux_valid) return TELBM_OK;
     int rc = ensure_dens(s, t);
     if (rc) return rc;
+    if (s->aux_valid) return TELBM_OK;  // completed together with the potentials
     StepArgs a = args_of(s, false);
     hipError_t e = timed_launch(s, a, 1, t);
     if (e != hipSuccess) return hip_fail(s, e, "chemical-potential launch");
@@ -287,7 +304,7 @@ int one_step(telbm_solver* s, bool diag, Timing* t = nullptr) {
     if (rc) return rc;
     StepArgs a = args_of(s, true);
     a.diag = diag ? 1 : 0;
-    hipError_t e = timed_launch(s, a, fz ? 3 : 2, t);
+    hipError_t e = timed_launch(s, a, fz ? 3 : (next3(s) ? 6 : 2), t);
     if (e != hipSuccess) return hip_fail(s, e, "collision launch");
     s->cur = 1 - s->cur;
     if (fz) {
@@ -302,7 +319,8 @@ int one_step(telbm_solver* s, bool diag, Timing* t = nullptr) {
         s->dsl = other_slot(s, s->dsl);
     }
     s->aux_valid = false;
-    s->dens_valid = fz;
+    s->dens_valid = fz || next3(s);
+    if (next3(s)) s->dens_partial = true;
     if (diag) {
         s->diag_step = s->steps;
         s->diag_unread = true;
@@ -381,6 +399,8 @@ int telbm_create(const telbm_params* p, void* device_arena, size_t bytes, telbm_
     for (int i = 0; i < 4; ++i) s->rhob[i] = i < L.n_rho ? (double*)(s->arena + L.o_rho[i]) : nullptr;
     for (int i = 0; i < 2; ++i) s->phib[i] = (double*)(s->arena + L.o_phi[i < L.n_phi ? i : 0]);
     for (int i = 0; i < 2; ++i) s->inbox[i] = i < L.n_inbox ? (double*)(s->arena + L.o_inbox[i]) : nullptr;
+    s->part3 = L.part3 ? (double*)(s->arena + L.o_part3) : nullptr;
+    s->inbox3 = L.inbox3 ? (double*)(s->arena + L.o_inbox3) : nullptr;
     s->mux = (double*)(s->arena + L.o_mux);
     s->mup = (double*)(s->arena + L.o_mup);
     s->partials = (double*)(s->arena + L.o_part);

@@ -128,6 +128,12 @@ __device__ __forceinline__ int wrap_any(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
+// Completed next-step moments of node (gx, gy, z) of a D3Q27 FP64 state left by
+// k_collide_next3 (defined with the inbox helpers below).
+__device__ __forceinline__ void next3_complete(const GridDims& g, const double* __restrict__ part,
+                                               const double* __restrict__ inbox, int gx, int gy, int z, int64_t n,
+                                               double& r, double& p);
+
 // Chemical potentials of D3Q27 along z-columns: the block walks CZ planes of
 // its BX x BY tile, holding three planes of rho and phi (with an x-y halo of
 // one node) in LDS and loading one new plane per step, so each plane is
@@ -137,9 +143,15 @@ __device__ __forceinline__ int wrap_any(int v, int n) {
 constexpr int CZ = 8;
 constexpr int CPX = BX + 2, CPY = BY + 2, CPN = CPX * CPY;
 
-__global__ __launch_bounds__(BX* BY) void k_chempot_col(GridDims g, PhysConst k, const double* __restrict__ rho,
-                                                        const double* __restrict__ phi, double* __restrict__ mux,
-                                                        double* __restrict__ mup) {
+// With PART the densities come as the three partial sums per node and the
+// inbox entries that the previous D3Q27 FP64 collision (k_collide_next3) left;
+// the kernel completes them while staging (see next3_complete) and also writes
+// the completed rho, phi of its nodes.
+template <bool PART>
+__global__ __launch_bounds__(BX* BY) void k_chempot_col(GridDims g, PhysConst k, double* __restrict__ rho,
+                                                        double* __restrict__ phi, double* __restrict__ mux,
+                                                        double* __restrict__ mup, const double* __restrict__ part,
+                                                        const double* __restrict__ inbox) {
     using Lt = Lattice<kD3Q27>;
     __shared__ double sr[3][CPN], sp[3][CPN];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -148,11 +160,20 @@ __global__ __launch_bounds__(BX* BY) void k_chempot_col(GridDims g, PhysConst k,
     const int x0 = bx * BX, y0 = by * BY, z0 = bzc * CZ;
     const int tid = threadIdx.y * BX + threadIdx.x;
     auto load_plane = [&](int slot, int z) {
-        const int64_t zo = (int64_t)wrap_any(z, g.nz) * g.ny;
+        const int zw = wrap_any(z, g.nz);
+        const int64_t zo = (int64_t)zw * g.ny;
         for (int e = tid; e < CPN; e += BX * BY) {
-            const int64_t n = (zo + wrap_any(y0 - 1 + e / CPX, g.ny)) * g.nx + wrap_any(x0 - 1 + e % CPX, g.nx);
-            sr[slot][e] = rho[n];
-            sp[slot][e] = phi[n];
+            const int gx = wrap_any(x0 - 1 + e % CPX, g.nx), gy = wrap_any(y0 - 1 + e / CPX, g.ny);
+            const int64_t n = (zo + gy) * g.nx + gx;
+            if (PART) {
+                double r, p;
+                next3_complete(g, part, inbox, gx, gy, zw, n, r, p);
+                sr[slot][e] = r;
+                sp[slot][e] = p;
+            } else {
+                sr[slot][e] = rho[n];
+                sp[slot][e] = phi[n];
+            }
         }
     };
     load_plane(0, z0 - 1);
@@ -180,6 +201,10 @@ __global__ __launch_bounds__(BX* BY) void k_chempot_col(GridDims g, PhysConst k,
             const int64_t n = ((int64_t)z * g.ny + y) * g.nx + x;
             mux[n] = mx;
             mup[n] = mp;
+            if (PART) {
+                rho[n] = r0;
+                phi[n] = p0;
+            }
         }
         __syncthreads();  // the next plane overwrites the slot just read as `below`
     }
@@ -233,50 +258,57 @@ constexpr int FBY = 8;                      // rows per workgroup of the fused s
 constexpr int FHX = BX + 4, FHY = FBY + 4;  // density tile with a halo of 2
 constexpr int FMX = BX + 2, FMY = FBY + 2;  // potential tile with a halo of 1
 
-// Inbox of a tile: sums of next-step moments that neighbouring tiles hold for
-// its edge nodes, (rho, phi) pairs.  Slots: bottom row from the tile below,
-// top row from the tile above, left and right columns from the side tiles,
-// then the four corners from the diagonal tiles (bottom-left, bottom-right,
-// top-left, top-right).
-constexpr int IB_DOWN = 0, IB_UP = BX, IB_LEFT = 2 * BX, IB_RIGHT = 2 * BX + FBY, IB_CORNER = 2 * BX + 2 * FBY;
-constexpr int INBOX = IB_CORNER + 4;
+// Inbox of a BX x TH tile: sums of next-step moments that neighbouring tiles
+// hold for its edge nodes, (rho, phi) pairs.  Slots: bottom row from the tile
+// below, top row from the tile above, left and right columns from the side
+// tiles, then the four corners from the diagonal tiles (bottom-left,
+// bottom-right, top-left, top-right).
+template <int TH>
+struct Inbox {
+    static constexpr int DOWN = 0, UP = BX, LEFT = 2 * BX, RIGHT = 2 * BX + TH, CORNER = 2 * BX + 2 * TH;
+    static constexpr int SIZE = CORNER + 4;
+};
+constexpr int INBOX = Inbox<FBY>::SIZE;  // the 2D step's tiles
 
-// Tile of a node and the node's place in it.
+// Tile (of the BX x TH tiling of an x-y plane) of a node and its place in it.
 struct TilePos {
     int tile, lx, ly, W, H;
 };
+template <int TH>
 __device__ __forceinline__ TilePos tile_pos(const GridDims& g, int gx, int gy) {
     const int bxc = (g.nx + BX - 1) / BX;
-    const int tbx = gx / BX, tby = gy / FBY;
+    const int tbx = gx / BX, tby = gy / TH;
     TilePos t;
     t.tile = tby * bxc + tbx;
     t.lx = gx - tbx * BX;
-    t.ly = gy - tby * FBY;
+    t.ly = gy - tby * TH;
     t.W = min(BX, g.nx - tbx * BX);
-    t.H = min(FBY, g.ny - tby * FBY);
+    t.H = min(TH, g.ny - tby * TH);
     return t;
 }
 
 // Add the inbox entries of node (gx, gy) to its tile's partial sums (r, p),
-// in a fixed order.
+// in a fixed order.  `in` is the inbox array of the node's plane.
+template <int TH>
 __device__ __forceinline__ void inbox_complete(const GridDims& g, const double* __restrict__ in, int gx, int gy,
                                                double& r, double& p) {
-    const TilePos t = tile_pos(g, gx, gy);
+    using I = Inbox<TH>;
+    const TilePos t = tile_pos<TH>(g, gx, gy);
     const bool x0 = t.lx == 0, x1 = t.lx == t.W - 1, y0 = t.ly == 0, y1 = t.ly == t.H - 1;
     if (!(x0 || x1 || y0 || y1)) return;
-    const double* b = in + (int64_t)t.tile * INBOX * 2;
+    const double* b = in + (int64_t)t.tile * I::SIZE * 2;
     auto add = [&](int slot) {
         r += b[2 * slot];
         p += b[2 * slot + 1];
     };
-    if (y0) add(IB_DOWN + t.lx);
-    if (y1) add(IB_UP + t.lx);
-    if (x0) add(IB_LEFT + t.ly);
-    if (x1) add(IB_RIGHT + t.ly);
-    if (x0 && y0) add(IB_CORNER + 0);
-    if (x1 && y0) add(IB_CORNER + 1);
-    if (x0 && y1) add(IB_CORNER + 2);
-    if (x1 && y1) add(IB_CORNER + 3);
+    if (y0) add(I::DOWN + t.lx);
+    if (y1) add(I::UP + t.lx);
+    if (x0) add(I::LEFT + t.ly);
+    if (x1) add(I::RIGHT + t.ly);
+    if (x0 && y0) add(I::CORNER + 0);
+    if (x1 && y0) add(I::CORNER + 1);
+    if (x0 && y1) add(I::CORNER + 2);
+    if (x1 && y1) add(I::CORNER + 3);
 }
 
 // The same completion with the entries loaded together: a node of a tile at
@@ -284,20 +316,22 @@ __device__ __forceinline__ void inbox_complete(const GridDims& g, const double* 
 // side, a horizontal side and a corner, taken in the order of inbox_complete;
 // the three loads are issued unconditionally (a missing entry reads the
 // tile's first slot and is not added).  Narrower tiles use inbox_complete.
+template <int TH>
 __device__ __forceinline__ void inbox_complete_fast(const GridDims& g, const double* __restrict__ in, int gx,
                                                     int gy, double& r, double& p) {
-    const TilePos t = tile_pos(g, gx, gy);
+    using I = Inbox<TH>;
+    const TilePos t = tile_pos<TH>(g, gx, gy);
     const bool x0 = t.lx == 0, x1 = t.lx == t.W - 1, y0 = t.ly == 0, y1 = t.ly == t.H - 1;
     if (!(x0 || x1 || y0 || y1)) return;
     if (t.W < 2 || t.H < 2) {
-        inbox_complete(g, in, gx, gy, r, p);
+        inbox_complete<TH>(g, in, gx, gy, r, p);
         return;
     }
-    const double2* b = reinterpret_cast<const double2*>(in) + (int64_t)t.tile * INBOX;
+    const double2* b = reinterpret_cast<const double2*>(in) + (int64_t)t.tile * I::SIZE;
     const bool hv = y0 || y1, hh = x0 || x1, hc = hv && hh;
-    const int sv = hv ? (y0 ? IB_DOWN : IB_UP) + t.lx : 0;
-    const int sh = hh ? (x0 ? IB_LEFT : IB_RIGHT) + t.ly : 0;
-    const int sc = hc ? IB_CORNER + (x1 ? 1 : 0) + (y1 ? 2 : 0) : 0;
+    const int sv = hv ? (y0 ? I::DOWN : I::UP) + t.lx : 0;
+    const int sh = hh ? (x0 ? I::LEFT : I::RIGHT) + t.ly : 0;
+    const int sc = hc ? I::CORNER + (x1 ? 1 : 0) + (y1 ? 2 : 0) : 0;
     const double2 v = b[sv], h = b[sh], c = b[sc];
     if (hv) {
         r += v.x;
@@ -313,21 +347,24 @@ __device__ __forceinline__ void inbox_complete_fast(const GridDims& g, const dou
     }
 }
 
-// Inbox slot (in the owning tile) that receives the ring position (ex, ey)
-// of a W x H tile at (x0, y0).  Returns the slot's index in the inbox array.
+// Inbox slot (in the owning tile of the same plane) that receives the ring
+// position (ex, ey) of a W x H tile at (x0, y0).  Returns the slot's index in
+// the plane's inbox array.
+template <int TH>
 __device__ __forceinline__ int64_t inbox_target(const GridDims& g, int x0, int y0, int W, int H, int ex, int ey) {
+    using I = Inbox<TH>;
     int tx = x0 + ex, ty = y0 + ey;
     tx += tx < 0 ? g.nx : (tx >= g.nx ? -g.nx : 0);
     ty += ty < 0 ? g.ny : (ty >= g.ny ? -g.ny : 0);
-    const TilePos t = tile_pos(g, tx, ty);
+    const TilePos t = tile_pos<TH>(g, tx, ty);
     // where the sending tile lies as seen from the receiving node
     const int dx = ex < 0 ? 1 : (ex >= W ? -1 : 0);
     const int dy = ey < 0 ? 1 : (ey >= H ? -1 : 0);
     int slot;
-    if (dx == 0) slot = (dy > 0 ? IB_UP : IB_DOWN) + t.lx;
-    else if (dy == 0) slot = (dx > 0 ? IB_RIGHT : IB_LEFT) + t.ly;
-    else slot = IB_CORNER + (dx > 0 ? 1 : 0) + (dy > 0 ? 2 : 0);
-    return (int64_t)t.tile * INBOX + slot;
+    if (dx == 0) slot = (dy > 0 ? I::UP : I::DOWN) + t.lx;
+    else if (dy == 0) slot = (dx > 0 ? I::RIGHT : I::LEFT) + t.ly;
+    else slot = I::CORNER + (dx > 0 ? 1 : 0) + (dy > 0 ? 2 : 0);
+    return (int64_t)t.tile * I::SIZE + slot;
 }
 
 struct LdsAux2 {
@@ -347,61 +384,93 @@ struct LdsAux2 {
     }
 };
 
-// Index of the D2Q9 direction (cx, cy), and the row offset of group ky
-// (0, +1, -1 for ky = 0, 1, 2).
-__host__ __device__ constexpr int d2q9_dir(int cx, int cy) {
-    for (int i = 0; i < 9; ++i)
-        if (Lattice<kD2Q9>::c[i][0] == cx && Lattice<kD2Q9>::c[i][1] == cy) return i;
+// Index of the lattice direction (cx, cy, cz), and the offset of D1Q3 index k
+// (0, +1, -1 for k = 0, 1, 2).
+template <int L>
+__host__ __device__ constexpr int lat_dir(int cx, int cy, int cz) {
+    for (int i = 0; i < Lattice<L>::Q; ++i)
+        if (Lattice<L>::c[i][0] == cx && Lattice<L>::c[i][1] == cy && Lattice<L>::c[i][2] == cz) return i;
     return -1;
 }
 __host__ __device__ constexpr int row_offset(int ky) { return ky == 0 ? 0 : (ky == 1 ? 1 : -1); }
-static_assert(d2q9_dir(0, 0) >= 0 && d2q9_dir(1, 0) >= 0 && d2q9_dir(-1, 0) >= 0 && d2q9_dir(0, 1) >= 0 &&
-                  d2q9_dir(1, 1) >= 0 && d2q9_dir(-1, 1) >= 0 && d2q9_dir(0, -1) >= 0 && d2q9_dir(1, -1) >= 0 &&
-                  d2q9_dir(-1, -1) >= 0,
-              "every D2Q9 direction present");
+template <int L>
+__host__ __device__ constexpr bool all_dirs_present() {
+    for (int kz = 0; kz < (Lattice<L>::D == 3 ? 3 : 1); ++kz)
+        for (int ky = 0; ky < 3; ++ky)
+            for (int kx = 0; kx < 3; ++kx)
+                if (lat_dir<L>(row_offset(kx), row_offset(ky), row_offset(kz)) < 0) return false;
+    return true;
+}
+static_assert(all_dirs_present<kD2Q9>() && all_dirs_present<kD3Q27>(), "every lattice direction present");
 
-// Per-row partial sums of the next moments.  For row offset c_y (group ky,
-// c_y = row_offset(ky)) the node at lane l leaves
-//   S_ky(l) = v(0, c_y)(l) + v(+1, c_y)(l - 1) + v(-1, c_y)(l + 1)
-// (terms from lanes of the tile only) in sum[field][ky][ly][l], and the
-// values that leave the tile sideways, v(-1, c_y) of lane 0 and v(+1, c_y) of
-// the last lane, in side[field][0 / 1][ky][ly].
+// Per-row partial sums of the next moments in a BX x TH tile.  Group
+// gi = ky + 3 kz holds the directions with c_y = row_offset(ky), c_z =
+// row_offset(kz) (D2Q9: kz = 0 only).  For group gi the node at lane l leaves
+//   S_gi(l) = v(0, c_y, c_z)(l) + v(+1, c_y, c_z)(l - 1) + v(-1, c_y, c_z)(l + 1)
+// (terms from lanes of the tile only) in sum[field][gi][ly][l], and the
+// values that leave the tile sideways, v(-1, .) of lane 0 and v(+1, .) of the
+// last lane, in side[field][0 / 1][gi][ly].
+template <int L, int TH>
 struct NextSink {
-    double* sum;   // [2][3][FBY][BX]
-    double* side;  // [2][2][3][FBY]
+    static constexpr int NG = Lattice<L>::D == 3 ? 9 : 3;
+    static constexpr int SUM = 2 * NG * TH * BX, SIDE = 2 * 2 * NG * TH;
+    double* sum;
+    double* side;
     int lx, ly, W;
     __device__ __forceinline__ void put(int field, const double* v) {
 #pragma unroll
-        for (int ky = 0; ky < 3; ++ky) {
-            const int cy = row_offset(ky);
-            const double a = v[d2q9_dir(0, cy)], b = v[d2q9_dir(1, cy)], c = v[d2q9_dir(-1, cy)];
+        for (int gi = 0; gi < NG; ++gi) {
+            const int cy = row_offset(gi % 3), cz = row_offset(gi / 3);
+            const double a = v[lat_dir<L>(0, cy, cz)], b = v[lat_dir<L>(1, cy, cz)], c = v[lat_dir<L>(-1, cy, cz)];
             const double bl = __shfl_up(b, 1);
             const double cr = __shfl_down(c, 1);
             double t = a;
             if (lx >= 1) t += bl;
             if (lx + 1 < W) t += cr;
-            sum[((field * 3 + ky) * FBY + ly) * BX + lx] = t;
-            if (lx == 0) side[((field * 2 + 0) * 3 + ky) * FBY + ly] = c;
-            if (lx == W - 1) side[((field * 2 + 1) * 3 + ky) * FBY + ly] = b;
+            sum[((field * NG + gi) * TH + ly) * BX + lx] = t;
+            if (lx == 0) side[((field * 2 + 0) * NG + gi) * TH + ly] = c;
+            if (lx == W - 1) side[((field * 2 + 1) * NG + gi) * TH + ly] = b;
         }
     }
-    template <int L, typename R>
+    template <int L2, typename R>
     __device__ __forceinline__ void post_f(const R* f, double r) {
         using Lt = Lattice<L>;
-        double v[9];
+        double v[Lt::Q];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
+        for (int i = 0; i < Lt::Q; ++i) {
             v[i] = double(f[i]);
             if (Deviation<R>::on) v[i] += Lt::w[i] * r;
         }
         put(0, v);
     }
-    template <int L, typename R>
+    template <int L2, typename R>
     __device__ __forceinline__ void post_g(const R* gg) {
-        double v[9];
+        double v[Lattice<L>::Q];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) v[i] = double(gg[i]);
+        for (int i = 0; i < Lattice<L>::Q; ++i) v[i] = double(gg[i]);
         put(1, v);
+    }
+    // sum over the tile's sources for target (ex, ey) of the ring-extended
+    // tile, in the target plane offset by c_z = row_offset(kz)
+    __device__ __forceinline__ void gather(int ex, int ey, int kz, int H, double& s0, double& s1) const {
+        s0 = 0.0;
+        s1 = 0.0;
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+            const int gi = ky + 3 * kz;
+            const int sy = ey - row_offset(ky);
+            if (sy < 0 || sy >= H) continue;
+            if (ex < 0) {
+                s0 += side[((0 * 2 + 0) * NG + gi) * TH + sy];
+                s1 += side[((1 * 2 + 0) * NG + gi) * TH + sy];
+            } else if (ex >= W) {
+                s0 += side[((0 * 2 + 1) * NG + gi) * TH + sy];
+                s1 += side[((1 * 2 + 1) * NG + gi) * TH + sy];
+            } else {
+                s0 += sum[((0 * NG + gi) * TH + sy) * BX + ex];
+                s1 += sum[((1 * NG + gi) * TH + sy) * BX + ex];
+            }
+        }
     }
 };
 
@@ -418,7 +487,8 @@ __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysCons
                                                            double* __restrict__ partials, int diag) {
     using Lt = Lattice<kD2Q9>;
     __shared__ double sr[FHX * FHY], sp[FHX * FHY], smx[FMX * FMY], smp[FMX * FMY];
-    __shared__ double nsum[2 * 3 * FBY * BX], nside[2 * 2 * 3 * FBY];
+    using Sink = NextSink<kD2Q9, FBY>;
+    __shared__ double nsum[Sink::SUM], nside[Sink::SIDE];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int bxc = (g.nx + BX - 1) / BX;
     const int bx = b % bxc, by = b / bxc;
@@ -432,7 +502,7 @@ __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysCons
         const int gx = wrap_any(x0 - 2 + hx, g.nx), gy = wrap_any(y0 - 2 + hy, g.ny);
         const int64_t n = (int64_t)gy * g.nx + gx;
         double r = rho[n], p = phi[n];
-        if (inbox_in) inbox_complete_fast(g, inbox_in, gx, gy, r, p);
+        if (inbox_in) inbox_complete_fast<FBY>(g, inbox_in, gx, gy, r, p);
         sr[e] = r;
         sp[e] = p;
     }
@@ -461,7 +531,7 @@ __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysCons
         const bool active = (int)threadIdx.x < W && (int)threadIdx.y < H;
         const LdsAux2 aux{sr, sp, smx, smp, lx, ly};
         if (rho_final && active) rho_final[(int64_t)(y0 + ly) * g.nx + x0 + lx] = aux.rho0(0);
-        NextSink sink{nsum, nside, (int)threadIdx.x, (int)threadIdx.y, W};
+        Sink sink{nsum, nside, (int)threadIdx.x, (int)threadIdx.y, W};
         node_collide_sink<kD2Q9, T>(g, k, src, dst, rho_ref, aux, x0 + lx, y0 + ly, 0, diag != 0, dv, active,
                                     sink);
     }
@@ -471,28 +541,15 @@ __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysCons
     for (int e = tid; e < (BX + 2) * (FBY + 2); e += BX * FBY) {
         const int ex = e % (BX + 2) - 1, ey = e / (BX + 2) - 1;
         if (ex > W || ey > H) continue;
-        double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-        for (int ky = 0; ky < 3; ++ky) {
-            const int sy = ey - row_offset(ky);
-            if (sy < 0 || sy >= H) continue;
-            if (ex < 0) {
-                s0 += nside[((0 * 2 + 0) * 3 + ky) * FBY + sy];
-                s1 += nside[((1 * 2 + 0) * 3 + ky) * FBY + sy];
-            } else if (ex >= W) {
-                s0 += nside[((0 * 2 + 1) * 3 + ky) * FBY + sy];
-                s1 += nside[((1 * 2 + 1) * 3 + ky) * FBY + sy];
-            } else {
-                s0 += nsum[((0 * 3 + ky) * FBY + sy) * BX + ex];
-                s1 += nsum[((1 * 3 + ky) * FBY + sy) * BX + ex];
-            }
-        }
+        double s0, s1;
+        const Sink view{nsum, nside, 0, 0, W};
+        view.gather(ex, ey, 0, H, s0, s1);
         if (ex >= 0 && ex < W && ey >= 0 && ey < H) {
             const int64_t n = (int64_t)(y0 + ey) * g.nx + x0 + ex;
             rho_next[n] = s0;
             phi_next[n] = s1;
         } else {
-            const int64_t q = 2 * inbox_target(g, x0, y0, W, H, ex, ey);
+            const int64_t q = 2 * inbox_target<FBY>(g, x0, y0, W, H, ex, ey);
             inbox_out[q] = s0;
             inbox_out[q + 1] = s1;
         }
@@ -531,9 +588,90 @@ __global__ __launch_bounds__(FIX_THREADS) void k_dens_complete2(GridDims g, doub
     }
     const int64_t n = (int64_t)(y0 + ly) * g.nx + x0 + lx;
     double r = rho[n], p = phi[n];
-    inbox_complete(g, inbox, x0 + lx, y0 + ly, r, p);
+    inbox_complete<FBY>(g, inbox, x0 + lx, y0 + ly, r, p);
     rho[n] = r;
     phi[n] = p;
+}
+
+// ---------------------------------------------------------------------------
+// D3Q27 FP64 collision that also leaves the next step's moments.  The block
+// (a BX x BY tile of one z plane) runs the collision of its nodes and sums its
+// post-collision values for the nodes they stream to: with the lane shuffles
+// of NextSink over the nine (c_y, c_z) groups, then per target plane z + c_z
+// for the tile and its one-node ring.  A node's moments are thus split over
+// three partial sums, one per source plane (part[k][n], k = c_z + 1, (rho,
+// phi) pairs), plus, for nodes on a tile edge, inbox entries from the
+// neighbouring tiles of each source plane (inbox[(z * 3 + k) * tiles + tile]).
+// The chemical-potential pass completes them while it stages the densities
+// (k_chempot_col<true>), so the moment pass over all populations is not run.
+// ---------------------------------------------------------------------------
+constexpr int INBOX3 = Inbox<BY>::SIZE;
+
+__device__ __forceinline__ void next3_complete(const GridDims& g, const double* __restrict__ part,
+                                               const double* __restrict__ inbox, int gx, int gy, int z, int64_t n,
+                                               double& r, double& p) {
+    const double2* P = reinterpret_cast<const double2*>(part);
+    const double2 a = P[n], b = P[g.N + n], c = P[2 * g.N + n];
+    r = a.x + b.x + c.x;
+    p = a.y + b.y + c.y;
+    const int64_t tiles = (int64_t)((g.nx + BX - 1) / BX) * ((g.ny + BY - 1) / BY);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        inbox_complete_fast<BY>(g, inbox + ((int64_t)z * 3 + k) * tiles * INBOX3 * 2, gx, gy, r, p);
+}
+
+__global__ __launch_bounds__(BX* BY) void k_collide_next3(GridDims g, PhysConst k, const double* __restrict__ src,
+                                                          double* __restrict__ dst, const double* __restrict__ rho,
+                                                          const double* __restrict__ phi,
+                                                          const double* __restrict__ mux,
+                                                          const double* __restrict__ mup, double* __restrict__ part,
+                                                          double* __restrict__ inbox, double* __restrict__ partials,
+                                                          int diag) {
+    using Sink = NextSink<kD3Q27, BY>;
+    __shared__ double nsum[Sink::SUM], nside[Sink::SIDE];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + BY - 1) / BY;
+    const int bx = b % bxc, rest = b / bxc, by = rest % byc, bz = rest / byc;
+    const int x0 = bx * BX, y0 = by * BY;
+    const int W = min(BX, g.nx - x0), H = min(BY, g.ny - y0);
+    const int tid = threadIdx.y * BX + threadIdx.x;
+    double dv[kDiag] = {0, 0, 0, 0, 0, 0, INFINITY, INFINITY, -INFINITY, 0};
+    {
+        // every lane runs a collision (lanes past a ragged edge on the tile's
+        // last node, without stores) so that the sink's shuffles see whole rows
+        const int lx = min((int)threadIdx.x, W - 1), ly = min((int)threadIdx.y, H - 1);
+        const bool active = (int)threadIdx.x < W && (int)threadIdx.y < H;
+        const GlobalAux aux{rho, phi, mux, mup};
+        Sink sink{nsum, nside, (int)threadIdx.x, (int)threadIdx.y, W};
+        node_collide_sink<kD3Q27, double>(g, k, src, dst, nullptr, aux, x0 + lx, y0 + ly, bz, diag != 0, dv, active,
+                                          sink);
+    }
+    if (diag) diag_block_reduce(dv, partials);
+    __syncthreads();
+    const int64_t tiles = (int64_t)bxc * byc;
+    const int tile = by * bxc + bx;
+    (void)tile;
+    constexpr int EXT = (BX + 2) * (BY + 2);
+    const Sink view{nsum, nside, 0, 0, W};
+    double2* P = reinterpret_cast<double2*>(part);
+    double2* I = reinterpret_cast<double2*>(inbox);
+    for (int e = tid; e < 3 * EXT; e += BX * BY) {
+        const int kz = e / EXT, rem = e % EXT;
+        const int ex = rem % (BX + 2) - 1, ey = rem / (BX + 2) - 1;
+        if (ex > W || ey > H) continue;
+        double s0, s1;
+        view.gather(ex, ey, kz, H, s0, s1);
+        const int dz = row_offset(kz);
+        int zt = bz + dz;
+        zt += zt < 0 ? g.nz : (zt >= g.nz ? -g.nz : 0);
+        const int kk = dz + 1;
+        if (ex >= 0 && ex < W && ey >= 0 && ey < H) {
+            P[kk * g.N + ((int64_t)zt * g.ny + y0 + ey) * g.nx + x0 + ex] = make_double2(s0, s1);
+        } else {
+            I[((int64_t)zt * 3 + kk) * tiles * INBOX3 + inbox_target<BY>(g, x0, y0, W, H, ex, ey)] =
+                make_double2(s0, s1);
+        }
+    }
 }
 
 // Deterministic second pass over the block partials (one workgroup).
@@ -682,6 +820,14 @@ unsigned fused_tiles(const GridDims& g) { return (unsigned)(((g.nx + BX - 1) / B
 
 size_t inbox_doubles(const GridDims& g) { return (size_t)fused_tiles(g) * INBOX * 2; }
 
+size_t inbox3_doubles(const GridDims& g) {
+    return (size_t)g.nz * 3 * ((g.nx + BX - 1) / BX) * ((g.ny + BY - 1) / BY) * INBOX3 * 2;
+}
+
+static inline unsigned col_blocks(const GridDims& g) {
+    return (unsigned)(((g.nx + BX - 1) / BX) * ((g.ny + BY - 1) / BY) * ((g.nz + CZ - 1) / CZ));
+}
+
 template <int L, typename T>
 static hipError_t launch_step_parts(const StepArgs& a, int part) {
     const dim3 blk(BX, BY, 1);
@@ -690,8 +836,8 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
         k_moments<L, T><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
     } else if (part == 1) {
         if (L == kD3Q27) {
-            const unsigned cb = (unsigned)(((a.g.nx + BX - 1) / BX) * ((a.g.ny + BY - 1) / BY) * ((a.g.nz + CZ - 1) / CZ));
-            k_chempot_col<<<cb, blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup);
+            k_chempot_col<false><<<col_blocks(a.g), blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup, nullptr,
+                                                                        nullptr);
         } else {
             k_chempot<L><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup);
         }
@@ -707,6 +853,15 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
             a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref, a.rho, a.phi, a.inbox_in, a.rho_next, a.phi_next,
             a.inbox_out, a.rho_final, a.partials, a.diag);
         if (a.diag) k_diag_final<<<1, 256, 0, a.stream>>>(a.partials, (int)fb, a.diag_out);
+    } else if (part == 5) {
+        if (L != kD3Q27 || !a.part3 || !a.inbox3) return hipErrorInvalidValue;
+        k_chempot_col<true><<<col_blocks(a.g), blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup, a.part3,
+                                                                   a.inbox3);
+    } else if (part == 6) {
+        if (L != kD3Q27 || Deviation<T>::on || !a.part3 || !a.inbox3) return hipErrorInvalidValue;
+        k_collide_next3<<<grd, blk, 0, a.stream>>>(a.g, a.k, (const double*)a.src, (double*)a.dst, a.rho, a.phi,
+                                                   a.mux, a.mup, a.part3, a.inbox3, a.partials, a.diag);
+        if (a.diag) k_diag_final<<<1, 256, 0, a.stream>>>(a.partials, (int)grd.x, a.diag_out);
     } else if (part == 4) {
         if (L != kD2Q9 || a.g.nz != 1 || !a.inbox_in) return hipErrorInvalidValue;
         k_dens_complete2<<<fused_tiles(a.g), FIX_THREADS, 0, a.stream>>>(a.g, a.rho, a.phi, a.inbox_in);

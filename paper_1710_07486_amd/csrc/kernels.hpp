@@ -35,6 +35,10 @@ struct StepArgs {
     // Part 4 completes rho / phi in place from inbox_in.
     const double* inbox_in;
     double *rho_next, *phi_next, *inbox_out, *rho_final;
+    // D3Q27 FP64: next-step moments as three partial sums per node (3 N
+    // (rho, phi) pairs) and their inbox entries (part 6 writes, part 5
+    // completes them while computing the chemical potentials)
+    double *part3, *inbox3;
     double* partials;    // per-block diagnostic partials
     double* diag_out;    // final diagnostics (kDiag doubles)
     int diag;
@@ -44,10 +48,13 @@ struct StepArgs {
 unsigned collide_blocks(const GridDims& g);
 unsigned fused_tiles(const GridDims& g);        // D2Q9 tiles of the fused step
 size_t inbox_doubles(const GridDims& g);        // size of one inbox array
+size_t inbox3_doubles(const GridDims& g);       // size of StepArgs::inbox3
 
 // part 0: moments, 1: chemical potentials, 2: collision (+ diagnostics);
 // D2Q9 only: 3: fused potentials + collision + tile sums of the next moments,
-// 4: completion of partial moments at the tile edges
+// 4: completion of partial moments at the tile edges; D3Q27 only: 5: chemical
+// potentials completing the partial moments, 6: FP64 collision + partial
+// sums of the next moments
 hipError_t launch_part(int lattice, int precision, const StepArgs& a, int part);
 hipError_t launch_init(int lattice, int precision, const StepArgs& a, const double* u0);
 hipError_t launch_check_init(const GridDims& g, int D, const double* rho, const double* phi, const double* u0,
