@@ -1,0 +1,123 @@
+"""GPU runs checked against what the model fixes in closed form.
+
+Laplace's law: a relaxed 2D drop of radius R has a bulk pressure jump
+dp = gamma / R, with the bulk pressure p = rho mu_rho + phi mu_phi - f_B of
+the free energy (Eqs. 2-3 and the chemical potentials defined after Eq. 7).
+The jump is taken between the drop centre and the far field, less the jump a
+relaxed flat interface of the same pair of phases shows on the lattice.
+
+Liquid-liquid tension: with lambda_2 / kappa_2 = lambda_3 / kappa_3 a flat
+interface between the two liquids keeps rho = rho_l and a tanh phase-field
+profile, whose excess free energy is sqrt((lambda_2 + lambda_3)(kappa_2 +
+kappa_3)) / 6 (the phi double well of Eq. 2 with the gradient coefficient of
+the f_I rewrite).  The measured tension must match it to the lattice's
+discretisation error.
+
+The liquid-gas tension has no closed form; for it only the 1/R scaling is
+checked.  The oracle serves the bulk pressure (a function of the node's rho
+and phi only).
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+RATIO = 10.0
+KAPPA = 0.3          # kappa_2 = kappa_3
+LAM = 0.3            # lambda_2 = lambda_3 (lambda / kappa = 1: interface ~2 nodes wide)
+CHI = 5.0
+N = 160
+RADII = (20.0, 28.0, 38.0)
+STEPS = 25000
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _setup(orc):
+    import paper_1710_07486_amd as T
+    from paper_1710_07486_amd.calibrate import discrete_coexistence
+    po = orc.coexisting_params(RATIO, lattice=0, nx=4, ny=4, nz=1, kappa2=KAPPA, kappa3=KAPPA, lambda2=LAM,
+                               lambda3=LAM, chi=CHI)
+
+    def params(nx, ny):
+        return T.Params(lattice=0, nx=nx, ny=ny, nz=1, T=po.T, kappa2=KAPPA, kappa3=KAPPA, lambda2=LAM,
+                        lambda3=LAM, chi=CHI)
+
+    rg, rl = discrete_coexistence(params(256, 256))
+    return T, po, params, rg, rl
+
+
+def _run(T, p, rho, phi, steps):
+    with T.Solver(p) as s:
+        s.init_fields(rho, phi)
+        s.step(steps)
+        return s.read("rho")[0], s.read("phi")[0]
+
+
+def _fields(kind, c, rg, rl):
+    """Drop (c = 1 inside) of liquid 1 in liquid 2 ("12") or in gas ("1g")."""
+    if kind == "12":
+        return np.full(c.shape, rl), CHI * (2.0 * c - 1.0)
+    return rg + (rl - rg) * c, CHI * c
+
+
+def _jump(orc, po, r, f, c0):
+    inner = orc.bulk_pressure(po, r[c0 - 1:c0 + 2, c0 - 1:c0 + 2].mean(), f[c0 - 1:c0 + 2, c0 - 1:c0 + 2].mean())
+    outer = orc.bulk_pressure(po, r[0:3, 0:3].mean(), f[0:3, 0:3].mean())
+    return inner - outer
+
+
+def _flat_offset(orc, T, po, params, kind, rg, rl, n=256, steps=30000):
+    x = np.arange(n, dtype=float)
+    c = 0.5 * (np.tanh((x - n / 4) / 3.0) - np.tanh((x - 3 * n / 4) / 3.0))
+    rho, phi = _fields(kind, c, rg, rl)
+    r, f = _run(T, params(n, 1), rho.reshape(1, 1, n), phi.reshape(1, 1, n), steps)
+    r, f = r.ravel(), f.ravel()
+    return orc.bulk_pressure(po, r[n // 2], f[n // 2]) - orc.bulk_pressure(po, r[0], f[0])
+
+
+def _laplace(orc, T, po, params, kind, rg, rl, offset):
+    yy, xx = np.mgrid[0:N, 0:N]
+    rr = np.sqrt((xx - N / 2) ** 2 + (yy - N / 2) ** 2)
+    dps, rads = [], []
+    for R in RADII:
+        say(kind, "drop R", R, f"{N}^2", STEPS, "steps")
+        c = 0.5 * (1.0 - np.tanh((rr - R) / 2.0))
+        rho, phi = _fields(kind, c, rg, rl)
+        r, f = _run(T, params(N, N), rho[None], phi[None], STEPS)
+        dps.append(_jump(orc, po, r, f, N // 2) - offset)
+        if kind == "12":
+            ind = (f / CHI + 1.0) / 2.0
+        else:
+            ind = (r - r[0:3, 0:3].mean()) / (r[N // 2, N // 2] - r[0:3, 0:3].mean())
+        rads.append(math.sqrt(ind.sum() / math.pi))
+    dps, rads = np.array(dps), np.array(rads)
+    x = 1.0 / rads
+    gamma = float(np.sum(dps * x) / np.sum(x * x))
+    pr = dps * rads
+    spread = float((pr.max() - pr.min()) / pr.mean())
+    return gamma, spread, pr
+
+
+def test_liquid_liquid_laplace_and_closed_form_tension(orc):
+    T, po, params, rg, rl = _setup(orc)
+    # equal kappa: the flat liquid-liquid interface is symmetric under phi -> -phi,
+    # its pressure jump vanishes identically
+    gamma, spread, pr = _laplace(orc, T, po, params, "12", rg, rl, 0.0)
+    closed = math.sqrt((2 * LAM) * (2 * KAPPA)) / 6.0
+    print(f"liquid-liquid: dp*R {np.round(pr, 5)}; tension {gamma:.5f} vs closed form {closed:.5f}", flush=True)
+    assert spread < 0.03, spread
+    assert abs(gamma - closed) < 0.03 * closed, (gamma, closed)
+
+
+def test_liquid_gas_laplace_scaling(orc):
+    T, po, params, rg, rl = _setup(orc)
+    offset = _flat_offset(orc, T, po, params, "1g", rg, rl)
+    gamma, spread, pr = _laplace(orc, T, po, params, "1g", rg, rl, offset)
+    print(f"liquid-gas: flat offset {offset:.3e}; dp*R {np.round(pr, 5)}; tension {gamma:.5f}", flush=True)
+    assert gamma > 0.0
+    assert spread < 0.03, spread
