@@ -649,28 +649,44 @@ __global__ __launch_bounds__(BX* BY) void k_collide_next3(GridDims g, PhysConst 
     if (diag) diag_block_reduce(dv, partials);
     __syncthreads();
     const int64_t tiles = (int64_t)bxc * byc;
-    const int tile = by * bxc + bx;
-    (void)tile;
-    constexpr int EXT = (BX + 2) * (BY + 2);
     const Sink view{nsum, nside, 0, 0, W};
     double2* P = reinterpret_cast<double2*>(part);
     double2* I = reinterpret_cast<double2*>(inbox);
-    for (int e = tid; e < 3 * EXT; e += BX * BY) {
-        const int kz = e / EXT, rem = e % EXT;
-        const int ex = rem % (BX + 2) - 1, ey = rem / (BX + 2) - 1;
-        if (ex > W || ey > H) continue;
+    // tile nodes: each thread gathers its own node's three target planes
+    if ((int)threadIdx.x < W && (int)threadIdx.y < H) {
+#pragma unroll
+        for (int kz = 0; kz < 3; ++kz) {
+            double s0, s1;
+            view.gather(threadIdx.x, threadIdx.y, kz, H, s0, s1);
+            const int dz = row_offset(kz);
+            int zt = bz + dz;
+            zt += zt < 0 ? g.nz : (zt >= g.nz ? -g.nz : 0);
+            P[(dz + 1) * g.N + ((int64_t)zt * g.ny + y0 + threadIdx.y) * g.nx + x0 + threadIdx.x] =
+                make_double2(s0, s1);
+        }
+    }
+    // ring nodes: the rows below and above the tile, then the side columns
+    constexpr int RING3 = 2 * (BX + 2) + 2 * BY;
+    for (int e = tid; e < 3 * RING3; e += BX * BY) {
+        const int kz = e / RING3, q = e % RING3;
+        int ex, ey;
+        if (q < 2 * (BX + 2)) {
+            ex = q % (BX + 2) - 1;
+            ey = q < BX + 2 ? -1 : H;
+            if (ex > W) continue;
+        } else {
+            const int c = q - 2 * (BX + 2);
+            ex = c < BY ? -1 : W;
+            ey = c % BY;
+            if (ey >= H) continue;
+        }
         double s0, s1;
         view.gather(ex, ey, kz, H, s0, s1);
         const int dz = row_offset(kz);
         int zt = bz + dz;
         zt += zt < 0 ? g.nz : (zt >= g.nz ? -g.nz : 0);
-        const int kk = dz + 1;
-        if (ex >= 0 && ex < W && ey >= 0 && ey < H) {
-            P[kk * g.N + ((int64_t)zt * g.ny + y0 + ey) * g.nx + x0 + ex] = make_double2(s0, s1);
-        } else {
-            I[((int64_t)zt * 3 + kk) * tiles * INBOX3 + inbox_target<BY>(g, x0, y0, W, H, ex, ey)] =
-                make_double2(s0, s1);
-        }
+        I[((int64_t)zt * 3 + dz + 1) * tiles * INBOX3 + inbox_target<BY>(g, x0, y0, W, H, ex, ey)] =
+            make_double2(s0, s1);
     }
 }
 
