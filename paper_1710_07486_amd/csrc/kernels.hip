@@ -537,22 +537,33 @@ __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysCons
     }
     if (diag) diag_block_reduce<BX * FBY>(dv, partials);
     __syncthreads();
-    // next moments of the tile and its ring, from the sources in the tile
-    for (int e = tid; e < (BX + 2) * (FBY + 2); e += BX * FBY) {
-        const int ex = e % (BX + 2) - 1, ey = e / (BX + 2) - 1;
-        if (ex > W || ey > H) continue;
+    // next moments of the tile (each thread its own node) and of its ring
+    const Sink view{nsum, nside, 0, 0, W};
+    if ((int)threadIdx.x < W && (int)threadIdx.y < H) {
         double s0, s1;
-        const Sink view{nsum, nside, 0, 0, W};
-        view.gather(ex, ey, 0, H, s0, s1);
-        if (ex >= 0 && ex < W && ey >= 0 && ey < H) {
-            const int64_t n = (int64_t)(y0 + ey) * g.nx + x0 + ex;
-            rho_next[n] = s0;
-            phi_next[n] = s1;
+        view.gather(threadIdx.x, threadIdx.y, 0, H, s0, s1);
+        const int64_t n = (int64_t)(y0 + threadIdx.y) * g.nx + x0 + threadIdx.x;
+        rho_next[n] = s0;
+        phi_next[n] = s1;
+    }
+    constexpr int RING2 = 2 * (BX + 2) + 2 * FBY;
+    for (int q = tid; q < RING2; q += BX * FBY) {
+        int ex, ey;
+        if (q < 2 * (BX + 2)) {
+            ex = q % (BX + 2) - 1;
+            ey = q < BX + 2 ? -1 : H;
+            if (ex > W) continue;
         } else {
-            const int64_t q = 2 * inbox_target<FBY>(g, x0, y0, W, H, ex, ey);
-            inbox_out[q] = s0;
-            inbox_out[q + 1] = s1;
+            const int c = q - 2 * (BX + 2);
+            ex = c < FBY ? -1 : W;
+            ey = c % FBY;
+            if (ey >= H) continue;
         }
+        double s0, s1;
+        view.gather(ex, ey, 0, H, s0, s1);
+        const int64_t q2 = 2 * inbox_target<FBY>(g, x0, y0, W, H, ex, ey);
+        inbox_out[q2] = s0;
+        inbox_out[q2 + 1] = s1;
     }
 }
 
