@@ -50,13 +50,14 @@ __device__ __forceinline__ int wrapn(int v, int n) {
 // (mask[p][co] > 0) (derivative of the ReLU that produced the layer input).
 // The weights are staged once per workgroup in LDS; each wavefront computes
 // four M tiles (64 pixels) x all COUT channels, so each B fragment read from
-// LDS feeds four matrix instructions, and persistent workgroups walk 256-pixel
-// chunks so the weights are fetched from L2 once per workgroup.  LDS rows are
+// LDS feeds four matrix instructions, and persistent workgroups of eight
+// wavefronts walk 512-pixel chunks so the weights are fetched from L2 once per
+// workgroup and shared by twice the wavefronts of a 256-thread workgroup.  LDS rows are
 // padded by 16 bytes so the 16 rows a fragment read touches fall in different
 // banks.
 // ---------------------------------------------------------------------------
 template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_conv_lds(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wp,
+__global__ __launch_bounds__(512) void k_conv_lds(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wp,
                                                   const float* __restrict__ bias, const uint16_t* __restrict__ mask,
                                                   uint16_t* __restrict__ out_bf, float* __restrict__ out_f32, int N,
                                                   int H, int W, int sgn, int dil, int relu) {
@@ -64,7 +65,7 @@ __global__ __launch_bounds__(256) void k_conv_lds(const uint16_t* __restrict__ i
     constexpr int KW = 9 * CIN;    // K extent of a weight row
     constexpr int ROW = KW + 8;    // padded LDS row, bf16 elements
     __shared__ __align__(16) uint16_t wl[COUT * ROW];
-    for (int e = threadIdx.x; e < COUT * (KW / 8); e += 256) {
+    for (int e = threadIdx.x; e < COUT * (KW / 8); e += 512) {
         const int r = e / (KW / 8), c8 = e % (KW / 8);
         *(uint4*)(wl + r * ROW + c8 * 8) = *(const uint4*)(wp + (int64_t)r * KW + c8 * 8);
     }
@@ -72,8 +73,8 @@ __global__ __launch_bounds__(256) void k_conv_lds(const uint16_t* __restrict__ i
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r16 = lane & 15, kg = lane >> 4;
     const int64_t P = (int64_t)N * H * W;
-    for (int64_t chunk = blockIdx.x; chunk * 256 < P; chunk += gridDim.x) {
-        const int64_t p0 = chunk * 256 + (int64_t)wv * 64;
+    for (int64_t chunk = blockIdx.x; chunk * 512 < P; chunk += gridDim.x) {
+        const int64_t p0 = chunk * 512 + (int64_t)wv * 64;
         if (p0 >= P) continue;
         int hh[MT], ww[MT], nn[MT];
 #pragma unroll
@@ -90,6 +91,7 @@ __global__ __launch_bounds__(256) void k_conv_lds(const uint16_t* __restrict__ i
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int dh = sgn * dil * (tap / 3 - 1), dw = sgn * dil * (tap % 3 - 1);
             int64_t src[MT];
@@ -447,10 +449,10 @@ static hipError_t conv_t(const uint16_t* in, const uint16_t* wp, const float* bi
                          uint16_t* out_bf, float* out_f32, int N, int H, int W, int sgn, int dil, int relu,
                          hipStream_t st) {
     const int64_t P = (int64_t)N * H * W;
-    const int64_t chunks = (P + 255) / 256;
+    const int64_t chunks = (P + 511) / 512;
     // persistent: two workgroups per CU (the weight stage is at most 75 KB)
     const unsigned blocks = (unsigned)(chunks < 512 ? chunks : 512);
-    k_conv_lds<CIN, COUT><<<blocks, 256, 0, st>>>(in, wp, bias, mask, out_bf, out_f32, N, H, W, sgn, dil, relu);
+    k_conv_lds<CIN, COUT><<<blocks, 512, 0, st>>>(in, wp, bias, mask, out_bf, out_f32, N, H, W, sgn, dil, relu);
     return hipGetLastError();
 }
 
