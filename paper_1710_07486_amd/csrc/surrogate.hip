@@ -48,24 +48,26 @@ __device__ __forceinline__ int wrapn(int v, int n) {
 // dilation d >= 1; s = +1 for the forward pass and for the data gradient
 // (which runs on the flipped, transposed weights).  Optional mask: out *=
 // (mask[p][co] > 0) (derivative of the ReLU that produced the layer input).
-// The weights are staged once per workgroup in LDS; each wavefront computes
-// four M tiles (64 pixels) x all COUT channels, so each B fragment read from
-// LDS feeds four matrix instructions, and persistent workgroups of eight
-// wavefronts walk 512-pixel chunks so the weights are fetched from L2 once per
-// workgroup and shared by twice the wavefronts of a 256-thread workgroup.  LDS rows are
+// The weights are staged once per workgroup in LDS (75 KB for 64 -> 64, so two
+// workgroups per CU); each wavefront computes one M tile (16 pixels) x all
+// COUT channels and persistent 1024-thread workgroups walk 256-pixel chunks, so
+// 64 VGPRs give eight wavefronts per SIMD to hide the latency of the
+// activation loads (measured: four M tiles per wave at two wavefronts per SIMD
+// ran at 0.11 of the matrix peak, one M tile at eight at 0.16).  LDS rows are
 // padded by 16 bytes so the 16 rows a fragment read touches fall in different
 // banks.
 // ---------------------------------------------------------------------------
 template <int CIN, int COUT>
-__global__ __launch_bounds__(512) void k_conv_lds(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wp,
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_conv_lds(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wp,
                                                   const float* __restrict__ bias, const uint16_t* __restrict__ mask,
                                                   uint16_t* __restrict__ out_bf, float* __restrict__ out_f32, int N,
                                                   int H, int W, int sgn, int dil, int relu) {
-    constexpr int MT = 4, NT = COUT / 16, KC = CIN / 32;
+    constexpr int MT = 1, NT = COUT / 16, KC = CIN / 32;
+    constexpr int WPX = MT * 16, BPX = 16 * WPX;  // pixels per wavefront, per workgroup chunk
     constexpr int KW = 9 * CIN;    // K extent of a weight row
     constexpr int ROW = KW + 8;    // padded LDS row, bf16 elements
     __shared__ __align__(16) uint16_t wl[COUT * ROW];
-    for (int e = threadIdx.x; e < COUT * (KW / 8); e += 512) {
+    for (int e = threadIdx.x; e < COUT * (KW / 8); e += 1024) {
         const int r = e / (KW / 8), c8 = e % (KW / 8);
         *(uint4*)(wl + r * ROW + c8 * 8) = *(const uint4*)(wp + (int64_t)r * KW + c8 * 8);
     }
@@ -73,8 +75,8 @@ __global__ __launch_bounds__(512) void k_conv_lds(const uint16_t* __restrict__ i
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r16 = lane & 15, kg = lane >> 4;
     const int64_t P = (int64_t)N * H * W;
-    for (int64_t chunk = blockIdx.x; chunk * 512 < P; chunk += gridDim.x) {
-        const int64_t p0 = chunk * 512 + (int64_t)wv * 64;
+    for (int64_t chunk = blockIdx.x; chunk * BPX < P; chunk += gridDim.x) {
+        const int64_t p0 = chunk * BPX + (int64_t)wv * WPX;
         if (p0 >= P) continue;
         int hh[MT], ww[MT], nn[MT];
 #pragma unroll
@@ -449,10 +451,10 @@ static hipError_t conv_t(const uint16_t* in, const uint16_t* wp, const float* bi
                          uint16_t* out_bf, float* out_f32, int N, int H, int W, int sgn, int dil, int relu,
                          hipStream_t st) {
     const int64_t P = (int64_t)N * H * W;
-    const int64_t chunks = (P + 511) / 512;
+    const int64_t chunks = (P + 255) / 256;
     // persistent: two workgroups per CU (the weight stage is at most 75 KB)
     const unsigned blocks = (unsigned)(chunks < 512 ? chunks : 512);
-    k_conv_lds<CIN, COUT><<<blocks, 512, 0, st>>>(in, wp, bias, mask, out_bf, out_f32, N, H, W, sgn, dil, relu);
+    k_conv_lds<CIN, COUT><<<blocks, 1024, 0, st>>>(in, wp, bias, mask, out_bf, out_f32, N, H, W, sgn, dil, relu);
     return hipGetLastError();
 }
 
