@@ -140,7 +140,7 @@ __device__ __forceinline__ void next3_complete(const GridDims& g, const double* 
 // fetched once per column instead of by every z-neighbour.  The Laplacian
 // terms are summed in the lattice order of node_chempot, so the potentials
 // are the same numbers.
-constexpr int CZ = 8;
+constexpr int CZ = 16;
 constexpr int CPX = BX + 2, CPY = BY + 2, CPN = CPX * CPY;
 
 // With PART the densities come as the three partial sums per node and the
