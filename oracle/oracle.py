@@ -45,6 +45,7 @@ class OrcParams(ctypes.Structure):
         ("kappa1", ctypes.c_double), ("kappa2", ctypes.c_double), ("kappa3", ctypes.c_double),
         ("chi", ctypes.c_double), ("nu", ctypes.c_double), ("mobility", ctypes.c_double),
         ("tau_phi", ctypes.c_double),
+        ("eos", ctypes.c_int32), ("pad", ctypes.c_int32), ("omega", ctypes.c_double),
     ]
 
 
@@ -72,6 +73,9 @@ class Params:
     nu: float = 0.167
     mobility: float = 0.5
     tau_phi: float = 1.0
+    eos: int = 0          # 0 Carnahan-Starling (Eq. 4), 1 van der Waals, 2 Peng-Robinson
+    pad: int = 0
+    omega: float = 0.344  # Peng-Robinson acentric factor
 
     def c_struct(self) -> OrcParams:
         return OrcParams(**{f: getattr(self, f) for f, _ in OrcParams._fields_})
@@ -103,6 +107,20 @@ def lib():
         for name in ("orc_pressure", "orc_dpdrho"):
             getattr(L, name).argtypes = [d, d, d, d, d]
             getattr(L, name).restype = d
+        I = ctypes.c_int
+        for name in ("orc_eos_psi", "orc_eos_psi_prime"):
+            getattr(L, name).argtypes = [I, d, d, d, d, d, d, d]
+            getattr(L, name).restype = d
+        L.orc_eos_pressure.argtypes = [I, d, d, d, d, d, d]
+        L.orc_eos_pressure.restype = d
+        L.orc_eos_attraction.argtypes = [I, d, d, d, d, d]
+        L.orc_eos_attraction.restype = d
+        L.orc_eos_critical_temperature.argtypes = [I, d, d, d, d, vp]
+        L.orc_eos_critical_temperature.restype = d
+        L.orc_eos_maxwell.argtypes = [I, d, d, d, d, d, vp]
+        L.orc_eos_maxwell.restype = ctypes.c_int
+        L.orc_eos_temperature_for_ratio.argtypes = [I, d, d, d, d, d, vp]
+        L.orc_eos_temperature_for_ratio.restype = ctypes.c_int
         L.orc_critical_temperature.argtypes = [d, d, d, vp]
         L.orc_critical_temperature.restype = d
         L.orc_maxwell.argtypes = [d, d, d, d, vp]
@@ -193,10 +211,52 @@ def temperature_for_ratio(ratio, a=0.037, b=0.2, R=1.0):
     return tuple(out)
 
 
+# Equations of state by kind: 0 Carnahan-Starling (Eq. 4), 1 van der Waals,
+# 2 Peng-Robinson (acentric factor omega).
+CS, VDW, PR = 0, 1, 2
+
+
+def eos_psi(kind, a, b, R, omega, T, C, rho):
+    return lib().orc_eos_psi(kind, a, b, R, omega, T, C, rho)
+
+
+def eos_psi_prime(kind, a, b, R, omega, T, C, rho):
+    return lib().orc_eos_psi_prime(kind, a, b, R, omega, T, C, rho)
+
+
+def eos_pressure(kind, a, b, R, omega, T, rho):
+    return lib().orc_eos_pressure(kind, a, b, R, omega, T, rho)
+
+
+def eos_attraction(kind, a, b, R, omega, T):
+    """a for CS and vdW; a alpha(T) for Peng-Robinson."""
+    return lib().orc_eos_attraction(kind, a, b, R, omega, T)
+
+
+def eos_critical_temperature(kind, a, b, R, omega=0.344):
+    rc = ctypes.c_double()
+    Tc = lib().orc_eos_critical_temperature(kind, a, b, R, omega, ctypes.byref(rc))
+    return Tc, rc.value
+
+
+def eos_maxwell(kind, T, a, b, R, omega=0.344):
+    out = np.zeros(4)
+    if lib().orc_eos_maxwell(kind, a, b, R, omega, T, _ptr(out)) != 0:
+        raise ValueError("T outside (0, T_c)")
+    return tuple(out)
+
+
+def eos_temperature_for_ratio(kind, ratio, a, b, R, omega=0.344):
+    out = np.zeros(5)
+    if lib().orc_eos_temperature_for_ratio(kind, a, b, R, omega, ratio, _ptr(out)) != 0:
+        raise ValueError("ratio must exceed 1")
+    return tuple(out)
+
+
 def coexisting_params(ratio: float, **kw) -> Params:
     """Params at the temperature whose Maxwell density ratio is ``ratio``."""
     p = Params(**kw)
-    T, rg, rl, C, _ = temperature_for_ratio(ratio, p.a, p.b, p.R)
+    T, rg, rl, C, _ = eos_temperature_for_ratio(p.eos, ratio, p.a, p.b, p.R, p.omega)
     p.T, p.rho_g, p.rho_l, p.C = T, rg, rl, C
     return p
 

@@ -38,7 +38,7 @@
 typedef struct {
     int32_t lattice;              /* 0: D2Q9, 1: D3Q27                       */
     int32_t nx, ny, nz;           /* periodic box; nz == 1 for D2Q9          */
-    double a, b, R, T;            /* Carnahan-Starling EOS, Eq. (4)          */
+    double a, b, R, T;            /* EOS constants (Eq. 4 for Carnahan-Starling) */
     double rho_g, rho_l;          /* coexisting gas / liquid densities       */
     double C;                     /* EOS constant C of Eq. (4)               */
     double lambda1, lambda2, lambda3; /* bulk free energy, Eq. (2)           */
@@ -47,6 +47,9 @@ typedef struct {
     double nu;                    /* kinematic viscosity eta/rho             */
     double mobility;              /* M of the Cahn-Hilliard equation (7)     */
     double tau_phi;               /* relaxation time of the phi populations  */
+    int32_t eos;                  /* 0 Carnahan-Starling (Eq. 4), 1 van der Waals, 2 Peng-Robinson */
+    int32_t pad;
+    double omega;                 /* Peng-Robinson acentric factor            */
 } orc_params;
 
 /* ------------------------------------------------------------------------- */
@@ -97,104 +100,156 @@ int orc_lattice_info(int lattice, int32_t *c_out, double *w_out)
 static const double CS2 = 1.0 / 3.0;  /* lattice speed of sound squared */
 
 /* ------------------------------------------------------------------------- */
-/* Thermodynamics of the Carnahan-Starling EOS, Eq. (4).                     */
+/* Thermodynamics of the liquid-gas equation of state.  The paper uses the   */
+/* Carnahan-Starling EOS, Eq. (4), and names Peng-Robinson and van der Waals */
+/* as alternatives.  Psi_eos follows from the EOS pressure through           */
+/* p = rho Psi' - Psi (stated above Eq. (4)); each Psi below is that integral */
+/* of the textbook pressure, up to the linear term C rho:                    */
+/*   van der Waals   p = rho RT/(1 - b rho) - a rho^2                         */
+/*     Psi = rho RT ln(rho/(1 - b rho)) - a rho^2 + C rho                     */
+/*   Peng-Robinson   p = rho RT/(1 - b rho) - A rho^2/(1 + 2 b rho - b^2 rho^2)*/
+/*     Psi = rho RT ln(rho/(1 - b rho))                                       */
+/*           - (A rho/(2 sqrt2 b)) ln[(1 + (1+sqrt2) b rho)/(1 + (1-sqrt2) b rho)]*/
+/*           + C rho,                                                         */
+/*     A = a alpha(T), alpha = [1 + m (1 - sqrt(T/T_c))]^2,                   */
+/*     m = 0.37464 + 1.54226 omega - 0.26992 omega^2 (omega: acentric factor).*/
 /* ------------------------------------------------------------------------- */
 
-/* Psi_eos(rho) of Eq. (4) with the constant C. */
-double orc_psi_eos(double a, double b, double R, double T, double C, double rho)
+typedef struct {
+    int32_t kind;       /* 0 Carnahan-Starling, 1 van der Waals, 2 Peng-Robinson */
+    double a, b, R, omega;
+} orc_eos;
+
+static const double SQRT2 = 1.41421356237309504880;
+
+/* Peng-Robinson critical temperature of a, b, R (alpha = 1 there). */
+static double pr_tc(const orc_eos *e);
+
+/* Attraction coefficient at temperature T. */
+static double eos_attraction(const orc_eos *e, double T)
 {
-    double br = b * rho;
-    return rho * (C - a * rho - 8.0 * R * T * (br - 6.0) / ((br - 4.0) * (br - 4.0))
-                  + R * T * log(rho));
+    if (e->kind != 2) return e->a;
+    double m = 0.37464 + 1.54226 * e->omega - 0.26992 * e->omega * e->omega;
+    double s = 1.0 + m * (1.0 - sqrt(T / pr_tc(e)));
+    return e->a * s * s;
 }
 
-/* d Psi_eos / d rho, differentiated term by term from Eq. (4):
- *   C - 2 a rho + RT (ln rho + 1) - 8RT (b rho - 6)/(b rho - 4)^2
- *     - 8 RT b rho (8 - b rho)/(b rho - 4)^3.                               */
-double orc_psi_prime(double a, double b, double R, double T, double C, double rho)
+/* Psi_eos(rho) with the constant C. */
+static double eos_psi_A(const orc_eos *e, double A, double T, double C, double rho)
 {
-    double br = b * rho;
-    double d = br - 4.0;
-    return C - 2.0 * a * rho + R * T * (log(rho) + 1.0)
-           - 8.0 * R * T * (br - 6.0) / (d * d)
-           - 8.0 * R * T * br * (8.0 - br) / (d * d * d);
+    double a = e->a, b = e->b, RT = e->R * T, br = b * rho;
+    if (e->kind == 0)
+        return rho * (C - a * rho - 8.0 * RT * (br - 6.0) / ((br - 4.0) * (br - 4.0)) + RT * log(rho));
+    double rep = rho * RT * log(rho / (1.0 - br));
+    if (e->kind == 1) return rep - A * rho * rho + C * rho;
+    return rep - A * rho / (2.0 * SQRT2 * b) * log((1.0 + (1.0 + SQRT2) * br) / (1.0 + (1.0 - SQRT2) * br)) + C * rho;
 }
 
-/* The EOS pressure p = rho Psi' - Psi, the relation stated after Eq. (3). */
-double orc_pressure(double a, double b, double R, double T, double rho)
+/* d Psi / d rho, differentiated term by term:
+ *   CS:  C - 2 a rho + RT (ln rho + 1) - 8RT (b rho - 6)/(b rho - 4)^2
+ *          - 8 RT b rho (8 - b rho)/(b rho - 4)^3
+ *   vdW: C + RT [ln(rho/(1 - b rho)) + 1/(1 - b rho)] - 2 a rho
+ *   PR:  C + RT [ln(rho/(1 - b rho)) + 1/(1 - b rho)]
+ *          - (A/(2 sqrt2 b)) ln[...] - A rho/(1 + 2 b rho - b^2 rho^2)        */
+static double eos_psi_prime_A(const orc_eos *e, double A, double T, double C, double rho)
 {
-    return rho * orc_psi_prime(a, b, R, T, 0.0, rho) - orc_psi_eos(a, b, R, T, 0.0, rho);
+    double a = e->a, b = e->b, RT = e->R * T, br = b * rho;
+    if (e->kind == 0) {
+        double d = br - 4.0;
+        return C - 2.0 * a * rho + RT * (log(rho) + 1.0) - 8.0 * RT * (br - 6.0) / (d * d)
+               - 8.0 * RT * br * (8.0 - br) / (d * d * d);
+    }
+    double rep = RT * (log(rho / (1.0 - br)) + 1.0 / (1.0 - br));
+    if (e->kind == 1) return C + rep - 2.0 * A * rho;
+    double D = 1.0 + 2.0 * br - br * br;
+    return C + rep - A / (2.0 * SQRT2 * b) * log((1.0 + (1.0 + SQRT2) * br) / (1.0 + (1.0 - SQRT2) * br))
+           - A * rho / D;
 }
 
-/* dp/drho = rho Psi''; Psi'' from differentiating Psi' once more. */
-static double psi_second(double a, double b, double R, double T, double rho)
+/* Psi'' = T q(rho) - A s(rho): q from the repulsive part (per unit T), s from
+ * the attractive part (per unit A).
+ *   CS:  q = R/rho - 8 R b (8 - br)/d^3 - 8 R b [(8 - 2 br) d - 3 br (8 - br)]/d^4, s = 2
+ *   vdW, PR: q = R [1/rho + b/(1 - br) + b/(1 - br)^2]
+ *   vdW: s = 2;  PR: s = 1/D + (1 + br^2)/D^2, D = 1 + 2 br - br^2            */
+static double eos_q(const orc_eos *e, double rho)
 {
-    double br = b * rho;
-    double d = br - 4.0;
-    /* d/drho [-8RT (br-6)/d^2] = -8RT b (8 - br)/d^3                        */
-    /* d/drho [-8RT br (8-br)/d^3] = -8RT b [ (8 - 2 br) d - 3 br (8 - br) ]/d^4 */
-    double t1 = -8.0 * R * T * b * (8.0 - br) / (d * d * d);
-    double t2 = -8.0 * R * T * b * ((8.0 - 2.0 * br) * d - 3.0 * br * (8.0 - br)) / (d * d * d * d);
-    return -2.0 * a + R * T / rho + t1 + t2;
+    double b = e->b, R = e->R, br = b * rho;
+    if (e->kind == 0) {
+        double d = br - 4.0;
+        double t1 = -8.0 * R * b * (8.0 - br) / (d * d * d);
+        double t2 = -8.0 * R * b * ((8.0 - 2.0 * br) * d - 3.0 * br * (8.0 - br)) / (d * d * d * d);
+        return R / rho + t1 + t2;
+    }
+    double m = 1.0 - br;
+    return R * (1.0 / rho + b / m + b / (m * m));
 }
 
-double orc_dpdrho(double a, double b, double R, double T, double rho)
+static double eos_s(const orc_eos *e, double rho)
 {
-    return rho * psi_second(a, b, R, T, rho);
+    if (e->kind != 2) return 2.0;
+    double br = e->b * rho, D = 1.0 + 2.0 * br - br * br;
+    return 1.0 / D + (1.0 + br * br) / (D * D);
 }
 
-/* Critical temperature: the spinodal condition dp/drho = 0 can be solved for
- * T at each density; the critical point is the maximum of that curve.  With
- * p = rho Psi' - Psi, dp/drho = rho Psi''(rho; T), and Psi'' is linear in T:
- * Psi'' = -2a + T * q(rho), so T_spin(rho) = 2a / q(rho).  Golden-section
- * search for its maximum on (0, 4/b).                                        */
-static double q_of_rho(double a, double b, double R, double rho)
+static double eos_rho_max(const orc_eos *e) { return e->kind == 0 ? 4.0 / e->b : 1.0 / e->b; }
+
+static double eos_pressure_A(const orc_eos *e, double A, double T, double rho)
 {
-    /* psi_second with a = 0 and T = 1 gives q(rho). */
-    return psi_second(0.0, b, R, 1.0, rho);
-    (void)a;
+    return rho * eos_psi_prime_A(e, A, T, 0.0, rho) - eos_psi_A(e, A, T, 0.0, rho);
 }
 
-double orc_critical_temperature(double a, double b, double R, double *rho_c)
+static double eos_dpdrho_A(const orc_eos *e, double A, double T, double rho)
 {
-    double lo = 1e-6, hi = 4.0 / b - 1e-6;
+    return rho * (T * eos_q(e, rho) - A * eos_s(e, rho));
+}
+
+/* Critical point with the attraction a (alpha = 1): the spinodal dp/drho = 0
+ * gives T_spin(rho) = a s(rho)/q(rho); the critical point is its maximum
+ * (golden-section search on (0, rho_max)).                                  */
+static double eos_tc(const orc_eos *e, double *rho_c)
+{
+    double lo = 1e-6, hi = eos_rho_max(e) * (1.0 - 1e-6);
     const double gr = 0.5 * (sqrt(5.0) - 1.0);
+#define TSPIN(r) (e->a * eos_s(e, r) / eos_q(e, r))
     double x1 = hi - gr * (hi - lo), x2 = lo + gr * (hi - lo);
-    double f1 = 2.0 * a / q_of_rho(a, b, R, x1), f2 = 2.0 * a / q_of_rho(a, b, R, x2);
+    double f1 = TSPIN(x1), f2 = TSPIN(x2);
     for (int it = 0; it < 300; ++it) {
         if (f1 < f2) {
             lo = x1; x1 = x2; f1 = f2;
             x2 = lo + gr * (hi - lo);
-            f2 = 2.0 * a / q_of_rho(a, b, R, x2);
+            f2 = TSPIN(x2);
         } else {
             hi = x2; x2 = x1; f2 = f1;
             x1 = hi - gr * (hi - lo);
-            f1 = 2.0 * a / q_of_rho(a, b, R, x1);
+            f1 = TSPIN(x1);
         }
     }
     double rc = 0.5 * (lo + hi);
     if (rho_c) *rho_c = rc;
-    return 2.0 * a / q_of_rho(a, b, R, rc);
+    return TSPIN(rc);
+#undef TSPIN
 }
 
+static double pr_tc(const orc_eos *e) { return eos_tc(e, NULL); }
+
 /* Bisection for p(rho) = P on an interval where p is monotonic increasing. */
-static double solve_p(double a, double b, double R, double T, double P, double lo, double hi)
+static double solve_p(const orc_eos *e, double A, double T, double P, double lo, double hi)
 {
     for (int it = 0; it < 400; ++it) {
         double mid = 0.5 * (lo + hi);
-        if (orc_pressure(a, b, R, T, mid) < P) lo = mid; else hi = mid;
+        if (eos_pressure_A(e, A, T, mid) < P) lo = mid; else hi = mid;
         if (hi - lo <= 1e-17 * hi) break;
     }
     return 0.5 * (lo + hi);
 }
 
 /* Root of dp/drho on [lo, hi] where it changes sign. */
-static double solve_dp(double a, double b, double R, double T, double lo, double hi)
+static double solve_dp(const orc_eos *e, double A, double T, double lo, double hi)
 {
-    double flo = orc_dpdrho(a, b, R, T, lo);
+    double flo = eos_dpdrho_A(e, A, T, lo);
     for (int it = 0; it < 400; ++it) {
         double mid = 0.5 * (lo + hi);
-        double fm = orc_dpdrho(a, b, R, T, mid);
+        double fm = eos_dpdrho_A(e, A, T, mid);
         if ((fm > 0) == (flo > 0)) { lo = mid; flo = fm; } else hi = mid;
         if (hi - lo <= 1e-17 * hi) break;
     }
@@ -210,56 +265,145 @@ static double solve_dp(double a, double b, double R, double T, double lo, double
  * Psi'(rho_g) = Psi'(rho_l) = 0, and Psi0 = Psi(rho_g) = Psi(rho_l), which with
  * that C equals -p_coex.  Returns 0 on success, -1 if T >= T_c.
  * out = {rho_g, rho_l, C, Psi0}.                                            */
-int orc_maxwell(double a, double b, double R, double T, double *out)
+static int eos_maxwell(const orc_eos *e, double T, double *out)
 {
     double rc;
-    double Tc = orc_critical_temperature(a, b, R, &rc);
+    double Tc = eos_tc(e, &rc);
     if (!(T > 0.0) || !(T < Tc)) return -1;
-    double rmax = 4.0 / b;
-    /* spinodals: dp/drho > 0 below rho_s1, < 0 between, > 0 above rho_s2 */
-    double s1 = solve_dp(a, b, R, T, 1e-12, rc);
-    double s2 = solve_dp(a, b, R, T, rc, rmax * (1.0 - 1e-12));
-    double pmax = orc_pressure(a, b, R, T, s1);
-    double pmin = orc_pressure(a, b, R, T, s2);
+    double A = eos_attraction(e, T);
+    double rmax = eos_rho_max(e);
+    /* spinodals: dp/drho > 0 below rho_s1, < 0 between, > 0 above rho_s2 (at
+     * T < T_c the unstable branch brackets the critical density for CS and
+     * vdW; for PR alpha(T) > 1 moves it, so search from the maximum of the
+     * spinodal curve at this attraction) */
+    double lo = 1e-6, hi = rmax * (1.0 - 1e-6);
+    const double gr = 0.5 * (sqrt(5.0) - 1.0);
+    double x1 = hi - gr * (hi - lo), x2 = lo + gr * (hi - lo);
+    double f1 = -eos_dpdrho_A(e, A, T, x1) / x1, f2 = -eos_dpdrho_A(e, A, T, x2) / x2;
+    for (int it = 0; it < 300; ++it) {
+        if (f1 < f2) { lo = x1; x1 = x2; f1 = f2; x2 = lo + gr * (hi - lo); f2 = -eos_dpdrho_A(e, A, T, x2) / x2; }
+        else { hi = x2; x2 = x1; f2 = f1; x1 = hi - gr * (hi - lo); f1 = -eos_dpdrho_A(e, A, T, x1) / x1; }
+    }
+    double rm = 0.5 * (lo + hi);  /* most unstable density at this T */
+    if (!(eos_dpdrho_A(e, A, T, rm) < 0.0)) return -1;
+    (void)rc;
+    double s1 = solve_dp(e, A, T, 1e-12, rm);
+    double s2 = solve_dp(e, A, T, rm, rmax * (1.0 - 1e-12));
+    double pmax = eos_pressure_A(e, A, T, s1);
+    double pmin = eos_pressure_A(e, A, T, s2);
     double Plo = pmin > 0.0 ? pmin : 0.0, Phi = pmax;
     double rg = 0, rl = 0;
     for (int it = 0; it < 300; ++it) {
         double P = 0.5 * (Plo + Phi);
-        rg = solve_p(a, b, R, T, P, 1e-300, s1);
-        rl = solve_p(a, b, R, T, P, s2, rmax * (1.0 - 1e-15));
-        double dmu = orc_psi_prime(a, b, R, T, 0.0, rl) - orc_psi_prime(a, b, R, T, 0.0, rg);
+        rg = solve_p(e, A, T, P, 1e-300, s1);
+        rl = solve_p(e, A, T, P, s2, rmax * (1.0 - 1e-15));
+        double dmu = eos_psi_prime_A(e, A, T, 0.0, rl) - eos_psi_prime_A(e, A, T, 0.0, rg);
         /* along an isotherm d mu = dp / rho, so d(mu_l - mu_g)/dP =
          * 1/rho_l - 1/rho_g < 0: a positive difference means P is too low */
         if (dmu > 0) Plo = P; else Phi = P;
         if (Phi - Plo <= 1e-17 * Phi) break;
     }
-    double C = -orc_psi_prime(a, b, R, T, 0.0, rg);
+    double C = -eos_psi_prime_A(e, A, T, 0.0, rg);
     out[0] = rg;
     out[1] = rl;
     out[2] = C;
-    out[3] = orc_psi_eos(a, b, R, T, C, rg);
+    out[3] = eos_psi_A(e, A, T, C, rg);
     return 0;
 }
 
 /* Temperature at which the Maxwell ratio rho_l / rho_g equals `ratio`
  * (the ratio decreases monotonically as T rises to T_c).  Bisection in T.
  * out = {T, rho_g, rho_l, C, Psi0}.                                         */
-int orc_temperature_for_ratio(double a, double b, double R, double ratio, double *out)
+static int eos_temperature_for_ratio(const orc_eos *e, double ratio, double *out)
 {
     if (!(ratio > 1.0)) return -1;
-    double Tc = orc_critical_temperature(a, b, R, NULL);
+    double Tc = eos_tc(e, NULL);
     double lo = 0.05 * Tc, hi = Tc * (1.0 - 1e-9);
     double m[4];
     for (int it = 0; it < 200; ++it) {
         double mid = 0.5 * (lo + hi);
-        if (orc_maxwell(a, b, R, mid, m) != 0) { hi = mid; continue; }
+        if (eos_maxwell(e, mid, m) != 0) { hi = mid; continue; }
         if (m[1] / m[0] > ratio) lo = mid; else hi = mid;
         if (hi - lo <= 1e-16 * hi) break;
     }
     out[0] = 0.5 * (lo + hi);
-    if (orc_maxwell(a, b, R, out[0], m) != 0) return -1;
+    if (eos_maxwell(e, out[0], m) != 0) return -1;
     out[1] = m[0]; out[2] = m[1]; out[3] = m[2]; out[4] = m[3];
     return 0;
+}
+
+/* Exported forms: orc_eos_* take (kind, a, b, R, omega); the unprefixed ones
+ * are the Carnahan-Starling EOS of Eq. (4). */
+static orc_eos make_eos(int kind, double a, double b, double R, double omega)
+{
+    orc_eos e = {kind, a, b, R, omega};
+    return e;
+}
+
+double orc_eos_psi(int kind, double a, double b, double R, double omega, double T, double C, double rho)
+{
+    orc_eos e = make_eos(kind, a, b, R, omega);
+    return eos_psi_A(&e, eos_attraction(&e, T), T, C, rho);
+}
+double orc_eos_psi_prime(int kind, double a, double b, double R, double omega, double T, double C, double rho)
+{
+    orc_eos e = make_eos(kind, a, b, R, omega);
+    return eos_psi_prime_A(&e, eos_attraction(&e, T), T, C, rho);
+}
+double orc_eos_pressure(int kind, double a, double b, double R, double omega, double T, double rho)
+{
+    orc_eos e = make_eos(kind, a, b, R, omega);
+    return eos_pressure_A(&e, eos_attraction(&e, T), T, rho);
+}
+double orc_eos_attraction(int kind, double a, double b, double R, double omega, double T)
+{
+    orc_eos e = make_eos(kind, a, b, R, omega);
+    return eos_attraction(&e, T);
+}
+double orc_eos_critical_temperature(int kind, double a, double b, double R, double omega, double *rho_c)
+{
+    orc_eos e = make_eos(kind, a, b, R, omega);
+    return eos_tc(&e, rho_c);
+}
+int orc_eos_maxwell(int kind, double a, double b, double R, double omega, double T, double *out)
+{
+    orc_eos e = make_eos(kind, a, b, R, omega);
+    return eos_maxwell(&e, T, out);
+}
+int orc_eos_temperature_for_ratio(int kind, double a, double b, double R, double omega, double ratio, double *out)
+{
+    orc_eos e = make_eos(kind, a, b, R, omega);
+    return eos_temperature_for_ratio(&e, ratio, out);
+}
+
+double orc_psi_eos(double a, double b, double R, double T, double C, double rho)
+{
+    return orc_eos_psi(0, a, b, R, 0.0, T, C, rho);
+}
+double orc_psi_prime(double a, double b, double R, double T, double C, double rho)
+{
+    return orc_eos_psi_prime(0, a, b, R, 0.0, T, C, rho);
+}
+double orc_pressure(double a, double b, double R, double T, double rho)
+{
+    return orc_eos_pressure(0, a, b, R, 0.0, T, rho);
+}
+double orc_dpdrho(double a, double b, double R, double T, double rho)
+{
+    orc_eos e = make_eos(0, a, b, R, 0.0);
+    return eos_dpdrho_A(&e, a, T, rho);
+}
+double orc_critical_temperature(double a, double b, double R, double *rho_c)
+{
+    return orc_eos_critical_temperature(0, a, b, R, 0.0, rho_c);
+}
+int orc_maxwell(double a, double b, double R, double T, double *out)
+{
+    return orc_eos_maxwell(0, a, b, R, 0.0, T, out);
+}
+int orc_temperature_for_ratio(double a, double b, double R, double ratio, double *out)
+{
+    return orc_eos_temperature_for_ratio(0, a, b, R, 0.0, ratio, out);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -301,7 +445,7 @@ void orc_mu_bulk(const orc_params *p, double rho, double phi, double *out)
     orc_concentrations(p, rho, phi, &c1, &c2);
     double w1v = dwell_half(c1), w2v = dwell_half(c2);
     double dlt = p->rho_g - p->rho_l;
-    out[0] = 0.5 * p->lambda1 * orc_psi_prime(p->a, p->b, p->R, p->T, p->C, rho)
+    out[0] = 0.5 * p->lambda1 * orc_eos_psi_prime(p->eos, p->a, p->b, p->R, p->omega, p->T, p->C, rho)
              - (p->lambda2 * w1v + p->lambda3 * w2v) / (2.0 * dlt);
     out[1] = (p->lambda2 * w1v - p->lambda3 * w2v) / (2.0 * p->chi);
 }
@@ -313,8 +457,8 @@ double orc_f_bulk(const orc_params *p, double rho, double phi)
 {
     double c1, c2;
     orc_concentrations(p, rho, phi, &c1, &c2);
-    double psi = orc_psi_eos(p->a, p->b, p->R, p->T, p->C, rho);
-    double psi0 = orc_psi_eos(p->a, p->b, p->R, p->T, p->C, p->rho_g);
+    double psi = orc_eos_psi(p->eos, p->a, p->b, p->R, p->omega, p->T, p->C, rho);
+    double psi0 = orc_eos_psi(p->eos, p->a, p->b, p->R, p->omega, p->T, p->C, p->rho_g);
     double d1 = c1 * (1.0 - c1), d2 = c2 * (1.0 - c2);
     return 0.5 * p->lambda1 * (psi - psi0) + 0.5 * p->lambda2 * d1 * d1 + 0.5 * p->lambda3 * d2 * d2;
 }
