@@ -68,8 +68,22 @@ extern "C" {
 #define TELBM_FIELD_FY 10
 #define TELBM_FIELD_FZ 11
 
+/* Liquid-gas equations of state of the bulk free energy (Eq. 2): the paper's
+ * Carnahan-Starling (Eq. 4), and van der Waals and Peng-Robinson, which it
+ * names as alternatives (their Psi follows from the textbook pressure through
+ * p = rho Psi' - Psi, stated above Eq. 4):
+ *   van der Waals  p = rho R T/(1 - b rho) - a rho^2
+ *   Peng-Robinson  p = rho R T/(1 - b rho) - a alpha(T) rho^2/(1 + 2 b rho - b^2 rho^2),
+ *                  alpha = [1 + m (1 - sqrt(T/T_c))]^2,
+ *                  m = 0.37464 + 1.54226 omega - 0.26992 omega^2.            */
+#define TELBM_EOS_CS 0
+#define TELBM_EOS_VDW 1
+#define TELBM_EOS_PR 2
+
 /* Parameters (plain data, copied by telbm_create).
- *  a, b, R, T          Carnahan-Starling equation of state, Eq. (4).
+ *  eos                 TELBM_EOS_*; omega: acentric factor (Peng-Robinson only).
+ *  a, b, R, T          constants of the equation of state (Eq. 4 for
+ *                      Carnahan-Starling); T the temperature.
  *  rho_g, rho_l        coexisting gas/liquid densities; both 0 means "solve the
  *                      Maxwell construction at T" (text after Eq. 4).
  *  lambda1..3          bulk free energy weights, Eq. (2).
@@ -87,7 +101,7 @@ typedef struct telbm_params {
     int32_t lattice;
     int32_t precision;
     int32_t nx, ny, nz;
-    int32_t reserved0;
+    int32_t eos;              /* TELBM_EOS_*: the liquid-gas equation of state  */
     double a, b, R, T;
     double rho_g, rho_l;
     double lambda1, lambda2, lambda3;
@@ -99,6 +113,7 @@ typedef struct telbm_params {
     double rho_ref;
     uint32_t diag_every;
     uint32_t reserved1;
+    double omega;             /* Peng-Robinson acentric factor (TELBM_EOS_PR)    */
 } telbm_params;
 
 /* Diagnostics of the state before step `step` (the last diagnosed step):
@@ -135,6 +150,14 @@ int telbm_coexistence(double a, double b, double R, double T,
 
 /* Temperature whose Maxwell ratio rho_l/rho_g equals `ratio` (> 1). */
 int telbm_temperature_for_ratio(double a, double b, double R, double ratio, double *T);
+
+/* The same three for any TELBM_EOS_* (omega used by Peng-Robinson only; its
+ * T_c is that of alpha = 1).  TELBM_ERR_INVAL for an unknown eos. */
+int telbm_eos_critical_temperature(int eos, double a, double b, double R, double omega, double *T_c);
+int telbm_eos_coexistence(int eos, double a, double b, double R, double omega, double T,
+                          double *rho_g, double *rho_l, double *C, double *Psi0);
+int telbm_eos_temperature_for_ratio(int eos, double a, double b, double R, double omega, double ratio,
+                                    double *T);
 
 /* Bytes of device arena telbm_create needs for these parameters. */
 int telbm_required_bytes(const telbm_params *p, size_t *bytes);

@@ -6,5 +6,5 @@ Mazloomi, Karlin and Kusumaatmaja, "Ternary free-energy entropic lattice
 Boltzmann model with high density ratio" (arXiv:1710.07486).
 """
 from ._lib import D2Q9, D3Q27, FP64, FP32_MIXED, FIELDS, TelbmError  # noqa: F401
-from .solver import (Params, Solver, coexistence, critical_temperature,  # noqa: F401
+from .solver import (EOS_CS, EOS_PR, EOS_VDW, Params, Solver, coexistence, critical_temperature,  # noqa: F401
                      required_bytes, temperature_for_ratio)

@@ -18,7 +18,7 @@ class TelbmParams(ctypes.Structure):
     _fields_ = [
         ("lattice", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("eos", ctypes.c_int32),
         ("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double), ("T", ctypes.c_double),
         ("rho_g", ctypes.c_double), ("rho_l", ctypes.c_double),
         ("lambda1", ctypes.c_double), ("lambda2", ctypes.c_double), ("lambda3", ctypes.c_double),
@@ -26,6 +26,7 @@ class TelbmParams(ctypes.Structure):
         ("chi", ctypes.c_double), ("nu", ctypes.c_double), ("mobility", ctypes.c_double),
         ("tau_phi", ctypes.c_double), ("rho_ref", ctypes.c_double),
         ("diag_every", ctypes.c_uint32), ("reserved1", ctypes.c_uint32),
+        ("omega", ctypes.c_double),
     ]
 
 
@@ -52,6 +53,9 @@ PROTOTYPES = {
     "telbm_critical_temperature": (_i, [_d, _d, _d, _pd]),
     "telbm_coexistence": (_i, [_d, _d, _d, _d, _pd, _pd, _pd, _pd]),
     "telbm_temperature_for_ratio": (_i, [_d, _d, _d, _d, _pd]),
+    "telbm_eos_critical_temperature": (_i, [_i, _d, _d, _d, _d, _pd]),
+    "telbm_eos_coexistence": (_i, [_i, _d, _d, _d, _d, _d, _pd, _pd, _pd, _pd]),
+    "telbm_eos_temperature_for_ratio": (_i, [_i, _d, _d, _d, _d, _d, _pd]),
     "telbm_required_bytes": (_i, [ctypes.POINTER(TelbmParams), ctypes.POINTER(_sz)]),
     "telbm_create": (_i, [ctypes.POINTER(TelbmParams), _vp, _sz, ctypes.POINTER(_vp)]),
     "telbm_set_stream": (_i, [_vp, _vp]),

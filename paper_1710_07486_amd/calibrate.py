@@ -20,7 +20,7 @@ def discrete_coexistence(p: Params, steps: int = 20000, n: int = 256, width: flo
     import dataclasses
     q = dataclasses.replace(p, nx=n, ny=1, nz=1, diag_every=0)
     from .solver import coexistence
-    rg, rl, _, _ = coexistence(p.T, p.a, p.b, p.R)
+    rg, rl, _, _ = coexistence(p.T, p.a, p.b, p.R, p.eos, p.omega)
     if p.rho_g and p.rho_l:
         rg, rl = p.rho_g, p.rho_l
     x = np.arange(n, dtype=np.float64)

@@ -120,8 +120,10 @@ int validate(const telbm_params* p, std::string* why) {
     if (p->lattice == TELBM_D2Q9 && p->nz != 1) { *why = "D2Q9 needs nz == 1"; return TELBM_ERR_INVAL; }
     const double N = (double)p->nx * p->ny * p->nz;
     if (N >= 1099511627776.0) { *why = "lattice too large"; return TELBM_ERR_INVAL; }
+    if (p->eos < TELBM_EOS_CS || p->eos > TELBM_EOS_PR) { *why = "unknown equation of state"; return TELBM_ERR_INVAL; }
+    if (p->eos == TELBM_EOS_PR && !isfinite(p->omega)) { *why = "omega must be finite"; return TELBM_ERR_INVAL; }
     double Tc;
-    if (!critical_point(p->a, p->b, p->R, &Tc, nullptr)) { *why = "a, b, R must be positive"; return TELBM_ERR_INVAL; }
+    if (!eos_critical_point(eos_of(*p), &Tc, nullptr)) { *why = "a, b, R must be positive"; return TELBM_ERR_INVAL; }
     if (!(p->T > 0.0 && p->T < Tc)) { *why = "T must lie in (0, T_c)"; return TELBM_ERR_INVAL; }
     if (!(p->nu > 0.0) || !isfinite(p->nu)) { *why = "nu must be positive"; return TELBM_ERR_INVAL; }
     if (!(p->tau_phi > 0.5) || !isfinite(p->tau_phi)) { *why = "tau_phi must exceed 1/2"; return TELBM_ERR_INVAL; }
@@ -162,6 +164,8 @@ PhysConst derive(const telbm_params& p, double rho_g, double rho_l, double C) {
     k.inv_beta = 2.0 * tau;
     k.omega_phi = 1.0 / p.tau_phi;
     k.Gamma = p.mobility / (p.tau_phi - 0.5);
+    k.eos = p.eos;
+    k.att = eos_attraction(eos_of(p), p.T);
     return k;
 }
 
@@ -358,6 +362,26 @@ int telbm_temperature_for_ratio(double a, double b, double R, double ratio, doub
     return temperature_for_ratio(a, b, R, ratio, T) ? TELBM_OK : TELBM_ERR_INVAL;
 }
 
+int telbm_eos_critical_temperature(int eos, double a, double b, double R, double omega, double* T_c) {
+    if (!T_c) return TELBM_ERR_INVAL;
+    return eos_critical_point(EosSpec{eos, a, b, R, omega}, T_c, nullptr) ? TELBM_OK : TELBM_ERR_INVAL;
+}
+
+int telbm_eos_coexistence(int eos, double a, double b, double R, double omega, double T, double* rho_g,
+                          double* rho_l, double* C, double* Psi0) {
+    if (!rho_g || !rho_l) return TELBM_ERR_INVAL;
+    double c = 0, p0 = 0;
+    if (!eos_maxwell(EosSpec{eos, a, b, R, omega}, T, rho_g, rho_l, &c, &p0)) return TELBM_ERR_INVAL;
+    if (C) *C = c;
+    if (Psi0) *Psi0 = p0;
+    return TELBM_OK;
+}
+
+int telbm_eos_temperature_for_ratio(int eos, double a, double b, double R, double omega, double ratio, double* T) {
+    if (!T) return TELBM_ERR_INVAL;
+    return eos_temperature_for_ratio(EosSpec{eos, a, b, R, omega}, ratio, T) ? TELBM_OK : TELBM_ERR_INVAL;
+}
+
 int telbm_required_bytes(const telbm_params* p, size_t* bytes) {
     std::string why;
     if (!bytes) return TELBM_ERR_INVAL;
@@ -378,7 +402,7 @@ int telbm_create(const telbm_params* p, void* device_arena, size_t bytes, telbm_
     if (bytes < L.total) return TELBM_ERR_NOMEM;
     double rg = p->rho_g, rl = p->rho_l, C = 0.0, psi0 = 0.0;
     double mg, ml;
-    if (!maxwell(p->a, p->b, p->R, p->T, &mg, &ml, &C, &psi0)) return TELBM_ERR_INVAL;
+    if (!eos_maxwell(eos_of(*p), p->T, &mg, &ml, &C, &psi0)) return TELBM_ERR_INVAL;
     if (rg == 0.0 && rl == 0.0) {
         rg = mg;
         rl = ml;

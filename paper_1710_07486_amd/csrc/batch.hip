@@ -78,7 +78,10 @@ __global__ __launch_bounds__(TBX* TBY) void kb_phase(const InstDesc* __restrict_
         if (PHASE == 0) {
             node_moments<L, T>(d.g, (const T*)d.pop[cur], rho_ref, rho, d.phi, x, y, z);
         } else {
-            node_chempot<L>(d.g, d.k, rho, d.phi, d.mux, d.mup, x, y, z);
+            // the members may differ in their equation of state
+            if (d.k.eos == 0) node_chempot<L, 0>(d.g, d.k, rho, d.phi, d.mux, d.mup, x, y, z);
+            else if (d.k.eos == 1) node_chempot<L, 1>(d.g, d.k, rho, d.phi, d.mux, d.mup, x, y, z);
+            else node_chempot<L, 2>(d.g, d.k, rho, d.phi, d.mux, d.mup, x, y, z);
         }
     }
 }
@@ -212,6 +215,8 @@ PhysConst physconst(const telbm_params& p, double rg, double rl, double C) {
     k.inv_beta = 2.0 * (3.0 * p.nu + 0.5);
     k.omega_phi = 1.0 / p.tau_phi;
     k.Gamma = p.mobility / (p.tau_phi - 0.5);
+    k.eos = p.eos;
+    k.att = eos_attraction(eos_of(p), p.T);
     return k;
 }
 
@@ -317,7 +322,7 @@ int telbm_batch_create(const telbm_params* p, int count, void* arena, size_t byt
     for (int i = 0; i < count; ++i) {
         const telbm_params& q = p[i];
         double mg, ml, C, psi0;
-        if (!maxwell(q.a, q.b, q.R, q.T, &mg, &ml, &C, &psi0)) {
+        if (!eos_maxwell(eos_of(q), q.T, &mg, &ml, &C, &psi0)) {
             delete b;
             return TELBM_ERR_INVAL;
         }

@@ -115,12 +115,12 @@ __global__ __launch_bounds__(BX* BY) void k_moments(GridDims g, const T* __restr
     if (t.in) node_moments<L, T>(g, pop, rho_ref, rho, phi, t.x, t.y, t.z);
 }
 
-template <int L>
+template <int L, int E>
 __global__ __launch_bounds__(BX* BY) void k_chempot(GridDims g, PhysConst k, const double* __restrict__ rho,
                                                     const double* __restrict__ phi, double* __restrict__ mux,
                                                     double* __restrict__ mup) {
     const Tile t = tile_coords(g);
-    if (t.in) node_chempot<L>(g, k, rho, phi, mux, mup, t.x, t.y, t.z);
+    if (t.in) node_chempot<L, E>(g, k, rho, phi, mux, mup, t.x, t.y, t.z);
 }
 
 __device__ __forceinline__ int wrap_any(int v, int n) {
@@ -147,7 +147,7 @@ constexpr int CPX = BX + 2, CPY = BY + 2, CPN = CPX * CPY;
 // inbox entries that the previous D3Q27 FP64 collision (k_collide_next3) left;
 // the kernel completes them while staging (see next3_complete) and also writes
 // the completed rho, phi of its nodes.
-template <bool PART>
+template <bool PART, int E>
 __global__ __launch_bounds__(BX* BY) void k_chempot_col(GridDims g, PhysConst k, double* __restrict__ rho,
                                                         double* __restrict__ phi, double* __restrict__ mux,
                                                         double* __restrict__ mup, const double* __restrict__ part,
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(BX* BY) void k_chempot_col(GridDims g, PhysConst k,
                 lp += Lt::w[i] * (sp[sl][o] - p0);
             }
             double mx, mp;
-            chem_pot(k, r0, p0, 6.0 * lr, 6.0 * lp, &mx, &mp);
+            chem_pot<E>(k, r0, p0, 6.0 * lr, 6.0 * lp, &mx, &mp);
             const int64_t n = ((int64_t)z * g.ny + y) * g.nx + x;
             mux[n] = mx;
             mup[n] = mp;
@@ -474,7 +474,7 @@ struct NextSink {
     }
 };
 
-template <typename T>
+template <typename T, int E>
 __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysConst k, const T* __restrict__ src,
                                                            T* __restrict__ dst, const double* __restrict__ rho_ref,
                                                            const double* __restrict__ rho,
@@ -518,7 +518,7 @@ __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysCons
             lp += Lt::w[i] * (sp[o] - p0);
         }
         double mx, mp;
-        chem_pot(k, r0, p0, 6.0 * lr, 6.0 * lp, &mx, &mp);
+        chem_pot<E>(k, r0, p0, 6.0 * lr, 6.0 * lp, &mx, &mp);
         smx[e] = mx;
         smp[e] = mp;
     }
@@ -855,7 +855,7 @@ static inline unsigned col_blocks(const GridDims& g) {
     return (unsigned)(((g.nx + BX - 1) / BX) * ((g.ny + BY - 1) / BY) * ((g.nz + CZ - 1) / CZ));
 }
 
-template <int L, typename T>
+template <int L, typename T, int E>
 static hipError_t launch_step_parts(const StepArgs& a, int part) {
     const dim3 blk(BX, BY, 1);
     const dim3 grd(grid_blocks(a.g), 1, 1);
@@ -863,10 +863,10 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
         k_moments<L, T><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
     } else if (part == 1) {
         if (L == kD3Q27) {
-            k_chempot_col<false><<<col_blocks(a.g), blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup, nullptr,
+            k_chempot_col<false, E><<<col_blocks(a.g), blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup, nullptr,
                                                                         nullptr);
         } else {
-            k_chempot<L><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup);
+            k_chempot<L, E><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup);
         }
     } else if (part == 2) {
         k_collide<L, T><<<grd, blk, 0, a.stream>>>(a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref, a.rho,
@@ -876,13 +876,13 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
         if (L != kD2Q9 || a.g.nz != 1 || !a.rho_next || !a.phi_next || !a.inbox_out) return hipErrorInvalidValue;
         if (Deviation<T>::on != (a.rho_final != nullptr)) return hipErrorInvalidValue;
         const unsigned fb = fused_tiles(a.g);
-        k_collide_fused2<T><<<fb, dim3(BX, FBY, 1), 0, a.stream>>>(
+        k_collide_fused2<T, E><<<fb, dim3(BX, FBY, 1), 0, a.stream>>>(
             a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref, a.rho, a.phi, a.inbox_in, a.rho_next, a.phi_next,
             a.inbox_out, a.rho_final, a.partials, a.diag);
         if (a.diag) k_diag_final<<<1, 256, 0, a.stream>>>(a.partials, (int)fb, a.diag_out);
     } else if (part == 5) {
         if (L != kD3Q27 || !a.part3 || !a.inbox3) return hipErrorInvalidValue;
-        k_chempot_col<true><<<col_blocks(a.g), blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup, a.part3,
+        k_chempot_col<true, E><<<col_blocks(a.g), blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup, a.part3,
                                                                    a.inbox3);
     } else if (part == 6) {
         if (L != kD3Q27 || Deviation<T>::on || !a.part3 || !a.inbox3) return hipErrorInvalidValue;
@@ -898,10 +898,20 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
     return hipGetLastError();
 }
 
-hipError_t launch_part(int lattice, int precision, const StepArgs& a, int part) {
+template <int E>
+static hipError_t launch_part_e(int lattice, int precision, const StepArgs& a, int part) {
     if (lattice == kD2Q9)
-        return precision ? launch_step_parts<kD2Q9, float>(a, part) : launch_step_parts<kD2Q9, double>(a, part);
-    return precision ? launch_step_parts<kD3Q27, float>(a, part) : launch_step_parts<kD3Q27, double>(a, part);
+        return precision ? launch_step_parts<kD2Q9, float, E>(a, part) : launch_step_parts<kD2Q9, double, E>(a, part);
+    return precision ? launch_step_parts<kD3Q27, float, E>(a, part) : launch_step_parts<kD3Q27, double, E>(a, part);
+}
+
+hipError_t launch_part(int lattice, int precision, const StepArgs& a, int part) {
+    switch (a.k.eos) {
+        case 0: return launch_part_e<0>(lattice, precision, a, part);
+        case 1: return launch_part_e<1>(lattice, precision, a, part);
+        case 2: return launch_part_e<2>(lattice, precision, a, part);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int L, typename T>

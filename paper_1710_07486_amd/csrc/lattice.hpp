@@ -66,6 +66,10 @@ struct PhysConst {
     double inv_beta;              // 2 tau
     double omega_phi;             // 1 / tau_phi
     double Gamma;                 // M / (tau_phi - 1/2)
+    // equation of state: 0 Carnahan-Starling (Eq. 4), 1 van der Waals, 2 Peng-Robinson;
+    // att: attraction a (CS, vdW) or a alpha(T) (PR)
+    int eos;
+    double att;
 };
 
 // Periodic neighbour offsets of one node: off[d][k] is the element offset of
@@ -310,13 +314,35 @@ __device__ __forceinline__ void equilibria(double rho_d, R phi, R mu_phi, const 
 // Chemical potentials of the free energy (Eqs. 2-4 and the f_I rewrite), in
 // FP64.  Returns mu_rho - cs2 ln rho (the excess potential whose gradient
 // drives the fluid) in *mu_x and mu_phi in *mu_p; lap_* are lattice
-// Laplacians.  Psi' of Eq. (4) is combined to
-//   C - 2 a rho + RT (ln rho + 1) - 16 RT (12 - b rho) / (b rho - 4)^3.
+// Laplacians.  Psi' of the equation of state:
+//   Carnahan-Starling (Eq. 4): C - 2 a rho + RT (ln rho + 1) - 16 RT (12 - b rho)/(b rho - 4)^3
+//   van der Waals:   C + RT [ln(rho/(1 - b rho)) + 1/(1 - b rho)] - 2 a rho
+//   Peng-Robinson:   C + RT [ln(rho/(1 - b rho)) + 1/(1 - b rho)]
+//                      - A [ln((1 + (1+sqrt2) b rho)/(1 + (1-sqrt2) b rho))/(2 sqrt2 b)
+//                           + rho/(1 + 2 b rho - b^2 rho^2)]
+// E is the equation of state (0, 1, 2 in the order above), fixed at compile
+// time so that the Carnahan-Starling kernels carry none of the other two's
+// registers; k.eos must equal E.
+template <int E>
+__device__ __forceinline__ double eos_psi_prime(const PhysConst& k, double rho, double lr) {
+    static_assert(E >= 0 && E <= 2, "equation of state 0..2");
+    if constexpr (E == 0) {
+        const double d = k.b * rho - 4.0;
+        return k.C - 2.0 * k.a * rho + k.RT * (lr + 1.0) - 16.0 * k.RT * (12.0 - k.b * rho) / (d * d * d);
+    }
+    const double br = k.b * rho, m = 1.0 - br;
+    const double rep = k.C + k.RT * (lr - log(m) + 1.0 / m);
+    if constexpr (E == 1) return rep - 2.0 * k.att * rho;
+    constexpr double s2 = 1.41421356237309504880;
+    const double D = 1.0 + 2.0 * br - br * br;
+    return rep - k.att * (log((1.0 + (1.0 + s2) * br) / (1.0 + (1.0 - s2) * br)) / (2.0 * s2 * k.b) + rho / D);
+}
+
+template <int E>
 __device__ __forceinline__ void chem_pot(const PhysConst& k, double rho, double phi, double lap_rho,
                                          double lap_phi, double* mu_x, double* mu_p) {
     const double lr = log(rho);
-    const double d = k.b * rho - 4.0;
-    const double psi_p = k.C - 2.0 * k.a * rho + k.RT * (lr + 1.0) - 16.0 * k.RT * (12.0 - k.b * rho) / (d * d * d);
+    const double psi_p = eos_psi_prime<E>(k, rho, lr);
     const double cg = (rho - k.rho_l) * k.inv_delta;
     const double c1 = 0.5 * (1.0 + phi * k.inv_chi - cg);
     const double c2 = 0.5 * (1.0 - phi * k.inv_chi - cg);

@@ -53,7 +53,7 @@ __device__ __forceinline__ void node_moments(const GridDims& g, const T* __restr
 
 // Phase 2: chemical potentials with the lattice Laplacians
 // lap psi(x) = 6 sum_i w_i [psi(x + c_i) - psi(x)].
-template <int L>
+template <int L, int E>
 __device__ __forceinline__ void node_chempot(const GridDims& g, const PhysConst& k, const double* __restrict__ rho,
                                              const double* __restrict__ phi, double* __restrict__ mux,
                                              double* __restrict__ mup, int x, int y, int z) {
@@ -70,7 +70,7 @@ __device__ __forceinline__ void node_chempot(const GridDims& g, const PhysConst&
         lp += Lt::w[i] * (phi[m] - p0);
     }
     double mx, mp;
-    chem_pot(k, r0, p0, 6.0 * lr, 6.0 * lp, &mx, &mp);
+    chem_pot<E>(k, r0, p0, 6.0 * lr, 6.0 * lp, &mx, &mp);
     mux[n] = mx;
     mup[n] = mp;
 }

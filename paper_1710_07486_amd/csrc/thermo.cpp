@@ -1,6 +1,7 @@
-// thermo.cpp -- host thermodynamics of the Carnahan-Starling equation of
-// state used by the free energy (Eq. 4 of arXiv:1710.07486): critical point,
-// Maxwell coexistence, temperature for a target density ratio.
+// thermo.cpp -- host thermodynamics of the equation of state used by the free
+// energy (Eq. 4 of arXiv:1710.07486 and the van der Waals / Peng-Robinson
+// alternatives): critical point, Maxwell coexistence, temperature for a
+// target density ratio.
 //
 // Written in the packing fraction e = b rho / 4, where the CS pressure is
 //   p = (4 R T / b) Z1(e) - (16 a / b^2) e^2,  Z1(e) = e (1 + e + e^2 - e^3)/(1 - e)^3,
@@ -137,6 +138,151 @@ bool temperature_for_ratio(double a, double b, double R, double ratio, double* T
     auto lr = [&](double t) {
         double rg, rl;
         if (!maxwell(a, b, R, t, &rg, &rl, nullptr, nullptr)) return -1e300;
+        return log(rl / rg) - log(ratio);
+    };
+    const double t = bisect(lr, 0.05 * Tc, Tc * (1.0 - 1e-9), 200);
+    *T = t;
+    return isfinite(t);
+}
+
+// ---------------------------------------------------------------------------
+// van der Waals and Peng-Robinson.  Both read p = rho RT/(1 - b rho) - A g(rho)
+// with g = rho^2 (vdW) or rho^2/(1 + 2 b rho - b^2 rho^2) (PR), A = a or
+// a alpha(T), alpha = [1 + m(1 - sqrt(T/T_c))]^2, m = 0.37464 + 1.54226 w
+// - 0.26992 w^2.  The matching Psi (p = rho Psi' - Psi, C = 0) is
+//   rho RT ln(rho/(1 - b rho)) - A rho^2                          (vdW)
+//   rho RT ln(rho/(1 - b rho)) - A rho/(2 sqrt2 b) ln[(1 + (1+sqrt2) b rho)
+//                                  / (1 + (1-sqrt2) b rho)]        (PR)
+// The spinodal dp/drho = 0 reads T = A g'(rho)(1 - b rho)^2 / R =: T_sp(rho);
+// the critical point is the maximum of T_sp at alpha = 1.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr double kSqrt2 = 1.41421356237309504880;
+
+double g_att(const EosSpec& e, double rho) {
+    const double br = e.b * rho;
+    return e.kind == 1 ? rho * rho : rho * rho / (1.0 + 2.0 * br - br * br);
+}
+
+double g_att_prime(const EosSpec& e, double rho) {  // dg/drho; PR: 2 rho (1 + b rho)/D^2
+    const double br = e.b * rho;
+    if (e.kind == 1) return 2.0 * rho;
+    const double D = 1.0 + 2.0 * br - br * br;
+    return 2.0 * rho * (1.0 + br) / (D * D);
+}
+
+double p_cubic(const EosSpec& e, double A, double T, double rho) {
+    return rho * e.R * T / (1.0 - e.b * rho) - A * g_att(e, rho);
+}
+
+double mu_cubic(const EosSpec& e, double A, double T, double rho) {  // Psi' with C = 0
+    const double br = e.b * rho, m = 1.0 - br;
+    const double rep = e.R * T * (log(rho / m) + 1.0 / m);
+    if (e.kind == 1) return rep - 2.0 * A * rho;
+    const double D = 1.0 + 2.0 * br - br * br;
+    return rep - A * (log((1.0 + (1.0 + kSqrt2) * br) / (1.0 + (1.0 - kSqrt2) * br)) / (2.0 * kSqrt2 * e.b) + rho / D);
+}
+
+double psi_cubic(const EosSpec& e, double A, double T, double rho) {  // Psi with C = 0
+    const double br = e.b * rho;
+    const double rep = rho * e.R * T * log(rho / (1.0 - br));
+    if (e.kind == 1) return rep - A * rho * rho;
+    return rep - A * rho / (2.0 * kSqrt2 * e.b) * log((1.0 + (1.0 + kSqrt2) * br) / (1.0 + (1.0 - kSqrt2) * br));
+}
+
+double t_sp(const EosSpec& e, double A, double rho) {
+    const double m = 1.0 - e.b * rho;
+    return A * g_att_prime(e, rho) * m * m / e.R;
+}
+
+// Density of the maximum of T_sp (bisection on the sign of its slope).
+double t_sp_peak(const EosSpec& e, double A) {
+    double lo = 1e-9 / e.b, hi = (1.0 - 1e-9) / e.b;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi), h = 1e-7 * mid;
+        if (t_sp(e, A, mid + h) > t_sp(e, A, mid - h)) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+bool cubic_critical(const EosSpec& e, double* Tc, double* rho_c) {
+    if (!(e.a > 0 && e.b > 0 && e.R > 0)) return false;
+    const double r = t_sp_peak(e, e.a);
+    if (Tc) *Tc = t_sp(e, e.a, r);
+    if (rho_c) *rho_c = r;
+    return true;
+}
+
+bool cubic_maxwell(const EosSpec& e, double T, double* rho_g, double* rho_l, double* C, double* Psi0) {
+    double Tc;
+    if (!cubic_critical(e, &Tc, nullptr) || !(T > 0.0 && T < Tc)) return false;
+    const double A = eos_attraction(e, T);
+    const double rm = t_sp_peak(e, A);
+    if (!(t_sp(e, A, rm) > T)) return false;
+    const double top = 1.0 / e.b;
+    const double s1 = bisect([&](double r) { return t_sp(e, A, r) - T; }, 1e-300, rm);
+    const double s2 = bisect([&](double r) { return T - t_sp(e, A, r); }, rm, top * (1.0 - 1e-14));
+    const double mu_s1 = mu_cubic(e, A, T, s1);
+    // as for Carnahan-Starling: the gas density with the liquid's chemical
+    // potential (mu rises from -inf on the gas branch), then shoot the
+    // pressure difference to zero
+    auto gas_for = [&](double y, bool* ok) {
+        const double m = mu_cubic(e, A, T, y);
+        if (m >= mu_s1) { *ok = false; return s1; }
+        *ok = true;
+        const double lx = bisect([&](double l) { return mu_cubic(e, A, T, exp(l)) - m; }, -745.0, log(s1));
+        return exp(lx);
+    };
+    auto resid = [&](double y) {
+        bool ok;
+        const double x = gas_for(y, &ok);
+        if (!ok) return -1.0;
+        return p_cubic(e, A, T, y) - p_cubic(e, A, T, x);
+    };
+    const double ystar = bisect([&](double yv) { return mu_cubic(e, A, T, yv) - mu_s1; }, s2, top * (1.0 - 1e-12));
+    const double y = bisect(resid, s2, ystar * (1.0 - 1e-13), 400);
+    bool ok;
+    const double x = gas_for(y, &ok);
+    if (!ok) return false;
+    const double c = -mu_cubic(e, A, T, x);
+    *rho_g = x;
+    *rho_l = y;
+    if (C) *C = c;
+    if (Psi0) *Psi0 = psi_cubic(e, A, T, x) + c * x;
+    return isfinite(x) && isfinite(y) && y > x;
+}
+
+}  // namespace
+
+double eos_attraction(const EosSpec& e, double T) {
+    if (e.kind != 2) return e.a;
+    double Tc;
+    if (!cubic_critical(e, &Tc, nullptr)) return e.a;
+    const double m = 0.37464 + 1.54226 * e.omega - 0.26992 * e.omega * e.omega;
+    const double s = 1.0 + m * (1.0 - sqrt(T / Tc));
+    return e.a * s * s;
+}
+
+bool eos_critical_point(const EosSpec& e, double* Tc, double* rho_c) {
+    if (e.kind == 0) return critical_point(e.a, e.b, e.R, Tc, rho_c);
+    if (e.kind == 2 && !isfinite(e.omega)) return false;
+    return (e.kind == 1 || e.kind == 2) && cubic_critical(e, Tc, rho_c);
+}
+
+bool eos_maxwell(const EosSpec& e, double T, double* rho_g, double* rho_l, double* C, double* Psi0) {
+    if (e.kind == 0) return maxwell(e.a, e.b, e.R, T, rho_g, rho_l, C, Psi0);
+    if (e.kind != 1 && e.kind != 2) return false;
+    return cubic_maxwell(e, T, rho_g, rho_l, C, Psi0);
+}
+
+bool eos_temperature_for_ratio(const EosSpec& e, double ratio, double* T) {
+    if (e.kind == 0) return temperature_for_ratio(e.a, e.b, e.R, ratio, T);
+    double Tc, rc;
+    if (!(ratio > 1.0) || !eos_critical_point(e, &Tc, &rc)) return false;
+    auto lr = [&](double t) {
+        double rg, rl;
+        if (!eos_maxwell(e, t, &rg, &rl, nullptr, nullptr)) return -1e300;
         return log(rl / rg) - log(ratio);
     };
     const double t = bisect(lr, 0.05 * Tc, Tc * (1.0 - 1e-9), 200);

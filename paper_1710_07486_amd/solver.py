@@ -42,6 +42,8 @@ class Params:
     tau_phi: float = 1.0
     rho_ref: float = 0.0
     diag_every: int = 0
+    eos: int = 0          # 0 Carnahan-Starling (Eq. 4), 1 van der Waals, 2 Peng-Robinson
+    omega: float = 0.344  # Peng-Robinson acentric factor
 
     def c_struct(self) -> TelbmParams:
         kw = {f: getattr(self, f) for f, _ in TelbmParams._fields_ if hasattr(self, f)}
@@ -69,23 +71,26 @@ def _check(rc: int, handle=None):
         raise TelbmError(rc, msg)
 
 
-def critical_temperature(a=0.037, b=0.2, R=1.0) -> float:
+EOS_CS, EOS_VDW, EOS_PR = 0, 1, 2
+
+
+def critical_temperature(a=0.037, b=0.2, R=1.0, eos=EOS_CS, omega=0.344) -> float:
     out = ctypes.c_double()
-    _check(_lib.load().telbm_critical_temperature(a, b, R, ctypes.byref(out)))
+    _check(_lib.load().telbm_eos_critical_temperature(eos, a, b, R, omega, ctypes.byref(out)))
     return out.value
 
 
-def coexistence(T, a=0.037, b=0.2, R=1.0):
+def coexistence(T, a=0.037, b=0.2, R=1.0, eos=EOS_CS, omega=0.344):
     """(rho_g, rho_l, C, Psi0) from the library's Maxwell construction."""
     rg, rl, C, p0 = (ctypes.c_double() for _ in range(4))
-    _check(_lib.load().telbm_coexistence(a, b, R, T, ctypes.byref(rg), ctypes.byref(rl), ctypes.byref(C),
-                                         ctypes.byref(p0)))
+    _check(_lib.load().telbm_eos_coexistence(eos, a, b, R, omega, T, ctypes.byref(rg), ctypes.byref(rl),
+                                             ctypes.byref(C), ctypes.byref(p0)))
     return rg.value, rl.value, C.value, p0.value
 
 
-def temperature_for_ratio(ratio, a=0.037, b=0.2, R=1.0) -> float:
+def temperature_for_ratio(ratio, a=0.037, b=0.2, R=1.0, eos=EOS_CS, omega=0.344) -> float:
     T = ctypes.c_double()
-    _check(_lib.load().telbm_temperature_for_ratio(a, b, R, ratio, ctypes.byref(T)))
+    _check(_lib.load().telbm_eos_temperature_for_ratio(eos, a, b, R, omega, ratio, ctypes.byref(T)))
     return T.value
 
 

@@ -64,6 +64,36 @@ def test_library_thermodynamics_match_oracle(orc):
         assert abs(T.temperature_for_ratio(ratio) / orc.temperature_for_ratio(ratio)[0] - 1) < 1e-11
 
 
+@pytest.mark.parametrize("kind,a,b", [(1, 9.0 / 49.0, 2.0 / 21.0), (2, 2.0 / 49.0, 2.0 / 21.0)], ids=["vdw", "pr"])
+def test_library_thermodynamics_match_oracle_other_eos(orc, kind, a, b):
+    """The library's van der Waals and Peng-Robinson critical point, Maxwell
+    construction and temperature for a ratio against the oracle's (written
+    apart: spinodal curve and chemical-potential shooting in the library,
+    golden-section critical point and pressure bisection in the oracle)."""
+    import paper_1710_07486_amd as T
+    Tc_l = T.critical_temperature(a, b, 1.0, kind)
+    Tc_o, _ = orc.eos_critical_temperature(kind, a, b, 1.0)
+    assert abs(Tc_l / Tc_o - 1) < 1e-12
+    for tr in (0.95, 0.8, 0.6, 0.5):
+        rg, rl, C, p0 = T.coexistence(tr * Tc_o, a, b, 1.0, kind)
+        og, ol, oC, op0 = orc.eos_maxwell(kind, tr * Tc_o, a, b, 1.0)
+        assert abs(rg / og - 1) < 1e-11 and abs(rl / ol - 1) < 1e-11
+        assert abs(C - oC) < 1e-11 and abs(p0 - op0) < 1e-11
+    for ratio in (10.0, 1000.0):
+        assert abs(T.temperature_for_ratio(ratio, a, b, 1.0, kind) /
+                   orc.eos_temperature_for_ratio(kind, ratio, a, b, 1.0)[0] - 1) < 1e-11
+
+
+def test_unknown_eos_is_rejected(orc):
+    import paper_1710_07486_amd as T
+    from paper_1710_07486_amd import _lib
+    p = T.Params(T=T.temperature_for_ratio(10.0), eos=3)
+    with pytest.raises(_lib.TelbmError):
+        T.required_bytes(p)
+    with pytest.raises(_lib.TelbmError):
+        T.critical_temperature(0.037, 0.2, 1.0, 3)
+
+
 def test_parameter_validation_without_device(orc):
     import paper_1710_07486_amd as T
     from paper_1710_07486_amd import _lib

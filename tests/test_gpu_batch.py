@@ -121,3 +121,38 @@ def test_batch_fp32_mixed_vs_fp64(orc):
     errs = [float(np.abs(a - c).max() / np.abs(c).max()) for a, c in zip(out["32"], out["64"])]
     print("per-instance relative density error", errs, flush=True)
     assert max(errs) < 1e-5
+
+
+def test_batch_mixed_equations_of_state(orc):
+    """Members with Carnahan-Starling (ratio 100), van der Waals (ratio 10)
+    and Peng-Robinson (ratio 100) free energies in one batch: each matches
+    the FP64 oracle run of its own free energy."""
+    import paper_1710_07486_amd as T
+    from paper_1710_07486_amd.batch import Batch
+    cases = [(dict(eos=0), 100.0, (48, 40)), (dict(eos=1, a=9.0 / 49.0, b=2.0 / 21.0), 10.0, (64, 50)),
+             (dict(eos=2, a=2.0 / 49.0, b=2.0 / 21.0), 100.0, (37, 60))]
+    inst = []
+    for k, (e, ratio, (nx, ny)) in enumerate(cases):
+        wl = W.lens(nx, ny, radius=min(nx, ny) / 6, ratio=ratio, kappa=0.1, seed=200 + k)
+        po = orc.coexisting_params(wl.ratio, **wl.physics(), **e)
+        rho, phi, u = W.fields(wl, po.rho_g, po.rho_l)
+        pl = T.Params(lattice=0, nx=nx, ny=ny, nz=1, T=po.T, rho_g=po.rho_g, rho_l=po.rho_l, eos=po.eos, a=po.a,
+                      b=po.b, omega=po.omega, lambda1=po.lambda1, lambda2=po.lambda2, lambda3=po.lambda3,
+                      kappa1=po.kappa1, kappa2=po.kappa2, kappa3=po.kappa3, chi=po.chi, nu=po.nu,
+                      mobility=po.mobility, tau_phi=po.tau_phi)
+        inst.append((po, pl, rho, phi))
+    steps = 60
+    say("batch with CS, vdW and PR members vs oracle")
+    with Batch([x[1] for x in inst]) as b:
+        for i, (_, _pl, r, p) in enumerate(inst):
+            b.init_fields(i, r, p, None)
+        b.step(steps)
+        got = [(b.read(i, "rho"), b.read(i, "phi")) for i in range(len(inst))]
+    for i, (po, _pl, r, p) in enumerate(inst):
+        st = orc.State(po, r, p, None)
+        st.run(steps)
+        ref = st.fields()
+        assert np.isfinite(ref["rho"]).all()
+        for g, key in zip(got[i], ("rho", "phi")):
+            err = np.abs(g - ref[key]).max() / np.abs(ref[key]).max()
+            assert err < 1e-10, (i, key, err)
