@@ -45,17 +45,19 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def library_params(T, wl, precision):
+def library_params(T, wl, precision, eos=None):
+    """Solver parameters of workload `wl`; `eos` optionally names another free
+    energy as {"eos": kind, "a": a, "b": b}."""
     import paper_1710_07486_amd as T_
     nz, ny, nx = wl.shape
     ph = wl.physics()
     return T_.Params(lattice=wl.lattice, precision=precision, nx=nx, ny=ny, nz=nz, T=T,
                      lambda1=ph["lambda1"], lambda2=ph["lambda2"], lambda3=ph["lambda3"],
                      kappa1=ph["kappa1"], kappa2=ph["kappa2"], kappa3=ph["kappa3"], chi=ph["chi"],
-                     nu=ph["nu"], mobility=ph["mobility"], tau_phi=ph["tau_phi"])
+                     nu=ph["nu"], mobility=ph["mobility"], tau_phi=ph["tau_phi"], **(eos or {}))
 
 
-def measure(wl, precision, steps, warmup, fields=None, coex=None):
+def measure(wl, precision, steps, warmup, fields=None, coex=None, eos=None):
     """Whole-step MLUPS with HIP events on the solver's stream, and the mean
     duration of each kernel kind.  Drops start at the discretised model's own
     coexistence densities (a 1D slab relaxed by the library, unless `coex`
@@ -64,11 +66,11 @@ def measure(wl, precision, steps, warmup, fields=None, coex=None):
     import paper_1710_07486_amd as T_
     from paper_1710_07486_amd.calibrate import discrete_coexistence
     from synth import workloads as W
-    T = T_.temperature_for_ratio(wl.ratio)
-    p = library_params(T, wl, precision)
+    T = T_.temperature_for_ratio(wl.ratio, **(eos or {}))
+    p = library_params(T, wl, precision, eos)
     rg = rl = None
     if fields is None:
-        rg, rl = coex if coex else discrete_coexistence(library_params(T, wl, T_.FP64))
+        rg, rl = coex if coex else discrete_coexistence(library_params(T, wl, T_.FP64, eos))
         log("discrete coexistence densities", rg, rl)
         fields = W.fields(wl, rg, rl)
     rho, phi, u = fields
@@ -183,6 +185,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the D3Q27 256^3 measurement")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed measurement")
+    ap.add_argument("--no-eos", action="store_true", help="skip the van der Waals / Peng-Robinson measurement")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate throughput measurement")
     ap.add_argument("--coex2d", type=float, nargs=2, metavar=("RHO_G", "RHO_L"),
                     help="coexistence densities of the 2D workload (skips their calibration run)")
@@ -251,6 +254,21 @@ def main():
                                 "speedup_vs_fp64": round(r32["mlups"] / r64["mlups"], 3),
                                 "rel_density_error_vs_fp64": rel_rho,
                                 "kernels_ms": {k: round(v, 5) for k, v in r32["kernels_ms"].items()}}
+    if not args.no_eos:
+        # the same drops with the other two free energies: Peng-Robinson at
+        # ratio 1000; van der Waals at ratio 100, since its moving drops at
+        # ratio 1000 diverge (the oracle's too, for a = 0.5/49 .. 1/49)
+        result["other_eos"] = {}
+        for name, e, ratio in (("van_der_waals", {"eos": T_.EOS_VDW, "a": 2.0 / 49.0, "b": 2.0 / 21.0}, 100.0),
+                               ("peng_robinson", {"eos": T_.EOS_PR, "a": 2.0 / 49.0, "b": 2.0 / 21.0}, 1000.0)):
+            wle = W.drops_2d(1024, ratio=ratio, seed=0)
+            re_, _ = measure(wle, T_.FP64, args.steps, args.warmup, eos=e)
+            log(name, {k: v for k, v in re_.items() if k != "rho"})
+            result["other_eos"][name] = {"workload": wle.name, "a": e["a"], "b": e["b"],
+                                         "fp64_mlups": round(re_["mlups"], 2),
+                                         "vs_carnahan_starling": round(re_["mlups"] / r64["mlups"], 3),
+                                         "collide_ms": round(re_["kernels_ms"]["collide"], 5),
+                                         "finite": bool(np.isfinite(re_["rho"]).all())}
     if not args.no_3d:
         wl3 = W.collision_3d(256, radius=32, ratio=1000.0, v_rel=0.04, kappa2=0.1, kappa3=0.1)
         s3 = max(10, args.steps // 4)

@@ -124,13 +124,13 @@ def test_batch_fp32_mixed_vs_fp64(orc):
 
 
 def test_batch_mixed_equations_of_state(orc):
-    """Members with Carnahan-Starling (ratio 100), van der Waals (ratio 10)
-    and Peng-Robinson (ratio 100) free energies in one batch: each matches
+    """Members with Carnahan-Starling (ratio 100), van der Waals (ratio 100)
+    and Peng-Robinson (ratio 1000) free energies in one batch: each matches
     the FP64 oracle run of its own free energy."""
     import paper_1710_07486_amd as T
     from paper_1710_07486_amd.batch import Batch
-    cases = [(dict(eos=0), 100.0, (48, 40)), (dict(eos=1, a=9.0 / 49.0, b=2.0 / 21.0), 10.0, (64, 50)),
-             (dict(eos=2, a=2.0 / 49.0, b=2.0 / 21.0), 100.0, (37, 60))]
+    cases = [(dict(eos=0), 100.0, (48, 40)), (dict(eos=1, a=2.0 / 49.0, b=2.0 / 21.0), 100.0, (64, 50)),
+             (dict(eos=2, a=2.0 / 49.0, b=2.0 / 21.0), 1000.0, (37, 60))]
     inst = []
     for k, (e, ratio, (nx, ny)) in enumerate(cases):
         wl = W.lens(nx, ny, radius=min(nx, ny) / 6, ratio=ratio, kappa=0.1, seed=200 + k)

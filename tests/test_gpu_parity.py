@@ -170,20 +170,21 @@ def test_diagnostics_and_device_read(orc):
         assert abs(float(rd.sum()) - ref[0]) < 1e-9 * abs(ref[0])
 
 
-# (eos, a, b, density ratio).  With these a, b the van der Waals liquid is
-# much stiffer than the Peng-Robinson one at the same ratio (dp/drho of the
-# liquid ~5 against ~0.5 at ratio 100), and the oracle itself diverges
-# beyond a ratio of about 10 on the 2D lens; Peng-Robinson runs at 100.
-EOS_CASES = {"vdw": (dict(eos=1, a=9.0 / 49.0, b=2.0 / 21.0), 10.0),
-             "pr": (dict(eos=2, a=2.0 / 49.0, b=2.0 / 21.0), 100.0)}
+# (free energy, density ratio).  The van der Waals runs use a small
+# attraction a: the density ratio at a given T/T_c does not depend on a, but
+# the liquid's dp/drho grows with it (a = 9/49 at ratio 100 gives ~5 against
+# c_s^2 = 1/3 and the oracle itself diverges).
+EOS_CASES = {"vdw100": (dict(eos=1, a=2.0 / 49.0, b=2.0 / 21.0), 100.0),
+             "vdw1000": (dict(eos=1, a=0.5 / 49.0, b=2.0 / 21.0), 1000.0),
+             "pr1000": (dict(eos=2, a=2.0 / 49.0, b=2.0 / 21.0), 1000.0)}
 
 
-@pytest.mark.parametrize("eos", ["vdw", "pr"])
+@pytest.mark.parametrize("eos", list(EOS_CASES))
 @pytest.mark.parametrize("lattice", [0, 1])
 def test_other_equations_of_state(orc, eos, lattice):
-    """van der Waals (ratio 10) and Peng-Robinson (ratio 100) free energies:
-    GPU against oracle, FP64 (D2Q9 lens 96 x 64, 300 steps; D3Q27 box
-    16 x 18 x 20, 40 steps)."""
+    """van der Waals and Peng-Robinson free energies at density ratios 100
+    and 1000: GPU against oracle, FP64 (D2Q9 lens 96 x 64, 300 steps; D3Q27
+    box 16 x 18 x 20, 40 steps)."""
     import paper_1710_07486_amd as T
     e, ratio = EOS_CASES[eos]
     if lattice == 0:

@@ -117,3 +117,25 @@ def test_temperature_for_ratio(orc, e):
     T, rg, rl, C, _ = orc.eos_temperature_for_ratio(k, 100.0, a, b, R, w)
     assert abs(rl / rg / 100.0 - 1) < 1e-9
     assert math.isclose(orc.eos_maxwell(k, T, a, b, R, w)[0], rg, rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("kind", [1, 2], ids=["vdw", "pr"])
+def test_flat_slab_approaches_the_maxwell_densities(orc, kind):
+    """A flat liquid-gas slab relaxed by the oracle's dynamics with the van der
+    Waals or Peng-Robinson free energy (ratio 10) ends at bulk densities near
+    the Maxwell ones, and nearer as the interface widens (kappa_1 up): the
+    lattice's discretisation error, as for Carnahan-Starling."""
+    nx = 160
+    errs = []
+    for k1 in (0.003, 0.03):
+        p = orc.coexisting_params(10.0, lattice=0, nx=nx, ny=1, nz=1, kappa1=k1, kappa2=0.1, kappa3=0.1,
+                                  lambda2=0.3125, lambda3=0.3125, eos=kind, a=2.0 / 49.0, b=2.0 / 21.0)
+        x = np.arange(nx, dtype=float)
+        c1 = 0.5 * (np.tanh((x - nx / 4) / 3.0) - np.tanh((x - 3 * nx / 4) / 3.0))
+        st = orc.State(p, (p.rho_g + (p.rho_l - p.rho_g) * c1).reshape(1, 1, nx), (p.chi * c1).reshape(1, 1, nx))
+        st.run(5000)
+        f = st.fields()
+        errs.append((abs(f["rho"][0, 0, 0] / p.rho_g - 1), abs(f["rho"][0, 0, nx // 2] / p.rho_l - 1)))
+        assert np.abs(f["u"]).max() < 2e-3
+    assert errs[1][1] < 1.2e-2 and errs[1][0] < 5e-2, errs
+    assert errs[1][0] < errs[0][0] and errs[1][1] < errs[0][1], errs
