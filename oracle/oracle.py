@@ -10,6 +10,7 @@ Arrays are numpy float64.  Population arrays have shape ``(Q, nz, ny, nx)``
 from __future__ import annotations
 
 import ctypes
+import math
 import dataclasses
 import os
 import subprocess
@@ -46,6 +47,9 @@ class OrcParams(ctypes.Structure):
         ("chi", ctypes.c_double), ("nu", ctypes.c_double), ("mobility", ctypes.c_double),
         ("tau_phi", ctypes.c_double),
         ("eos", ctypes.c_int32), ("pad", ctypes.c_int32), ("omega", ctypes.c_double),
+        ("walls", ctypes.c_int32), ("pad2", ctypes.c_int32),
+        ("theta_rho_lo", ctypes.c_double), ("theta_rho_hi", ctypes.c_double),
+        ("theta_phi_lo", ctypes.c_double), ("theta_phi_hi", ctypes.c_double),
     ]
 
 
@@ -76,6 +80,12 @@ class Params:
     eos: int = 0          # 0 Carnahan-Starling (Eq. 4), 1 van der Waals, 2 Peng-Robinson
     pad: int = 0
     omega: float = 0.344  # Peng-Robinson acentric factor
+    walls: int = 0        # 1: solid walls at y = -1/2 and y = ny - 1/2 (bounce-back, geometric wetting)
+    pad2: int = 0
+    theta_rho_lo: float = math.pi / 2  # contact angles in radians, measured in the phase
+    theta_rho_hi: float = math.pi / 2  # where the field is large; lo = bottom wall, hi = top
+    theta_phi_lo: float = math.pi / 2
+    theta_phi_hi: float = math.pi / 2
 
     def c_struct(self) -> OrcParams:
         return OrcParams(**{f: getattr(self, f) for f, _ in OrcParams._fields_})

@@ -50,6 +50,10 @@ typedef struct {
     int32_t eos;                  /* 0 Carnahan-Starling (Eq. 4), 1 van der Waals, 2 Peng-Robinson */
     int32_t pad;
     double omega;                 /* Peng-Robinson acentric factor            */
+    int32_t walls;                /* 1: solid walls at y = -1/2 and y = ny - 1/2 */
+    int32_t pad2;
+    double theta_rho_lo, theta_rho_hi; /* contact angles (radians) of the      */
+    double theta_phi_lo, theta_phi_hi; /* rho and phi fields, bottom / top wall */
 } orc_params;
 
 /* ------------------------------------------------------------------------- */
@@ -70,6 +74,13 @@ static void direction(int i, int c[3])
     c[0] = K2C[i % 3];
     c[1] = K2C[(i / 3) % 3];
     c[2] = K2C[i / 9];
+}
+
+/* Index of -c_i: negating every component maps k = 1 <-> 2 and keeps 0. */
+static int opposite(int i)
+{
+    static const int NEG[3] = {0, 2, 1};
+    return NEG[i % 3] + 3 * NEG[(i / 3) % 3] + 9 * NEG[i / 9];
 }
 
 static double w1(int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
@@ -496,7 +507,47 @@ static int64_t neighbour(const orc_params *p, int64_t node, const int c[3])
 
 static int64_t num_nodes(const orc_params *p) { return (int64_t)p->nx * p->ny * p->nz; }
 
-void orc_laplacian(const orc_params *p, const double *psi, double *out)
+/* ------------------------------------------------------------------------- */
+/* Solid walls (the wetting boundary conditions the paper's outlook names;    */
+/* of the approaches it cites, the geometric one).  With walls set, the       */
+/* planes y = -1/2 and y = ny - 1/2 are flat solids and the box stays         */
+/* periodic in x (and z).  Reading:                                          */
+/*  - populations that would stream into a wall return to their node with    */
+/*    the opposite velocity (halfway bounce-back), for f and g alike: no     */
+/*    slip, no flux of mass or phase field through the wall;                 */
+/*  - the stencils see one ghost row beyond each wall.  For rho and phi it   */
+/*    holds the geometric wetting condition n.grad psi = -cot(theta)         */
+/*    |grad_t psi| (theta measured in the phase where psi is large, n the     */
+/*    normal into the fluid), discretised across the wall as                  */
+/*      psi(ghost) = psi(wall row) + cot(theta) |grad_t psi(wall row)|        */
+/*    with central differences along the wall; for the chemical potentials   */
+/*    the ghost repeats the wall row (zero normal gradient, no diffusive     */
+/*    flux).  theta = pi/2 makes every ghost a mirror.                        */
+/* ------------------------------------------------------------------------- */
+
+enum { GHOST_MIRROR = 0, GHOST_WET_RHO = 1, GHOST_WET_PHI = 2 };
+
+/* psi at node n + c, with the ghost rule `mode` where n + c lies beyond a wall. */
+static double stencil_at(const orc_params *p, const double *psi, int64_t n, const int c[3], int mode)
+{
+    int64_t x = n % p->nx, y = (n / p->nx) % p->ny, z = n / ((int64_t)p->nx * p->ny);
+    int64_t yy = y + c[1];
+    if (!p->walls || (yy >= 0 && yy < p->ny)) return psi[neighbour(p, n, c)];
+    int top = yy >= p->ny;
+    int64_t yw = top ? p->ny - 1 : 0;
+    int64_t xx = wrap(x + c[0], p->nx), zz = wrap(z + c[2], p->nz);
+    double v = psi[node_index(p, xx, yw, zz)];
+    if (mode == GHOST_MIRROR) return v;
+    double th = mode == GHOST_WET_RHO ? (top ? p->theta_rho_hi : p->theta_rho_lo)
+                                      : (top ? p->theta_phi_hi : p->theta_phi_lo);
+    double tx = 0.5 * (psi[node_index(p, wrap(xx + 1, p->nx), yw, zz)] - psi[node_index(p, wrap(xx - 1, p->nx), yw, zz)]);
+    double tz = 0.0;
+    if (p->lattice == 1)
+        tz = 0.5 * (psi[node_index(p, xx, yw, wrap(zz + 1, p->nz))] - psi[node_index(p, xx, yw, wrap(zz - 1, p->nz))]);
+    return v + cos(th) / sin(th) * sqrt(tx * tx + tz * tz);
+}
+
+static void laplacian_mode(const orc_params *p, const double *psi, double *out, int mode)
 {
     int Q = lattice_Q(p->lattice);
     int64_t N = num_nodes(p);
@@ -506,14 +557,14 @@ void orc_laplacian(const orc_params *p, const double *psi, double *out)
         for (int i = 0; i < Q; ++i) {
             int c[3];
             direction(i, c);
-            s += weight_lat(p->lattice, i) * (psi[neighbour(p, n, c)] - psi[n]);
+            s += weight_lat(p->lattice, i) * (stencil_at(p, psi, n, c, mode) - psi[n]);
         }
         out[n] = (2.0 / CS2) * s;
     }
 }
 
 /* out is [3][N]; component z stays 0 on D2Q9. */
-void orc_gradient(const orc_params *p, const double *psi, double *out)
+static void gradient_mode(const orc_params *p, const double *psi, double *out, int mode)
 {
     int Q = lattice_Q(p->lattice);
     int64_t N = num_nodes(p);
@@ -523,7 +574,7 @@ void orc_gradient(const orc_params *p, const double *psi, double *out)
         for (int i = 0; i < Q; ++i) {
             int c[3];
             direction(i, c);
-            double v = weight_lat(p->lattice, i) * psi[neighbour(p, n, c)];
+            double v = weight_lat(p->lattice, i) * stencil_at(p, psi, n, c, mode);
             s[0] += v * c[0];
             s[1] += v * c[1];
             s[2] += v * c[2];
@@ -532,6 +583,17 @@ void orc_gradient(const orc_params *p, const double *psi, double *out)
         out[N + n] = s[1] / CS2;
         out[2 * N + n] = s[2] / CS2;
     }
+}
+
+/* The lattice operators on a periodic box (walls, if set, act as mirrors). */
+void orc_laplacian(const orc_params *p, const double *psi, double *out)
+{
+    laplacian_mode(p, psi, out, GHOST_MIRROR);
+}
+
+void orc_gradient(const orc_params *p, const double *psi, double *out)
+{
+    gradient_mode(p, psi, out, GHOST_MIRROR);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -733,8 +795,8 @@ static void chemical_potentials(const orc_params *p, orc_work *w)
     int64_t N = num_nodes(p);
     double abd[3];
     orc_gradient_coefficients(p, abd);
-    orc_laplacian(p, w->rho, w->lap_rho);
-    orc_laplacian(p, w->phi, w->lap_phi);
+    laplacian_mode(p, w->rho, w->lap_rho, GHOST_WET_RHO);
+    laplacian_mode(p, w->phi, w->lap_phi, GHOST_WET_PHI);
 #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; ++n) {
         double mb[2];
@@ -759,8 +821,8 @@ static void thermodynamic_force(const orc_params *p, orc_work *w)
     double *excess = w->lap_rho;   /* reuse: the Laplacian is no longer needed */
 #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; ++n) excess[n] = w->mu_rho[n] - CS2 * log(w->rho[n]);
-    orc_gradient(p, excess, w->grad_rho);
-    orc_gradient(p, w->mu_phi, w->grad_mu_phi);
+    gradient_mode(p, excess, w->grad_rho, GHOST_MIRROR);
+    gradient_mode(p, w->mu_phi, w->grad_mu_phi, GHOST_MIRROR);
 #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; ++n)
         for (int a = 0; a < 3; ++a)
@@ -889,15 +951,19 @@ int orc_run(const orc_params *p, double *f, double *g, int64_t nsteps, double *d
             }
             memcpy(diag + 10 * step, s, sizeof(s));
         }
-        /* 10. streaming: f(x + c_i, t + 1) = f*(x, t) */
+        /* 10. streaming: f(x + c_i, t + 1) = f*(x, t); into a wall: bounce-back,
+         * f_{-i}(x, t + 1) = f*_i(x, t) */
 #pragma omp parallel for schedule(static)
         for (int64_t n = 0; n < N; ++n) {
+            int64_t y = (n / p->nx) % p->ny;
             for (int i = 0; i < Q; ++i) {
                 int c[3];
                 direction(i, c);
-                int64_t m = neighbour(p, n, c);
-                f[(int64_t)i * N + m] = fs[(int64_t)i * N + n];
-                g[(int64_t)i * N + m] = gs[(int64_t)i * N + n];
+                int64_t m = n, j = i;
+                if (p->walls && (y + c[1] < 0 || y + c[1] >= p->ny)) j = opposite(i);
+                else m = neighbour(p, n, c);
+                f[j * N + m] = fs[(int64_t)i * N + n];
+                g[j * N + m] = gs[(int64_t)i * N + n];
             }
         }
     }
