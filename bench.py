@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import subprocess
 import sys
@@ -45,19 +46,21 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def library_params(T, wl, precision, eos=None):
+def library_params(T, wl, precision, eos=None, extra=None):
     """Solver parameters of workload `wl`; `eos` optionally names another free
-    energy as {"eos": kind, "a": a, "b": b}."""
+    energy as {"eos": kind, "a": a, "b": b}; `extra` adds fields (walls,
+    contact angles)."""
     import paper_1710_07486_amd as T_
     nz, ny, nx = wl.shape
     ph = wl.physics()
     return T_.Params(lattice=wl.lattice, precision=precision, nx=nx, ny=ny, nz=nz, T=T,
                      lambda1=ph["lambda1"], lambda2=ph["lambda2"], lambda3=ph["lambda3"],
                      kappa1=ph["kappa1"], kappa2=ph["kappa2"], kappa3=ph["kappa3"], chi=ph["chi"],
-                     nu=ph["nu"], mobility=ph["mobility"], tau_phi=ph["tau_phi"], **(eos or {}))
+                     nu=ph["nu"], mobility=ph["mobility"], tau_phi=ph["tau_phi"], walls=ph.get("walls", 0),
+                     **(eos or {}), **(extra or {}))
 
 
-def measure(wl, precision, steps, warmup, fields=None, coex=None, eos=None):
+def measure(wl, precision, steps, warmup, fields=None, coex=None, eos=None, extra=None):
     """Whole-step MLUPS with HIP events on the solver's stream, and the mean
     duration of each kernel kind.  Drops start at the discretised model's own
     coexistence densities (a 1D slab relaxed by the library, unless `coex`
@@ -67,10 +70,12 @@ def measure(wl, precision, steps, warmup, fields=None, coex=None, eos=None):
     from paper_1710_07486_amd.calibrate import discrete_coexistence
     from synth import workloads as W
     T = T_.temperature_for_ratio(wl.ratio, **(eos or {}))
-    p = library_params(T, wl, precision, eos)
+    p = library_params(T, wl, precision, eos, extra)
     rg = rl = None
     if fields is None:
-        rg, rl = coex if coex else discrete_coexistence(library_params(T, wl, T_.FP64, eos))
+        slab = library_params(T, wl, T_.FP64, eos)
+        slab.walls = 0
+        rg, rl = coex if coex else discrete_coexistence(slab)
         log("discrete coexistence densities", rg, rl)
         fields = W.fields(wl, rg, rl)
     rho, phi, u = fields
@@ -185,6 +190,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the D3Q27 256^3 measurement")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed measurement")
+    ap.add_argument("--no-walls", action="store_true", help="skip the wall-bounded channel measurement")
     ap.add_argument("--no-eos", action="store_true", help="skip the van der Waals / Peng-Robinson measurement")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate throughput measurement")
     ap.add_argument("--coex2d", type=float, nargs=2, metavar=("RHO_G", "RHO_L"),
@@ -269,6 +275,20 @@ def main():
                                          "vs_carnahan_starling": round(re_["mlups"] / r64["mlups"], 3),
                                          "collide_ms": round(re_["kernels_ms"]["collide"], 5),
                                          "finite": bool(np.isfinite(re_["rho"]).all())}
+    if not args.no_walls:
+        # a channel between wetting walls (60 / 120 degrees), caps of liquid 1
+        # and 2 on the walls, same size and ratio as the drops
+        wlw = W.wall_drops(1024, 1024, radius=200.0, ratio=1000.0)
+        ang = {"theta_rho_lo": math.radians(60.0), "theta_phi_lo": math.radians(60.0),
+               "theta_rho_hi": math.radians(120.0), "theta_phi_hi": math.radians(120.0)}
+        result["walls"] = {"workload": wlw.name, "angles_deg": [60.0, 120.0]}
+        for tag, prec in (("fp64", T_.FP64), ("fp32_mixed", T_.FP32_MIXED)):
+            rw, _ = measure(wlw, prec, args.steps, args.warmup, coex=r64["coex"], extra=ang)
+            log("walls", tag, {k: v for k, v in rw.items() if k != "rho"})
+            result["walls"][tag + "_mlups"] = round(rw["mlups"], 2)
+            result["walls"][tag + "_vs_periodic"] = round(rw["mlups"] / (r64["mlups"] if tag == "fp64" else
+                                                                         result.get("fp32_mixed", {}).get("value", float("nan"))), 3)
+            result["walls"][tag + "_finite"] = bool(np.isfinite(rw["rho"]).all())
     if not args.no_3d:
         wl3 = W.collision_3d(256, radius=32, ratio=1000.0, v_rel=0.04, kappa2=0.1, kappa3=0.1)
         s3 = max(10, args.steps // 4)

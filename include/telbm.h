@@ -95,6 +95,21 @@ extern "C" {
  *  rho_ref             reserved (the FP32 form takes each writer's own density).
  *  diag_every          conservation/health diagnostics every this many steps
  *                      (0 disables).
+ *  walls               1: flat solid walls at y = -1/2 and y = ny - 1/2, the
+ *                      box staying periodic in x (and z) -- the wetting
+ *                      boundary conditions the paper's outlook names, in the
+ *                      geometric form it cites first.  Populations streaming
+ *                      into a wall return with the opposite velocity (halfway
+ *                      bounce-back: no slip, no flux of mass or phi).  The
+ *                      stencils see one ghost row beyond each wall: for rho and
+ *                      phi psi(ghost) = psi(wall row) + cot(theta) |grad_t psi|
+ *                      (central differences along the wall), which imposes
+ *                      n.grad psi = -cot(theta) |grad_t psi|, theta the contact
+ *                      angle measured in the phase where psi is large; for the
+ *                      chemical potentials the ghost repeats the wall row.
+ *                      theta_* in (0, pi); pi/2 is neutral.  Needs ny >= 2 and
+ *                      is not available for D3Q27 in the FP32-mixed form nor in
+ *                      the batched form (TELBM_ERR_INVAL).
  * Validation: 0 < T < T_c, rho_l > rho_g > 0, nu > 0, tau_phi > 1/2, chi != 0,
  * sizes >= 1 (nz == 1 for D2Q9), nx*ny*nz < 2^40.                           */
 typedef struct telbm_params {
@@ -114,6 +129,10 @@ typedef struct telbm_params {
     uint32_t diag_every;
     uint32_t reserved1;
     double omega;             /* Peng-Robinson acentric factor (TELBM_EOS_PR)    */
+    int32_t walls;            /* 0: periodic box; 1: solid walls normal to y     */
+    uint32_t reserved2;
+    double theta_rho_lo, theta_rho_hi;  /* contact angles (radians) of the walls */
+    double theta_phi_lo, theta_phi_hi;  /* at y = -1/2 (lo) and ny - 1/2 (hi)    */
 } telbm_params;
 
 /* Diagnostics of the state before step `step` (the last diagnosed step):

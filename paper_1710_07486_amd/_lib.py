@@ -27,6 +27,9 @@ class TelbmParams(ctypes.Structure):
         ("tau_phi", ctypes.c_double), ("rho_ref", ctypes.c_double),
         ("diag_every", ctypes.c_uint32), ("reserved1", ctypes.c_uint32),
         ("omega", ctypes.c_double),
+        ("walls", ctypes.c_int32), ("reserved2", ctypes.c_uint32),
+        ("theta_rho_lo", ctypes.c_double), ("theta_rho_hi", ctypes.c_double),
+        ("theta_phi_lo", ctypes.c_double), ("theta_phi_hi", ctypes.c_double),
     ]
 
 

@@ -122,6 +122,16 @@ int validate(const telbm_params* p, std::string* why) {
     if (N >= 1099511627776.0) { *why = "lattice too large"; return TELBM_ERR_INVAL; }
     if (p->eos < TELBM_EOS_CS || p->eos > TELBM_EOS_PR) { *why = "unknown equation of state"; return TELBM_ERR_INVAL; }
     if (p->eos == TELBM_EOS_PR && !isfinite(p->omega)) { *why = "omega must be finite"; return TELBM_ERR_INVAL; }
+    if (p->walls != 0 && p->walls != 1) { *why = "walls must be 0 or 1"; return TELBM_ERR_INVAL; }
+    if (p->walls) {
+        if (p->ny < 2) { *why = "walls need ny >= 2"; return TELBM_ERR_INVAL; }
+        if (p->lattice == TELBM_D3Q27 && p->precision == TELBM_FP32_MIXED) {
+            *why = "walls are not available for D3Q27 in the FP32-mixed form";
+            return TELBM_ERR_INVAL;
+        }
+        for (double t : {p->theta_rho_lo, p->theta_rho_hi, p->theta_phi_lo, p->theta_phi_hi})
+            if (!(t > 0.0 && t < M_PI)) { *why = "contact angles must lie in (0, pi)"; return TELBM_ERR_INVAL; }
+    }
     double Tc;
     if (!eos_critical_point(eos_of(*p), &Tc, nullptr)) { *why = "a, b, R must be positive"; return TELBM_ERR_INVAL; }
     if (!(p->T > 0.0 && p->T < Tc)) { *why = "T must lie in (0, T_c)"; return TELBM_ERR_INVAL; }
@@ -166,6 +176,12 @@ PhysConst derive(const telbm_params& p, double rho_g, double rho_l, double C) {
     k.Gamma = p.mobility / (p.tau_phi - 0.5);
     k.eos = p.eos;
     k.att = eos_attraction(eos_of(p), p.T);
+    if (p.walls) {
+        k.cot_rho[0] = cos(p.theta_rho_lo) / sin(p.theta_rho_lo);
+        k.cot_rho[1] = cos(p.theta_rho_hi) / sin(p.theta_rho_hi);
+        k.cot_phi[0] = cos(p.theta_phi_lo) / sin(p.theta_phi_lo);
+        k.cot_phi[1] = cos(p.theta_phi_hi) / sin(p.theta_phi_hi);
+    }
     return k;
 }
 
@@ -414,7 +430,7 @@ int telbm_create(const telbm_params* p, void* device_arena, size_t bytes, telbm_
     s->p.rho_l = rl;
     s->k = derive(*p, rg, rl, C);
     s->Q = p->lattice == TELBM_D2Q9 ? 9 : 27;
-    s->g = GridDims{p->nx, p->ny, p->nz, 0, (int64_t)p->nx * p->ny * p->nz};
+    s->g = GridDims{p->nx, p->ny, p->nz, p->walls, (int64_t)p->nx * p->ny * p->nz};
     s->pop_bytes = L.pop;
     s->arena = (char*)device_arena;
     s->arena_bytes = bytes;

@@ -183,6 +183,10 @@ int check_params(const telbm_params* p, int count, std::string* why) {
             *why = "all instances of a batch share lattice and precision";
             return TELBM_ERR_INVAL;
         }
+        if (p[i].walls) {
+            *why = "the batched form runs periodic boxes only (instance " + std::to_string(i) + " has walls)";
+            return TELBM_ERR_INVAL;
+        }
         size_t b;
         const int rc = telbm_required_bytes(&p[i], &b);
         if (rc) {

@@ -107,20 +107,22 @@ __device__ void diag_block_reduce(double* vals, double* __restrict__ out) {
 // ---------------------------------------------------------------------------
 // Kernels of the three phases over one lattice (one node per thread).
 // ---------------------------------------------------------------------------
-template <int L, typename T>
+// W: instance for lattices with walls (the periodic instance carries none of
+// the wall logic and keeps its registers).
+template <int L, typename T, bool W>
 __global__ __launch_bounds__(BX* BY) void k_moments(GridDims g, const T* __restrict__ pop,
                                                     const double* __restrict__ rho_ref,
                                                     double* __restrict__ rho, double* __restrict__ phi) {
     const Tile t = tile_coords(g);
-    if (t.in) node_moments<L, T>(g, pop, rho_ref, rho, phi, t.x, t.y, t.z);
+    if (t.in) node_moments<L, T, W>(g, pop, rho_ref, rho, phi, t.x, t.y, t.z);
 }
 
-template <int L, int E>
+template <int L, int E, bool W>
 __global__ __launch_bounds__(BX* BY) void k_chempot(GridDims g, PhysConst k, const double* __restrict__ rho,
                                                     const double* __restrict__ phi, double* __restrict__ mux,
                                                     double* __restrict__ mup) {
     const Tile t = tile_coords(g);
-    if (t.in) node_chempot<L, E>(g, k, rho, phi, mux, mup, t.x, t.y, t.z);
+    if (t.in) node_chempot<L, E, W>(g, k, rho, phi, mux, mup, t.x, t.y, t.z);
 }
 
 __device__ __forceinline__ int wrap_any(int v, int n) {
@@ -147,7 +149,7 @@ constexpr int CPX = BX + 2, CPY = BY + 2, CPN = CPX * CPY;
 // inbox entries that the previous D3Q27 FP64 collision (k_collide_next3) left;
 // the kernel completes them while staging (see next3_complete) and also writes
 // the completed rho, phi of its nodes.
-template <bool PART, int E>
+template <bool PART, int E, bool W>
 __global__ __launch_bounds__(BX* BY) void k_chempot_col(GridDims g, PhysConst k, double* __restrict__ rho,
                                                         double* __restrict__ phi, double* __restrict__ mux,
                                                         double* __restrict__ mup, const double* __restrict__ part,
@@ -159,21 +161,37 @@ __global__ __launch_bounds__(BX* BY) void k_chempot_col(GridDims g, PhysConst k,
     const int bx = b % bxc, rest = b / bxc, by = rest % byc, bzc = rest / byc;
     const int x0 = bx * BX, y0 = by * BY, z0 = bzc * CZ;
     const int tid = threadIdx.y * BX + threadIdx.x;
+    // the (completed) densities of node (gx, gy, zw)
+    auto get = [&](int gx, int gy, int zw, double& r, double& p) {
+        const int64_t n = ((int64_t)zw * g.ny + gy) * g.nx + gx;
+        if (PART) {
+            next3_complete(g, part, inbox, gx, gy, zw, n, r, p);
+        } else {
+            r = rho[n];
+            p = phi[n];
+        }
+    };
     auto load_plane = [&](int slot, int z) {
         const int zw = wrap_any(z, g.nz);
-        const int64_t zo = (int64_t)zw * g.ny;
         for (int e = tid; e < CPN; e += BX * BY) {
-            const int gx = wrap_any(x0 - 1 + e % CPX, g.nx), gy = wrap_any(y0 - 1 + e / CPX, g.ny);
-            const int64_t n = (zo + gy) * g.nx + gx;
-            if (PART) {
-                double r, p;
-                next3_complete(g, part, inbox, gx, gy, zw, n, r, p);
-                sr[slot][e] = r;
-                sp[slot][e] = p;
+            const int gx = wrap_any(x0 - 1 + e % CPX, g.nx), yy = y0 - 1 + e / CPX;
+            double r, p;
+            if (W && g.walls && (yy < 0 || yy >= g.ny)) {
+                // beyond a wall: the wetting ghost of the wall-row node
+                const int top = yy >= g.ny, yw = top ? g.ny - 1 : 0;
+                double rxm, pxm, rxp, pxp, rzm, pzm, rzp, pzp;
+                get(gx == 0 ? g.nx - 1 : gx - 1, yw, zw, rxm, pxm);
+                get(gx + 1 == g.nx ? 0 : gx + 1, yw, zw, rxp, pxp);
+                get(gx, yw, zw == 0 ? g.nz - 1 : zw - 1, rzm, pzm);
+                get(gx, yw, zw + 1 == g.nz ? 0 : zw + 1, rzp, pzp);
+                get(gx, yw, zw, r, p);
+                r = wet_ghost(r, 0.5 * (rxp - rxm), 0.5 * (rzp - rzm), k.cot_rho[top]);
+                p = wet_ghost(p, 0.5 * (pxp - pxm), 0.5 * (pzp - pzm), k.cot_phi[top]);
             } else {
-                sr[slot][e] = rho[n];
-                sp[slot][e] = phi[n];
+                get(gx, wrap_any(yy, g.ny), zw, r, p);
             }
+            sr[slot][e] = r;
+            sp[slot][e] = p;
         }
     };
     load_plane(0, z0 - 1);
@@ -294,7 +312,9 @@ __device__ __forceinline__ void inbox_complete(const GridDims& g, const double* 
                                                double& r, double& p) {
     using I = Inbox<TH>;
     const TilePos t = tile_pos<TH>(g, gx, gy);
-    const bool x0 = t.lx == 0, x1 = t.lx == t.W - 1, y0 = t.ly == 0, y1 = t.ly == t.H - 1;
+    // a tile edge on a wall receives nothing from beyond it
+    const bool x0 = t.lx == 0, x1 = t.lx == t.W - 1;
+    const bool y0 = t.ly == 0 && !(g.walls && gy == 0), y1 = t.ly == t.H - 1 && !(g.walls && gy == g.ny - 1);
     if (!(x0 || x1 || y0 || y1)) return;
     const double* b = in + (int64_t)t.tile * I::SIZE * 2;
     auto add = [&](int slot) {
@@ -321,7 +341,8 @@ __device__ __forceinline__ void inbox_complete_fast(const GridDims& g, const dou
                                                     int gy, double& r, double& p) {
     using I = Inbox<TH>;
     const TilePos t = tile_pos<TH>(g, gx, gy);
-    const bool x0 = t.lx == 0, x1 = t.lx == t.W - 1, y0 = t.ly == 0, y1 = t.ly == t.H - 1;
+    const bool x0 = t.lx == 0, x1 = t.lx == t.W - 1;
+    const bool y0 = t.ly == 0 && !(g.walls && gy == 0), y1 = t.ly == t.H - 1 && !(g.walls && gy == g.ny - 1);
     if (!(x0 || x1 || y0 || y1)) return;
     if (t.W < 2 || t.H < 2) {
         inbox_complete<TH>(g, in, gx, gy, r, p);
@@ -417,7 +438,21 @@ struct NextSink {
     double* sum;
     double* side;
     int lx, ly, W;
+    // c_y of the directions that stream into a wall from this node's row (-1
+    // on the bottom wall row, +1 on the top one, 0 elsewhere; uniform over a
+    // wavefront): they bounce back to the node itself, so their values join
+    // the node's own target (group c_y = c_z = 0)
+    int wall_cy;
     __device__ __forceinline__ void put(int field, const double* v) {
+        double back = 0.0;
+        if (wall_cy != 0) {
+#pragma unroll
+            for (int gi = 0; gi < NG; ++gi) {
+                const int cy = row_offset(gi % 3), cz = row_offset(gi / 3);
+                if (cy != wall_cy) continue;
+                back += v[lat_dir<L>(0, cy, cz)] + v[lat_dir<L>(1, cy, cz)] + v[lat_dir<L>(-1, cy, cz)];
+            }
+        }
 #pragma unroll
         for (int gi = 0; gi < NG; ++gi) {
             const int cy = row_offset(gi % 3), cz = row_offset(gi / 3);
@@ -427,6 +462,7 @@ struct NextSink {
             double t = a;
             if (lx >= 1) t += bl;
             if (lx + 1 < W) t += cr;
+            if (cy == 0 && cz == 0) t += back;
             sum[((field * NG + gi) * TH + ly) * BX + lx] = t;
             if (lx == 0) side[((field * 2 + 0) * NG + gi) * TH + ly] = c;
             if (lx == W - 1) side[((field * 2 + 1) * NG + gi) * TH + ly] = b;
@@ -497,18 +533,37 @@ __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysCons
     const int tid = threadIdx.y * BX + threadIdx.x;
     // densities of the tile and its halo; partial sums (inbox_in set) are
     // completed with the inbox entries of their nodes
+    auto load = [&](int gx, int gy, double& r, double& p) {
+        const int64_t n = (int64_t)gy * g.nx + gx;
+        r = rho[n];
+        p = phi[n];
+        if (inbox_in) inbox_complete_fast<FBY>(g, inbox_in, gx, gy, r, p);
+    };
     for (int e = tid; e < FHX * FHY; e += BX * FBY) {
         const int hx = e % FHX, hy = e / FHX;
-        const int gx = wrap_any(x0 - 2 + hx, g.nx), gy = wrap_any(y0 - 2 + hy, g.ny);
-        const int64_t n = (int64_t)gy * g.nx + gx;
-        double r = rho[n], p = phi[n];
-        if (inbox_in) inbox_complete_fast<FBY>(g, inbox_in, gx, gy, r, p);
+        const int gx = wrap_any(x0 - 2 + hx, g.nx), yy = y0 - 2 + hy;
+        double r, p;
+        if (g.walls && (yy < 0 || yy >= g.ny)) {
+            // beyond a wall: the wetting ghost of the wall-row node below/above
+            const int top = yy >= g.ny, yw = top ? g.ny - 1 : 0;
+            double rm, pm, rp, pp;
+            load(gx == 0 ? g.nx - 1 : gx - 1, yw, rm, pm);
+            load(gx + 1 == g.nx ? 0 : gx + 1, yw, rp, pp);
+            load(gx, yw, r, p);
+            r = wet_ghost(r, 0.5 * (rp - rm), 0.0, k.cot_rho[top]);
+            p = wet_ghost(p, 0.5 * (pp - pm), 0.0, k.cot_phi[top]);
+        } else {
+            load(gx, wrap_any(yy, g.ny), r, p);
+        }
         sr[e] = r;
         sp[e] = p;
     }
     __syncthreads();
     for (int e = tid; e < FMX * FMY; e += BX * FBY) {
-        const int c = (e / FMX + 1) * FHX + e % FMX + 1;
+        // beyond a wall the potentials repeat the wall row
+        const int yy = y0 - 1 + e / FMX;
+        const int my = g.walls ? (yy < 0 ? 1 : (yy == g.ny ? -1 : 0)) : 0;
+        const int c = (e / FMX + 1 + my) * FHX + e % FMX + 1;
         const double r0 = sr[c], p0 = sp[c];
         double lr = 0.0, lp = 0.0;
 #pragma unroll
@@ -531,14 +586,15 @@ __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysCons
         const bool active = (int)threadIdx.x < W && (int)threadIdx.y < H;
         const LdsAux2 aux{sr, sp, smx, smp, lx, ly};
         if (rho_final && active) rho_final[(int64_t)(y0 + ly) * g.nx + x0 + lx] = aux.rho0(0);
-        Sink sink{nsum, nside, (int)threadIdx.x, (int)threadIdx.y, W};
+        const int wy = g.walls ? (y0 + ly == 0 ? -1 : (y0 + ly == g.ny - 1 ? 1 : 0)) : 0;
+        Sink sink{nsum, nside, (int)threadIdx.x, (int)threadIdx.y, W, wy};
         node_collide_sink<kD2Q9, T>(g, k, src, dst, rho_ref, aux, x0 + lx, y0 + ly, 0, diag != 0, dv, active,
                                     sink);
     }
     if (diag) diag_block_reduce<BX * FBY>(dv, partials);
     __syncthreads();
     // next moments of the tile (each thread its own node) and of its ring
-    const Sink view{nsum, nside, 0, 0, W};
+    const Sink view{nsum, nside, 0, 0, W, 0};
     if ((int)threadIdx.x < W && (int)threadIdx.y < H) {
         double s0, s1;
         view.gather(threadIdx.x, threadIdx.y, 0, H, s0, s1);
@@ -559,6 +615,8 @@ __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysCons
             ey = c % FBY;
             if (ey >= H) continue;
         }
+        // nothing streams into a wall (those values bounced back in the sink)
+        if (g.walls && ((ey < 0 && y0 == 0) || (ey >= H && y0 + H == g.ny))) continue;
         double s0, s1;
         view.gather(ex, ey, 0, H, s0, s1);
         const int64_t q2 = 2 * inbox_target<FBY>(g, x0, y0, W, H, ex, ey);
@@ -631,6 +689,7 @@ __device__ __forceinline__ void next3_complete(const GridDims& g, const double* 
         inbox_complete_fast<BY>(g, inbox + ((int64_t)z * 3 + k) * tiles * INBOX3 * 2, gx, gy, r, p);
 }
 
+template <bool WALL>
 __global__ __launch_bounds__(BX* BY) void k_collide_next3(GridDims g, PhysConst k, const double* __restrict__ src,
                                                           double* __restrict__ dst, const double* __restrict__ rho,
                                                           const double* __restrict__ phi,
@@ -653,14 +712,15 @@ __global__ __launch_bounds__(BX* BY) void k_collide_next3(GridDims g, PhysConst 
         const int lx = min((int)threadIdx.x, W - 1), ly = min((int)threadIdx.y, H - 1);
         const bool active = (int)threadIdx.x < W && (int)threadIdx.y < H;
         const GlobalAux aux{rho, phi, mux, mup};
-        Sink sink{nsum, nside, (int)threadIdx.x, (int)threadIdx.y, W};
-        node_collide_sink<kD3Q27, double>(g, k, src, dst, nullptr, aux, x0 + lx, y0 + ly, bz, diag != 0, dv, active,
-                                          sink);
+        const int wy = (WALL && g.walls) ? (y0 + ly == 0 ? -1 : (y0 + ly == g.ny - 1 ? 1 : 0)) : 0;
+        Sink sink{nsum, nside, (int)threadIdx.x, (int)threadIdx.y, W, wy};
+        node_collide_sink<kD3Q27, double, GlobalAux, Sink, WALL>(g, k, src, dst, nullptr, aux, x0 + lx, y0 + ly, bz,
+                                                              diag != 0, dv, active, sink);
     }
     if (diag) diag_block_reduce(dv, partials);
     __syncthreads();
     const int64_t tiles = (int64_t)bxc * byc;
-    const Sink view{nsum, nside, 0, 0, W};
+    const Sink view{nsum, nside, 0, 0, W, 0};
     double2* P = reinterpret_cast<double2*>(part);
     double2* I = reinterpret_cast<double2*>(inbox);
     // tile nodes: each thread gathers its own node's three target planes
@@ -691,6 +751,8 @@ __global__ __launch_bounds__(BX* BY) void k_collide_next3(GridDims g, PhysConst 
             ey = c % BY;
             if (ey >= H) continue;
         }
+        // nothing streams into a wall (those values bounced back in the sink)
+        if (WALL && g.walls && ((ey < 0 && y0 == 0) || (ey >= H && y0 + H == g.ny))) continue;
         double s0, s1;
         view.gather(ex, ey, kz, H, s0, s1);
         const int dz = row_offset(kz);
@@ -757,12 +819,16 @@ __global__ __launch_bounds__(BX* BY) void k_init(GridDims g, PhysConst k, const 
     equilibria<L, R>(r, R(phi[n]), R(mup[n]), u, R(k.Gamma), Deviation<T>::on ? r : 0.0, fd, gg);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const int64_t m = n + nbr_off<L>(nb, i, -1);
+        // the slot the pull of direction i at this node reads: that of x - c_i,
+        // or this node's slot of -c_i where x - c_i lies beyond a wall
+        const bool bb = bounce(g, t.y, Lt::c[i][1]);
+        const int64_t m = bb ? n : n + nbr_off<L>(nb, i, -1);
+        const int s = bb ? opp_dir(i) : i;
         // FP32: the value stored at m is relative to the density held for m
         R v = fd[i];
         if (Deviation<T>::on) v += R(Lt::w[i] * (r - rho[m]));
-        pop[(int64_t)i * g.N + m] = v;
-        pop[(int64_t)(Q + i) * g.N + m] = gg[i];
+        pop[(int64_t)s * g.N + m] = v;
+        pop[(int64_t)(Q + s) * g.N + m] = gg[i];
     }
 }
 
@@ -796,7 +862,7 @@ __global__ __launch_bounds__(BX* BY) void k_macro(GridDims g, PhysConst k, const
     constexpr int Q = Lt::Q;
     const Tile t = tile_coords(g);
     if (!t.in) return;
-    const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
+    const Nbr nb = make_nbr_w(g, t.x, t.y, t.z);
     const int64_t n = node_of(g, t);
     const double r = rho[n], p = phi[n];
     double v = 0.0;
@@ -823,8 +889,9 @@ __global__ __launch_bounds__(BX* BY) void k_macro(GridDims g, PhysConst k, const
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 if (Lt::c[i][d] == 0) continue;
-                const int64_t m = n + nbr_off<L>(nb, i, -1);
-                double fi = double(pop[(int64_t)i * g.N + m]);
+                const bool bb = bounce(g, t.y, Lt::c[i][1]);
+                const int64_t m = bb ? n : n + nbr_off<L>(nb, i, -1);
+                double fi = double(pop[(int64_t)(bb ? opp_dir(i) : i) * g.N + m]);
                 if (Deviation<T>::on) fi += Lt::w[i] * rho_ref[m];
                 j += Lt::c[i][d] > 0 ? fi : -fi;
             }
@@ -859,14 +926,21 @@ template <int L, typename T, int E>
 static hipError_t launch_step_parts(const StepArgs& a, int part) {
     const dim3 blk(BX, BY, 1);
     const dim3 grd(grid_blocks(a.g), 1, 1);
+    const bool w = a.g.walls != 0;
     if (part == 0) {
-        k_moments<L, T><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
+        if (w) k_moments<L, T, true><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
+        else k_moments<L, T, false><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
     } else if (part == 1) {
         if (L == kD3Q27) {
-            k_chempot_col<false, E><<<col_blocks(a.g), blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup, nullptr,
-                                                                        nullptr);
+            if (w)
+                k_chempot_col<false, E, true><<<col_blocks(a.g), blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux,
+                                                                                   a.mup, nullptr, nullptr);
+            else
+                k_chempot_col<false, E, false><<<col_blocks(a.g), blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux,
+                                                                                    a.mup, nullptr, nullptr);
         } else {
-            k_chempot<L, E><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup);
+            if (w) k_chempot<L, E, true><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup);
+            else k_chempot<L, E, false><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup);
         }
     } else if (part == 2) {
         k_collide<L, T><<<grd, blk, 0, a.stream>>>(a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref, a.rho,
@@ -882,12 +956,22 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
         if (a.diag) k_diag_final<<<1, 256, 0, a.stream>>>(a.partials, (int)fb, a.diag_out);
     } else if (part == 5) {
         if (L != kD3Q27 || !a.part3 || !a.inbox3) return hipErrorInvalidValue;
-        k_chempot_col<true, E><<<col_blocks(a.g), blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup, a.part3,
-                                                                   a.inbox3);
+        if (w)
+            k_chempot_col<true, E, true><<<col_blocks(a.g), blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup,
+                                                                              a.part3, a.inbox3);
+        else
+            k_chempot_col<true, E, false><<<col_blocks(a.g), blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux,
+                                                                               a.mup, a.part3, a.inbox3);
     } else if (part == 6) {
         if (L != kD3Q27 || Deviation<T>::on || !a.part3 || !a.inbox3) return hipErrorInvalidValue;
-        k_collide_next3<<<grd, blk, 0, a.stream>>>(a.g, a.k, (const double*)a.src, (double*)a.dst, a.rho, a.phi,
-                                                   a.mux, a.mup, a.part3, a.inbox3, a.partials, a.diag);
+        if (w)
+            k_collide_next3<true><<<grd, blk, 0, a.stream>>>(a.g, a.k, (const double*)a.src, (double*)a.dst, a.rho,
+                                                             a.phi, a.mux, a.mup, a.part3, a.inbox3, a.partials,
+                                                             a.diag);
+        else
+            k_collide_next3<false><<<grd, blk, 0, a.stream>>>(a.g, a.k, (const double*)a.src, (double*)a.dst, a.rho,
+                                                              a.phi, a.mux, a.mup, a.part3, a.inbox3, a.partials,
+                                                              a.diag);
         if (a.diag) k_diag_final<<<1, 256, 0, a.stream>>>(a.partials, (int)grd.x, a.diag_out);
     } else if (part == 4) {
         if (L != kD2Q9 || a.g.nz != 1 || !a.inbox_in) return hipErrorInvalidValue;

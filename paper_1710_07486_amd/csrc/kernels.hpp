@@ -17,7 +17,7 @@ constexpr int kFieldRho = 0, kFieldPhi = 1, kFieldUx = 2, kFieldUy = 3, kFieldUz
 
 struct GridDims {
     int nx, ny, nz;
-    int pad;
+    int walls;  // 1: solid walls at y = -1/2 and y = ny - 1/2 (x, z stay periodic)
     int64_t N;
 };
 

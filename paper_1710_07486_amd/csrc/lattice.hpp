@@ -49,6 +49,17 @@ struct Lattice<kD3Q27> {
         1.0 / 216, 1.0 / 216, 1.0 / 216, 1.0 / 216, 1.0 / 216, 1.0 / 216, 1.0 / 216, 1.0 / 216};
 };
 
+// Index of -c_i: opposite directions are adjacent pairs (2p-1, 2p).
+__host__ __device__ constexpr int opp_dir(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+template <int L>
+__host__ __device__ constexpr bool opposites_paired() {
+    for (int i = 0; i < Lattice<L>::Q; ++i)
+        for (int d = 0; d < 3; ++d)
+            if (Lattice<L>::c[opp_dir(i)][d] != -Lattice<L>::c[i][d]) return false;
+    return true;
+}
+static_assert(opposites_paired<kD2Q9>() && opposites_paired<kD3Q27>(), "opposite directions are paired");
+
 // Per-instance constants, precomputed on the host from the parameters.
 struct PhysConst {
     // equation of state (Eq. 4) and bulk free energy (Eq. 2)
@@ -70,7 +81,17 @@ struct PhysConst {
     // att: attraction a (CS, vdW) or a alpha(T) (PR)
     int eos;
     double att;
+    // solid walls at y = -1/2 and y = ny - 1/2 (GridDims::walls): cot of the
+    // contact angles of rho and phi at the bottom [0] and top [1] wall
+    double cot_rho[2], cot_phi[2];
 };
+
+// Ghost value of rho or phi beyond a wall (geometric wetting condition): the
+// wall-row value v plus cot(theta) times the magnitude of its gradient along
+// the wall, from central differences tx (along x) and tz (along z, 0 in 2D).
+__device__ __forceinline__ double wet_ghost(double v, double tx, double tz, double cot) {
+    return v + cot * sqrt(tx * tx + tz * tz);
+}
 
 // Periodic neighbour offsets of one node: off[d][k] is the element offset of
 // the neighbour at displacement k-1 along axis d.

@@ -28,9 +28,54 @@ __device__ __forceinline__ int64_t node_index(const GridDims& g, int x, int y, i
     return ((int64_t)z * g.ny + y) * g.nx + x;
 }
 
+// Solid walls at y = -1/2 and y = ny - 1/2 (g.walls).  A population whose
+// pull source x - c_i lies beyond a wall comes back from the node's own slot
+// of -c_i (halfway bounce-back); bounce(g, y, cy) says so for c_y = cy.
+__device__ __forceinline__ bool bounce(const GridDims& g, int y, int cy) {
+    return g.walls && ((cy > 0 && y == 0) || (cy < 0 && y == g.ny - 1));
+}
+// Stencil neighbour y + cy beyond a wall.
+__device__ __forceinline__ bool beyond_wall(const GridDims& g, int y, int cy) {
+    return g.walls && ((cy < 0 && y == 0) || (cy > 0 && y == g.ny - 1));
+}
+
+// Neighbour offsets that repeat the wall row beyond a wall (the ghost rule of
+// the chemical potentials); periodic elsewhere.
+__device__ __forceinline__ Nbr make_nbr_w(const GridDims& g, int x, int y, int z) {
+    Nbr n = make_nbr(x, y, z, g.nx, g.ny, g.nz);
+    if (g.walls) {
+        if (y == 0) n.oy[0] = 0;
+        if (y == g.ny - 1) n.oy[2] = 0;
+    }
+    return n;
+}
+
+// Wetting ghosts of rho and phi beyond the wall next to the wall-row node
+// (xw, yw, zw) (top: the wall at y = ny - 1/2).
+template <int L>
+__device__ __forceinline__ void wall_ghosts(const GridDims& g, const PhysConst& k, const double* __restrict__ rho,
+                                            const double* __restrict__ phi, int xw, int yw, int zw, int top,
+                                            double& gr, double& gp) {
+    const int64_t c = node_index(g, xw, yw, zw);
+    const int64_t ep = node_index(g, xw + 1 == g.nx ? 0 : xw + 1, yw, zw);
+    const int64_t em = node_index(g, xw == 0 ? g.nx - 1 : xw - 1, yw, zw);
+    const double rx = 0.5 * (rho[ep] - rho[em]), px = 0.5 * (phi[ep] - phi[em]);
+    double rz = 0.0, pz = 0.0;
+    if (Lattice<L>::D == 3) {
+        const int64_t zp = node_index(g, xw, yw, zw + 1 == g.nz ? 0 : zw + 1);
+        const int64_t zm = node_index(g, xw, yw, zw == 0 ? g.nz - 1 : zw - 1);
+        rz = 0.5 * (rho[zp] - rho[zm]);
+        pz = 0.5 * (phi[zp] - phi[zm]);
+    }
+    gr = wet_ghost(rho[c], rx, rz, k.cot_rho[top]);
+    gp = wet_ghost(phi[c], px, pz, k.cot_phi[top]);
+}
+
 // Phase 1: rho = sum_i f_i, phi = sum_i g_i of the pulled populations, FP64
 // accumulation.  rho_ref: densities the stored f values are relative to.
-template <int L, typename T>
+// W: the lattice may have walls (kernels instantiated without them carry none
+// of the wall logic).
+template <int L, typename T, bool W = false>
 __device__ __forceinline__ void node_moments(const GridDims& g, const T* __restrict__ pop,
                                              const double* __restrict__ rho_ref, double* __restrict__ rho,
                                              double* __restrict__ phi, int x, int y, int z) {
@@ -41,11 +86,13 @@ __device__ __forceinline__ void node_moments(const GridDims& g, const T* __restr
     double r = 0.0, p = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const int64_t m = n + nbr_off<L>(nb, i, -1);
-        double fi = double(pop[(int64_t)i * g.N + m]);
+        const bool bb = W && bounce(g, y, Lt::c[i][1]);
+        const int64_t m = bb ? n : n + nbr_off<L>(nb, i, -1);
+        const int s = bb ? opp_dir(i) : i;
+        double fi = double(pop[(int64_t)s * g.N + m]);
         if (Deviation<T>::on) fi += Lt::w[i] * rho_ref[m];
         r += fi;
-        p += double(pop[(int64_t)(Q + i) * g.N + m]);
+        p += double(pop[(int64_t)(Q + s) * g.N + m]);
     }
     rho[n] = r;
     phi[n] = p;
@@ -53,7 +100,7 @@ __device__ __forceinline__ void node_moments(const GridDims& g, const T* __restr
 
 // Phase 2: chemical potentials with the lattice Laplacians
 // lap psi(x) = 6 sum_i w_i [psi(x + c_i) - psi(x)].
-template <int L, int E>
+template <int L, int E, bool W = false>
 __device__ __forceinline__ void node_chempot(const GridDims& g, const PhysConst& k, const double* __restrict__ rho,
                                              const double* __restrict__ phi, double* __restrict__ mux,
                                              double* __restrict__ mup, int x, int y, int z) {
@@ -65,9 +112,18 @@ __device__ __forceinline__ void node_chempot(const GridDims& g, const PhysConst&
     double lr = 0.0, lp = 0.0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        const int64_t m = n + nbr_off<L>(nb, i, +1);
-        lr += Lt::w[i] * (rho[m] - r0);
-        lp += Lt::w[i] * (phi[m] - p0);
+        double rm, pm;
+        if (W && beyond_wall(g, y, Lt::c[i][1])) {
+            const int xw = x + Lt::c[i][0], zw = z + Lt::c[i][2];
+            wall_ghosts<L>(g, k, rho, phi, xw < 0 ? g.nx - 1 : (xw == g.nx ? 0 : xw), y,
+                           zw < 0 ? g.nz - 1 : (zw == g.nz ? 0 : zw), y != 0, rm, pm);
+        } else {
+            const int64_t m = n + nbr_off<L>(nb, i, +1);
+            rm = rho[m];
+            pm = phi[m];
+        }
+        lr += Lt::w[i] * (rm - r0);
+        lp += Lt::w[i] * (pm - p0);
     }
     double mx, mp;
     chem_pot<E>(k, r0, p0, 6.0 * lr, 6.0 * lp, &mx, &mp);
@@ -128,6 +184,18 @@ __device__ __forceinline__ Nbr32 make_nbr32(int x, int y, int z, int nx, int ny,
     n.oz[1] = 0;
     n.oz[0] = (z == 0 ? nz - 1 : -1) * sz;
     n.oz[2] = (z == nz - 1 ? -(nz - 1) : 1) * sz;
+    return n;
+}
+
+// The same with the wall row repeated beyond a wall (walls set): potentials
+// read there take the ghost rule of the chemical potentials, and the pulls of
+// bounced directions address the node's own row (read from the slot of -c_i).
+__device__ __forceinline__ Nbr32 make_nbr32_w(const GridDims& g, int x, int y, int z) {
+    Nbr32 n = make_nbr32(x, y, z, g.nx, g.ny, g.nz);
+    if (g.walls) {
+        if (y == 0) n.oy[0] = 0;
+        if (y == g.ny - 1) n.oy[2] = 0;
+    }
     return n;
 }
 
@@ -208,7 +276,8 @@ struct NoSink {
 // so that their loads do not all become live at once.  With active false the
 // node is computed but nothing is stored or reported (lanes past a ragged
 // edge that run on a clamped node so that the sink sees a full wavefront).
-template <int L, typename T, typename AUX, typename SINK>
+// W false: the lattice has no walls (the kernel carries none of their logic).
+template <int L, typename T, typename AUX, typename SINK, bool W = true>
 __device__ __forceinline__ void node_collide_sink(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
                                                   T* __restrict__ dst, const double* __restrict__ rho_ref,
                                                   const AUX& aux, int x, int y, int z, bool diag, double* dv,
@@ -216,7 +285,7 @@ __device__ __forceinline__ void node_collide_sink(const GridDims& g, const PhysC
     using Lt = Lattice<L>;
     using R = T;
     constexpr int Q = Lt::Q;
-    const Nbr32 nb = make_nbr32(x, y, z, g.nx, g.ny, g.nz);
+    const Nbr32 nb = W ? make_nbr32_w(g, x, y, z) : make_nbr32(x, y, z, g.nx, g.ny, g.nz);
     const uint32_t n = (uint32_t)node_index(g, x, y, z);
     const double r = aux.rho0(n), p = aux.phi0(n);
 
@@ -248,9 +317,12 @@ __device__ __forceinline__ void node_collide_sink(const GridDims& g, const PhysC
     R jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
+        // a bounced direction reads the node's own slot of -c_i (its address
+        // below is the node itself: the wall row repeats beyond the wall)
+        const bool bb = W && bounce(g, y, Lt::c[i][1]);
         const uint32_t m = nbr32<L>(nb, n, i, -1);
-        R v = ld_pop<L>(src + (size_t)i * g.N, m);
-        if (Deviation<T>::on) v += R(Lt::w[i] * (ld(rho_ref, m) - r));
+        R v = bb ? ld_pop<L>(src + (size_t)opp_dir(i) * g.N, n) : ld_pop<L>(src + (size_t)i * g.N, m);
+        if (Deviation<T>::on) v += R(Lt::w[i] * (ld(rho_ref, bb ? n : m) - r));
         f[i] = v;
         if (Lt::c[i][0]) jx += Lt::c[i][0] > 0 ? v : -v;
         if (Lt::c[i][1]) jy += Lt::c[i][1] > 0 ? v : -v;
@@ -270,7 +342,9 @@ __device__ __forceinline__ void node_collide_sink(const GridDims& g, const PhysC
 
     R gg[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) gg[i] = ld_pop<L>(src + (size_t)(Q + i) * g.N, nbr32<L>(nb, n, i, -1));
+    for (int i = 0; i < Q; ++i)
+        gg[i] = (W && bounce(g, y, Lt::c[i][1])) ? ld_pop<L>(src + (size_t)(Q + opp_dir(i)) * g.N, n)
+                                          : ld_pop<L>(src + (size_t)(Q + i) * g.N, nbr32<L>(nb, n, i, -1));
     R up[3] = {u[0] + R(0.5) * du[0], u[1] + R(0.5) * du[1], u[2] + R(0.5) * du[2]};
     collide_g<L, R>(gg, R(p), R(aux.mup0(n)), up, R(k.Gamma), R(k.omega_phi));
     if (active) {

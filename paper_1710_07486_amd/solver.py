@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import math
 from typing import Optional
 
 import numpy as np
@@ -44,6 +45,11 @@ class Params:
     diag_every: int = 0
     eos: int = 0          # 0 Carnahan-Starling (Eq. 4), 1 van der Waals, 2 Peng-Robinson
     omega: float = 0.344  # Peng-Robinson acentric factor
+    walls: int = 0        # 1: solid walls at y = -1/2 and y = ny - 1/2 (bounce-back, geometric wetting)
+    theta_rho_lo: float = math.pi / 2  # contact angles (radians) at the bottom (lo) and top (hi)
+    theta_rho_hi: float = math.pi / 2  # wall, measured in the phase where rho / phi is large
+    theta_phi_lo: float = math.pi / 2
+    theta_phi_hi: float = math.pi / 2
 
     def c_struct(self) -> TelbmParams:
         kw = {f: getattr(self, f) for f, _ in TelbmParams._fields_ if hasattr(self, f)}

@@ -27,13 +27,17 @@ def _min_image(d, n):
     return d - n * np.round(d / n)
 
 
-def drop_indicator(shape, center: Sequence[float], radius: float, width: float = 3.0) -> np.ndarray:
-    """Smooth indicator of a disc/ball of ``radius`` at ``center`` (x, y[, z])."""
+def drop_indicator(shape, center: Sequence[float], radius: float, width: float = 3.0,
+                   periodic_y: bool = True) -> np.ndarray:
+    """Smooth indicator of a disc/ball of ``radius`` at ``center`` (x, y[, z]);
+    with periodic_y False the distance along y is not wrapped (a box bounded
+    by walls in y)."""
     nz, ny, nx = shape
     x, y, z = _coords(shape)
     cx, cy = center[0], center[1]
     cz = center[2] if len(center) > 2 else 0.0
-    r2 = _min_image(x - cx, nx) ** 2 + _min_image(y - cy, ny) ** 2
+    dy = _min_image(y - cy, ny) if periodic_y else y - cy
+    r2 = _min_image(x - cx, nx) ** 2 + dy ** 2
     if nz > 1:
         r2 = r2 + _min_image(z - cz, nz) ** 2
     r = np.sqrt(r2)
@@ -41,7 +45,7 @@ def drop_indicator(shape, center: Sequence[float], radius: float, width: float =
 
 
 def two_drop_fields(shape, drops, rho_g: float, rho_l: float, chi: float, seed: int,
-                    noise: float = 1e-4, width: float = 3.0):
+                    noise: float = 1e-4, width: float = 3.0, periodic_y: bool = True):
     """Fields for a list of drops.
 
     ``drops`` is a sequence of dicts with keys ``center``, ``radius``,
@@ -52,7 +56,7 @@ def two_drop_fields(shape, drops, rho_g: float, rho_l: float, chi: float, seed: 
     c2 = np.zeros(shape)
     u = np.zeros((3,) + tuple(shape))
     for d in drops:
-        ind = drop_indicator(shape, d["center"], d["radius"], width)
+        ind = drop_indicator(shape, d["center"], d["radius"], width, periodic_y)
         if d["liquid"] == 1:
             c1 += ind
         else:

@@ -42,6 +42,7 @@ class Workload:
     tau_phi: float = 1.0
     noise: float = 1e-4
     width: float = 3.0
+    walls: int = 0          # 1: solid walls at y = -1/2 and y = ny - 1/2
 
     @property
     def lambda2(self) -> float:
@@ -61,7 +62,7 @@ class Workload:
         return dict(lattice=self.lattice, nx=nx, ny=ny, nz=nz, lambda1=self.lambda1,
                     lambda2=self.lambda2, lambda3=self.lambda3, kappa1=self.kappa1,
                     kappa2=self.kappa2, kappa3=self.kappa3, chi=self.chi, nu=self.nu,
-                    mobility=self.mobility, tau_phi=self.tau_phi)
+                    mobility=self.mobility, tau_phi=self.tau_phi, walls=self.walls)
 
 
 def lens(nx: int = 128, ny: int = 128, radius: float = 20.0, ratio: float = 10.0,
@@ -142,4 +143,21 @@ def fields(w: Workload, rho_g: float, rho_l: float, noise: Optional[float] = Non
     """(rho, phi, u) for a workload, given its coexisting densities."""
     from .fields import two_drop_fields
     return two_drop_fields(w.shape, w.drops, rho_g, rho_l, w.chi, w.seed,
-                           w.noise if noise is None else noise, w.width)
+                           w.noise if noise is None else noise, w.width, periodic_y=not w.walls)
+
+
+def wall_drops(nx: int = 96, ny: int = 48, nz: int = 1, radius: float = 14.0, ratio: float = 10.0,
+               kappa: float = 0.1, start_deg=(70.0, 110.0), steps: int = 2000, seed: int = 0) -> Workload:
+    """A channel bounded by solid walls at y = -1/2 and y = ny - 1/2: a cap of
+    liquid 1 on the bottom wall and one of liquid 2 on the top wall, each a
+    disc of ``radius`` cut by its wall at the angle start_deg (inside the
+    drop).  D3Q27 when nz > 1."""
+    c0, c1 = math.cos(math.radians(start_deg[0])), math.cos(math.radians(start_deg[1]))
+    zc = nz / 2.0
+    drops = [
+        {"center": (nx / 3.0, -0.5 - radius * c0, zc), "radius": radius, "liquid": 1},
+        {"center": (2.0 * nx / 3.0, ny - 0.5 + radius * c1, zc), "radius": radius, "liquid": 2},
+    ]
+    return Workload(name=f"wall_drops_{'d3q27' if nz > 1 else 'd2q9'}_{nx}x{ny}x{nz}_ratio{ratio:g}",
+                    lattice=D3Q27 if nz > 1 else D2Q9, shape=(nz, ny, nx), ratio=ratio, kappa2=kappa,
+                    kappa3=kappa, drops=drops, steps=steps, seed=seed, width=2.0, walls=1)

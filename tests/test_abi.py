@@ -125,3 +125,27 @@ def test_null_arguments_are_rejected(lib):
     assert lib.telbm_destroy(None) == _lib.ERR_INVAL
     assert lib.telbm_required_bytes(None, None) == _lib.ERR_INVAL
     assert lib.telbm_coexistence(0.037, 0.2, 1.0, 1.0, None, None, None, None) == _lib.ERR_INVAL
+
+
+def test_wall_parameters_are_validated(orc):
+    """Walls: accepted on D2Q9 (both precisions) and D3Q27 FP64; rejected on
+    D3Q27 FP32-mixed, with ny < 2, with contact angles outside (0, pi), with
+    walls other than 0/1, and in the batched form."""
+    import math
+    import paper_1710_07486_amd as T
+    from paper_1710_07486_amd import _lib
+    from paper_1710_07486_amd.batch import required_bytes as batch_bytes
+    T0 = orc.temperature_for_ratio(10.0)[0]
+    for kw in (dict(), dict(precision=T.FP32_MIXED), dict(lattice=T.D3Q27, nz=8)):
+        assert T.required_bytes(T.Params(nx=16, ny=16, T=T0, walls=1, **kw)) > 0
+    bad = [dict(lattice=T.D3Q27, nz=8, precision=T.FP32_MIXED), dict(ny=1), dict(theta_rho_lo=0.0),
+           dict(theta_phi_hi=math.pi), dict(theta_rho_hi=float("nan")), dict(walls=2)]
+    for kw in bad:
+        p = T.Params(nx=16, ny=16, T=T0, walls=1)
+        for k, v in kw.items():
+            setattr(p, k, v)
+        with pytest.raises(T.TelbmError) as e:
+            T.required_bytes(p)
+        assert e.value.code == _lib.ERR_INVAL, kw
+    with pytest.raises(T.TelbmError):
+        batch_bytes([T.Params(nx=16, ny=16, T=T0, walls=1)])
