@@ -50,6 +50,7 @@ class OrcParams(ctypes.Structure):
         ("walls", ctypes.c_int32), ("pad2", ctypes.c_int32),
         ("theta_rho_lo", ctypes.c_double), ("theta_rho_hi", ctypes.c_double),
         ("theta_phi_lo", ctypes.c_double), ("theta_phi_hi", ctypes.c_double),
+        ("glattice", ctypes.c_int32), ("pad3", ctypes.c_int32),
     ]
 
 
@@ -86,6 +87,8 @@ class Params:
     theta_rho_hi: float = math.pi / 2  # where the field is large; lo = bottom wall, hi = top
     theta_phi_lo: float = math.pi / 2
     theta_phi_hi: float = math.pi / 2
+    glattice: int = 0     # phase-field lattice: 0 as for f, 1 reduced (D2Q5 / D3Q7)
+    pad3: int = 0
 
     def c_struct(self) -> OrcParams:
         return OrcParams(**{f: getattr(self, f) for f, _ in OrcParams._fields_})
@@ -147,6 +150,7 @@ def lib():
         L.orc_gradient.argtypes = [P, vp, vp]
         L.orc_feq.argtypes = [ctypes.c_int, d, vp, vp]
         L.orc_geq.argtypes = [ctypes.c_int, d, d, d, vp, vp]
+        L.orc_geq_reduced.argtypes = [ctypes.c_int, d, d, d, vp, vp]
         L.orc_kbc_split.argtypes = [ctypes.c_int, vp, vp, vp]
         L.orc_kbc_gamma.argtypes = [ctypes.c_int, d, vp, vp, vp]
         L.orc_kbc_gamma.restype = d
@@ -329,11 +333,14 @@ def feq(lattice, rho, u):
     return out
 
 
-def geq(lattice, phi, mu_phi, Gamma, u):
+def geq(lattice, phi, mu_phi, Gamma, u, reduced=False):
+    """Phase-field equilibrium on the full lattice, or (reduced) on its rest
+    and axis directions (D2Q5 / D3Q7; zero elsewhere)."""
     Q = 9 if lattice == D2Q9 else 27
     u = np.ascontiguousarray(np.resize(np.asarray(u, dtype=np.float64), 3))
     out = np.zeros(Q)
-    lib().orc_geq(lattice, phi, mu_phi, Gamma, _ptr(u), _ptr(out))
+    fn = lib().orc_geq_reduced if reduced else lib().orc_geq
+    fn(lattice, phi, mu_phi, Gamma, _ptr(u), _ptr(out))
     return out
 
 

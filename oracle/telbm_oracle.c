@@ -54,6 +54,8 @@ typedef struct {
     int32_t pad2;
     double theta_rho_lo, theta_rho_hi; /* contact angles (radians) of the      */
     double theta_phi_lo, theta_phi_hi; /* rho and phi fields, bottom / top wall */
+    int32_t glattice;             /* phase-field lattice: 0 as for f, 1 reduced (D2Q5 / D3Q7) */
+    int32_t pad3;
 } orc_params;
 
 /* ------------------------------------------------------------------------- */
@@ -652,6 +654,45 @@ void orc_geq(int lattice, double phi, double mu_phi, double Gamma, const double 
     geq[0] = phi - rest;
 }
 
+/* Reduced phase-field lattice (the paper leaves the lattice of g open): the
+ * rest and axis directions of D2Q9 / D3Q27 (D2Q5 / D3Q7), axis weights 1/6
+ * so that sum_i w_i c_i c_i = cs2 I as on the full lattice, and the
+ * equilibrium to first order in u (a five- or seven-velocity set cannot
+ * carry the second-order terms isotropically):
+ *   geq_i = w_i [Gamma mu_phi / cs2 + phi c_i.u / cs2] (axis directions),
+ *   geq_0 = phi - sum of those, and 0 on the other directions.
+ * Its first two moments equal those of the full equilibrium (phi, phi u,
+ * Gamma mu_phi I + phi u u without the u u term), so Eq. (7) is recovered
+ * with the same mobility M = Gamma (tau_phi - 1/2).                         */
+static int axis_direction(int i)
+{
+    int c[3];
+    direction(i, c);
+    return abs(c[0]) + abs(c[1]) + abs(c[2]) == 1;
+}
+
+void orc_geq_reduced(int lattice, double phi, double mu_phi, double Gamma, const double *u, double *geq)
+{
+    int Q = lattice_Q(lattice);
+    double rest = 0.0;
+    for (int i = 1; i < Q; ++i) {
+        geq[i] = 0.0;
+        if (!axis_direction(i)) continue;
+        int c[3];
+        direction(i, c);
+        double cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+        geq[i] = (1.0 / 6.0) * (Gamma * mu_phi / CS2 + phi * cu / CS2);
+        rest += geq[i];
+    }
+    geq[0] = phi - rest;
+}
+
+static void geq_of(const orc_params *p, double phi, double mu_phi, double Gamma, const double *u, double *geq)
+{
+    if (p->glattice) orc_geq_reduced(p->lattice, phi, mu_phi, Gamma, u, geq);
+    else orc_geq(p->lattice, phi, mu_phi, Gamma, u, geq);
+}
+
 /* ------------------------------------------------------------------------- */
 /* KBC entropic collision.                                                   */
 /* ------------------------------------------------------------------------- */
@@ -880,7 +921,7 @@ int orc_init(const orc_params *p, const double *rho0, const double *phi0, const 
         double u[3] = {0, 0, 0}, fe[27], ge[27];
         if (u0) { u[0] = u0[n]; u[1] = u0[N + n]; if (p->lattice == 1) u[2] = u0[2 * N + n]; }
         orc_feq(p->lattice, rho0[n], u, fe);
-        orc_geq(p->lattice, phi0[n], w.mu_phi[n], Gam, u, ge);
+        geq_of(p, phi0[n], w.mu_phi[n], Gam, u, ge);
         for (int i = 0; i < Q; ++i) {
             f[(int64_t)i * N + n] = fe[i];
             g[(int64_t)i * N + n] = ge[i];
@@ -931,7 +972,7 @@ int orc_run(const orc_params *p, double *f, double *g, int64_t nsteps, double *d
             double r = w.rho[n];
             for (int a = 0; a < 3; ++a) up[a] = (w.j[a * N + n] + 0.5 * F[a]) / r;
             if (p->lattice == 0) up[2] = 0.0;
-            orc_geq(p->lattice, w.phi[n], w.mu_phi[n], Gam, up, ge);
+            geq_of(p, w.phi[n], w.mu_phi[n], Gam, up, ge);
             for (int i = 0; i < Q; ++i) {
                 fs[(int64_t)i * N + n] = fo[i];
                 gs[(int64_t)i * N + n] = gn[i] - (gn[i] - ge[i]) / tau_phi;
