@@ -110,6 +110,14 @@ extern "C" {
  *                      theta_* in (0, pi); pi/2 is neutral.  Needs ny >= 2 and
  *                      is not available for D3Q27 in the FP32-mixed form nor in
  *                      the batched form (TELBM_ERR_INVAL).
+ *  glattice            lattice of the phase-field populations g, which the
+ *                      paper leaves open: 0 the lattice of f; 1 its rest and
+ *                      axis directions (D2Q5 / D3Q7) with axis weights 1/6 and
+ *                      the equilibrium to first order in u,
+ *                      g_i = (1/6)(3 Gamma mu_phi + 3 phi c_i.u), g_0 = phi - sum,
+ *                      which keeps the moments phi, phi u and Gamma mu_phi I of
+ *                      Eq. (7) and moves 2 (Q + 5 or 7) instead of 4 Q values
+ *                      per node and step.  Same availability as walls.
  * Validation: 0 < T < T_c, rho_l > rho_g > 0, nu > 0, tau_phi > 1/2, chi != 0,
  * sizes >= 1 (nz == 1 for D2Q9), nx*ny*nz < 2^40.                           */
 typedef struct telbm_params {
@@ -133,6 +141,8 @@ typedef struct telbm_params {
     uint32_t reserved2;
     double theta_rho_lo, theta_rho_hi;  /* contact angles (radians) of the walls */
     double theta_phi_lo, theta_phi_hi;  /* at y = -1/2 (lo) and ny - 1/2 (hi)    */
+    int32_t glattice;         /* phase-field lattice: 0 as for f, 1 reduced      */
+    uint32_t reserved3;
 } telbm_params;
 
 /* Diagnostics of the state before step `step` (the last diagnosed step):

@@ -30,6 +30,7 @@ class TelbmParams(ctypes.Structure):
         ("walls", ctypes.c_int32), ("reserved2", ctypes.c_uint32),
         ("theta_rho_lo", ctypes.c_double), ("theta_rho_hi", ctypes.c_double),
         ("theta_phi_lo", ctypes.c_double), ("theta_phi_hi", ctypes.c_double),
+        ("glattice", ctypes.c_int32), ("reserved3", ctypes.c_uint32),
     ]
 
 

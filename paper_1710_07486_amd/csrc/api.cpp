@@ -73,13 +73,19 @@ struct Layout {
     size_t o_pop0, o_pop1, o_rho[4], o_phi[2], o_inbox[2], o_part3, o_inbox3, o_mux, o_mup, o_part, o_diag, o_bad;
 };
 
-Layout layout_of(const telbm_params& p) {
+// Population values per node: f on the lattice, g on the full or reduced one.
+int pops_per_node(const telbm_params& p) {
     const int Q = p.lattice == TELBM_D2Q9 ? 9 : 27;
+    const int QG = p.glattice ? (p.lattice == TELBM_D2Q9 ? 5 : 7) : Q;
+    return Q + QG;
+}
+
+Layout layout_of(const telbm_params& p) {
     const int64_t N = (int64_t)p.nx * p.ny * p.nz;
     const size_t s = p.precision == TELBM_FP32_MIXED ? 4 : 8;
     GridDims g{p.nx, p.ny, p.nz, 0, N};
     Layout L{};
-    L.pop = align_up((size_t)2 * Q * N * s);
+    L.pop = align_up((size_t)pops_per_node(p) * N * s);
     L.aux = align_up((size_t)N * sizeof(double));
     // D2Q9 (fused step): current and next moments, FP32 form also the
     // reference and next reference densities; two inboxes
@@ -123,6 +129,11 @@ int validate(const telbm_params* p, std::string* why) {
     if (p->eos < TELBM_EOS_CS || p->eos > TELBM_EOS_PR) { *why = "unknown equation of state"; return TELBM_ERR_INVAL; }
     if (p->eos == TELBM_EOS_PR && !isfinite(p->omega)) { *why = "omega must be finite"; return TELBM_ERR_INVAL; }
     if (p->walls != 0 && p->walls != 1) { *why = "walls must be 0 or 1"; return TELBM_ERR_INVAL; }
+    if (p->glattice != 0 && p->glattice != 1) { *why = "glattice must be 0 or 1"; return TELBM_ERR_INVAL; }
+    if (p->glattice && p->lattice == TELBM_D3Q27 && p->precision == TELBM_FP32_MIXED) {
+        *why = "the reduced phase-field lattice is not available for D3Q27 in the FP32-mixed form";
+        return TELBM_ERR_INVAL;
+    }
     if (p->walls) {
         if (p->ny < 2) { *why = "walls need ny >= 2"; return TELBM_ERR_INVAL; }
         if (p->lattice == TELBM_D3Q27 && p->precision == TELBM_FP32_MIXED) {
@@ -176,6 +187,7 @@ PhysConst derive(const telbm_params& p, double rho_g, double rho_l, double C) {
     k.Gamma = p.mobility / (p.tau_phi - 0.5);
     k.eos = p.eos;
     k.att = eos_attraction(eos_of(p), p.T);
+    k.glat = p.glattice;
     if (p.walls) {
         k.cot_rho[0] = cos(p.theta_rho_lo) / sin(p.theta_rho_lo);
         k.cot_rho[1] = cos(p.theta_rho_hi) / sin(p.theta_rho_hi);
@@ -617,7 +629,7 @@ const char* telbm_kernel_name(const telbm_solver* s, int kind) {
 double telbm_algorithmic_bytes_per_update(const telbm_solver* s) {
     if (!s) return 0.0;
     const double b = s->p.precision == TELBM_FP32_MIXED ? 4.0 : 8.0;
-    return 2.0 * 2.0 * s->Q * b;
+    return 2.0 * pops_per_node(s->p) * b;
 }
 
 int telbm_destroy(telbm_solver* s) {

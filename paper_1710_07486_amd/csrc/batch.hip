@@ -183,8 +183,9 @@ int check_params(const telbm_params* p, int count, std::string* why) {
             *why = "all instances of a batch share lattice and precision";
             return TELBM_ERR_INVAL;
         }
-        if (p[i].walls) {
-            *why = "the batched form runs periodic boxes only (instance " + std::to_string(i) + " has walls)";
+        if (p[i].walls || p[i].glattice) {
+            *why = "the batched form runs periodic boxes on the full phase-field lattice only (instance " +
+                   std::to_string(i) + ")";
             return TELBM_ERR_INVAL;
         }
         size_t b;

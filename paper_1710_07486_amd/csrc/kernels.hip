@@ -109,12 +109,12 @@ __device__ void diag_block_reduce(double* vals, double* __restrict__ out) {
 // ---------------------------------------------------------------------------
 // W: instance for lattices with walls (the periodic instance carries none of
 // the wall logic and keeps its registers).
-template <int L, typename T, bool W>
+template <int L, typename T, bool W, bool RG>
 __global__ __launch_bounds__(BX* BY) void k_moments(GridDims g, const T* __restrict__ pop,
                                                     const double* __restrict__ rho_ref,
                                                     double* __restrict__ rho, double* __restrict__ phi) {
     const Tile t = tile_coords(g);
-    if (t.in) node_moments<L, T, W>(g, pop, rho_ref, rho, phi, t.x, t.y, t.z);
+    if (t.in) node_moments<L, T, W, RG>(g, pop, rho_ref, rho, phi, t.x, t.y, t.z);
 }
 
 template <int L, int E, bool W>
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(BX* BY) void k_chempot_col(GridDims g, PhysConst k,
     }
 }
 
-template <int L, typename T>
+template <int L, typename T, bool RG>
 __global__ __launch_bounds__(BX* BY) void k_collide(GridDims g, PhysConst k, const T* __restrict__ src,
                                                     T* __restrict__ dst, const double* __restrict__ rho_ref,
                                                     const double* __restrict__ rho,
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(BX* BY) void k_collide(GridDims g, PhysConst k, con
     const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + BY - 1) / BY;
     const int bx = b % bxc, rest = b / bxc, by = rest % byc, bz = rest / byc;
     double dv[kDiag] = {0, 0, 0, 0, 0, 0, INFINITY, INFINITY, -INFINITY, 0};
-    tile_collide<L, T, BX * BY>(g, k, src, dst, rho_ref, rho, phi, mux, mup, bx * BX, by * BY, bz, BX, BY,
+    tile_collide<L, T, BX * BY, RG>(g, k, src, dst, rho_ref, rho, phi, mux, mup, bx * BX, by * BY, bz, BX, BY,
                                      threadIdx.y * BX + threadIdx.x, diag != 0, dv);
     if (diag) diag_block_reduce(dv, partials);
 }
@@ -393,7 +393,13 @@ struct LdsAux2 {
     const double* sp;
     const double* smx;
     const double* smp;
+    const double* sref;  // reference densities of the tile and its halo (FP32 form)
     int lx, ly;  // the node's position in the tile
+    template <int L>
+    __device__ __forceinline__ double ref(const double*, const Nbr32&, uint32_t, int i, bool bb) const {
+        return bb ? sref[(ly + 2) * FHX + lx + 2]
+                  : sref[(ly + 2 - Lattice<L>::c[i][1]) * FHX + lx + 2 - Lattice<L>::c[i][0]];
+    }
     __device__ __forceinline__ double rho0(uint32_t) const { return sr[(ly + 2) * FHX + lx + 2]; }
     __device__ __forceinline__ double phi0(uint32_t) const { return sp[(ly + 2) * FHX + lx + 2]; }
     __device__ __forceinline__ double mup0(uint32_t) const { return smp[(ly + 1) * FMX + lx + 1]; }
@@ -479,11 +485,12 @@ struct NextSink {
         }
         put(0, v);
     }
-    template <int L2, typename R>
+    template <int L2, typename R, int QG>
     __device__ __forceinline__ void post_g(const R* gg) {
+        // a reduced phase-field lattice has no populations beyond its QG
         double v[Lattice<L>::Q];
 #pragma unroll
-        for (int i = 0; i < Lattice<L>::Q; ++i) v[i] = double(gg[i]);
+        for (int i = 0; i < Lattice<L>::Q; ++i) v[i] = i < QG ? double(gg[i]) : 0.0;
         put(1, v);
     }
     // sum over the tile's sources for target (ex, ey) of the ring-extended
@@ -510,7 +517,7 @@ struct NextSink {
     }
 };
 
-template <typename T, int E>
+template <typename T, int E, bool RG, bool WALL>
 __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysConst k, const T* __restrict__ src,
                                                            T* __restrict__ dst, const double* __restrict__ rho_ref,
                                                            const double* __restrict__ rho,
@@ -523,6 +530,7 @@ __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysCons
                                                            double* __restrict__ partials, int diag) {
     using Lt = Lattice<kD2Q9>;
     __shared__ double sr[FHX * FHY], sp[FHX * FHY], smx[FMX * FMY], smp[FMX * FMY];
+    __shared__ double sref[Deviation<T>::on ? FHX * FHY : 1];
     using Sink = NextSink<kD2Q9, FBY>;
     __shared__ double nsum[Sink::SUM], nside[Sink::SIDE];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -543,7 +551,7 @@ __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysCons
         const int hx = e % FHX, hy = e / FHX;
         const int gx = wrap_any(x0 - 2 + hx, g.nx), yy = y0 - 2 + hy;
         double r, p;
-        if (g.walls && (yy < 0 || yy >= g.ny)) {
+        if (WALL && g.walls && (yy < 0 || yy >= g.ny)) {
             // beyond a wall: the wetting ghost of the wall-row node below/above
             const int top = yy >= g.ny, yw = top ? g.ny - 1 : 0;
             double rm, pm, rp, pp;
@@ -557,12 +565,13 @@ __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysCons
         }
         sr[e] = r;
         sp[e] = p;
+        if (Deviation<T>::on) sref[e] = rho_ref[(int64_t)wrap_any(yy, g.ny) * g.nx + gx];
     }
     __syncthreads();
     for (int e = tid; e < FMX * FMY; e += BX * FBY) {
         // beyond a wall the potentials repeat the wall row
         const int yy = y0 - 1 + e / FMX;
-        const int my = g.walls ? (yy < 0 ? 1 : (yy == g.ny ? -1 : 0)) : 0;
+        const int my = (WALL && g.walls) ? (yy < 0 ? 1 : (yy == g.ny ? -1 : 0)) : 0;
         const int c = (e / FMX + 1 + my) * FHX + e % FMX + 1;
         const double r0 = sr[c], p0 = sp[c];
         double lr = 0.0, lp = 0.0;
@@ -584,12 +593,12 @@ __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysCons
         // last node, without stores) so that the sink's shuffles see whole rows
         const int lx = min((int)threadIdx.x, W - 1), ly = min((int)threadIdx.y, H - 1);
         const bool active = (int)threadIdx.x < W && (int)threadIdx.y < H;
-        const LdsAux2 aux{sr, sp, smx, smp, lx, ly};
+        const LdsAux2 aux{sr, sp, smx, smp, sref, lx, ly};
         if (rho_final && active) rho_final[(int64_t)(y0 + ly) * g.nx + x0 + lx] = aux.rho0(0);
-        const int wy = g.walls ? (y0 + ly == 0 ? -1 : (y0 + ly == g.ny - 1 ? 1 : 0)) : 0;
+        const int wy = (WALL && g.walls) ? (y0 + ly == 0 ? -1 : (y0 + ly == g.ny - 1 ? 1 : 0)) : 0;
         Sink sink{nsum, nside, (int)threadIdx.x, (int)threadIdx.y, W, wy};
-        node_collide_sink<kD2Q9, T>(g, k, src, dst, rho_ref, aux, x0 + lx, y0 + ly, 0, diag != 0, dv, active,
-                                    sink);
+        node_collide_sink<kD2Q9, T, LdsAux2, Sink, WALL, RG>(g, k, src, dst, rho_ref, aux, x0 + lx, y0 + ly, 0,
+                                                             diag != 0, dv, active, sink);
     }
     if (diag) diag_block_reduce<BX * FBY>(dv, partials);
     __syncthreads();
@@ -616,7 +625,7 @@ __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysCons
             if (ey >= H) continue;
         }
         // nothing streams into a wall (those values bounced back in the sink)
-        if (g.walls && ((ey < 0 && y0 == 0) || (ey >= H && y0 + H == g.ny))) continue;
+        if (WALL && g.walls && ((ey < 0 && y0 == 0) || (ey >= H && y0 + H == g.ny))) continue;
         double s0, s1;
         view.gather(ex, ey, 0, H, s0, s1);
         const int64_t q2 = 2 * inbox_target<FBY>(g, x0, y0, W, H, ex, ey);
@@ -689,7 +698,7 @@ __device__ __forceinline__ void next3_complete(const GridDims& g, const double* 
         inbox_complete_fast<BY>(g, inbox + ((int64_t)z * 3 + k) * tiles * INBOX3 * 2, gx, gy, r, p);
 }
 
-template <bool WALL>
+template <bool WALL, bool RG>
 __global__ __launch_bounds__(BX* BY) void k_collide_next3(GridDims g, PhysConst k, const double* __restrict__ src,
                                                           double* __restrict__ dst, const double* __restrict__ rho,
                                                           const double* __restrict__ phi,
@@ -714,8 +723,8 @@ __global__ __launch_bounds__(BX* BY) void k_collide_next3(GridDims g, PhysConst 
         const GlobalAux aux{rho, phi, mux, mup};
         const int wy = (WALL && g.walls) ? (y0 + ly == 0 ? -1 : (y0 + ly == g.ny - 1 ? 1 : 0)) : 0;
         Sink sink{nsum, nside, (int)threadIdx.x, (int)threadIdx.y, W, wy};
-        node_collide_sink<kD3Q27, double, GlobalAux, Sink, WALL>(g, k, src, dst, nullptr, aux, x0 + lx, y0 + ly, bz,
-                                                              diag != 0, dv, active, sink);
+        node_collide_sink<kD3Q27, double, GlobalAux, Sink, WALL, RG>(g, k, src, dst, nullptr, aux, x0 + lx, y0 + ly,
+                                                                  bz, diag != 0, dv, active, sink);
     }
     if (diag) diag_block_reduce(dv, partials);
     __syncthreads();
@@ -796,7 +805,7 @@ __global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ p
 // Initialisation: equilibrium populations of (rho0, phi0, u0), written so that
 // the next pull sees them at their own node (pop[i][x - c_i] = f_i(x)).
 // ---------------------------------------------------------------------------
-template <int L, typename T>
+template <int L, typename T, bool RG>
 __global__ __launch_bounds__(BX* BY) void k_init(GridDims g, PhysConst k, const double* __restrict__ rho,
                                                  const double* __restrict__ phi,
                                                  const double* __restrict__ mup,
@@ -814,9 +823,9 @@ __global__ __launch_bounds__(BX* BY) void k_init(GridDims g, PhysConst k, const 
         u[1] = R(u0[g.N + n]);
         if (Lt::D == 3) u[2] = R(u0[2 * g.N + n]);
     }
-    R fd[Q], gg[Q];
+    R fd[Q], gg[GLattice<L, RG>::Q];
     const double r = rho[n];
-    equilibria<L, R>(r, R(phi[n]), R(mup[n]), u, R(k.Gamma), Deviation<T>::on ? r : 0.0, fd, gg);
+    equilibria<L, R, RG>(r, R(phi[n]), R(mup[n]), u, R(k.Gamma), Deviation<T>::on ? r : 0.0, fd, gg);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         // the slot the pull of direction i at this node reads: that of x - c_i,
@@ -828,7 +837,7 @@ __global__ __launch_bounds__(BX* BY) void k_init(GridDims g, PhysConst k, const 
         R v = fd[i];
         if (Deviation<T>::on) v += R(Lt::w[i] * (r - rho[m]));
         pop[(int64_t)s * g.N + m] = v;
-        pop[(int64_t)(Q + s) * g.N + m] = gg[i];
+        if (i < GLattice<L, RG>::Q) pop[(int64_t)(Q + s) * g.N + m] = gg[i];
     }
 }
 
@@ -926,10 +935,11 @@ template <int L, typename T, int E>
 static hipError_t launch_step_parts(const StepArgs& a, int part) {
     const dim3 blk(BX, BY, 1);
     const dim3 grd(grid_blocks(a.g), 1, 1);
-    const bool w = a.g.walls != 0;
+    const bool w = a.g.walls != 0, rg = a.k.glat != 0;
     if (part == 0) {
-        if (w) k_moments<L, T, true><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
-        else k_moments<L, T, false><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
+        if (rg) k_moments<L, T, true, true><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
+        else if (w) k_moments<L, T, true, false><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
+        else k_moments<L, T, false, false><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
     } else if (part == 1) {
         if (L == kD3Q27) {
             if (w)
@@ -943,16 +953,28 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
             else k_chempot<L, E, false><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup);
         }
     } else if (part == 2) {
-        k_collide<L, T><<<grd, blk, 0, a.stream>>>(a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref, a.rho,
-                                                     a.phi, a.mux, a.mup, a.partials, a.diag);
+        // the pair split (D3Q27 FP32) runs the full phase-field lattice only
+        if (rg && L == kD3Q27 && Deviation<T>::on) return hipErrorInvalidValue;
+        if (rg)
+            k_collide<L, T, true><<<grd, blk, 0, a.stream>>>(a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref,
+                                                             a.rho, a.phi, a.mux, a.mup, a.partials, a.diag);
+        else
+            k_collide<L, T, false><<<grd, blk, 0, a.stream>>>(a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref,
+                                                              a.rho, a.phi, a.mux, a.mup, a.partials, a.diag);
         if (a.diag) k_diag_final<<<1, 256, 0, a.stream>>>(a.partials, (int)grd.x, a.diag_out);
     } else if (part == 3) {
         if (L != kD2Q9 || a.g.nz != 1 || !a.rho_next || !a.phi_next || !a.inbox_out) return hipErrorInvalidValue;
         if (Deviation<T>::on != (a.rho_final != nullptr)) return hipErrorInvalidValue;
         const unsigned fb = fused_tiles(a.g);
-        k_collide_fused2<T, E><<<fb, dim3(BX, FBY, 1), 0, a.stream>>>(
-            a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref, a.rho, a.phi, a.inbox_in, a.rho_next, a.phi_next,
-            a.inbox_out, a.rho_final, a.partials, a.diag);
+#define TELBM_FUSED2(RGV, WV)                                                                                 \
+    k_collide_fused2<T, E, RGV, WV><<<fb, dim3(BX, FBY, 1), 0, a.stream>>>(                                   \
+        a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref, a.rho, a.phi, a.inbox_in, a.rho_next, a.phi_next,      \
+        a.inbox_out, a.rho_final, a.partials, a.diag)
+        if (rg && w) TELBM_FUSED2(true, true);
+        else if (rg) TELBM_FUSED2(true, false);
+        else if (w) TELBM_FUSED2(false, true);
+        else TELBM_FUSED2(false, false);
+#undef TELBM_FUSED2
         if (a.diag) k_diag_final<<<1, 256, 0, a.stream>>>(a.partials, (int)fb, a.diag_out);
     } else if (part == 5) {
         if (L != kD3Q27 || !a.part3 || !a.inbox3) return hipErrorInvalidValue;
@@ -964,14 +986,20 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
                                                                                a.mup, a.part3, a.inbox3);
     } else if (part == 6) {
         if (L != kD3Q27 || Deviation<T>::on || !a.part3 || !a.inbox3) return hipErrorInvalidValue;
-        if (w)
-            k_collide_next3<true><<<grd, blk, 0, a.stream>>>(a.g, a.k, (const double*)a.src, (double*)a.dst, a.rho,
-                                                             a.phi, a.mux, a.mup, a.part3, a.inbox3, a.partials,
-                                                             a.diag);
+        auto* sp = (const double*)a.src;
+        auto* dp = (double*)a.dst;
+        if (w && rg)
+            k_collide_next3<true, true><<<grd, blk, 0, a.stream>>>(a.g, a.k, sp, dp, a.rho, a.phi, a.mux, a.mup,
+                                                                   a.part3, a.inbox3, a.partials, a.diag);
+        else if (w)
+            k_collide_next3<true, false><<<grd, blk, 0, a.stream>>>(a.g, a.k, sp, dp, a.rho, a.phi, a.mux, a.mup,
+                                                                    a.part3, a.inbox3, a.partials, a.diag);
+        else if (rg)
+            k_collide_next3<false, true><<<grd, blk, 0, a.stream>>>(a.g, a.k, sp, dp, a.rho, a.phi, a.mux, a.mup,
+                                                                    a.part3, a.inbox3, a.partials, a.diag);
         else
-            k_collide_next3<false><<<grd, blk, 0, a.stream>>>(a.g, a.k, (const double*)a.src, (double*)a.dst, a.rho,
-                                                              a.phi, a.mux, a.mup, a.part3, a.inbox3, a.partials,
-                                                              a.diag);
+            k_collide_next3<false, false><<<grd, blk, 0, a.stream>>>(a.g, a.k, sp, dp, a.rho, a.phi, a.mux, a.mup,
+                                                                     a.part3, a.inbox3, a.partials, a.diag);
         if (a.diag) k_diag_final<<<1, 256, 0, a.stream>>>(a.partials, (int)grd.x, a.diag_out);
     } else if (part == 4) {
         if (L != kD2Q9 || a.g.nz != 1 || !a.inbox_in) return hipErrorInvalidValue;
@@ -1000,8 +1028,12 @@ hipError_t launch_part(int lattice, int precision, const StepArgs& a, int part) 
 
 template <int L, typename T>
 static hipError_t launch_init_t(const StepArgs& a, const double* u0) {
-    k_init<L, T><<<grid_blocks(a.g), dim3(BX, BY, 1), 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mup, u0,
-                                                                     (T*)a.dst);
+    if (a.k.glat)
+        k_init<L, T, true><<<grid_blocks(a.g), dim3(BX, BY, 1), 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mup, u0,
+                                                                               (T*)a.dst);
+    else
+        k_init<L, T, false><<<grid_blocks(a.g), dim3(BX, BY, 1), 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mup, u0,
+                                                                                (T*)a.dst);
     return hipGetLastError();
 }
 

@@ -84,6 +84,8 @@ struct PhysConst {
     // solid walls at y = -1/2 and y = ny - 1/2 (GridDims::walls): cot of the
     // contact angles of rho and phi at the bottom [0] and top [1] wall
     double cot_rho[2], cot_phi[2];
+    // phase-field lattice: 0 as for f, 1 reduced (D2Q5 / D3Q7)
+    int glat;
 };
 
 // Ghost value of rho or phi beyond a wall (geometric wetting condition): the
@@ -314,8 +316,49 @@ __device__ __forceinline__ void collide_g(R* g, R phi, R mu_phi, const R* u, R G
     }
 }
 
-// Equilibrium populations for initialisation, f in offset form about rho_ref.
+// Reduced phase-field lattice (RG): the rest and axis directions, the first
+// 1 + 2D of the order above (D2Q5 / D3Q7), axis weights 1/6 (sum_i w_i c_i c_i
+// = cs2 I as on the full lattice) and the equilibrium to first order in u:
+//   geq_i = (1/6)(3 Gamma mu_phi + 3 phi c_i.u) on the axes, geq_0 = phi - sum.
+template <int L, bool RG>
+struct GLattice {
+    static constexpr int Q = RG ? 1 + 2 * Lattice<L>::D : Lattice<L>::Q;
+};
+template <int L>
+__host__ __device__ constexpr bool axes_first() {
+    for (int i = 1; i <= 2 * Lattice<L>::D; ++i) {
+        int n = 0;
+        for (int d = 0; d < 3; ++d) n += Lattice<L>::c[i][d] != 0;
+        if (n != 1) return false;
+    }
+    return true;
+}
+static_assert(axes_first<kD2Q9>() && axes_first<kD3Q27>(), "axis directions come right after rest");
+
 template <int L, typename R>
+__device__ __forceinline__ void collide_g_reduced(R* g, R phi, R mu_phi, const R* u, R Gamma, R omega) {
+    constexpr int QG = 1 + 2 * Lattice<L>::D;
+    const R half_gm = R(0.5) * Gamma * mu_phi;
+    R rest = R(0);
+#pragma unroll
+    for (int i = 1; i < QG; ++i) {
+        const R cu = R(Lattice<L>::c[i][0]) * u[0] + R(Lattice<L>::c[i][1]) * u[1] + R(Lattice<L>::c[i][2]) * u[2];
+        const R geq = half_gm + R(0.5) * phi * cu;
+        rest += geq;
+        g[i] = g[i] + omega * (geq - g[i]);
+    }
+    g[0] = g[0] + omega * ((phi - rest) - g[0]);
+}
+
+template <int L, typename R, bool RG>
+__device__ __forceinline__ void collide_g_lat(R* g, R phi, R mu_phi, const R* u, R Gamma, R omega) {
+    if constexpr (RG) collide_g_reduced<L, R>(g, phi, mu_phi, u, Gamma, omega);
+    else collide_g<L, R>(g, phi, mu_phi, u, Gamma, omega);
+}
+
+// Equilibrium populations for initialisation, f in offset form about rho_ref
+// (g: GLattice<L, RG>::Q values).
+template <int L, typename R, bool RG = false>
 __device__ __forceinline__ void equilibria(double rho_d, R phi, R mu_phi, const R* u, R Gamma,
                                            double rho_ref, R* fd, R* g) {
     using Lt = Lattice<L>;
@@ -328,8 +371,8 @@ __device__ __forceinline__ void equilibria(double rho_d, R phi, R mu_phi, const 
     const R drho = R(rho_d - rho_ref);
 #pragma unroll
     for (int i = 0; i < Q; ++i) fd[i] = R(Lt::w[i]) * (drho + rho * eq_excess<L, R>(ax, i));
-    for (int i = 0; i < Q; ++i) g[i] = R(0);
-    collide_g<L, R>(g, phi, mu_phi, u, Gamma, R(1));
+    for (int i = 0; i < GLattice<L, RG>::Q; ++i) g[i] = R(0);
+    collide_g_lat<L, R, RG>(g, phi, mu_phi, u, Gamma, R(1));
 }
 
 // Chemical potentials of the free energy (Eqs. 2-4 and the f_I rewrite), in

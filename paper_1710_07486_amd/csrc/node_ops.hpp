@@ -75,7 +75,7 @@ __device__ __forceinline__ void wall_ghosts(const GridDims& g, const PhysConst& 
 // accumulation.  rho_ref: densities the stored f values are relative to.
 // W: the lattice may have walls (kernels instantiated without them carry none
 // of the wall logic).
-template <int L, typename T, bool W = false>
+template <int L, typename T, bool W = false, bool RG = false>
 __device__ __forceinline__ void node_moments(const GridDims& g, const T* __restrict__ pop,
                                              const double* __restrict__ rho_ref, double* __restrict__ rho,
                                              double* __restrict__ phi, int x, int y, int z) {
@@ -92,7 +92,7 @@ __device__ __forceinline__ void node_moments(const GridDims& g, const T* __restr
         double fi = double(pop[(int64_t)s * g.N + m]);
         if (Deviation<T>::on) fi += Lt::w[i] * rho_ref[m];
         r += fi;
-        p += double(pop[(int64_t)(Q + s) * g.N + m]);
+        if (i < GLattice<L, RG>::Q) p += double(pop[(int64_t)(Q + s) * g.N + m]);
     }
     rho[n] = r;
     phi[n] = p;
@@ -258,6 +258,11 @@ struct GlobalAux {
         a = ld(mux, m);
         b = ld(mup, m);
     }
+    // reference density of the pull source of direction i (FP32 form)
+    template <int L>
+    __device__ __forceinline__ double ref(const double* rho_ref, const Nbr32& nb, uint32_t n, int i, bool bb) const {
+        return ld(rho_ref, bb ? n : nbr32<L>(nb, n, i, -1));
+    }
 };
 
 // Receiver of a node's post-collision populations, called right after they
@@ -265,7 +270,7 @@ struct GlobalAux {
 struct NoSink {
     template <int L, typename R>
     __device__ __forceinline__ void post_f(const R*, double) {}
-    template <int L, typename R>
+    template <int L, typename R, int QG>
     __device__ __forceinline__ void post_g(const R*) {}
 };
 
@@ -277,7 +282,8 @@ struct NoSink {
 // node is computed but nothing is stored or reported (lanes past a ragged
 // edge that run on a clamped node so that the sink sees a full wavefront).
 // W false: the lattice has no walls (the kernel carries none of their logic).
-template <int L, typename T, typename AUX, typename SINK, bool W = true>
+// RG: the phase field lives on the reduced lattice (GLattice).
+template <int L, typename T, typename AUX, typename SINK, bool W = true, bool RG = false>
 __device__ __forceinline__ void node_collide_sink(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
                                                   T* __restrict__ dst, const double* __restrict__ rho_ref,
                                                   const AUX& aux, int x, int y, int z, bool diag, double* dv,
@@ -322,7 +328,7 @@ __device__ __forceinline__ void node_collide_sink(const GridDims& g, const PhysC
         const bool bb = W && bounce(g, y, Lt::c[i][1]);
         const uint32_t m = nbr32<L>(nb, n, i, -1);
         R v = bb ? ld_pop<L>(src + (size_t)opp_dir(i) * g.N, n) : ld_pop<L>(src + (size_t)i * g.N, m);
-        if (Deviation<T>::on) v += R(Lt::w[i] * (ld(rho_ref, bb ? n : m) - r));
+        if (Deviation<T>::on) v += R(Lt::w[i] * (aux.template ref<L>(rho_ref, nb, n, i, bb) - r));
         f[i] = v;
         if (Lt::c[i][0]) jx += Lt::c[i][0] > 0 ? v : -v;
         if (Lt::c[i][1]) jy += Lt::c[i][1] > 0 ? v : -v;
@@ -340,18 +346,19 @@ __device__ __forceinline__ void node_collide_sink(const GridDims& g, const PhysC
     sink.template post_f<L, R>(f, r);
     phase_fence();
 
-    R gg[Q];
+    constexpr int QG = GLattice<L, RG>::Q;
+    R gg[QG];
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
+    for (int i = 0; i < QG; ++i)
         gg[i] = (W && bounce(g, y, Lt::c[i][1])) ? ld_pop<L>(src + (size_t)(Q + opp_dir(i)) * g.N, n)
                                           : ld_pop<L>(src + (size_t)(Q + i) * g.N, nbr32<L>(nb, n, i, -1));
     R up[3] = {u[0] + R(0.5) * du[0], u[1] + R(0.5) * du[1], u[2] + R(0.5) * du[2]};
-    collide_g<L, R>(gg, R(p), R(aux.mup0(n)), up, R(k.Gamma), R(k.omega_phi));
+    collide_g_lat<L, R, RG>(gg, R(p), R(aux.mup0(n)), up, R(k.Gamma), R(k.omega_phi));
     if (active) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) st_pop<L>(dst + (size_t)(Q + i) * g.N, n, gg[i]);
+        for (int i = 0; i < QG; ++i) st_pop<L>(dst + (size_t)(Q + i) * g.N, n, gg[i]);
     }
-    sink.template post_g<L, R>(gg);
+    sink.template post_g<L, R, QG>(gg);
 
     if (diag && active) {
         const double ux = double(jx) * ir + 0.5 * F[0] * ir;
@@ -372,22 +379,22 @@ __device__ __forceinline__ void node_collide_sink(const GridDims& g, const PhysC
     }
 }
 
-template <int L, typename T, typename AUX>
+template <int L, typename T, typename AUX, bool RG = false>
 __device__ __forceinline__ void node_collide_aux(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
                                                  T* __restrict__ dst, const double* __restrict__ rho_ref,
                                                  const AUX& aux, int x, int y, int z, bool diag, double* dv) {
     NoSink none;
-    node_collide_sink<L, T>(g, k, src, dst, rho_ref, aux, x, y, z, diag, dv, true, none);
+    node_collide_sink<L, T, AUX, NoSink, true, RG>(g, k, src, dst, rho_ref, aux, x, y, z, diag, dv, true, none);
 }
 
-template <int L, typename T>
+template <int L, typename T, bool RG = false>
 __device__ __forceinline__ void node_collide(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
                                              T* __restrict__ dst, const double* __restrict__ rho_ref,
                                              const double* __restrict__ rho, const double* __restrict__ phi,
                                              const double* __restrict__ mux, const double* __restrict__ mup,
                                              int x, int y, int z, bool diag, double* dv) {
     const GlobalAux aux{rho, phi, mux, mup};
-    node_collide_aux<L, T>(g, k, src, dst, rho_ref, aux, x, y, z, diag, dv);
+    node_collide_aux<L, T, GlobalAux, RG>(g, k, src, dst, rho_ref, aux, x, y, z, diag, dv);
 }
 
 // ---------------------------------------------------------------------------
@@ -648,20 +655,22 @@ struct UsePairs {
 
 // All nodes of a tile of TW x TH nodes at (x0, y0, z) with the block's NT
 // threads, in the collision form UsePairs selects.
-template <int L, typename T, int NT>
+// RG: reduced phase-field lattice (one node per lane; the pair split runs the
+// full lattice only).
+template <int L, typename T, int NT, bool RG = false>
 __device__ __forceinline__ void tile_collide(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
                                              T* __restrict__ dst, const double* __restrict__ rho_ref,
                                              const double* __restrict__ rho, const double* __restrict__ phi,
                                              const double* __restrict__ mux, const double* __restrict__ mup,
                                              int x0, int y0, int z, int TW, int TH, int tid, bool diag, double* dv) {
-    if (UsePairs<L, T>::value) {
+    if constexpr (UsePairs<L, T>::value && !RG) {
         tile_collide_pair<L, T, NT>(g, k, src, dst, rho_ref, rho, phi, mux, mup, x0, y0, z, TW, TH, tid, diag, dv);
         return;
     }
     for (int kk = tid; kk < TW * TH; kk += NT) {
         const int x = x0 + kk % TW, y = y0 + kk / TW;
         if (x < g.nx && y < g.ny && z < g.nz)
-            node_collide<L, T>(g, k, src, dst, rho_ref, rho, phi, mux, mup, x, y, z, diag, dv);
+            node_collide<L, T, RG>(g, k, src, dst, rho_ref, rho, phi, mux, mup, x, y, z, diag, dv);
     }
 }
 

@@ -50,6 +50,7 @@ class Params:
     theta_rho_hi: float = math.pi / 2  # wall, measured in the phase where rho / phi is large
     theta_phi_lo: float = math.pi / 2
     theta_phi_hi: float = math.pi / 2
+    glattice: int = 0     # phase-field lattice: 0 as for f, 1 reduced (D2Q5 / D3Q7)
 
     def c_struct(self) -> TelbmParams:
         kw = {f: getattr(self, f) for f, _ in TelbmParams._fields_ if hasattr(self, f)}

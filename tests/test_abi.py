@@ -149,3 +149,26 @@ def test_wall_parameters_are_validated(orc):
         assert e.value.code == _lib.ERR_INVAL, kw
     with pytest.raises(T.TelbmError):
         batch_bytes([T.Params(nx=16, ny=16, T=T0, walls=1)])
+
+
+def test_reduced_phase_field_lattice_parameters(orc):
+    """glattice 1: accepted on D2Q9 (both precisions) and D3Q27 FP64, with a
+    smaller arena and algorithmic byte count; rejected on D3Q27 FP32-mixed,
+    with other values, and in the batched form."""
+    import paper_1710_07486_amd as T
+    from paper_1710_07486_amd import _lib
+    from paper_1710_07486_amd.batch import required_bytes as batch_bytes
+    T0 = orc.temperature_for_ratio(10.0)[0]
+    full = T.required_bytes(T.Params(nx=256, ny=256, T=T0))
+    red = T.required_bytes(T.Params(nx=256, ny=256, T=T0, glattice=1))
+    assert red < full
+    assert T.required_bytes(T.Params(lattice=T.D3Q27, nx=8, ny=8, nz=8, T=T0, glattice=1)) > 0
+    for kw in (dict(lattice=T.D3Q27, nz=8, precision=T.FP32_MIXED, glattice=1), dict(glattice=2)):
+        p = T.Params(nx=16, ny=16, T=T0)
+        for k, v in kw.items():
+            setattr(p, k, v)
+        with pytest.raises(T.TelbmError) as e:
+            T.required_bytes(p)
+        assert e.value.code == _lib.ERR_INVAL, kw
+    with pytest.raises(T.TelbmError):
+        batch_bytes([T.Params(nx=16, ny=16, T=T0, glattice=1)])
