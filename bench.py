@@ -190,6 +190,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the D3Q27 256^3 measurement")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed measurement")
+    ap.add_argument("--no-reduced", action="store_true", help="skip the reduced phase-field lattice measurement")
     ap.add_argument("--no-walls", action="store_true", help="skip the wall-bounded channel measurement")
     ap.add_argument("--no-eos", action="store_true", help="skip the van der Waals / Peng-Robinson measurement")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate throughput measurement")
@@ -289,6 +290,14 @@ def main():
             result["walls"][tag + "_vs_periodic"] = round(rw["mlups"] / (r64["mlups"] if tag == "fp64" else
                                                                          result.get("fp32_mixed", {}).get("value", float("nan"))), 3)
             result["walls"][tag + "_finite"] = bool(np.isfinite(rw["rho"]).all())
+    if not args.no_reduced:
+        # the same drops with the phase field on D2Q5 (fewer bytes per update)
+        rr, _ = measure(wl, T_.FP64, args.steps, args.warmup, fields, extra={"glattice": 1})
+        log("reduced g lattice", {k: v for k, v in rr.items() if k != "rho"})
+        result["reduced_g_lattice"] = {"lattice": "D2Q9 + D2Q5", "fp64_mlups": round(rr["mlups"], 2),
+                                       "vs_full": round(rr["mlups"] / r64["mlups"], 3),
+                                       "bytes_per_update": rr["bytes_per_update"],
+                                       "collide_ms": round(rr["kernels_ms"]["collide"], 5)}
     if not args.no_3d:
         wl3 = W.collision_3d(256, radius=32, ratio=1000.0, v_rel=0.04, kappa2=0.1, kappa3=0.1)
         s3 = max(10, args.steps // 4)
@@ -296,6 +305,7 @@ def main():
         r3, f3 = measure(wl3, T_.FP64, s3, 5, coex=args.coex3d)
         cache["3d"] = r3["coex"]
         r3m, _ = measure(wl3, T_.FP32_MIXED, s3, 5, f3)
+        r3r = None if args.no_reduced else measure(wl3, T_.FP64, s3, 5, f3, extra={"glattice": 1})[0]
         k3 = r3["kernels_ms"]
         result["d3q27_256"] = {
             "fp64_mlups": round(r3["mlups"], 2), "fp32_mixed_mlups": round(r3m["mlups"], 2),
@@ -305,6 +315,9 @@ def main():
             "fp32_mixed_kernels_ms": {k: round(v, 5) for k, v in r3m["kernels_ms"].items()},
             "rel_density_error_mixed_vs_fp64": float(np.abs(r3m["rho"] - r3["rho"]).max() / np.abs(r3["rho"]).max()),
         }
+        if r3r is not None:
+            result["d3q27_256"]["fp64_reduced_g_mlups"] = round(r3r["mlups"], 2)
+            result["d3q27_256"]["fp64_reduced_g_vs_full"] = round(r3r["mlups"] / r3["mlups"], 3)
     if args.coex_cache and not os.path.exists(args.coex_cache):
         with open(args.coex_cache, "w") as fh:
             json.dump(cache, fh)
