@@ -254,22 +254,40 @@ def _window(arr, center, r):
     return arr[..., idx[0][:, None, None], idx[1][None, :, None], idx[2][None, None, :]]
 
 
-@pytest.mark.parametrize("case", ["d3q27_256_fp64", "d3q27_256_mixed", "d2q9_1024_fp64"])
+FULL_CASES = ["d3q27_256_fp64", "d3q27_256_mixed", "d2q9_1024_fp64", "d2q9_1024_fp64_reduced",
+              "d3q27_256_fp64_reduced", "d2q9_1024_fp64_walls"]
+
+
+@pytest.mark.parametrize("case", FULL_CASES)
 def test_full_size_sampled(orc, case):
     """Full-size lattices in the benchmark's launch configuration, checked on
     sampled nodes: after k steps a node depends on the initial fields within
     radius 3k + 3, so the oracle on a periodic window of half-width 3k + 4
-    reproduces that node exactly."""
+    reproduces that node exactly.  With walls the window is cut at the walls
+    (and closed by walls beyond the dependency radius elsewhere)."""
+    import math
     import paper_1710_07486_amd as T
     k = 2
+    walls = case.endswith("walls")
     if case.startswith("d3q27"):
         wl = W.collision_3d(256, radius=32, ratio=1000.0, v_rel=0.04, kappa2=0.1, kappa3=0.1)
+    elif walls:
+        wl = W.wall_drops(1024, 1024, radius=200.0, ratio=1000.0)
     else:
         wl = W.drops_2d(1024, ratio=1000.0, seed=0)
         wl.kappa2 = wl.kappa3 = 0.1
     precision = 1 if case.endswith("mixed") else 0
     say("full size", case)
     po, pl, rho, phi, u = make(orc, wl, precision)
+    if case.endswith("reduced"):
+        po.glattice = pl.glattice = 1
+    if walls:
+        ang = dict(theta_rho_lo=math.radians(60.0), theta_phi_lo=math.radians(70.0),
+                   theta_rho_hi=math.radians(120.0), theta_phi_hi=math.radians(100.0))
+        for key, v in ang.items():
+            setattr(po, key, v)
+            setattr(pl, key, v)
+        pl.walls = 1
     uu = u if np.abs(u).max() > 0 else None
     with T.Solver(pl) as s:
         s.init_fields(rho, phi, uu)
@@ -277,12 +295,20 @@ def test_full_size_sampled(orc, case):
         g = {f: s.read(f) for f in ("rho", "phi", "ux", "uy")}
     rng = np.random.default_rng(7)
     nz, ny, nx = wl.shape
-    r = 3 * k + 4
+    # the wetting ghost reads the wall row's neighbours along the wall: one
+    # more node of reach per step there
+    r = 3 * k + 4 + (k if walls else 0)
     # samples in the drops, on interfaces and in the gas
     pts = [tuple(int(c) for c in (rng.integers(nz), rng.integers(ny), rng.integers(nx))) for _ in range(6)]
     for d in wl.drops:
         c = d["center"]
         cz = int(c[2]) if nz > 1 else 0
+        if walls:
+            # the cap's contact line and its edge one node off each wall
+            cy = 0 if c[1] < ny / 2 else ny - 1
+            half = math.sqrt(max(d["radius"] ** 2 - (cy - c[1]) ** 2, 0.0))
+            pts += [(0, cy, int(c[0] + half)), (0, cy, int(c[0])), (0, abs(cy - 1), int(c[0] - half))]
+            continue
         pts.append((cz, int(c[1]), int(c[0])))
         pts.append((cz, int(c[1]), int(c[0] + d["radius"])))
     # absolute tolerances: FP64 1e-10 of the field scale; FP32 storage 1e-5 of it
@@ -291,16 +317,20 @@ def test_full_size_sampled(orc, case):
     worst = {k: 0.0 for k in scale}
     for (z, y, x) in pts:
         wz = 1 if nz == 1 else 2 * r + 1
-        sub = orc.Params(**{**po.__dict__, "nx": 2 * r + 1, "ny": 2 * r + 1, "nz": wz})
-        rw = np.ascontiguousarray(_window(rho, (z, y, x), r))
-        pw = np.ascontiguousarray(_window(phi, (z, y, x), r))
-        uw = None if uu is None else np.ascontiguousarray(_window(uu, (z, y, x), r))
+        ylo, yhi, cy = y - r, y + r, r
+        if walls:
+            ylo, yhi = max(0, y - r), min(ny - 1, y + r)
+            cy = y - ylo
+        sub = orc.Params(**{**po.__dict__, "nx": 2 * r + 1, "ny": yhi - ylo + 1, "nz": wz})
+        rw = np.ascontiguousarray(_window(rho, (z, y, x), r)[:, (ylo - y + r):(yhi - y + r + 1)])
+        pw = np.ascontiguousarray(_window(phi, (z, y, x), r)[:, (ylo - y + r):(yhi - y + r + 1)])
+        uw = None if uu is None else np.ascontiguousarray(_window(uu, (z, y, x), r)[..., (ylo - y + r):(yhi - y + r + 1), :])
         st = orc.State(sub, rw, pw, uw)
         st.run(k)
         f = st.fields()
         cz = 0 if nz == 1 else r
         for name, ref in (("rho", f["rho"]), ("phi", f["phi"]), ("ux", f["u"][0]), ("uy", f["u"][1])):
-            worst[name] = max(worst[name], abs(g[name][z, y, x] - ref[cz, r, r]) / scale[name])
+            worst[name] = max(worst[name], abs(g[name][z, y, x] - ref[cz, cy, r]) / scale[name])
     print("sampled max error / scale", case, worst, flush=True)
     for name, v in worst.items():
         assert v <= tol, (case, name, v)
