@@ -114,7 +114,41 @@ __global__ __launch_bounds__(BX* BY) void k_moments(GridDims g, const T* __restr
                                                     const double* __restrict__ rho_ref,
                                                     double* __restrict__ rho, double* __restrict__ phi) {
     const Tile t = tile_coords(g);
-    if (t.in) node_moments<L, T, W, RG>(g, pop, rho_ref, rho, phi, t.x, t.y, t.z);
+    if constexpr (Deviation<T>::on && L == kD3Q27) {
+        // FP32 D3Q27 (the moment pass of every step): the reference densities
+        // of the pull sources come from an LDS copy of the tile with a halo of
+        // one node in x, y and z instead of 27 scattered loads per node
+        using Lt = Lattice<L>;
+        constexpr int RX = BX + 2, RY = BY + 2, RP = RX * RY;
+        __shared__ double sref[3][RP];
+        const int x0 = t.x - (int)threadIdx.x, y0 = t.y - (int)threadIdx.y;
+        for (int e = threadIdx.y * BX + threadIdx.x; e < 3 * RP; e += BX * BY) {
+            const int pl = e / RP, q = e % RP;
+            auto wr = [](int v, int m) { v %= m; return v < 0 ? v + m : v; };
+            const int gx = wr(x0 - 1 + q % RX, g.nx), gy = wr(y0 - 1 + q / RX, g.ny);
+            const int gz = wr(t.z - 1 + pl, g.nz);
+            sref[pl][q] = rho_ref[((int64_t)gz * g.ny + gy) * g.nx + gx];
+        }
+        __syncthreads();
+        if (!t.in) return;
+        const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
+        const int64_t n = node_index(g, t.x, t.y, t.z);
+        const int c0 = ((int)threadIdx.y + 1) * RX + (int)threadIdx.x + 1;
+        double r = 0.0, p = 0.0;
+#pragma unroll
+        for (int i = 0; i < Lt::Q; ++i) {
+            const bool bb = W && bounce(g, t.y, Lt::c[i][1]);
+            const int64_t m = bb ? n : n + nbr_off<L>(nb, i, -1);
+            const int s = bb ? opp_dir(i) : i;
+            const double ref = bb ? sref[1][c0] : sref[1 - Lt::c[i][2]][c0 - Lt::c[i][1] * RX - Lt::c[i][0]];
+            r += double(pop[(int64_t)s * g.N + m]) + Lt::w[i] * ref;
+            if (i < GLattice<L, RG>::Q) p += double(pop[(int64_t)(Lt::Q + s) * g.N + m]);
+        }
+        rho[n] = r;
+        phi[n] = p;
+    } else {
+        if (t.in) node_moments<L, T, W, RG>(g, pop, rho_ref, rho, phi, t.x, t.y, t.z);
+    }
 }
 
 template <int L, int E, bool W>
