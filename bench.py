@@ -103,6 +103,60 @@ def measure(wl, precision, steps, warmup, fields=None, coex=None, eos=None, extr
     return out, fields
 
 
+def batch_throughput(steps=100, warmup=10, count=64, lo=256, hi=1024):
+    """The batching form: `count` uneven D2Q9 instances (sides U{256..1024},
+    ratio U[100, 1000], FP32-mixed) advanced together (persistent launches,
+    graph-captured runs of steps, tile shape and workgroups per CU from the
+    autotuner's timed sweep), against the same instances advanced one after
+    another by the single-instance solver.  Aggregate MLUPS both ways."""
+    import torch
+    import paper_1710_07486_amd as T_
+    from paper_1710_07486_amd import autotune
+    from paper_1710_07486_amd.batch import Batch
+    from synth import workloads as W
+    insts = W.batch_instances(count, seed=3, lo=lo, hi=hi)
+    params, fields = [], []
+    for wl in insts:
+        T = T_.temperature_for_ratio(wl.ratio)
+        rg, rl, _, _ = T_.coexistence(T)
+        p = library_params(T, wl, T_.FP32_MIXED)
+        p.rho_g, p.rho_l = rg, rl
+        params.append(p)
+        fields.append(W.fields(wl, rg, rl))
+    nodes = sum(wl.nodes for wl in insts)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with Batch(params) as b:
+        for i, (r, ph, u) in enumerate(fields):
+            b.init_fields(i, r, ph, u)
+        rec = autotune.tune(b, steps=10, warmup=4, cache=None)
+        b.step(warmup)
+        b.sync()
+        e0.record(b.stream)
+        b.step(steps)
+        e1.record(b.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        finite = all(bool(np.isfinite(b.read(i, "rho")).all()) for i in range(0, count, 8))
+    seq_ms = 0.0
+    s_steps = max(10, steps // 5)
+    for p, (r, ph, u) in zip(params, fields):
+        with T_.Solver(p) as s:
+            s.init_fields(r, ph, u)
+            s.step(3)
+            s.sync()
+            e0.record(s.stream)
+            s.step(s_steps)
+            e1.record(s.stream)
+            torch.cuda.synchronize()
+            seq_ms += e0.elapsed_time(e1) / s_steps
+        torch.cuda.empty_cache()
+    return {"instances": count, "sides": [lo, hi], "nodes": nodes, "precision": "fp32_mixed",
+            "batched_mlups": round(nodes / ms / 1e3, 2),
+            "ms_per_step": round(ms, 4), "one_by_one_mlups": round(nodes / seq_ms / 1e3, 2),
+            "speedup_vs_one_by_one": round(seq_ms / ms, 3), "tile_shape": rec["shape"], "wg_per_cu": rec["wg_per_cu"],
+            "finite": finite}
+
+
 def cpu_baseline(wl, budget_s=15.0):
     """The FP64 oracle on the host cores, on a bounded number of steps of the
     same workload."""
@@ -190,6 +244,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the D3Q27 256^3 measurement")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--no-reduced", action="store_true", help="skip the reduced phase-field lattice measurement")
     ap.add_argument("--no-walls", action="store_true", help="skip the wall-bounded channel measurement")
     ap.add_argument("--no-eos", action="store_true", help="skip the van der Waals / Peng-Robinson measurement")
@@ -321,6 +376,14 @@ def main():
     if args.coex_cache and not os.path.exists(args.coex_cache):
         with open(args.coex_cache, "w") as fh:
             json.dump(cache, fh)
+    if not args.no_batch:
+        log("batched form")
+        # the batch workload (sides 256..1024), and small lattices (32..128)
+        # whose single launches leave most of the GPU idle
+        result["batch"] = batch_throughput()
+        log("batch", result["batch"])
+        result["batch_small"] = batch_throughput(steps=200, warmup=20, count=64, lo=32, hi=128)
+        log("batch_small", result["batch_small"])
     if not args.no_surrogate:
         log("surrogate throughput")
         result["surrogate"] = surrogate_throughput()
