@@ -153,7 +153,10 @@ def batch_throughput(steps=100, warmup=10, count=64, lo=256, hi=1024):
     return {"instances": count, "sides": [lo, hi], "nodes": nodes, "precision": "fp32_mixed",
             "batched_mlups": round(nodes / ms / 1e3, 2),
             "ms_per_step": round(ms, 4), "one_by_one_mlups": round(nodes / seq_ms / 1e3, 2),
-            "speedup_vs_one_by_one": round(seq_ms / ms, 3), "tile_shape": rec["shape"], "wg_per_cu": rec["wg_per_cu"],
+            "speedup_vs_one_by_one": round(seq_ms / ms, 3),
+            "mode": "fused per instance" if rec.get("mode") == 1 else "persistent three-phase",
+            "persistent_best_mlups": round(nodes / min(r["ms_per_step"] for r in rec["table"] if r["mode"] == 0) / 1e3, 2),
+            "tile_shape": rec["shape"], "wg_per_cu": rec["wg_per_cu"],
             "finite": finite}
 
 

@@ -270,6 +270,14 @@ int telbm_batch_set_tiles(telbm_batch *b, int variant, int wg_per_cu);
 /* Steps per captured graph (even; 0 disables graphs).  Default 10. */
 int telbm_batch_set_graph_steps(telbm_batch *b, int steps_per_graph);
 
+/* Step mode of a D2Q9 batch: 0 (default) the persistent launches above; 1
+ * every instance takes the single solver's fused one-launch step, the
+ * instances on parallel branches of the captured graphs (pays for larger
+ * lattices, whose three-phase steps move ~480 B/node against 332).  The
+ * state carries over between the modes; may be changed between steps.
+ * TELBM_ERR_INVAL for D3Q27 batches or other values. */
+int telbm_batch_set_mode(telbm_batch *b, int mode);
+
 /* Initialise instance idx (same semantics as telbm_init_fields).  Every
  * instance must be initialised before the first telbm_batch_step. */
 int telbm_batch_init_fields(telbm_batch *b, int idx, const double *rho, const double *phi,

@@ -2,8 +2,10 @@
 
 For every compiled tile shape (threads along x and y of a workgroup) and
 every workgroups-per-CU count, the batch is stepped on the device and timed
-with HIP events on its stream; the fastest pair is applied and cached in a
-JSON file keyed by lattice, precision, device and problem-size class.
+with HIP events on its stream; a D2Q9 batch is also timed in its fused mode
+(the single solver's fused step per instance).  The fastest configuration is
+applied and cached in a JSON file keyed by lattice, precision, device and
+problem-size class.
 """
 from __future__ import annotations
 
@@ -56,17 +58,27 @@ def tune(batch: Batch, steps: int = 20, warmup: int = 10, wg_options: Sequence[i
     if not force and key in db:
         rec = db[key]
         batch.set_tiles(rec["variant"], rec["wg_per_cu"])
+        batch.set_mode(rec.get("mode", 0))
         return rec
     shapes = tile_variants()
     table = []
+    batch.set_mode(0)
     for v, shape in enumerate(shapes):
         for wg in wg_options:
             ms = time_config(batch, v, wg, steps, warmup)
-            table.append({"variant": v, "shape": list(shape), "wg_per_cu": wg, "ms_per_step": ms})
+            table.append({"mode": 0, "variant": v, "shape": list(shape), "wg_per_cu": wg, "ms_per_step": ms})
+    best0 = min(table, key=lambda r: r["ms_per_step"])
+    if batch.params[0].lattice == 0:
+        # the fused mode (one fused launch per instance and step)
+        batch.set_mode(1)
+        ms = time_config(batch, best0["variant"], best0["wg_per_cu"], steps, warmup)
+        table.append({"mode": 1, "variant": best0["variant"], "shape": best0["shape"],
+                      "wg_per_cu": best0["wg_per_cu"], "ms_per_step": ms})
     best = min(table, key=lambda r: r["ms_per_step"])
-    rec = {"variant": best["variant"], "shape": best["shape"], "wg_per_cu": best["wg_per_cu"],
+    rec = {"mode": best["mode"], "variant": best["variant"], "shape": best["shape"], "wg_per_cu": best["wg_per_cu"],
            "ms_per_step": best["ms_per_step"], "table": table}
     batch.set_tiles(rec["variant"], rec["wg_per_cu"])
+    batch.set_mode(rec["mode"])
     if cache:
         db[key] = rec
         os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)

@@ -24,6 +24,7 @@ PROTOTYPES = {
     "telbm_batch_tile_shape": (_i, [_i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "telbm_batch_set_tiles": (_i, [_vp, _i, _i]),
     "telbm_batch_set_graph_steps": (_i, [_vp, _i]),
+    "telbm_batch_set_mode": (_i, [_vp, _i]),
     "telbm_batch_init_fields": (_i, [_vp, _i, _vp, _vp, _vp, _i]),
     "telbm_batch_step": (_i, [_vp, _i64]),
     "telbm_batch_read": (_i, [_vp, _i, _i, _vp, _i]),
@@ -79,6 +80,7 @@ class Batch:
             raise RuntimeError("telbm needs a GPU: no HIP device is visible")
         self.L = _load()
         self.params = list(params)
+        self.mode = 0
         nbytes = required_bytes(self.params)
         self.arena = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self._cs = _arr(self.params)
@@ -118,6 +120,12 @@ class Batch:
 
     def set_graph_steps(self, n: int):
         self._check(self.L.telbm_batch_set_graph_steps(self.h, int(n)))
+
+    def set_mode(self, mode: int):
+        """0: persistent launches over (instance, tile) work lists; 1 (D2Q9):
+        the single solver's fused step per instance on parallel graph branches."""
+        self._check(self.L.telbm_batch_set_mode(self.h, int(mode)))
+        self.mode = int(mode)
 
     def init_fields(self, idx: int, rho, phi, u=None):
         p = self.params[idx]

@@ -9,6 +9,15 @@
 // capture an even number of steps (so the ping-pong parity returns to its
 // start).  The tile shape is a template parameter chosen at run time
 // (telbm_batch_set_tiles, driven by the autotuner in autotune.py).
+//
+// D2Q9 batches also have a second mode (telbm_batch_set_mode): every step
+// of every instance is the single solver's fused one-launch step (potentials,
+// collision and next-step moment sums with tile inboxes), captured into the
+// graphs on a few parallel branches (instance i on branch i mod kBranches)
+// so that small instances run side by side.  Both modes share the state at a
+// step boundary (populations, and for the FP32 form the reference densities
+// rhob[ref]); the fused mode adds per-instance partial densities, phase
+// field and inboxes, rebuilt from the populations whenever it is entered.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -36,7 +45,12 @@ struct InstDesc {
     double* rhob[2];
     double *phi, *mux, *mup;
     int bxc, byc;  // tiles along x and y for the current tile shape
+    // fused mode (D2Q9): current / next partial densities and phase field,
+    // and the two inbox arrays
+    double *xr[2], *xp[2], *inbox[2];
 };
+
+constexpr int kBranches = 4;  // parallel graph branches of the fused mode
 
 struct TileShape {
     int bx, by;
@@ -140,8 +154,16 @@ struct telbm_batch {
     int cur, ref;
     int64_t steps;
     int chunk;  // steps per captured graph (even)
-    std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;  // (shape, wg, chunk, cur, ref)
+    std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;  // (mode, shape, wg, chunk, cur, ref)
     std::string err;
+    // fused mode: on (1) or off (0); whether xr[fp], xp[fp] hold the current
+    // densities and phase field (fvalid) and whether they are partial sums
+    // still to be completed from inbox[fp] (fpartial)
+    int mode;
+    int fp;
+    bool fvalid, fpartial;
+    hipStream_t br[kBranches];  // capture branches
+    hipEvent_t fork, join[kBranches];
 };
 
 namespace {
@@ -154,11 +176,18 @@ int bfail(telbm_batch* b, int code, const std::string& m) {
     return code;
 }
 
+size_t fused_extra_bytes(const telbm_params& p) {
+    if (p.lattice != TELBM_D2Q9) return 0;
+    const size_t N = (size_t)p.nx * p.ny * p.nz;
+    GridDims g{p.nx, p.ny, p.nz, 0, (int64_t)N};
+    return 4 * al(N * sizeof(double)) + 2 * al(inbox_doubles(g) * sizeof(double));
+}
+
 size_t inst_bytes(const telbm_params& p) {
     const int Q = p.lattice == TELBM_D2Q9 ? 9 : 27;
     const size_t N = (size_t)p.nx * p.ny * p.nz;
     const size_t s = p.precision == TELBM_FP32_MIXED ? 4 : 8;
-    return 2 * al(2 * Q * N * s) + 5 * al(N * sizeof(double));
+    return 2 * al(2 * Q * N * s) + 5 * al(N * sizeof(double)) + fused_extra_bytes(p);
 }
 
 size_t max_tiles(const telbm_params* p, int count) {
@@ -266,6 +295,58 @@ void advance(telbm_batch* b) {
     b->cur = 1 - b->cur;
     if (b->precision == TELBM_FP32_MIXED) b->ref = 1 - b->ref;
     b->steps += 1;
+    if (b->mode == 1) {
+        b->fp = 1 - b->fp;
+        b->fpartial = true;
+    } else {
+        b->fvalid = false;
+    }
+}
+
+// One fused step of instance i on stream st, from state (cur, ref, fp); the
+// densities of the first step after entering the mode are complete
+// (partial false).
+hipError_t fused_step(telbm_batch* b, int i, hipStream_t st, int cur, int ref, int fp, bool partial) {
+    const InstDesc& d = b->desc[i];
+    const bool mixed = b->precision == TELBM_FP32_MIXED;
+    StepArgs a{};
+    a.g = d.g;
+    a.k = d.k;
+    a.src = d.pop[cur];
+    a.dst = d.pop[1 - cur];
+    a.rho_ref = mixed ? d.rhob[ref] : nullptr;
+    a.rho = d.xr[fp];
+    a.phi = d.xp[fp];
+    a.inbox_in = partial ? d.inbox[fp] : nullptr;
+    a.rho_next = d.xr[1 - fp];
+    a.phi_next = d.xp[1 - fp];
+    a.inbox_out = d.inbox[1 - fp];
+    a.rho_final = mixed ? d.rhob[1 - ref] : nullptr;
+    a.diag = 0;
+    a.stream = st;
+    return launch_part(b->lattice, b->precision, a, 3);
+}
+
+// Enter the fused mode: the current densities and phase field of every
+// instance from its populations (relative to rhob[ref] in the FP32 form).
+hipError_t fused_enter(telbm_batch* b) {
+    const bool mixed = b->precision == TELBM_FP32_MIXED;
+    for (int i = 0; i < b->count; ++i) {
+        const InstDesc& d = b->desc[i];
+        StepArgs a{};
+        a.g = d.g;
+        a.k = d.k;
+        a.src = d.pop[b->cur];
+        a.rho_ref = mixed ? d.rhob[b->ref] : nullptr;
+        a.rho = d.xr[b->fp];
+        a.phi = d.xp[b->fp];
+        a.stream = b->stream;
+        hipError_t e = launch_part(b->lattice, b->precision, a, 0);
+        if (e != hipSuccess) return e;
+    }
+    b->fvalid = true;
+    b->fpartial = false;
+    return hipSuccess;
 }
 
 StepArgs inst_args(telbm_batch* b, int i, bool init) {
@@ -358,6 +439,17 @@ int telbm_batch_create(const telbm_params* p, int count, void* arena, size_t byt
         o += al(N * sizeof(double));
         d.mup = (double*)(a + o);
         o += al(N * sizeof(double));
+        for (int j = 0; j < 2; ++j) d.xr[j] = d.xp[j] = d.inbox[j] = nullptr;
+        if (q.lattice == TELBM_D2Q9) {
+            for (int j = 0; j < 2; ++j) {
+                d.xr[j] = (double*)(a + o);
+                o += al(N * sizeof(double));
+                d.xp[j] = (double*)(a + o);
+                o += al(N * sizeof(double));
+                d.inbox[j] = (double*)(a + o);
+                o += al(inbox_doubles(d.g) * sizeof(double));
+            }
+        }
     }
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -370,17 +462,43 @@ int telbm_batch_create(const telbm_params* p, int count, void* arena, size_t byt
     b->ref = 0;
     b->steps = 0;
     b->chunk = 10;
-    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+    b->mode = 0;
+    b->fp = 0;
+    b->fvalid = b->fpartial = false;
+    bool ok = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess;
+    for (int j = 0; j < kBranches; ++j) {
+        b->br[j] = nullptr;
+        b->join[j] = nullptr;
+    }
+    b->fork = nullptr;
+    ok = ok && hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+    for (int j = 0; j < kBranches && ok; ++j)
+        ok = hipStreamCreateWithFlags(&b->br[j], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&b->join[j], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        for (int j = 0; j < kBranches; ++j) {
+            if (b->br[j]) (void)hipStreamDestroy(b->br[j]);
+            if (b->join[j]) (void)hipEventDestroy(b->join[j]);
+        }
+        if (b->fork) (void)hipEventDestroy(b->fork);
+        if (b->cap) (void)hipStreamDestroy(b->cap);
         delete b;
         return TELBM_ERR_DEVICE;
     }
     rc = build_work(b);
     if (rc) {
-        (void)hipStreamDestroy(b->cap);
-        delete b;
+        (void)telbm_batch_destroy(b);
         return rc;
     }
     *out = b;
+    return TELBM_OK;
+}
+
+int telbm_batch_set_mode(telbm_batch* b, int mode) {
+    if (!b || mode < 0 || mode > 1) return TELBM_ERR_INVAL;
+    if (mode == 1 && b->lattice != TELBM_D2Q9) return bfail(b, TELBM_ERR_INVAL, "the fused mode is for D2Q9 batches");
+    b->mode = mode;
+    if (mode == 0) b->fvalid = false;
     return TELBM_OK;
 }
 
@@ -445,11 +563,62 @@ int telbm_batch_init_fields(telbm_batch* b, int idx, const double* rho, const do
     return TELBM_OK;
 }
 
+int fused_steps(telbm_batch* b, int64_t n) {
+    while (n > 0) {
+        if (!b->fvalid) {
+            hipError_t e = fused_enter(b);
+            if (e != hipSuccess) return bfail(b, TELBM_ERR_DEVICE, std::string("fused enter: ") + hipGetErrorString(e));
+        }
+        if (b->fpartial && b->chunk > 0 && n >= b->chunk) {
+            auto key = std::make_tuple(1, 0, 0, b->chunk, b->cur, b->ref * 2 + b->fp);
+            auto it = b->graphs.find(key);
+            if (it == b->graphs.end()) {
+                // the chunk's steps on kBranches parallel branches (instance i
+                // on branch i mod kBranches), forked from and joined to b->cap
+                hipGraph_t g;
+                hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) e = hipEventRecord(b->fork, b->cap);
+                for (int j = 0; j < kBranches && e == hipSuccess; ++j) e = hipStreamWaitEvent(b->br[j], b->fork, 0);
+                int cur = b->cur, ref = b->ref, fp = b->fp;
+                for (int s = 0; s < b->chunk && e == hipSuccess; ++s) {
+                    for (int i = 0; i < b->count && e == hipSuccess; ++i)
+                        e = fused_step(b, i, b->br[i % kBranches], cur, ref, fp, true);
+                    cur = 1 - cur;
+                    fp = 1 - fp;
+                    if (b->precision == TELBM_FP32_MIXED) ref = 1 - ref;
+                }
+                for (int j = 0; j < kBranches && e == hipSuccess; ++j) e = hipEventRecord(b->join[j], b->br[j]);
+                for (int j = 0; j < kBranches && e == hipSuccess; ++j) e = hipStreamWaitEvent(b->cap, b->join[j], 0);
+                hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+                if (e != hipSuccess || e2 != hipSuccess) return bfail(b, TELBM_ERR_DEVICE, "graph capture failed");
+                hipGraphExec_t ex;
+                e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) return bfail(b, TELBM_ERR_DEVICE, "graph instantiate failed");
+                it = b->graphs.emplace(key, ex).first;
+            }
+            hipError_t e = hipGraphLaunch(it->second, b->stream);
+            if (e != hipSuccess) return bfail(b, TELBM_ERR_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+            for (int s = 0; s < b->chunk; ++s) advance(b);
+            n -= b->chunk;
+        } else {
+            for (int i = 0; i < b->count; ++i) {
+                hipError_t e = fused_step(b, i, b->stream, b->cur, b->ref, b->fp, b->fpartial);
+                if (e != hipSuccess) return bfail(b, TELBM_ERR_DEVICE, std::string("fused step: ") + hipGetErrorString(e));
+            }
+            advance(b);
+            n -= 1;
+        }
+    }
+    return TELBM_OK;
+}
+
 int telbm_batch_step(telbm_batch* b, int64_t n) {
     if (!b || n < 0) return TELBM_ERR_INVAL;
+    if (b->mode == 1) return fused_steps(b, n);
     while (n > 0) {
         if (b->chunk > 0 && n >= b->chunk) {
-            auto key = std::make_tuple(b->shape, b->wg_per_cu, b->chunk, b->cur, b->ref);
+            auto key = std::make_tuple(0, b->shape, b->wg_per_cu, b->chunk, b->cur, b->ref);
             auto it = b->graphs.find(key);
             if (it == b->graphs.end()) {
                 hipGraph_t g;
@@ -512,8 +681,15 @@ int telbm_batch_step_count(const telbm_batch* b, int64_t* steps) {
 int telbm_batch_destroy(telbm_batch* b) {
     if (!b) return TELBM_ERR_INVAL;
     (void)hipStreamSynchronize(b->stream);
+    for (int j = 0; j < kBranches; ++j)
+        if (b->br[j]) (void)hipStreamSynchronize(b->br[j]);
     drop_graphs(b);
-    (void)hipStreamDestroy(b->cap);
+    for (int j = 0; j < kBranches; ++j) {
+        if (b->br[j]) (void)hipStreamDestroy(b->br[j]);
+        if (b->join[j]) (void)hipEventDestroy(b->join[j]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
     delete b;
     return TELBM_OK;
 }

@@ -156,3 +156,51 @@ def test_batch_mixed_equations_of_state(orc):
         for g, key in zip(got[i], ("rho", "phi")):
             err = np.abs(g - ref[key]).max() / np.abs(ref[key]).max()
             assert err < 1e-10, (i, key, err)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_mode_matches_single(orc, precision):
+    """The fused mode (the single solver's fused step per instance, graph
+    branches) gives the single runs' results: 4 eager steps then two graph
+    chunks of 10."""
+    from paper_1710_07486_amd.batch import Batch
+    inst = instances(orc, precision)
+    steps = 24
+    say("batch fused mode vs single solvers, precision", precision)
+    singles = [run_single(pl, r, p, u, steps) for (_, pl, r, p, u) in inst]
+    with Batch([pl for (_, pl, *_r) in inst]) as b:
+        b.set_mode(1)
+        for i, (_, pl, r, p, u) in enumerate(inst):
+            b.init_fields(i, r, p, u)
+        b.step(4)
+        b.step(20)
+        for i in range(len(inst)):
+            for k in ("rho", "phi", "ux", "uy"):
+                got, ref = b.read(i, k), singles[i][k]
+                err = np.abs(got - ref).max() / np.abs(ref).max()
+                assert err <= 1e-12, (i, k, err)
+
+
+def test_switching_modes_and_reading_mid_run(orc):
+    """Persistent 6 steps, fused 10 (a graph chunk), a read, fused 4,
+    persistent 4: the state carries over and matches 24 single steps."""
+    from paper_1710_07486_amd.batch import Batch
+    inst = instances(orc, 0)
+    say("batch mode switching")
+    singles = [run_single(pl, r, p, u, 24) for (_, pl, r, p, u) in inst]
+    with Batch([pl for (_, pl, *_r) in inst]) as b:
+        for i, (_, pl, r, p, u) in enumerate(inst):
+            b.init_fields(i, r, p, u)
+        b.step(6)
+        b.set_mode(1)
+        b.step(10)
+        b.read(2, "rho")
+        b.step(4)
+        b.set_mode(0)
+        b.step(4)
+        assert b.steps == 24
+        for i in range(len(inst)):
+            for k in ("rho", "phi", "ux"):
+                got, ref = b.read(i, k), singles[i][k]
+                err = np.abs(got - ref).max() / np.abs(ref).max()
+                assert err <= 1e-12, (i, k, err)
