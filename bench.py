@@ -154,7 +154,7 @@ def batch_throughput(steps=100, warmup=10, count=64, lo=256, hi=1024):
             "batched_mlups": round(nodes / ms / 1e3, 2),
             "ms_per_step": round(ms, 4), "one_by_one_mlups": round(nodes / seq_ms / 1e3, 2),
             "speedup_vs_one_by_one": round(seq_ms / ms, 3),
-            "mode": "fused per instance" if rec.get("mode") == 1 else "persistent three-phase",
+            "mode": {0: "persistent three-phase", 1: "fused per instance", 2: "fused, one launch"}[rec.get("mode", 0)],
             "persistent_best_mlups": round(nodes / min(r["ms_per_step"] for r in rec["table"] if r["mode"] == 0) / 1e3, 2),
             "tile_shape": rec["shape"], "wg_per_cu": rec["wg_per_cu"],
             "finite": finite}

@@ -272,10 +272,12 @@ int telbm_batch_set_graph_steps(telbm_batch *b, int steps_per_graph);
 
 /* Step mode of a D2Q9 batch: 0 (default) the persistent launches above; 1
  * every instance takes the single solver's fused one-launch step, the
- * instances on parallel branches of the captured graphs (pays for larger
- * lattices, whose three-phase steps move ~480 B/node against 332).  The
- * state carries over between the modes; may be changed between steps.
- * TELBM_ERR_INVAL for D3Q27 batches or other values. */
+ * instances on parallel branches of the captured graphs; 2 the same fused
+ * step for all instances in one launch over an (instance, 64 x 8 tile) work
+ * list (one launch per equation of state present).  The fused step moves
+ * 332 B/node against ~480 for the three-phase step.  The state carries over
+ * between the modes; may be changed between steps.  TELBM_ERR_INVAL for
+ * D3Q27 batches or other values. */
 int telbm_batch_set_mode(telbm_batch *b, int mode);
 
 /* Initialise instance idx (same semantics as telbm_init_fields).  Every

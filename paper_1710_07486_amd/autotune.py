@@ -2,8 +2,9 @@
 
 For every compiled tile shape (threads along x and y of a workgroup) and
 every workgroups-per-CU count, the batch is stepped on the device and timed
-with HIP events on its stream; a D2Q9 batch is also timed in its fused mode
-(the single solver's fused step per instance).  The fastest configuration is
+with HIP events on its stream; a D2Q9 batch is also timed in its two fused
+modes (the single solver's fused step per instance, or for all instances in
+one launch).  The fastest configuration is
 applied and cached in a JSON file keyed by lattice, precision, device and
 problem-size class.
 """
@@ -69,11 +70,12 @@ def tune(batch: Batch, steps: int = 20, warmup: int = 10, wg_options: Sequence[i
             table.append({"mode": 0, "variant": v, "shape": list(shape), "wg_per_cu": wg, "ms_per_step": ms})
     best0 = min(table, key=lambda r: r["ms_per_step"])
     if batch.params[0].lattice == 0:
-        # the fused mode (one fused launch per instance and step)
-        batch.set_mode(1)
-        ms = time_config(batch, best0["variant"], best0["wg_per_cu"], steps, warmup)
-        table.append({"mode": 1, "variant": best0["variant"], "shape": best0["shape"],
-                      "wg_per_cu": best0["wg_per_cu"], "ms_per_step": ms})
+        # the fused modes: one fused launch per instance, or one for all
+        for mode in (1, 2):
+            batch.set_mode(mode)
+            ms = time_config(batch, best0["variant"], best0["wg_per_cu"], steps, warmup)
+            table.append({"mode": mode, "variant": best0["variant"], "shape": best0["shape"],
+                          "wg_per_cu": best0["wg_per_cu"], "ms_per_step": ms})
     best = min(table, key=lambda r: r["ms_per_step"])
     rec = {"mode": best["mode"], "variant": best["variant"], "shape": best["shape"], "wg_per_cu": best["wg_per_cu"],
            "ms_per_step": best["ms_per_step"], "table": table}

@@ -122,8 +122,9 @@ class Batch:
         self._check(self.L.telbm_batch_set_graph_steps(self.h, int(n)))
 
     def set_mode(self, mode: int):
-        """0: persistent launches over (instance, tile) work lists; 1 (D2Q9):
-        the single solver's fused step per instance on parallel graph branches."""
+        """0: persistent three-phase launches over (instance, tile) work lists;
+        D2Q9 only: 1, the single solver's fused step per instance on parallel
+        graph branches; 2, that fused step for all instances in one launch."""
         self._check(self.L.telbm_batch_set_mode(self.h, int(mode)))
         self.mode = int(mode)
 

@@ -10,14 +10,16 @@
 // start).  The tile shape is a template parameter chosen at run time
 // (telbm_batch_set_tiles, driven by the autotuner in autotune.py).
 //
-// D2Q9 batches also have a second mode (telbm_batch_set_mode): every step
-// of every instance is the single solver's fused one-launch step (potentials,
-// collision and next-step moment sums with tile inboxes), captured into the
-// graphs on a few parallel branches (instance i on branch i mod kBranches)
-// so that small instances run side by side.  Both modes share the state at a
-// step boundary (populations, and for the FP32 form the reference densities
-// rhob[ref]); the fused mode adds per-instance partial densities, phase
-// field and inboxes, rebuilt from the populations whenever it is entered.
+// D2Q9 batches have two more modes (telbm_batch_set_mode) that take the
+// single solver's fused one-launch step (potentials, collision and
+// next-step moment sums with tile inboxes): mode 1 launches it per instance,
+// captured into the graphs on a few parallel branches (instance i on branch
+// i mod kBranches); mode 2 runs it for all instances in one launch over an
+// (instance, 64 x 8 tile) work list (one launch per equation of state
+// present).  All modes share the state at a step boundary (populations, and
+// for the FP32 form the reference densities rhob[ref]); the fused modes add
+// per-instance partial densities, phase field and inboxes, rebuilt from the
+// populations whenever they are entered.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -156,10 +158,14 @@ struct telbm_batch {
     int chunk;  // steps per captured graph (even)
     std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;  // (mode, shape, wg, chunk, cur, ref)
     std::string err;
-    // fused mode: on (1) or off (0); whether xr[fp], xp[fp] hold the current
-    // densities and phase field (fvalid) and whether they are partial sums
-    // still to be completed from inbox[fp] (fpartial)
+    // mode 0 (persistent three-phase), 1 (fused per instance) or 2 (fused,
+    // one launch); whether xr[fp], xp[fp] hold the current densities and
+    // phase field (fvalid) and whether they are partial sums still to be
+    // completed from inbox[fp] (fpartial)
     int mode;
+    FusedDesc* fdesc_dev;  // mode 2: per-instance pointers
+    int2* fwork_dev;       // mode 2: (instance, tile) items grouped by equation of state
+    int fwork_off[3], fwork_cnt[3];
     int fp;
     bool fvalid, fpartial;
     hipStream_t br[kBranches];  // capture branches
@@ -188,6 +194,14 @@ size_t inst_bytes(const telbm_params& p) {
     const size_t N = (size_t)p.nx * p.ny * p.nz;
     const size_t s = p.precision == TELBM_FP32_MIXED ? 4 : 8;
     return 2 * al(2 * Q * N * s) + 5 * al(N * sizeof(double)) + fused_extra_bytes(p);
+}
+
+// (instance, 64 x 8 tile) items of the fused one-launch mode (D2Q9 only)
+size_t fused_items(const telbm_params* p, int count) {
+    size_t t = 0;
+    for (int i = 0; i < count; ++i)
+        if (p[i].lattice == TELBM_D2Q9) t += (size_t)fused_tiles_x(p[i].nx) * ((p[i].ny + 7) / 8);
+    return t;
 }
 
 size_t max_tiles(const telbm_params* p, int count) {
@@ -276,6 +290,52 @@ int build_work(telbm_batch* b) {
     return TELBM_OK;
 }
 
+// Descriptors and the equation-of-state-grouped work list of mode 2.
+int build_fused(telbm_batch* b) {
+    std::vector<FusedDesc> fd(b->count);
+    std::vector<int2> work;
+    for (int i = 0; i < b->count; ++i) {
+        const InstDesc& d = b->desc[i];
+        FusedDesc& f = fd[i];
+        f.g = d.g;
+        f.k = d.k;
+        for (int j = 0; j < 2; ++j) {
+            f.pop[j] = d.pop[j];
+            f.rhob[j] = d.rhob[j];
+            f.xr[j] = d.xr[j];
+            f.xp[j] = d.xp[j];
+            f.inbox[j] = d.inbox[j];
+        }
+    }
+    for (int e = 0; e < 3; ++e) {
+        b->fwork_off[e] = (int)work.size();
+        for (int i = 0; i < b->count; ++i) {
+            if (b->desc[i].k.eos != e) continue;
+            const int nt = fused_tiles_x(b->desc[i].g.nx) * ((b->desc[i].g.ny + 7) / 8);
+            for (int t = 0; t < nt; ++t) work.push_back(make_int2(i, t));
+        }
+        b->fwork_cnt[e] = (int)work.size() - b->fwork_off[e];
+    }
+    hipError_t e = hipMemcpyAsync(b->fdesc_dev, fd.data(), b->count * sizeof(FusedDesc), hipMemcpyHostToDevice,
+                                  b->stream);
+    if (e == hipSuccess && !work.empty())
+        e = hipMemcpyAsync(b->fwork_dev, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, TELBM_ERR_DEVICE, std::string("fused work list: ") + hipGetErrorString(e));
+    return TELBM_OK;
+}
+
+// One step of every instance in mode 2 (one launch per equation of state).
+hipError_t fused_launches(telbm_batch* b, hipStream_t st, int cur, int ref, int fp, bool partial) {
+    for (int e = 0; e < 3; ++e) {
+        if (b->fwork_cnt[e] == 0) continue;
+        hipError_t r = launch_batch_fused2(b->precision, e, 0, st, b->fdesc_dev, b->fwork_dev + b->fwork_off[e],
+                                           b->fwork_cnt[e], cur, ref, fp, partial ? 1 : 0);
+        if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+}
+
 void drop_graphs(telbm_batch* b) {
     for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
     b->graphs.clear();
@@ -295,7 +355,7 @@ void advance(telbm_batch* b) {
     b->cur = 1 - b->cur;
     if (b->precision == TELBM_FP32_MIXED) b->ref = 1 - b->ref;
     b->steps += 1;
-    if (b->mode == 1) {
+    if (b->mode != 0) {
         b->fp = 1 - b->fp;
         b->fpartial = true;
     } else {
@@ -377,6 +437,7 @@ int telbm_batch_required_bytes(const telbm_params* p, int count, size_t* bytes) 
     int rc = check_params(p, count, &why);
     if (rc) return rc;
     size_t total = al(count * sizeof(InstDesc)) + al(max_tiles(p, count) * sizeof(int2)) + al(sizeof(unsigned long long));
+    total += al(count * sizeof(FusedDesc)) + al(fused_items(p, count) * sizeof(int2));
     for (int i = 0; i < count; ++i) total += inst_bytes(p[i]);
     *bytes = total;
     return TELBM_OK;
@@ -405,6 +466,10 @@ int telbm_batch_create(const telbm_params* p, int count, void* arena, size_t byt
     b->work_dev = (int2*)(a + o);
     o += al(b->work_cap * sizeof(int2));
     o += al(sizeof(unsigned long long));
+    b->fdesc_dev = (FusedDesc*)(a + o);
+    o += al(count * sizeof(FusedDesc));
+    b->fwork_dev = (int2*)(a + o);
+    o += al(fused_items(p, count) * sizeof(int2));
     for (int i = 0; i < count; ++i) {
         const telbm_params& q = p[i];
         double mg, ml, C, psi0;
@@ -486,6 +551,7 @@ int telbm_batch_create(const telbm_params* p, int count, void* arena, size_t byt
         return TELBM_ERR_DEVICE;
     }
     rc = build_work(b);
+    if (rc == TELBM_OK && b->lattice == TELBM_D2Q9) rc = build_fused(b);
     if (rc) {
         (void)telbm_batch_destroy(b);
         return rc;
@@ -495,8 +561,8 @@ int telbm_batch_create(const telbm_params* p, int count, void* arena, size_t byt
 }
 
 int telbm_batch_set_mode(telbm_batch* b, int mode) {
-    if (!b || mode < 0 || mode > 1) return TELBM_ERR_INVAL;
-    if (mode == 1 && b->lattice != TELBM_D2Q9) return bfail(b, TELBM_ERR_INVAL, "the fused mode is for D2Q9 batches");
+    if (!b || mode < 0 || mode > 2) return TELBM_ERR_INVAL;
+    if (mode != 0 && b->lattice != TELBM_D2Q9) return bfail(b, TELBM_ERR_INVAL, "the fused modes are for D2Q9 batches");
     b->mode = mode;
     if (mode == 0) b->fvalid = false;
     return TELBM_OK;
@@ -570,9 +636,26 @@ int fused_steps(telbm_batch* b, int64_t n) {
             if (e != hipSuccess) return bfail(b, TELBM_ERR_DEVICE, std::string("fused enter: ") + hipGetErrorString(e));
         }
         if (b->fpartial && b->chunk > 0 && n >= b->chunk) {
-            auto key = std::make_tuple(1, 0, 0, b->chunk, b->cur, b->ref * 2 + b->fp);
+            auto key = std::make_tuple(b->mode, 0, 0, b->chunk, b->cur, b->ref * 2 + b->fp);
             auto it = b->graphs.find(key);
-            if (it == b->graphs.end()) {
+            if (it == b->graphs.end() && b->mode == 2) {
+                hipGraph_t g;
+                hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+                int cur = b->cur, ref = b->ref, fp = b->fp;
+                for (int s = 0; s < b->chunk && e == hipSuccess; ++s) {
+                    e = fused_launches(b, b->cap, cur, ref, fp, true);
+                    cur = 1 - cur;
+                    fp = 1 - fp;
+                    if (b->precision == TELBM_FP32_MIXED) ref = 1 - ref;
+                }
+                hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+                if (e != hipSuccess || e2 != hipSuccess) return bfail(b, TELBM_ERR_DEVICE, "graph capture failed");
+                hipGraphExec_t ex;
+                e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) return bfail(b, TELBM_ERR_DEVICE, "graph instantiate failed");
+                it = b->graphs.emplace(key, ex).first;
+            } else if (it == b->graphs.end()) {
                 // the chunk's steps on kBranches parallel branches (instance i
                 // on branch i mod kBranches), forked from and joined to b->cap
                 hipGraph_t g;
@@ -602,9 +685,15 @@ int fused_steps(telbm_batch* b, int64_t n) {
             for (int s = 0; s < b->chunk; ++s) advance(b);
             n -= b->chunk;
         } else {
-            for (int i = 0; i < b->count; ++i) {
-                hipError_t e = fused_step(b, i, b->stream, b->cur, b->ref, b->fp, b->fpartial);
+            if (b->mode == 2) {
+                hipError_t e = fused_launches(b, b->stream, b->cur, b->ref, b->fp, b->fpartial);
                 if (e != hipSuccess) return bfail(b, TELBM_ERR_DEVICE, std::string("fused step: ") + hipGetErrorString(e));
+            } else {
+                for (int i = 0; i < b->count; ++i) {
+                    hipError_t e = fused_step(b, i, b->stream, b->cur, b->ref, b->fp, b->fpartial);
+                    if (e != hipSuccess)
+                        return bfail(b, TELBM_ERR_DEVICE, std::string("fused step: ") + hipGetErrorString(e));
+                }
             }
             advance(b);
             n -= 1;
@@ -615,7 +704,7 @@ int fused_steps(telbm_batch* b, int64_t n) {
 
 int telbm_batch_step(telbm_batch* b, int64_t n) {
     if (!b || n < 0) return TELBM_ERR_INVAL;
-    if (b->mode == 1) return fused_steps(b, n);
+    if (b->mode != 0) return fused_steps(b, n);
     while (n > 0) {
         if (b->chunk > 0 && n >= b->chunk) {
             auto key = std::make_tuple(0, b->shape, b->wg_per_cu, b->chunk, b->cur, b->ref);

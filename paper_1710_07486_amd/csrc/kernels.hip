@@ -551,25 +551,34 @@ struct NextSink {
     }
 };
 
-template <typename T, int E, bool RG, bool WALL>
-__global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysConst k, const T* __restrict__ src,
-                                                           T* __restrict__ dst, const double* __restrict__ rho_ref,
-                                                           const double* __restrict__ rho,
-                                                           const double* __restrict__ phi,
-                                                           const double* __restrict__ inbox_in,
-                                                           double* __restrict__ rho_next,
-                                                           double* __restrict__ phi_next,
-                                                           double* __restrict__ inbox_out,
-                                                           double* __restrict__ rho_final,
-                                                           double* __restrict__ partials, int diag) {
-    using Lt = Lattice<kD2Q9>;
-    __shared__ double sr[FHX * FHY], sp[FHX * FHY], smx[FMX * FMY], smp[FMX * FMY];
-    __shared__ double sref[Deviation<T>::on ? FHX * FHY : 1];
+// LDS of one fused 2D tile step.
+template <typename T>
+struct Fused2Lds {
     using Sink = NextSink<kD2Q9, FBY>;
-    __shared__ double nsum[Sink::SUM], nside[Sink::SIDE];
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int bxc = (g.nx + BX - 1) / BX;
-    const int bx = b % bxc, by = b / bxc;
+    double sr[FHX * FHY], sp[FHX * FHY], smx[FMX * FMY], smp[FMX * FMY];
+    double sref[Deviation<T>::on ? FHX * FHY : 1];
+    double nsum[Sink::SUM], nside[Sink::SIDE];
+};
+
+// One tile (bx, by) of the fused 2D step: the body of k_collide_fused2, also
+// walked over (instance, tile) work lists by the batched form.
+template <typename T, int E, bool RG, bool WALL>
+__device__ __forceinline__ void fused2_tile(Fused2Lds<T>& sh, const GridDims& g, const PhysConst& k,
+                                            const T* __restrict__ src, T* __restrict__ dst,
+                                            const double* __restrict__ rho_ref, const double* __restrict__ rho,
+                                            const double* __restrict__ phi, const double* __restrict__ inbox_in,
+                                            double* __restrict__ rho_next, double* __restrict__ phi_next,
+                                            double* __restrict__ inbox_out, double* __restrict__ rho_final,
+                                            double* __restrict__ partials, int diag, int bx, int by) {
+    using Lt = Lattice<kD2Q9>;
+    using Sink = NextSink<kD2Q9, FBY>;
+    double* sr = sh.sr;
+    double* sp = sh.sp;
+    double* smx = sh.smx;
+    double* smp = sh.smp;
+    double* sref = sh.sref;
+    double* nsum = sh.nsum;
+    double* nside = sh.nside;
     const int x0 = bx * BX, y0 = by * FBY;
     const int W = min(BX, g.nx - x0), H = min(FBY, g.ny - y0);
     const int tid = threadIdx.y * BX + threadIdx.x;
@@ -667,6 +676,69 @@ __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysCons
         inbox_out[q2 + 1] = s1;
     }
 }
+
+template <typename T, int E, bool RG, bool WALL>
+__global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysConst k, const T* __restrict__ src,
+                                                           T* __restrict__ dst, const double* __restrict__ rho_ref,
+                                                           const double* __restrict__ rho,
+                                                           const double* __restrict__ phi,
+                                                           const double* __restrict__ inbox_in,
+                                                           double* __restrict__ rho_next,
+                                                           double* __restrict__ phi_next,
+                                                           double* __restrict__ inbox_out,
+                                                           double* __restrict__ rho_final,
+                                                           double* __restrict__ partials, int diag) {
+    __shared__ Fused2Lds<T> sh;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int bxc = (g.nx + BX - 1) / BX;
+    fused2_tile<T, E, RG, WALL>(sh, g, k, src, dst, rho_ref, rho, phi, inbox_in, rho_next, phi_next, inbox_out,
+                                rho_final, partials, diag, b % bxc, b / bxc);
+}
+
+// The fused 2D step of a batch of periodic lattices in one launch: one
+// workgroup per (instance, 64 x 8 tile) item of the work list, consecutive
+// items on one XCD.  State: cur (populations), ref (FP32 reference
+// densities), fp (densities, phase field and inbox of the current step),
+// partial (those densities still to be completed from the inbox).
+template <typename T, int E>
+__global__ __launch_bounds__(BX* FBY) void k_batch_fused2(const FusedDesc* __restrict__ inst,
+                                                          const int2* __restrict__ work, int nwork, int cur,
+                                                          int ref, int fp, int partial) {
+    __shared__ Fused2Lds<T> sh;
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    if (w >= nwork) return;  // uniform over the block
+    const int2 it = work[w];
+    const FusedDesc& d = inst[it.x];
+    const int bxc = (d.g.nx + BX - 1) / BX;
+    const bool mixed = Deviation<T>::on;
+    fused2_tile<T, E, false, false>(sh, d.g, d.k, (const T*)d.pop[cur], (T*)d.pop[1 - cur],
+                                    mixed ? d.rhob[ref] : nullptr, d.xr[fp], d.xp[fp],
+                                    partial ? d.inbox[fp] : nullptr, d.xr[1 - fp], d.xp[1 - fp], d.inbox[1 - fp],
+                                    mixed ? d.rhob[1 - ref] : nullptr, nullptr, 0, it.y % bxc, it.y / bxc);
+}
+
+template <typename T>
+static hipError_t launch_batch_fused2_t(int eos, int grid, hipStream_t st, const FusedDesc* inst, const int2* work,
+                                        int nwork, int cur, int ref, int fp, int partial) {
+    const dim3 blk(BX, FBY, 1);
+    (void)grid;
+    grid = nwork;  // one workgroup per item
+    switch (eos) {
+        case 0: k_batch_fused2<T, 0><<<grid, blk, 0, st>>>(inst, work, nwork, cur, ref, fp, partial); break;
+        case 1: k_batch_fused2<T, 1><<<grid, blk, 0, st>>>(inst, work, nwork, cur, ref, fp, partial); break;
+        case 2: k_batch_fused2<T, 2><<<grid, blk, 0, st>>>(inst, work, nwork, cur, ref, fp, partial); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_fused2(int precision, int eos, int grid, hipStream_t st, const FusedDesc* inst,
+                               const int2* work, int nwork, int cur, int ref, int fp, int partial) {
+    return precision ? launch_batch_fused2_t<float>(eos, grid, st, inst, work, nwork, cur, ref, fp, partial)
+                     : launch_batch_fused2_t<double>(eos, grid, st, inst, work, nwork, cur, ref, fp, partial);
+}
+
+int fused_tiles_x(int nx) { return (nx + BX - 1) / BX; }
 
 // Completes partial next-step moments in place with their inbox entries (the
 // edge nodes of every tile), before the densities are read outside the fused

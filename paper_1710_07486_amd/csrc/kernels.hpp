@@ -45,6 +45,24 @@ struct StepArgs {
     hipStream_t stream;
 };
 
+// Per-instance pointers of the batched fused 2D step (k_batch_fused2).
+struct FusedDesc {
+    GridDims g;
+    PhysConst k;
+    void* pop[2];
+    double* rhob[2];            // FP32 form: reference / completed densities
+    double *xr[2], *xp[2];      // current / next (partial) densities and phase field
+    double* inbox[2];
+};
+
+// One launch of the fused 2D step over an (instance, tile) work list (tile
+// index = by * fused_tiles_x(nx) + bx on 64 x 8 tiles, one workgroup per
+// item; `grid` is unused) whose instances all have the equation of state
+// `eos`.
+hipError_t launch_batch_fused2(int precision, int eos, int grid, hipStream_t st, const FusedDesc* inst,
+                               const int2* work, int nwork, int cur, int ref, int fp, int partial);
+int fused_tiles_x(int nx);
+
 unsigned collide_blocks(const GridDims& g);
 unsigned fused_tiles(const GridDims& g);        // D2Q9 tiles of the fused step
 size_t inbox_doubles(const GridDims& g);        // size of one inbox array

@@ -158,18 +158,19 @@ def test_batch_mixed_equations_of_state(orc):
             assert err < 1e-10, (i, key, err)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_fused_mode_matches_single(orc, precision):
-    """The fused mode (the single solver's fused step per instance, graph
-    branches) gives the single runs' results: 4 eager steps then two graph
-    chunks of 10."""
+def test_fused_mode_matches_single(orc, precision, mode):
+    """The fused modes (the single solver's fused step per instance on graph
+    branches, or for all instances in one launch) give the single runs'
+    results: 4 eager steps then two graph chunks of 10."""
     from paper_1710_07486_amd.batch import Batch
     inst = instances(orc, precision)
     steps = 24
-    say("batch fused mode vs single solvers, precision", precision)
+    say("batch fused mode", mode, "vs single solvers, precision", precision)
     singles = [run_single(pl, r, p, u, steps) for (_, pl, r, p, u) in inst]
     with Batch([pl for (_, pl, *_r) in inst]) as b:
-        b.set_mode(1)
+        b.set_mode(mode)
         for i, (_, pl, r, p, u) in enumerate(inst):
             b.init_fields(i, r, p, u)
         b.step(4)
@@ -182,12 +183,13 @@ def test_fused_mode_matches_single(orc, precision):
 
 
 def test_switching_modes_and_reading_mid_run(orc):
-    """Persistent 6 steps, fused 10 (a graph chunk), a read, fused 4,
-    persistent 4: the state carries over and matches 24 single steps."""
+    """Persistent 6 steps, fused per instance 10 (a graph chunk), a read,
+    fused in one launch 11, persistent 3: the state carries over and matches
+    30 single steps."""
     from paper_1710_07486_amd.batch import Batch
     inst = instances(orc, 0)
     say("batch mode switching")
-    singles = [run_single(pl, r, p, u, 24) for (_, pl, r, p, u) in inst]
+    singles = [run_single(pl, r, p, u, 30) for (_, pl, r, p, u) in inst]
     with Batch([pl for (_, pl, *_r) in inst]) as b:
         for i, (_, pl, r, p, u) in enumerate(inst):
             b.init_fields(i, r, p, u)
@@ -195,10 +197,11 @@ def test_switching_modes_and_reading_mid_run(orc):
         b.set_mode(1)
         b.step(10)
         b.read(2, "rho")
-        b.step(4)
+        b.set_mode(2)
+        b.step(11)
         b.set_mode(0)
-        b.step(4)
-        assert b.steps == 24
+        b.step(3)
+        assert b.steps == 30
         for i in range(len(inst)):
             for k in ("rho", "phi", "ux"):
                 got, ref = b.read(i, k), singles[i][k]
