@@ -30,7 +30,7 @@ BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, TFLOP/s
 # counter passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, scales from a 1 GiB copy
 # in the same runs; profiles/collide_d2q9_1024_fp64_traffic.md), valid only for
 # the kernel sources whose hash is recorded with it.
-COLLIDE_TRAFFIC = {"bytes_per_launch": 348243365, "sources_sha256_16": "d951448317473982"}
+COLLIDE_TRAFFIC = {"bytes_per_launch": 348263540, "sources_sha256_16": "23c3c63e8f701e57"}
 
 
 def kernel_sources_hash():
