@@ -123,10 +123,12 @@ def test_batch_fp32_mixed_vs_fp64(orc):
     assert max(errs) < 1e-5
 
 
-def test_batch_mixed_equations_of_state(orc):
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_batch_mixed_equations_of_state(orc, mode):
     """Members with Carnahan-Starling (ratio 100), van der Waals (ratio 100)
     and Peng-Robinson (ratio 1000) free energies in one batch: each matches
-    the FP64 oracle run of its own free energy."""
+    the FP64 oracle run of its own free energy, in every batch mode (the
+    one-launch mode runs one launch per free energy present)."""
     import paper_1710_07486_amd as T
     from paper_1710_07486_amd.batch import Batch
     cases = [(dict(eos=0), 100.0, (48, 40)), (dict(eos=1, a=2.0 / 49.0, b=2.0 / 21.0), 100.0, (64, 50)),
@@ -142,10 +144,11 @@ def test_batch_mixed_equations_of_state(orc):
                       mobility=po.mobility, tau_phi=po.tau_phi)
         inst.append((po, pl, rho, phi))
     steps = 60
-    say("batch with CS, vdW and PR members vs oracle")
+    say("batch with CS, vdW and PR members vs oracle, mode", mode)
     with Batch([x[1] for x in inst]) as b:
         for i, (_, _pl, r, p) in enumerate(inst):
             b.init_fields(i, r, p, None)
+        b.set_mode(mode)
         b.step(steps)
         got = [(b.read(i, "rho"), b.read(i, "phi")) for i in range(len(inst))]
     for i, (po, _pl, r, p) in enumerate(inst):
@@ -207,3 +210,61 @@ def test_switching_modes_and_reading_mid_run(orc):
                 got, ref = b.read(i, k), singles[i][k]
                 err = np.abs(got - ref).max() / np.abs(ref).max()
                 assert err <= 1e-12, (i, k, err)
+
+
+def full_batch():
+    """The 64-instance batch workload (sides U{256..1024}, ratio U[100, 1000],
+    seed 3) at full size, started at each instance's Maxwell densities:
+    FP64 and FP32-mixed parameters, and the initial fields."""
+    import dataclasses
+    import paper_1710_07486_amd as T
+    params, fields = [], []
+    for wl in W.batch_instances(64, seed=3, lo=256, hi=1024):
+        t = T.temperature_for_ratio(wl.ratio)
+        rg, rl, _, _ = T.coexistence(t)
+        ph = wl.physics()
+        nz, ny, nx = wl.shape
+        params.append(T.Params(lattice=0, precision=0, nx=nx, ny=ny, nz=1, T=t, rho_g=rg, rho_l=rl,
+                               lambda1=ph["lambda1"], lambda2=ph["lambda2"], lambda3=ph["lambda3"],
+                               kappa1=ph["kappa1"], kappa2=ph["kappa2"], kappa3=ph["kappa3"], chi=ph["chi"],
+                               nu=ph["nu"], mobility=ph["mobility"], tau_phi=ph["tau_phi"]))
+        fields.append(W.fields(wl, rg, rl))
+    return params, [dataclasses.replace(p, precision=1) for p in params], fields
+
+
+SAMPLED = (0, 21, 42, 63)
+
+
+def test_full_size_batch_modes_fp32_vs_fp64():
+    """The full 64-instance workload (27.4 M nodes), 40 steps: the FP64
+    batch in the one-launch mode equals single-solver FP64 runs of sampled
+    instances to round-off; the FP32-mixed batch, in the persistent and the
+    one-launch mode, is within 1e-5 of the FP64 batch for every instance."""
+    from paper_1710_07486_amd.batch import Batch
+    steps = 40
+    say("full-size batch: coexistence temperatures and fields of 64 instances (host, ~30 s)")
+    p64, p32, fields = full_batch()
+    say("full-size batch, FP64 one-launch mode")
+    with Batch(p64) as b:
+        for i, (r, ph, u) in enumerate(fields):
+            b.init_fields(i, r, ph, u)
+        b.set_mode(2)
+        b.step(steps)
+        ref = [b.read(i, "rho") for i in range(len(p64))]
+        phi_ref = {i: b.read(i, "phi") for i in SAMPLED}
+    for i in SAMPLED:
+        say("single FP64 run of instance", i, p64[i].nx, p64[i].ny)
+        single = run_single(p64[i], *fields[i], steps)
+        for k, got in (("rho", ref[i]), ("phi", phi_ref[i])):
+            err = np.abs(got - single[k]).max() / np.abs(single[k]).max()
+            assert err <= 1e-12, (i, k, err)
+    for mode in (0, 2):
+        say("full-size batch, FP32-mixed, mode", mode)
+        with Batch(p32) as b:
+            for i, (r, ph, u) in enumerate(fields):
+                b.init_fields(i, r, ph, u)
+            b.set_mode(mode)
+            b.step(steps)
+            errs = [float(np.abs(b.read(i, "rho") - ref[i]).max() / np.abs(ref[i]).max()) for i in range(len(p32))]
+        print("mode", mode, "max relative density error over instances", max(errs), flush=True)
+        assert all(np.isfinite(errs)) and max(errs) < 1e-5, (mode, max(errs))
