@@ -94,8 +94,9 @@ def measure(wl, precision, steps, warmup, fields=None, coex=None, eos=None, extr
     ms = e0.elapsed_time(e1)
     kern = s.time_kernels(max(3, min(steps, 20)))
     d = s.diagnostics(check=False)
+    taken = s.steps
     out = {"mlups": wl.nodes * steps / (ms * 1e-3) / 1e6, "ms_per_step": ms / steps, "kernels_ms": kern,
-           "bytes_per_update": s.algorithmic_bytes_per_update(), "diag": d, "coex": [rg, rl]}
+           "bytes_per_update": s.algorithmic_bytes_per_update(), "diag": d, "coex": [rg, rl], "steps_taken": taken}
     out["rho"] = s.read("rho", check=False)
     s.close()
     del s
@@ -242,8 +243,10 @@ def copy_probe(nbytes=1 << 30):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    # 1000 timed steps after 200 warm-up (80 ms of D2Q9 FP64 work): with 200
+    # after 20 the short timed region read 5-15 % below the steady rate
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the D3Q27 256^3 measurement")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed measurement")
@@ -314,10 +317,16 @@ def main():
     if not args.no_fp32:
         r32, _ = measure(wl, T_.FP32_MIXED, args.steps, args.warmup, fields)
         log("fp32-mixed", {k: v for k, v in r32.items() if k != "rho"})
-        rel_rho = float(np.abs(r32["rho"] - r64["rho"]).max() / np.abs(r64["rho"]).max())
+        diff = np.abs(r32["rho"] - r64["rho"])
+        rel_rho = float(diff.max() / np.abs(r64["rho"]).max())
+        # the max-norm error sits on the interfaces (a shift of an interface
+        # by a small fraction of a node at ratio 1000); the mean-norm one is
+        # what the bulk sees.  Both runs have taken the same steps.
         result["fp32_mixed"] = {"value": round(r32["mlups"], 2), "unit": "MLUPS",
                                 "speedup_vs_fp64": round(r32["mlups"] / r64["mlups"], 3),
                                 "rel_density_error_vs_fp64": rel_rho,
+                                "rel_density_error_mean_norm_vs_fp64": float(diff.mean() / np.abs(r64["rho"]).mean()),
+                                "error_after_steps": r32["steps_taken"],
                                 "kernels_ms": {k: round(v, 5) for k, v in r32["kernels_ms"].items()}}
     if not args.no_eos:
         # the same drops with the other two free energies: Peng-Robinson at
@@ -372,6 +381,9 @@ def main():
             "fp64_kernels_ms": {k: round(v, 5) for k, v in k3.items()},
             "fp32_mixed_kernels_ms": {k: round(v, 5) for k, v in r3m["kernels_ms"].items()},
             "rel_density_error_mixed_vs_fp64": float(np.abs(r3m["rho"] - r3["rho"]).max() / np.abs(r3["rho"]).max()),
+            "rel_density_error_mean_norm_mixed_vs_fp64": float(np.abs(r3m["rho"] - r3["rho"]).mean()
+                                                               / np.abs(r3["rho"]).mean()),
+            "error_after_steps": r3m["steps_taken"],
         }
         if r3r is not None:
             result["d3q27_256"]["fp64_reduced_g_mlups"] = round(r3r["mlups"], 2)
@@ -385,7 +397,7 @@ def main():
         # whose single launches leave most of the GPU idle
         result["batch"] = batch_throughput()
         log("batch", result["batch"])
-        result["batch_small"] = batch_throughput(steps=200, warmup=20, count=64, lo=32, hi=128)
+        result["batch_small"] = batch_throughput(steps=2000, warmup=200, count=64, lo=32, hi=128)
         log("batch_small", result["batch_small"])
     if not args.no_surrogate:
         log("surrogate throughput")
