@@ -172,3 +172,20 @@ def test_reduced_phase_field_lattice_parameters(orc):
         assert e.value.code == _lib.ERR_INVAL, kw
     with pytest.raises(T.TelbmError):
         batch_bytes([T.Params(nx=16, ny=16, T=T0, glattice=1)])
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built HIP library every entry (solver, batch, surrogate
+    kernels) raises: there is no CPU fallback."""
+    import paper_1710_07486_amd as T
+    from paper_1710_07486_amd import _lib as L
+    from paper_1710_07486_amd import batch as B
+    from paper_1710_07486_amd import surrogate as S
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", "/nonexistent/libtelbm.so")
+    for call in (L.load, B._load, S._load, lambda: T.temperature_for_ratio(100.0)):
+        with pytest.raises(ImportError, match="is missing"):
+            call()
+    # the solver refuses first for want of a GPU where there is none
+    with pytest.raises((ImportError, RuntimeError)):
+        T.Solver(T.Params(nx=8, ny=8, T=0.03, rho_g=0.1, rho_l=1.0))
