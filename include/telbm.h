@@ -119,7 +119,8 @@ extern "C" {
  *                      Eq. (7) and moves 2 (Q + 5 or 7) instead of 4 Q values
  *                      per node and step.  Same availability as walls.
  * Validation: 0 < T < T_c, rho_l > rho_g > 0, nu > 0, tau_phi > 1/2, chi != 0,
- * sizes >= 1 (nz == 1 for D2Q9), nx*ny*nz < 2^40.                           */
+ * sizes >= 1 (nz == 1 for D2Q9), nx*ny*nz < 2^29 (the kernels address each
+ * FP64 slice of N values with 32-bit byte offsets).                        */
 typedef struct telbm_params {
     int32_t lattice;
     int32_t precision;
@@ -228,7 +229,10 @@ int telbm_step_count(const telbm_solver *s, int64_t *steps);
 
 /* Kernel-level timing: run n steps recording a HIP event pair around each
  * kernel launch, and return the mean duration in milliseconds of each kernel
- * kind (ms[k] for k < *kinds; names via telbm_kernel_name).  Synchronises. */
+ * kind (ms[k] for k < *kinds; names via telbm_kernel_name) and, in
+ * ms[*kinds], the mean time per step over the whole span from the first
+ * launch's start event to the last launch's end event.  `ms` must hold at
+ * least 4 values (3 kinds + the span).  Synchronises. */
 int telbm_time_kernels(telbm_solver *s, int64_t n, double *ms, int *kinds);
 const char *telbm_kernel_name(const telbm_solver *s, int kind);
 

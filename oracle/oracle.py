@@ -267,12 +267,24 @@ def eos_temperature_for_ratio(kind, ratio, a, b, R, omega=0.344):
     return tuple(out)
 
 
-def coexisting_params(ratio: float, **kw) -> Params:
-    """Params at the temperature whose Maxwell density ratio is ``ratio``."""
+def coexisting_params(ratio: float, T: Optional[float] = None, **kw) -> Params:
+    """Params at the temperature whose Maxwell density ratio is ``ratio``, or,
+    if ``T`` is given, at that temperature (rho_g, rho_l and C are always the
+    Maxwell construction's at the temperature used)."""
     p = Params(**kw)
-    T, rg, rl, C, _ = eos_temperature_for_ratio(p.eos, ratio, p.a, p.b, p.R, p.omega)
+    if T:
+        rg, rl, C, _ = eos_maxwell(p.eos, T, p.a, p.b, p.R, p.omega)
+    else:
+        T, rg, rl, C, _ = eos_temperature_for_ratio(p.eos, ratio, p.a, p.b, p.R, p.omega)
     p.T, p.rho_g, p.rho_l, p.C = T, rg, rl, C
     return p
+
+
+def workload_params(wl) -> Params:
+    """Params of a synthetic workload: its temperature if it fixes one (a
+    temperature chosen for the lattice model's own density ratio), else the
+    temperature of its Maxwell density ratio."""
+    return coexisting_params(wl.ratio, T=getattr(wl, "T", 0.0) or None, **wl.physics())
 
 
 # ---------------------------------------------------------------------------

@@ -124,8 +124,14 @@ int validate(const telbm_params* p, std::string* why) {
     if (p->precision != TELBM_FP64 && p->precision != TELBM_FP32_MIXED) { *why = "unknown precision"; return TELBM_ERR_INVAL; }
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) { *why = "sizes must be >= 1"; return TELBM_ERR_INVAL; }
     if (p->lattice == TELBM_D2Q9 && p->nz != 1) { *why = "D2Q9 needs nz == 1"; return TELBM_ERR_INVAL; }
+    // The kernels address each per-direction population slice and each FP64
+    // field with 32-bit byte offsets and 32-bit node indices, so an FP64
+    // slice (N * 8 bytes) must stay below 4 GiB: N < 2^29 nodes.
     const double N = (double)p->nx * p->ny * p->nz;
-    if (N >= 1099511627776.0) { *why = "lattice too large"; return TELBM_ERR_INVAL; }
+    if (N * 8.0 >= 4294967296.0) {
+        *why = "lattice too large: at most 2^29 - 1 nodes (32-bit byte offsets of the FP64 slices)";
+        return TELBM_ERR_INVAL;
+    }
     if (p->eos < TELBM_EOS_CS || p->eos > TELBM_EOS_PR) { *why = "unknown equation of state"; return TELBM_ERR_INVAL; }
     if (p->eos == TELBM_EOS_PR && !isfinite(p->omega)) { *why = "omega must be finite"; return TELBM_ERR_INVAL; }
     if (p->walls != 0 && p->walls != 1) { *why = "walls must be 0 or 1"; return TELBM_ERR_INVAL; }
@@ -611,6 +617,12 @@ int telbm_time_kernels(telbm_solver* s, int64_t n, double* ms, int* kinds) {
             cnt[t.kind[i]] += 1;
         }
         for (int k = 0; k < kKinds; ++k) ms[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
+        // the whole timed span per step: first launch's start event to the
+        // last launch's end event, on the solver's stream
+        float span = 0.f;
+        ms[kKinds] = 0.0;
+        if (t.used > 0 && hipEventElapsedTime(&span, t.pool[0].first, t.pool[t.used - 1].second) == hipSuccess)
+            ms[kKinds] = span / (double)n;
         *kinds = kKinds;
     }
     for (size_t i = 0; i < made; ++i) {

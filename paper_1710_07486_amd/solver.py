@@ -217,12 +217,15 @@ class Solver:
         _check(self.L.telbm_step_count(self.h, ctypes.byref(n)), self.h)
         return n.value
 
-    def time_kernels(self, n: int) -> dict:
-        """Mean HIP-event duration (ms) of each kernel kind over n steps."""
+    def time_kernels(self, n: int, span: bool = False):
+        """Mean HIP-event duration (ms) of each kernel kind over n steps; with
+        ``span`` also the mean time per step over the whole timed span (first
+        launch start to last launch end), as (kinds dict, ms per step)."""
         ms = (ctypes.c_double * 8)()
         kinds = ctypes.c_int()
         _check(self.L.telbm_time_kernels(self.h, int(n), ms, ctypes.byref(kinds)), self.h)
-        return {self.L.telbm_kernel_name(self.h, k).decode(): ms[k] for k in range(kinds.value)}
+        per = {self.L.telbm_kernel_name(self.h, k).decode(): ms[k] for k in range(kinds.value)}
+        return (per, ms[kinds.value]) if span else per
 
     def algorithmic_bytes_per_update(self) -> float:
         return self.L.telbm_algorithmic_bytes_per_update(self.h)

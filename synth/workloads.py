@@ -6,9 +6,14 @@ but gives no grid sizes.  These workloads stand in for them.  Shared free
 energy parameters follow the paper's lens caption and text: lambda1 = 0.6,
 kappa1 = 1e-3, lambda_i = 3.125 kappa_i, chi = 5, nu = 0.167, M = 0.5.
 
-A workload names its liquid/gas density ratio; the temperature and the
-coexisting densities that realise it are computed by whoever consumes the
-workload (the oracle in tests, the library in the benchmark).
+A workload names its liquid/gas density ratio.  By default that is the
+Maxwell ratio of the equation of state, and the temperature and coexisting
+densities that realise it are computed by whoever consumes the workload (the
+oracle in tests, the library in the benchmark).  A workload built with
+``lattice_ratio=True`` instead carries a fixed temperature ``T`` at which the
+lattice model's relaxed flat interface holds the named ratio; those
+temperatures were computed once by the oracle (``python -m
+oracle.lattice_ratio``) and are stored below as inputs.
 """
 from __future__ import annotations
 
@@ -22,13 +27,30 @@ from .rng import uniform
 
 D2Q9, D3Q27 = 0, 1
 
+# Temperatures at which the relaxed flat liquid-1 slab in gas (256 nodes)
+# holds the named lattice density ratio, computed by oracle.lattice_ratio.
+# Keys: ("drops_2d", seed, ratio) with that seed's liquid coefficients, and
+# ("collision_3d", kappa2 = kappa3, ratio).  Maxwell ratios at these
+# temperatures: 12,864 and 6,715.
+LATTICE_RATIO_T = {
+    ("drops_2d", 0, 1000.0): 0.027515478,
+    ("collision_3d", 0.2, 800.0): 0.028859406,
+}
+
+
+def lattice_ratio_temperature(*key) -> float:
+    try:
+        return LATTICE_RATIO_T[tuple(key)]
+    except KeyError:
+        raise KeyError(f"no lattice-ratio temperature stored for {key}")
+
 
 @dataclasses.dataclass
 class Workload:
     name: str
     lattice: int
     shape: tuple            # (nz, ny, nx)
-    ratio: float            # Maxwell liquid/gas density ratio
+    ratio: float            # liquid/gas density ratio (Maxwell's, unless T is set)
     kappa2: float
     kappa3: float
     drops: list
@@ -43,6 +65,7 @@ class Workload:
     noise: float = 1e-4
     width: float = 3.0
     walls: int = 0          # 1: solid walls at y = -1/2 and y = ny - 1/2
+    T: float = 0.0          # temperature; 0: the one whose Maxwell ratio is `ratio`
 
     @property
     def lambda2(self) -> float:
@@ -75,10 +98,14 @@ def lens(nx: int = 128, ny: int = 128, radius: float = 20.0, ratio: float = 10.0
                     kappa, kappa, drops, steps, seed)
 
 
-def drops_2d(n: int = 1024, ratio: float = 1000.0, seed: int = 0, steps: int = 20000) -> Workload:
+def drops_2d(n: int = 1024, ratio: float = 1000.0, seed: int = 0, steps: int = 20000,
+             lattice_ratio: bool = False) -> Workload:
     """Two touching drops of seeded radii in [n*80/1024, n*160/1024] and a seeded
-    axis angle; liquid gradient coefficients drawn log-uniformly, so that the
-    tension ratios span partial wetting and encapsulation."""
+    axis angle; liquid gradient coefficients drawn log-uniformly around 0.37,
+    so that the tension ratios span partial wetting and encapsulation.  With
+    ``lattice_ratio`` the temperature is the one at which a flat slab of
+    liquid 1 in gas with this seed's coefficients holds ``ratio`` on the
+    lattice (stored for seed 0 and ratio 1000)."""
     r = uniform(seed * 7919 + 17, 5)
     s = n / 1024.0
     R1 = s * (80.0 + 80.0 * r[0])
@@ -92,14 +119,18 @@ def drops_2d(n: int = 1024, ratio: float = 1000.0, seed: int = 0, steps: int = 2
         {"center": (c - d * math.cos(ang) * R1 / d, c - d * math.sin(ang) * R1 / d), "radius": R1, "liquid": 1},
         {"center": (c + d * math.cos(ang) * R2 / d, c + d * math.sin(ang) * R2 / d), "radius": R2, "liquid": 2},
     ]
-    return Workload(f"drops_d2q9_{n}x{n}_ratio{ratio:g}_seed{seed}", D2Q9, (1, n, n), ratio,
-                    k2, k3, drops, steps, seed)
+    T = lattice_ratio_temperature("drops_2d", seed, ratio) if lattice_ratio else 0.0
+    tag = "latticeratio" if lattice_ratio else "ratio"
+    return Workload(f"drops_d2q9_{n}x{n}_{tag}{ratio:g}_seed{seed}", D2Q9, (1, n, n), ratio,
+                    k2, k3, drops, steps, seed, T=T)
 
 
 def collision_3d(n: int = 256, radius: float = 32.0, ratio: float = 1000.0, v_rel: float = 0.04,
                  impact: float = 0.0, kappa2: float = 0.37, kappa3: float = 0.37,
-                 steps: int = 10000, seed: int = 0) -> Workload:
-    """Binary collision of a liquid-1 and a liquid-2 drop in a periodic cube."""
+                 steps: int = 10000, seed: int = 0, lattice_ratio: bool = False) -> Workload:
+    """Binary collision of a liquid-1 and a liquid-2 drop in a periodic cube.
+    With ``lattice_ratio`` (kappa2 = kappa3 required) the temperature is the
+    one at which a flat slab holds ``ratio`` on the lattice."""
     shape = (n, n, n)
     off = radius + 4.0
     b = impact * 2.0 * radius
@@ -110,8 +141,13 @@ def collision_3d(n: int = 256, radius: float = 32.0, ratio: float = 1000.0, v_re
         {"center": (c + off, c + b / 2.0, c), "radius": radius, "liquid": 2,
          "velocity": (-0.5 * v_rel, 0.0, 0.0)},
     ]
-    return Workload(f"collision_d3q27_{n}^3_ratio{ratio:g}_B{impact:g}", D3Q27, shape, ratio,
-                    kappa2, kappa3, drops, steps, seed)
+    T = 0.0
+    if lattice_ratio:
+        assert kappa2 == kappa3, "lattice-ratio temperatures are stored for equal liquid coefficients"
+        T = lattice_ratio_temperature("collision_3d", kappa2, ratio)
+    tag = "latticeratio" if lattice_ratio else "ratio"
+    return Workload(f"collision_d3q27_{n}^3_{tag}{ratio:g}_B{impact:g}", D3Q27, shape, ratio,
+                    kappa2, kappa3, drops, steps, seed, T=T)
 
 
 def batch_instances(count: int = 64, seed: int = 3, lo: int = 256, hi: int = 1024,

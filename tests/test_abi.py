@@ -118,6 +118,26 @@ def test_parameter_validation_without_device(orc):
     assert T.required_bytes(p3) >= 2 * 54 * 512 * 8
 
 
+def test_lattices_beyond_32_bit_offsets_are_rejected(orc):
+    """The kernels address each FP64 slice of N values with 32-bit byte
+    offsets: N = 2^29 is refused (single solver and batch member), N just
+    below is accepted, in 2D and 3D."""
+    import ctypes
+    import paper_1710_07486_amd as T
+    from paper_1710_07486_amd import _lib
+    T0 = orc.temperature_for_ratio(10.0)[0]
+    for kw in (dict(nx=1 << 15, ny=1 << 14), dict(lattice=T.D3Q27, nx=1 << 10, ny=1 << 10, nz=1 << 9)):
+        p = T.Params(T=T0, **kw)
+        with pytest.raises(T.TelbmError) as e:
+            T.required_bytes(p)
+        assert e.value.code == _lib.ERR_INVAL
+        arr = (_lib.TelbmParams * 1)(p.c_struct())
+        n = ctypes.c_size_t()
+        assert _lib.load().telbm_batch_required_bytes(arr, 1, ctypes.byref(n)) == _lib.ERR_INVAL
+    ok = T.Params(T=T0, nx=(1 << 15) - 1, ny=1 << 14)
+    assert T.required_bytes(ok) > 0
+
+
 def test_null_arguments_are_rejected(lib):
     from paper_1710_07486_amd import _lib
     assert lib.telbm_step(None, 1) == _lib.ERR_INVAL

@@ -27,7 +27,7 @@ def rel(a, b, floor=1e-300):
 def make(orc, wl, precision=0):
     """Oracle params and library params for one workload, plus its fields."""
     import paper_1710_07486_amd as T
-    po = orc.coexisting_params(wl.ratio, **wl.physics())
+    po = orc.workload_params(wl)
     rho, phi, u = W.fields(wl, po.rho_g, po.rho_l)
     nz, ny, nx = wl.shape
     pl = T.Params(lattice=wl.lattice, precision=precision, nx=nx, ny=ny, nz=nz, T=po.T, rho_g=po.rho_g,
@@ -116,7 +116,68 @@ def test_fp32_mixed_error_vs_oracle(orc, lattice):
     e["rho_gas_pointwise"] = float(np.abs(fg["rho"][gas] / fo["rho"][gas] - 1).max())
     print("fp32-mixed errors", e, flush=True)
     assert e["rho"] <= 1e-5 and e["phi"] <= 1e-5
-    assert e["u"] <= 1e-3
+    assert e["u"] <= 1e-4
+
+
+def wide_box(shape, k2=0.1, k3=0.3, v_rel=0.04, ratio=1000.0, walls=0):
+    """Two drops approaching along x in a box that spans several tiles of the
+    3D kernels in x (64 wide) and y (4 high), with a ragged last tile: the
+    drops cross tile edges, so cross-tile moment sums (inboxes) and the
+    staged halos of neighbouring tiles all carry interface values."""
+    nz, ny, nx = shape
+    R = min(5.0, 0.45 * min(ny, nz) + 1.5)
+    wl = W.collision_3d(n=16, radius=R, ratio=ratio, v_rel=v_rel, kappa2=k2, kappa3=k3)
+    wl.shape = tuple(shape)
+    for d, cx in zip(wl.drops, (nx / 2 - R - 2.5, nx / 2 + R + 2.5)):
+        d["center"] = (cx, ny / 2 + 0.3, nz / 2 - 0.2)
+    if walls:
+        wl.walls = 1
+    return wl
+
+
+WIDE = {"fp64": (0, 0, 0), "fp32": (1, 0, 0), "fp64_d3q7": (0, 1, 0), "fp64_walls": (0, 0, 1)}
+
+
+@pytest.mark.parametrize("shape", [(9, 13, 200), (7, 10, 130)])
+@pytest.mark.parametrize("case", list(WIDE))
+def test_d3q27_multi_tile(orc, shape, case):
+    """D3Q27 boxes three tiles wide in x and y (200 x 13 x 9, and 130 x 10 x 7
+    with two-node ragged last tiles), 200 steps, element by element against
+    the oracle: FP64 (full and reduced phase-field lattice, and with wetting
+    walls) within 1e-10, FP32-mixed within 1e-5 (rho, phi) and 1e-4 of the
+    largest velocity (u)."""
+    import math
+    import paper_1710_07486_amd as T
+    precision, glat, walls = WIDE[case]
+    if precision == 1 and (glat or walls):
+        pytest.skip("not available in the FP32-mixed 3D form")
+    wl = wide_box(shape, walls=walls)
+    say("D3Q27 multi-tile", case, shape)
+    po, pl, rho, phi, u = make(orc, wl, precision)
+    po.glattice = pl.glattice = glat
+    if walls:
+        pl.walls = 1
+        ang = dict(theta_rho_lo=math.radians(60.0), theta_phi_lo=math.radians(75.0),
+                   theta_rho_hi=math.radians(115.0), theta_phi_hi=math.radians(100.0))
+        for key, v in ang.items():
+            setattr(po, key, v)
+            setattr(pl, key, v)
+    steps = 200
+    st = orc.State(po, rho, phi, u)
+    st.run(steps)
+    fo = st.fields()
+    with T.Solver(pl) as s:
+        s.init_fields(rho, phi, u)
+        s.step(steps)
+        fg = s.fields()
+    assert np.isfinite(fo["rho"]).all()
+    if precision == 0:
+        check_fp64(fo, fg)
+    else:
+        e = {"rho": rel(fg["rho"], fo["rho"]), "phi": rel(fg["phi"], fo["phi"]),
+             "u": rel(fg["u"], fo["u"], 1e-14)}
+        print("fp32-mixed multi-tile errors", e, flush=True)
+        assert e["rho"] <= 1e-5 and e["phi"] <= 1e-5 and e["u"] <= 1e-4
 
 
 def test_init_rejects_bad_fields(orc):
@@ -254,28 +315,67 @@ def _window(arr, center, r):
     return arr[..., idx[0][:, None, None], idx[1][None, :, None], idx[2][None, None, :]]
 
 
-FULL_CASES = ["d3q27_256_fp64", "d3q27_256_mixed", "d2q9_1024_fp64", "d2q9_1024_fp64_reduced",
+FULL_CASES = ["d3q27_256_fp64", "d3q27_256_mixed", "d2q9_1024_fp64", "d2q9_1024_mixed", "d2q9_1024_fp64_reduced",
               "d3q27_256_fp64_reduced", "d2q9_1024_fp64_walls"]
+
+
+def tile_edge_samples(wl, rng, count):
+    """`count` nodes on tile edges of the step kernels (x = 0 or 63 mod 64;
+    y = 0 or the last row of a tile: 4 rows in 3D, 8 in 2D), three in four
+    on a drop interface (within 3 nodes of its starting radius, or with walls
+    in the wall rows within half a tile of a contact line; in 3D the z
+    of such a node is taken on the sphere), the rest anywhere.  In 3D, a
+    node on the interface is moved to z = 0 or 15 mod 16 (the potential
+    pass's column edges) when one lies within 2 planes."""
+    import math
+    nz, ny, nx = wl.shape
+    ty = 4 if nz > 1 else 8
+    xe = [x for x in range(nx) if x % 64 in (0, 63) or x == nx - 1]
+    ye = [y for y in range(ny) if y % ty in (0, ty - 1) or y == ny - 1]
+    near = []
+    for d in wl.drops:
+        c, R = d["center"], d["radius"]
+        for X in xe:
+            for Y in ye:
+                if wl.walls and 3 <= Y <= ny - 4:
+                    continue
+                rxy = math.hypot(X - c[0], Y - c[1])
+                if nz == 1:
+                    # wall rows: the contact line and its neighbourhood
+                    if abs(rxy - R) < (34 if wl.walls else 3):
+                        near.append((0, Y, X))
+                elif rxy < R:
+                    for sgn in (-1, 1):
+                        z = int(round(c[2] + sgn * math.sqrt(R * R - rxy * rxy))) % nz
+                        ze = [zz for zz in range(z - 2, z + 3) if zz % 16 in (0, 15)]
+                        near.append(((ze[0] if ze else z) % nz, Y, X))
+    near = sorted(set(near))
+    pick = [near[i] for i in rng.choice(len(near), size=min(len(near), 3 * count // 4), replace=False)]
+    out = set(pick)
+    while len(out) < count:
+        out.add((int(rng.integers(nz)), int(rng.choice(ye)), int(rng.choice(xe))))
+    return sorted(out)
 
 
 @pytest.mark.parametrize("case", FULL_CASES)
 def test_full_size_sampled(orc, case):
-    """Full-size lattices in the benchmark's launch configuration, checked on
-    sampled nodes: after k steps a node depends on the initial fields within
-    radius 3k + 3, so the oracle on a periodic window of half-width 3k + 4
-    reproduces that node exactly.  With walls the window is cut at the walls
-    (and closed by walls beyond the dependency radius elsewhere)."""
+    """The benchmark's full-size lattices in its launch configuration, checked
+    on 64 sampled nodes on tile edges after 6 steps: after k steps a node
+    depends on the initial fields within radius 3k + 3, so the oracle on a
+    periodic window of half-width 3k + 4 reproduces that node exactly.  With
+    walls the window is cut at the walls (and closed by walls beyond the
+    dependency radius elsewhere)."""
     import math
     import paper_1710_07486_amd as T
-    k = 2
+    k = 6
     walls = case.endswith("walls")
     if case.startswith("d3q27"):
-        wl = W.collision_3d(256, radius=32, ratio=1000.0, v_rel=0.04, kappa2=0.1, kappa3=0.1)
+        wl = W.collision_3d(256, radius=32, ratio=800.0, v_rel=0.04, kappa2=0.2, kappa3=0.2, lattice_ratio=True)
     elif walls:
         wl = W.wall_drops(1024, 1024, radius=200.0, ratio=1000.0)
+        wl.T = W.lattice_ratio_temperature("drops_2d", 0, 1000.0)
     else:
-        wl = W.drops_2d(1024, ratio=1000.0, seed=0)
-        wl.kappa2 = wl.kappa3 = 0.1
+        wl = W.drops_2d(1024, ratio=1000.0, seed=0, lattice_ratio=True)
     precision = 1 if case.endswith("mixed") else 0
     say("full size", case)
     po, pl, rho, phi, u = make(orc, wl, precision)
@@ -298,23 +398,11 @@ def test_full_size_sampled(orc, case):
     # the wetting ghost reads the wall row's neighbours along the wall: one
     # more node of reach per step there
     r = 3 * k + 4 + (k if walls else 0)
-    # samples in the drops, on interfaces and in the gas
-    pts = [tuple(int(c) for c in (rng.integers(nz), rng.integers(ny), rng.integers(nx))) for _ in range(6)]
-    for d in wl.drops:
-        c = d["center"]
-        cz = int(c[2]) if nz > 1 else 0
-        if walls:
-            # the cap's contact line and its edge one node off each wall
-            cy = 0 if c[1] < ny / 2 else ny - 1
-            half = math.sqrt(max(d["radius"] ** 2 - (cy - c[1]) ** 2, 0.0))
-            pts += [(0, cy, int(c[0] + half)), (0, cy, int(c[0])), (0, abs(cy - 1), int(c[0] - half))]
-            continue
-        pts.append((cz, int(c[1]), int(c[0])))
-        pts.append((cz, int(c[1]), int(c[0] + d["radius"])))
+    pts = tile_edge_samples(wl, rng, 64)
     # absolute tolerances: FP64 1e-10 of the field scale; FP32 storage 1e-5 of it
     scale = {"rho": po.rho_l, "phi": po.chi, "ux": 0.05, "uy": 0.05}
     tol = FP64_TOL if precision == 0 else 1e-5
-    worst = {k: 0.0 for k in scale}
+    worst = {k_: 0.0 for k_ in scale}
     for (z, y, x) in pts:
         wz = 1 if nz == 1 else 2 * r + 1
         ylo, yhi, cy = y - r, y + r, r
@@ -331,22 +419,22 @@ def test_full_size_sampled(orc, case):
         cz = 0 if nz == 1 else r
         for name, ref in (("rho", f["rho"]), ("phi", f["phi"]), ("ux", f["u"][0]), ("uy", f["u"][1])):
             worst[name] = max(worst[name], abs(g[name][z, y, x] - ref[cz, cy, r]) / scale[name])
-    print("sampled max error / scale", case, worst, flush=True)
+    print("sampled max error / scale", case, len(pts), "nodes", worst, flush=True)
     for name, v in worst.items():
         assert v <= tol, (case, name, v)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_full_size_3d_collision_stays_finite_and_conserves_mass(orc, precision):
-    """The D3Q27 256^3 ratio-1000 collision started at the model's own
-    coexistence densities (oracle 1D relaxation): 300 steps on the GPU stay
-    finite with bounded velocities, and total mass is conserved (FP64 to 1e-12
-    relative; the FP32 storage form to 1e-7)."""
+    """The benchmark's D3Q27 256^3 collision (lattice density ratio 800)
+    started at the model's own coexistence densities (oracle 1D relaxation):
+    600 steps on the GPU stay finite with bounded velocities, and total mass
+    is conserved (FP64 to 1e-12 relative; the FP32 storage form to 1e-7)."""
     import paper_1710_07486_amd as T
-    wl = W.collision_3d(256, radius=32, ratio=1000.0, v_rel=0.04, kappa2=0.1, kappa3=0.1)
-    po = orc.coexisting_params(wl.ratio, **wl.physics())
+    wl = W.collision_3d(256, radius=32, ratio=800.0, v_rel=0.04, kappa2=0.2, kappa3=0.2, lattice_ratio=True)
+    po = orc.workload_params(wl)
     pd = orc.Params(**{**po.__dict__, "lattice": 1})
-    rg, rl = orc.discrete_coexistence(pd, steps=6000, n=128)
+    rg, rl = orc.discrete_coexistence(pd, steps=20000, n=256)
     say("3D 256^3 discrete start", precision, rg, rl)
     rho, phi, u = W.fields(wl, rg, rl)
     nz, ny, nx = wl.shape
@@ -357,7 +445,7 @@ def test_full_size_3d_collision_stays_finite_and_conserves_mass(orc, precision):
     with T.Solver(pl) as s:
         s.init_fields(rho, phi, u)
         d0 = s.diagnostics()
-        for _ in range(6):
+        for _ in range(12):
             s.step(50)
             d = s.diagnostics()
             assert d["nonfinite"] == 0 and d["max_u"] < 0.3 and d["min_rho"] > 0
