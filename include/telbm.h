@@ -371,6 +371,24 @@ int telbm_surrogate_decode(const float *y, const double *rho_in, const double *p
                            void *workspace, size_t workspace_bytes, void *stream);
 int telbm_surrogate_decode_workspace_bytes(int n, int h, int w, size_t *bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * decode as telbm_surrogate_decode, with its workspace in a static device
+ * array of telbm_surrogate_decode_noalloc_max_bytes() = 16 MiB that the
+ * library holds on each GPU it runs on until the process ends.  Calls no
+ * hipMalloc, hipFree or allocating routine.  Returns TELBM_ERR_NOMEM when the
+ * decode needs more workspace than that (telbm_surrogate_decode_workspace_bytes;
+ * about 2 million pixels), TELBM_ERR_INVAL for invalid arguments as
+ * telbm_surrogate_decode, TELBM_ERR_DEVICE if the array's address cannot be
+ * obtained on the current device.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (on different streams, or from
+ * different threads) race and must be serialised by the caller. */
+int telbm_surrogate_decode_noalloc(const float *y, const double *rho_in, const double *phi_in, const double *ux_in,
+                                   const double *uy_in, int n, int h, int w, double rho_g, double rho_l, double chi,
+                                   double u_scale, double *rho_out, double *phi_out, double *ux_out, double *uy_out,
+                                   void *stream);
+size_t telbm_surrogate_decode_noalloc_max_bytes(void);
+
 /* One Adam step (Kingma and Ba 2015) on n FP32 weights at step t >= 1. */
 int telbm_adam_step(float *w, const float *g, float *m, float *v, int64_t n, float lr, float beta1,
                     float beta2, float eps, int64_t t, void *stream);

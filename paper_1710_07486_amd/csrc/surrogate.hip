@@ -14,6 +14,8 @@
 
 #include <stdint.h>
 
+#include <mutex>
+
 #include "../../include/telbm.h"
 
 namespace telbm {
@@ -486,7 +488,39 @@ static hipError_t wgrad_dispatch(int cin, int cout, const uint16_t* in, const ui
 
 using namespace telbm;
 
+// Workspace of the allocation-free decode (telbm_surrogate_decode_noalloc):
+// a file-scope device array that each GPU holds for the life of the process.
+// Host code never passes its name to a kernel: `scratch` names a host-side
+// stand-in there; the device address comes from hipGetSymbolAddress, once
+// per device, and is kept in g_scratch_ptr.
+constexpr size_t kDecodeScratchBytes = size_t(16) << 20;
+__device__ __align__(256) double scratch[kDecodeScratchBytes / sizeof(double)];
+
 namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device (looked up on the
+// first call per device); nullptr with *rc set on failure.
+void* scratch_ptr(int* rc) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        *rc = TELBM_ERR_DEVICE;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            *rc = TELBM_ERR_DEVICE;
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
 bool conv_shape_ok(int cin, int cout) {
     return (cin == 32 || cin == 64) && (cout == 32 || cout == 64);
 }
@@ -632,6 +666,24 @@ int telbm_surrogate_decode(const float* y, const double* rho_in, const double* p
     k_decode_stats<<<blocks, 256, 0, (hipStream_t)stream>>>(a);
     k_decode_apply<<<blocks, 256, 0, (hipStream_t)stream>>>(a);
     return hipGetLastError() == hipSuccess ? TELBM_OK : TELBM_ERR_DEVICE;
+}
+
+size_t telbm_surrogate_decode_noalloc_max_bytes(void) { return kDecodeScratchBytes; }
+
+int telbm_surrogate_decode_noalloc(const float* y, const double* rho_in, const double* phi_in, const double* ux_in,
+                                   const double* uy_in, int n, int h, int w, double rho_g, double rho_l, double chi,
+                                   double u_scale, double* rho_out, double* phi_out, double* ux_out, double* uy_out,
+                                   void* stream) {
+    size_t need = 0;
+    if (telbm_surrogate_decode_workspace_bytes(n, h, w, &need) != TELBM_OK) return TELBM_ERR_INVAL;
+    if (need > kDecodeScratchBytes) return TELBM_ERR_NOMEM;
+    int rc = TELBM_OK;
+    void* ws = scratch_ptr(&rc);
+    if (!ws) return rc;
+    // both decode passes overwrite every workspace entry they read, so the
+    // previous call's contents need no clearing
+    return telbm_surrogate_decode(y, rho_in, phi_in, ux_in, uy_in, n, h, w, rho_g, rho_l, chi, u_scale, rho_out,
+                                  phi_out, ux_out, uy_out, ws, kDecodeScratchBytes, stream);
 }
 
 int telbm_adam_step(float* w, const float* g, float* m, float* v, int64_t n, float lr, float beta1, float beta2,

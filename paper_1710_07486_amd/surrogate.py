@@ -39,6 +39,9 @@ PROTOTYPES = {
     "telbm_surrogate_decode": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _vp, _vp, _vp, _vp, _vp,
                                     _sz, _vp]),
     "telbm_surrogate_decode_workspace_bytes": (_i, [_i, _i, _i, ctypes.POINTER(_sz)]),
+    "telbm_surrogate_decode_noalloc": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _vp, _vp, _vp, _vp,
+                                            _vp]),
+    "telbm_surrogate_decode_noalloc_max_bytes": (_sz, []),
 }
 
 CH = 32          # stored channels at the network's ends
