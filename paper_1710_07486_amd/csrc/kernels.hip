@@ -804,7 +804,9 @@ __device__ __forceinline__ void next3_complete(const GridDims& g, const double* 
         inbox_complete_fast<BY>(g, inbox + ((int64_t)z * 3 + k) * tiles * INBOX3 * 2, gx, gy, r, p);
 }
 
-template <bool WALL, bool RG>
+// DIAG: the instance that also reduces the health diagnostics (launched on the
+// steps that take them; the other keeps none of their registers).
+template <bool WALL, bool RG, bool DIAG>
 __global__ __launch_bounds__(BX* BY) void k_collide_next3(GridDims g, PhysConst k, const double* __restrict__ src,
                                                           double* __restrict__ dst, const double* __restrict__ rho,
                                                           const double* __restrict__ phi,
@@ -830,9 +832,9 @@ __global__ __launch_bounds__(BX* BY) void k_collide_next3(GridDims g, PhysConst 
         const int wy = (WALL && g.walls) ? (y0 + ly == 0 ? -1 : (y0 + ly == g.ny - 1 ? 1 : 0)) : 0;
         Sink sink{nsum, nside, (int)threadIdx.x, (int)threadIdx.y, W, wy};
         node_collide_sink<kD3Q27, double, GlobalAux, Sink, WALL, RG>(g, k, src, dst, nullptr, aux, x0 + lx, y0 + ly,
-                                                                  bz, diag != 0, dv, active, sink);
+                                                                  bz, DIAG, dv, active, sink);
     }
-    if (diag) diag_block_reduce(dv, partials);
+    if (DIAG) diag_block_reduce(dv, partials);
     __syncthreads();
     const int64_t tiles = (int64_t)bxc * byc;
     const Sink view{nsum, nside, 0, 0, W, 0};
@@ -1094,18 +1096,21 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
         if (L != kD3Q27 || Deviation<T>::on || !a.part3 || !a.inbox3) return hipErrorInvalidValue;
         auto* sp = (const double*)a.src;
         auto* dp = (double*)a.dst;
-        if (w && rg)
-            k_collide_next3<true, true><<<grd, blk, 0, a.stream>>>(a.g, a.k, sp, dp, a.rho, a.phi, a.mux, a.mup,
-                                                                   a.part3, a.inbox3, a.partials, a.diag);
-        else if (w)
-            k_collide_next3<true, false><<<grd, blk, 0, a.stream>>>(a.g, a.k, sp, dp, a.rho, a.phi, a.mux, a.mup,
-                                                                    a.part3, a.inbox3, a.partials, a.diag);
-        else if (rg)
-            k_collide_next3<false, true><<<grd, blk, 0, a.stream>>>(a.g, a.k, sp, dp, a.rho, a.phi, a.mux, a.mup,
-                                                                    a.part3, a.inbox3, a.partials, a.diag);
-        else
-            k_collide_next3<false, false><<<grd, blk, 0, a.stream>>>(a.g, a.k, sp, dp, a.rho, a.phi, a.mux, a.mup,
-                                                                     a.part3, a.inbox3, a.partials, a.diag);
+#define TELBM_NEXT3(WV, RGV, DV)                                                                               \
+    k_collide_next3<WV, RGV, DV><<<grd, blk, 0, a.stream>>>(a.g, a.k, sp, dp, a.rho, a.phi, a.mux, a.mup, a.part3, \
+                                                            a.inbox3, a.partials, a.diag)
+        if (a.diag) {
+            if (w && rg) TELBM_NEXT3(true, true, true);
+            else if (w) TELBM_NEXT3(true, false, true);
+            else if (rg) TELBM_NEXT3(false, true, true);
+            else TELBM_NEXT3(false, false, true);
+        } else {
+            if (w && rg) TELBM_NEXT3(true, true, false);
+            else if (w) TELBM_NEXT3(true, false, false);
+            else if (rg) TELBM_NEXT3(false, true, false);
+            else TELBM_NEXT3(false, false, false);
+        }
+#undef TELBM_NEXT3
         if (a.diag) k_diag_final<<<1, 256, 0, a.stream>>>(a.partials, (int)grd.x, a.diag_out);
     } else if (part == 4) {
         if (L != kD2Q9 || a.g.nz != 1 || !a.inbox_in) return hipErrorInvalidValue;
