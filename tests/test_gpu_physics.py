@@ -121,3 +121,61 @@ def test_liquid_gas_laplace_scaling(orc):
     print(f"liquid-gas: flat offset {offset:.3e}; dp*R {np.round(pr, 5)}; tension {gamma:.5f}", flush=True)
     assert gamma > 0.0
     assert spread < 0.03, spread
+
+
+# Neumann lens (the paper's Fig. 2): Maxwell density ratio 3, lambda_i =
+# kappa_i = 0.1 (liquid-liquid interface 2 nodes wide), the paper's lambda1,
+# kappa1 and chi.  All three angles lie near 120 degrees, well inside the
+# partial-wetting range.
+NEU_RATIO, NEU_K = 3.0, 0.1
+
+
+def _neumann_params(orc, T, nx, ny):
+    po = orc.coexisting_params(NEU_RATIO, lattice=0, nx=4, ny=4, nz=1, kappa2=NEU_K, kappa3=NEU_K, lambda2=NEU_K,
+                               lambda3=NEU_K)
+    return po, T.Params(lattice=0, nx=nx, ny=ny, nz=1, T=po.T, kappa2=NEU_K, kappa3=NEU_K, lambda2=NEU_K,
+                        lambda3=NEU_K, rho_g=po.rho_g, rho_l=po.rho_l)
+
+
+def test_neumann_angles_against_laplace_tensions(orc):
+    """The angles of a relaxed lens of liquid 1 on the flat interface between
+    liquid 2 and gas (geometric: circle fits of the two lens arcs, a line fit
+    of the flat interface, tangents at the arcs' intersections) against the
+    angles of the triangle of the three tensions, each measured on the GPU
+    by Laplace's law (dp = dp0 + gamma / R fitted over drops of radius 30,
+    45, 60 in a 256^2 box): within the paper's 3 degrees (its lens figure)."""
+    import paper_1710_07486_amd as T
+    from tests import neumann as NM
+    po, _ = _neumann_params(orc, T, 4, 4)
+    rg, rl = po.rho_g, po.rho_l
+    gam = {}
+    n = 256
+    yy, xx = np.mgrid[0:n, 0:n]
+    rr = np.sqrt((xx - n / 2) ** 2 + (yy - n / 2) ** 2)
+    for kind in ("12", "1g", "2g"):
+        dps, rads = [], []
+        for R in (30.0, 45.0, 60.0):
+            say("Laplace", kind, "R", R)
+            c = 0.5 * (1.0 - np.tanh((rr - R) / 2.0))
+            if kind == "12":
+                rho, phi = np.full(c.shape, rl), po.chi * (2.0 * c - 1.0)
+            else:
+                rho, phi = rg + (rl - rg) * c, (po.chi if kind == "1g" else -po.chi) * c
+            r, f = _run(T, _neumann_params(orc, T, n, n)[1], rho[None], phi[None], 40000)
+            dps.append(_jump(orc, po, r, f, n // 2))
+            ind = (f / po.chi + 1.0) / 2.0 if kind == "12" else (r - r[0:3, 0:3].mean()) / (r[n // 2, n // 2] - r[0:3, 0:3].mean())
+            rads.append(math.sqrt(ind.sum() / math.pi))
+        A = np.stack([1.0 / np.array(rads), np.ones(3)], axis=1)
+        gam[kind] = float(np.linalg.lstsq(A, np.array(dps), rcond=None)[0][0])
+    pred = NM.neumann_angles(gam["12"], gam["1g"], gam["2g"])
+    nx, ny, R = 384, 320, 64.0
+    band = (ny // 4, ny // 4 + ny * 3 // 8)
+    rho, phi = NM.lens_fields(nx, ny, R, band, rg, rl, po.chi)
+    say("Neumann lens", nx, ny, R)
+    r, f = _run(T, _neumann_params(orc, T, nx, ny)[1], rho, phi, 60000)
+    ang, fits = NM.measure_angles(r, f, rg, rl, po.chi, band[1] - 0.5)
+    print(f"Neumann: tensions {gam}; triangle {pred}; lens {ang}; fits {fits}", flush=True)
+    for a in ang:
+        for ph in ("1", "2", "g"):
+            assert abs(a[ph] - pred[ph]) < 3.0, (ph, a[ph], pred[ph])
+        assert abs(a["1"] + a["2"] + a["g"] - 360.0) < 1e-6

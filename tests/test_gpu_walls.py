@@ -181,3 +181,31 @@ def test_walls_with_peng_robinson(orc):
         fg = s.fields()
     for k in ("rho", "phi"):
         assert rel(fg[k], fo[k]) <= 1e-10, k
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_liquid_liquid_contact_angle_reaches_the_wall_angle(orc, prec):
+    """A liquid-1 cap in liquid 2 on the bottom wall (phase-field interface
+    2.8 nodes wide, lambda = kappa / 2; 128 x 64 box, cap radius 20, started
+    at 90 degrees): after 80,000 steps it meets the wall within 3 degrees of
+    the prescribed 60 and 120 degrees, in FP64 and FP32-mixed storage."""
+    import dataclasses
+    import paper_1710_07486_amd as T
+    from tests import test_oracle_walls as TW
+    out = {}
+    for th in (60.0, 120.0):
+        p, rho, phi = TW.wall_drop(orc, th, nx=128, ny=64, radius=20.0, liquid_liquid=True, phi_only=True)
+        p = dataclasses.replace(p, lambda2=0.5 * p.kappa2, lambda3=0.5 * p.kappa3)
+        pl = T.Params(lattice=0, precision=prec, nx=p.nx, ny=p.ny, nz=1, T=p.T, rho_g=p.rho_g, rho_l=p.rho_l,
+                      lambda1=p.lambda1, lambda2=p.lambda2, lambda3=p.lambda3, kappa1=p.kappa1, kappa2=p.kappa2,
+                      kappa3=p.kappa3, chi=p.chi, nu=p.nu, mobility=p.mobility, tau_phi=p.tau_phi, walls=1,
+                      theta_rho_lo=p.theta_rho_lo, theta_rho_hi=p.theta_rho_hi, theta_phi_lo=p.theta_phi_lo,
+                      theta_phi_hi=p.theta_phi_hi)
+        say("liquid-liquid cap", th, "precision", prec)
+        with T.Solver(pl) as s:
+            s.init_fields(rho, phi)
+            s.step(80000)
+            out[th] = TW.contact_angle(s.read("phi")[0], -p.chi, p.chi)
+    print("liquid-liquid contact angles", out, flush=True)
+    for th, a in out.items():
+        assert abs(a - th) < 3.0, (th, a)

@@ -128,30 +128,37 @@ def test_top_wall_mirrors_bottom_wall(orc):
     assert np.abs(a["u"][1] + b["u"][1][:, ::-1]).max() < 1e-13
 
 
-def test_liquid_liquid_contact_angle_moves_towards_the_wall_angle(orc):
-    """A liquid-1 half disc in liquid 2 (rho uniform, the phase field carries
-    the interface): from 90 degrees its angle moves towards the prescribed
-    60 or 120 degrees (contact-line motion by Cahn-Hilliard diffusion)."""
+def test_liquid_liquid_contact_angle_reaches_the_wall_angle(orc):
+    """A liquid-1 cap in liquid 2 on the wall (rho uniform, the phase field
+    carries the interface, lambda = kappa / 2 so that the interface is
+    2.8 nodes wide): started at 90 degrees, its contact line moves by
+    Cahn-Hilliard diffusion until the cap meets the wall at the prescribed
+    angle, within 3 degrees for 60 and 120 degrees (measured 61.4 and 122.0
+    after 30,000 steps on this 80 x 40 box with a cap of radius 14; the same
+    cap at 90 degrees stays at 90)."""
     ang = {}
-    for th in (60.0, 120.0):
-        p, rho, phi = wall_drop(orc, th, liquid_liquid=True, phi_only=True)
+    for th in (60.0, 90.0, 120.0):
+        p, rho, phi = wall_drop(orc, th, nx=80, ny=40, radius=14.0, liquid_liquid=True, phi_only=True)
+        p = dataclasses.replace(p, lambda2=0.5 * p.kappa2, lambda3=0.5 * p.kappa3)
         st = orc.State(p, rho, phi)
-        first = None
-        for k in range(2):
-            st.run(2000)
-            a = contact_angle(st.fields()["phi"][0], -p.chi, p.chi)
-            first = a if first is None else first
-        ang[th] = (first, a)
-    assert ang[60.0][1] < ang[60.0][0] < 88.0, ang
-    assert ang[120.0][1] > ang[120.0][0] > 92.0, ang
+        st.run(30000 if th != 90.0 else 2000)
+        ang[th] = contact_angle(st.fields()["phi"][0], -p.chi, p.chi)
+    print("liquid-liquid contact angles", ang)
+    assert abs(ang[90.0] - 90.0) < 1.0, ang
+    assert abs(ang[60.0] - 60.0) < 3.0, ang
+    assert abs(ang[120.0] - 120.0) < 3.0, ang
 
 
 def test_liquid_gas_contact_angle_follows_the_wall_angle(orc):
     """A liquid-1 drop in gas: the relaxed angle lies on the prescribed side
     of 90 degrees, symmetric about 90 for 60 and 120 degrees, and nearer the
     prescribed angle when the interfaces are wider (kappa_1 = 0.03 against
-    1e-3: the geometric condition acts through one ghost row, which a
-    one-node liquid-gas interface barely bends)."""
+    1e-3).  The geometric condition acts on the density through one ghost
+    row, weighted by the small density gradient coefficient against the
+    stiff equation of state, and does not reach the prescribed angle for a
+    liquid-gas contact line (measured 85 / 95 degrees for 60 / 120 at the
+    paper's kappa_1, steady from 3,000 to 100,000 steps and for caps of
+    radius 16 and 48; 79 / 101 at a Maxwell ratio of 3)."""
     ang = {}
     for k1 in (1e-3, 3e-2):
         for th in (60.0, 90.0, 120.0):
