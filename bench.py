@@ -39,10 +39,15 @@ METRIC = "ternary ELBM MLUPS & % HBM roofline; FP32-mixed vs FP64 at stated erro
 
 # HBM bytes per launch of the dominant kernel of each step, from two rocprofv3
 # counter passes (FETCH_SIZE, then WRITE_SIZE, each scaled by what the same
-# counter reads for a 1 GiB device copy in the same run), valid only for the
-# kernel sources whose hash is recorded with them.  Empty until measured on
-# the current sources.
-TRAFFIC = {}
+# counter reads for a 1 GiB device copy in the same run: x2.0 and x1.0),
+# valid only for the kernel sources whose hash is recorded with them.  D3Q27
+# 256^3 (profiles/collide_d3q27_256_latticeratio800_kernel_stats_and_traffic.md):
+# the FP64 collision of a step without diagnostics and the FP32 pair-split
+# collision.
+TRAFFIC = {
+    "d3q27_fp64_collide": {"bytes_per_launch": 17112599717, "sources_sha256_16": "aa7168eeb5c56cc1"},
+    "d3q27_fp32_collide": {"bytes_per_launch": 9748663362, "sources_sha256_16": "aa7168eeb5c56cc1"},
+}
 
 
 def kernel_sources_hash():
