@@ -108,8 +108,7 @@ extern "C" {
  *                      angle measured in the phase where psi is large; for the
  *                      chemical potentials the ghost repeats the wall row.
  *                      theta_* in (0, pi); pi/2 is neutral.  Needs ny >= 2 and
- *                      is not available for D3Q27 in the FP32-mixed form nor in
- *                      the batched form (TELBM_ERR_INVAL).
+ *                      is not available in the batched form (TELBM_ERR_INVAL).
  *  glattice            lattice of the phase-field populations g, which the
  *                      paper leaves open: 0 the lattice of f; 1 its rest and
  *                      axis directions (D2Q5 / D3Q7) with axis weights 1/6 and
@@ -117,7 +116,9 @@ extern "C" {
  *                      g_i = (1/6)(3 Gamma mu_phi + 3 phi c_i.u), g_0 = phi - sum,
  *                      which keeps the moments phi, phi u and Gamma mu_phi I of
  *                      Eq. (7) and moves 2 (Q + 5 or 7) instead of 4 Q values
- *                      per node and step.  Same availability as walls.
+ *                      per node and step.  Not available for D3Q27 in the
+ *                      FP32-mixed form nor in the batched form
+ *                      (TELBM_ERR_INVAL).
  * Validation: 0 < T < T_c, rho_l > rho_g > 0, nu > 0, tau_phi > 1/2, chi != 0,
  * sizes >= 1 (nz == 1 for D2Q9), nx*ny*nz < 2^29 (the kernels address each
  * FP64 slice of N values with 32-bit byte offsets).                        */

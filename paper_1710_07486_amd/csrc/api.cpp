@@ -142,10 +142,6 @@ int validate(const telbm_params* p, std::string* why) {
     }
     if (p->walls) {
         if (p->ny < 2) { *why = "walls need ny >= 2"; return TELBM_ERR_INVAL; }
-        if (p->lattice == TELBM_D3Q27 && p->precision == TELBM_FP32_MIXED) {
-            *why = "walls are not available for D3Q27 in the FP32-mixed form";
-            return TELBM_ERR_INVAL;
-        }
         for (double t : {p->theta_rho_lo, p->theta_rho_hi, p->theta_phi_lo, p->theta_phi_hi})
             if (!(t > 0.0 && t < M_PI)) { *why = "contact angles must lie in (0, pi)"; return TELBM_ERR_INVAL; }
     }

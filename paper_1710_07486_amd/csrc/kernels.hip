@@ -262,7 +262,7 @@ __global__ __launch_bounds__(BX* BY) void k_chempot_col(GridDims g, PhysConst k,
     }
 }
 
-template <int L, typename T, bool RG>
+template <int L, typename T, bool RG, bool W = false>
 __global__ __launch_bounds__(BX* BY) void k_collide(GridDims g, PhysConst k, const T* __restrict__ src,
                                                     T* __restrict__ dst, const double* __restrict__ rho_ref,
                                                     const double* __restrict__ rho,
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(BX* BY) void k_collide(GridDims g, PhysConst k, con
     const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + BY - 1) / BY;
     const int bx = b % bxc, rest = b / bxc, by = rest % byc, bz = rest / byc;
     double dv[kDiag] = {0, 0, 0, 0, 0, 0, INFINITY, INFINITY, -INFINITY, 0};
-    tile_collide<L, T, BX * BY, RG>(g, k, src, dst, rho_ref, rho, phi, mux, mup, bx * BX, by * BY, bz, BX, BY,
+    tile_collide<L, T, BX * BY, RG, W>(g, k, src, dst, rho_ref, rho, phi, mux, mup, bx * BX, by * BY, bz, BX, BY,
                                      threadIdx.y * BX + threadIdx.x, diag != 0, dv);
     if (diag) diag_block_reduce(dv, partials);
 }
@@ -1063,12 +1063,17 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
     } else if (part == 2) {
         // the pair split (D3Q27 FP32) runs the full phase-field lattice only
         if (rg && L == kD3Q27 && Deviation<T>::on) return hipErrorInvalidValue;
-        if (rg)
-            k_collide<L, T, true><<<grd, blk, 0, a.stream>>>(a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref,
-                                                             a.rho, a.phi, a.mux, a.mup, a.partials, a.diag);
-        else
-            k_collide<L, T, false><<<grd, blk, 0, a.stream>>>(a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref,
-                                                              a.rho, a.phi, a.mux, a.mup, a.partials, a.diag);
+#define TELBM_COLLIDE(RGV, WV)                                                                                  \
+    k_collide<L, T, RGV, WV><<<grd, blk, 0, a.stream>>>(a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref, a.rho,  \
+                                                        a.phi, a.mux, a.mup, a.partials, a.diag)
+        if (rg) TELBM_COLLIDE(true, false);
+        else if constexpr (UsePairs<L, T>::value) {
+            // the pair split has an instance with the wall logic (the one-node
+            // collision checks walls at run time)
+            if (w) TELBM_COLLIDE(false, true);
+            else TELBM_COLLIDE(false, false);
+        } else TELBM_COLLIDE(false, false);
+#undef TELBM_COLLIDE
         if (a.diag) k_diag_final<<<1, 256, 0, a.stream>>>(a.partials, (int)grd.x, a.diag_out);
     } else if (part == 3) {
         if (L != kD2Q9 || a.g.nz != 1 || !a.rho_next || !a.phi_next || !a.inbox_out) return hipErrorInvalidValue;

@@ -411,7 +411,10 @@ __device__ __forceinline__ void node_collide(const GridDims& g, const PhysConst&
 __device__ __forceinline__ double xhalf(double v) { return __shfl_xor(v, 32); }
 __device__ __forceinline__ float xhalf(float v) { return __shfl_xor(v, 32); }
 
-template <int L, typename T>
+// W: the lattice may have walls (halfway bounce-back as in node_collide_sink:
+// a pull whose source lies beyond a wall reads the node's own slot of the
+// opposite direction; the potentials beyond a wall repeat the wall row).
+template <int L, typename T, bool W = false>
 __device__ __forceinline__ void node_collide_pair(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
                                                   T* __restrict__ dst, const double* __restrict__ rho_ref,
                                                   const double* __restrict__ rho, const double* __restrict__ phi,
@@ -423,7 +426,7 @@ __device__ __forceinline__ void node_collide_pair(const GridDims& g, const PhysC
     constexpr int NP = (Q - 1) / 2;
     constexpr int D = Lt::D;
     const bool B = side != 0;
-    Nbr32 nb = make_nbr32(x, y, z, g.nx, g.ny, g.nz);
+    Nbr32 nb = W ? make_nbr32_w(g, x, y, z) : make_nbr32(x, y, z, g.nx, g.ny, g.nz);
     if (B) {  // this side's frame is mirrored: +c here is -c on the lattice
         int32_t t;
         t = nb.ox[0]; nb.ox[0] = nb.ox[2]; nb.ox[2] = t;
@@ -471,8 +474,12 @@ __device__ __forceinline__ void node_collide_pair(const GridDims& g, const PhysC
     for (int q = 1; q <= NP; ++q) {
         const int i = 2 * q - 1;
         const uint32_t m = nbr32<L>(nb, n, i, -1);
-        R v = ld_pop<L>(src + (size_t)i * g.N, soff + m);
-        if (Deviation<T>::on) v += R(Lt::w[i] * (ld(rho_ref, m) - r));
+        // this side's lattice direction is c_i (A) or -c_i (B); bounced, it
+        // reads the node's own slot of the other one
+        const bool bb = W && bounce(g, y, B ? -Lt::c[i][1] : Lt::c[i][1]);
+        R v = bb ? ld_pop<L>(src + (size_t)i * g.N, (B ? 0u : (uint32_t)g.N) + n)
+                 : ld_pop<L>(src + (size_t)i * g.N, soff + m);
+        if (Deviation<T>::on) v += R(Lt::w[i] * (ld(rho_ref, bb ? n : m) - r));
         f[q - 1] = v;
         const int cx = Lt::c[i][0], cy = Lt::c[i][1], cz = Lt::c[i][2];
         if (cx) jx += cx > 0 ? v : -v;
@@ -585,7 +592,9 @@ __device__ __forceinline__ void node_collide_pair(const GridDims& g, const PhysC
 #pragma unroll
     for (int q = 1; q <= NP; ++q) {
         const int i = 2 * q - 1;
-        const R gi = ld_pop<L>(src + (size_t)(Q + i) * g.N, soff + nbr32<L>(nb, n, i, -1));
+        const bool bb = W && bounce(g, y, B ? -Lt::c[i][1] : Lt::c[i][1]);
+        const R gi = bb ? ld_pop<L>(src + (size_t)(Q + i) * g.N, (B ? 0u : (uint32_t)g.N) + n)
+                        : ld_pop<L>(src + (size_t)(Q + i) * g.N, soff + nbr32<L>(nb, n, i, -1));
         const R cu = R(Lt::c[i][0]) * up[0] + R(Lt::c[i][1]) * up[1] + R(Lt::c[i][2]) * up[2];
         const R geq = R(Lt::w[i]) * (base + R(3) * ph * cu + R(4.5) * ph * cu * cu);
         st_pop<L>(dst + (size_t)(Q + i) * g.N, soff + n, gi + om * (geq - gi));
@@ -617,7 +626,7 @@ __device__ __forceinline__ void node_collide_pair(const GridDims& g, const PhysC
 
 // All nodes of a tile of TW x TH nodes at (x0, y0, z), processed by a block
 // of NT threads with the two sides of each node on lanes l and l ^ 32.
-template <int L, typename T, int NT>
+template <int L, typename T, int NT, bool W = false>
 __device__ __forceinline__ void tile_collide_pair(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
                                                   T* __restrict__ dst, const double* __restrict__ rho_ref,
                                                   const double* __restrict__ rho, const double* __restrict__ phi,
@@ -631,7 +640,7 @@ __device__ __forceinline__ void tile_collide_pair(const GridDims& g, const PhysC
         const int x = x0 + kk % TW, y = y0 + kk / TW;
         if (kk < TW * TH && x < g.nx && y < g.ny && z < g.nz) {
             double d1[kDiag] = {0, 0, 0, 0, 0, 0, INFINITY, INFINITY, -INFINITY, 0};
-            node_collide_pair<L, T>(g, k, src, dst, rho_ref, rho, phi, mux, mup, x, y, z, side, diag, d1);
+            node_collide_pair<L, T, W>(g, k, src, dst, rho_ref, rho, phi, mux, mup, x, y, z, side, diag, d1);
             if (diag) {
                 for (int v = 0; v < 5; ++v) dv[v] += d1[v];
                 dv[5] = fmax(dv[5], d1[5]);
@@ -657,14 +666,14 @@ struct UsePairs {
 // threads, in the collision form UsePairs selects.
 // RG: reduced phase-field lattice (one node per lane; the pair split runs the
 // full lattice only).
-template <int L, typename T, int NT, bool RG = false>
+template <int L, typename T, int NT, bool RG = false, bool W = false>
 __device__ __forceinline__ void tile_collide(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
                                              T* __restrict__ dst, const double* __restrict__ rho_ref,
                                              const double* __restrict__ rho, const double* __restrict__ phi,
                                              const double* __restrict__ mux, const double* __restrict__ mup,
                                              int x0, int y0, int z, int TW, int TH, int tid, bool diag, double* dv) {
     if constexpr (UsePairs<L, T>::value && !RG) {
-        tile_collide_pair<L, T, NT>(g, k, src, dst, rho_ref, rho, phi, mux, mup, x0, y0, z, TW, TH, tid, diag, dv);
+        tile_collide_pair<L, T, NT, W>(g, k, src, dst, rho_ref, rho, phi, mux, mup, x0, y0, z, TW, TH, tid, diag, dv);
         return;
     }
     for (int kk = tid; kk < TW * TH; kk += NT) {

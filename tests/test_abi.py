@@ -148,17 +148,18 @@ def test_null_arguments_are_rejected(lib):
 
 
 def test_wall_parameters_are_validated(orc):
-    """Walls: accepted on D2Q9 (both precisions) and D3Q27 FP64; rejected on
-    D3Q27 FP32-mixed, with ny < 2, with contact angles outside (0, pi), with
-    walls other than 0/1, and in the batched form."""
+    """Walls: accepted on D2Q9 and D3Q27 in both precisions; rejected with
+    ny < 2, with contact angles outside (0, pi), with walls other than 0/1,
+    and in the batched form."""
     import math
     import paper_1710_07486_amd as T
     from paper_1710_07486_amd import _lib
     from paper_1710_07486_amd.batch import required_bytes as batch_bytes
     T0 = orc.temperature_for_ratio(10.0)[0]
-    for kw in (dict(), dict(precision=T.FP32_MIXED), dict(lattice=T.D3Q27, nz=8)):
+    for kw in (dict(), dict(precision=T.FP32_MIXED), dict(lattice=T.D3Q27, nz=8),
+               dict(lattice=T.D3Q27, nz=8, precision=T.FP32_MIXED)):
         assert T.required_bytes(T.Params(nx=16, ny=16, T=T0, walls=1, **kw)) > 0
-    bad = [dict(lattice=T.D3Q27, nz=8, precision=T.FP32_MIXED), dict(ny=1), dict(theta_rho_lo=0.0),
+    bad = [dict(ny=1), dict(theta_rho_lo=0.0),
            dict(theta_phi_hi=math.pi), dict(theta_rho_hi=float("nan")), dict(walls=2)]
     for kw in bad:
         p = T.Params(nx=16, ny=16, T=T0, walls=1)

@@ -135,7 +135,8 @@ def wide_box(shape, k2=0.1, k3=0.3, v_rel=0.04, ratio=1000.0, walls=0):
     return wl
 
 
-WIDE = {"fp64": (0, 0, 0), "fp32": (1, 0, 0), "fp64_d3q7": (0, 1, 0), "fp64_walls": (0, 0, 1)}
+WIDE = {"fp64": (0, 0, 0), "fp32": (1, 0, 0), "fp64_d3q7": (0, 1, 0), "fp64_walls": (0, 0, 1),
+        "fp32_walls": (1, 0, 1)}
 
 
 @pytest.mark.parametrize("shape", [(9, 13, 200), (7, 10, 130)])
@@ -144,13 +145,11 @@ def test_d3q27_multi_tile(orc, shape, case):
     """D3Q27 boxes three tiles wide in x and y (200 x 13 x 9, and 130 x 10 x 7
     with two-node ragged last tiles), 200 steps, element by element against
     the oracle: FP64 (full and reduced phase-field lattice, and with wetting
-    walls) within 1e-10, FP32-mixed within 1e-5 (rho, phi) and 1e-4 of the
-    largest velocity (u)."""
+    walls) within 1e-10, FP32-mixed (periodic and with wetting walls) within
+    1e-5 (rho, phi) and 1e-4 of the largest velocity (u)."""
     import math
     import paper_1710_07486_amd as T
     precision, glat, walls = WIDE[case]
-    if precision == 1 and (glat or walls):
-        pytest.skip("not available in the FP32-mixed 3D form")
     wl = wide_box(shape, walls=walls)
     say("D3Q27 multi-tile", case, shape)
     po, pl, rho, phi, u = make(orc, wl, precision)

@@ -4,8 +4,8 @@ the FP64 oracle and a closed form.
 Parity: a liquid-1 cap on the bottom wall and a liquid-2 cap on the top wall
 of a channel (walls at y = -1/2 and ny - 1/2), wetting angles that differ per
 wall and per field, several grid shapes including ragged tiles; FP64 within
-1e-10 of the oracle, FP32-mixed within 1e-5 (densities).  Closed form: a
-shear wave between the walls decays at nu k^2, k = pi / ny."""
+1e-10 of the oracle, FP32-mixed (D2Q9 and D3Q27) within 1e-5 (densities).
+Closed form: a shear wave between the walls decays at nu k^2, k = pi / ny."""
 import math
 
 import numpy as np
@@ -97,6 +97,21 @@ def test_d2q9_walls_fp32_mixed(orc):
     e = {k: rel(fg[k], fo[k]) for k in ("rho", "phi")}
     e["u"] = rel(fg["u"], fo["u"], 1e-14)
     print("errors", e, flush=True)
+    assert e["rho"] <= 1e-5 and e["phi"] <= 1e-5 and e["u"] <= 1e-4, e
+
+
+@pytest.mark.parametrize("shape", SHAPES_3D, ids=[f"{a}x{b}x{c}" for a, b, c in SHAPES_3D])
+def test_d3q27_walls_fp32_mixed(orc, shape):
+    """The pair-split FP32 collision with bounce-back on both sides of each
+    node (a lane pulling c_i and its partner pulling -c_i)."""
+    nx, ny, nz = shape
+    wl = W.wall_drops(nx, ny, nz, radius=0.3 * min(nx, 2 * ny), ratio=100.0)
+    say("D3Q27 walls FP32-mixed", shape)
+    fo, fg = run(orc, wl, 40, precision=1)
+    e = {k: rel(fg[k], fo[k]) for k in ("rho", "phi")}
+    e["u"] = rel(fg["u"], fo["u"], 1e-14)
+    print("errors", e, flush=True)
+    assert np.isfinite(fo["rho"]).all()
     assert e["rho"] <= 1e-5 and e["phi"] <= 1e-5 and e["u"] <= 1e-4, e
 
 
