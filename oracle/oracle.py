@@ -102,6 +102,24 @@ class Params:
         return (self.nz, self.ny, self.nx)
 
 
+class OrcNL(ctypes.Structure):
+    _fields_ = [("lambda4", ctypes.c_double), ("kappa4", ctypes.c_double),
+                ("mobility_form", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+@dataclasses.dataclass
+class NLParams:
+    """The third liquid of the extension to more liquid components: its double
+    well and gradient coefficients, and the mobility form (0 consistent
+    matrix, 1 one mobility per order parameter)."""
+    lambda4: float = 0.140625
+    kappa4: float = 0.045
+    mobility_form: int = 0
+
+    def c_struct(self) -> OrcNL:
+        return OrcNL(self.lambda4, self.kappa4, self.mobility_form, 0)
+
+
 _lib = None
 
 
@@ -161,6 +179,19 @@ def lib():
         L.orc_run.restype = ctypes.c_int
         L.orc_fields.argtypes = [P, vp, vp] + [vp] * 8
         L.orc_fields.restype = ctypes.c_int
+        NP = ctypes.POINTER(OrcNL)
+        L.orc_nl_concentrations.argtypes = [P, d, d, d, vp]
+        L.orc_nl_mobility.argtypes = [P, NP, vp]
+        L.orc_nl_mobility.restype = ctypes.c_int
+        L.orc_nl_mu_bulk.argtypes = [P, NP, d, d, d, vp]
+        L.orc_nl_f_bulk.argtypes = [P, NP, d, d, d]
+        L.orc_nl_f_bulk.restype = d
+        L.orc_nl_init.argtypes = [P, NP] + [vp] * 7
+        L.orc_nl_init.restype = ctypes.c_int
+        L.orc_nl_run.argtypes = [P, NP, vp, vp, vp, ctypes.c_int64]
+        L.orc_nl_run.restype = ctypes.c_int
+        L.orc_nl_fields.argtypes = [P, NP] + [vp] * 10
+        L.orc_nl_fields.restype = ctypes.c_int
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -422,6 +453,77 @@ class State:
                               _ptr(out["force"]))
         if rc != 0:
             raise MemoryError("oracle fields failed")
+        return out
+
+
+# ---------------------------------------------------------------------------
+# Three liquids and the gas (the extension to more liquid components)
+# ---------------------------------------------------------------------------
+
+def nl_concentrations(p: Params, rho, phi, psi):
+    out = np.zeros(3)
+    lib().orc_nl_concentrations(ctypes.byref(p.c_struct()), float(rho), float(phi), float(psi), _ptr(out))
+    return tuple(out)
+
+
+def nl_mobility(p: Params, nl: NLParams) -> np.ndarray:
+    """The (phi, psi) mobility matrix divided by M."""
+    out = np.zeros(4)
+    if lib().orc_nl_mobility(ctypes.byref(p.c_struct()), ctypes.byref(nl.c_struct()), _ptr(out)) != 0:
+        raise ValueError("the consistent mobility needs positive kappas")
+    return out.reshape(2, 2)
+
+
+def nl_mu_bulk(p: Params, nl: NLParams, rho, phi, psi):
+    out = np.zeros(3)
+    lib().orc_nl_mu_bulk(ctypes.byref(p.c_struct()), ctypes.byref(nl.c_struct()), float(rho), float(phi),
+                         float(psi), _ptr(out))
+    return tuple(out)
+
+
+def nl_f_bulk(p: Params, nl: NLParams, rho, phi, psi):
+    return lib().orc_nl_f_bulk(ctypes.byref(p.c_struct()), ctypes.byref(nl.c_struct()), float(rho), float(phi),
+                               float(psi))
+
+
+class NLState:
+    """Post-streaming populations f, g, h of shape (Q, nz, ny, nx) of the
+    three-liquid model."""
+
+    def __init__(self, p: Params, nl: NLParams, rho0, phi0, psi0, u0=None):
+        self.p, self.nl = p, nl
+        self.f = np.zeros((p.Q,) + p.shape)
+        self.g = np.zeros((p.Q,) + p.shape)
+        self.h = np.zeros((p.Q,) + p.shape)
+        arr = [np.ascontiguousarray(v, dtype=np.float64).reshape(p.shape) for v in (rho0, phi0, psi0)]
+        u = None
+        if u0 is not None:
+            u = np.zeros((3,) + p.shape)
+            u0 = np.asarray(u0, dtype=np.float64)
+            u[: u0.shape[0]] = u0.reshape((u0.shape[0],) + p.shape)
+        rc = lib().orc_nl_init(ctypes.byref(p.c_struct()), ctypes.byref(nl.c_struct()), *(_ptr(v) for v in arr),
+                               _ptr(u), _ptr(self.f), _ptr(self.g), _ptr(self.h))
+        if rc != 0:
+            raise ValueError("three-liquid oracle init failed (walls, reduced lattice or kappa <= 0?)")
+        self.steps = 0
+
+    def run(self, nsteps: int):
+        rc = lib().orc_nl_run(ctypes.byref(self.p.c_struct()), ctypes.byref(self.nl.c_struct()), _ptr(self.f),
+                              _ptr(self.g), _ptr(self.h), int(nsteps))
+        if rc != 0:
+            raise MemoryError("three-liquid oracle run failed")
+        self.steps += nsteps
+
+    def fields(self):
+        sh = self.p.shape
+        out = {k: np.zeros(sh) for k in ("rho", "phi", "psi")}
+        for k in ("u", "c", "mu", "force"):
+            out[k] = np.zeros((3,) + sh)
+        rc = lib().orc_nl_fields(ctypes.byref(self.p.c_struct()), ctypes.byref(self.nl.c_struct()), _ptr(self.f),
+                                 _ptr(self.g), _ptr(self.h), _ptr(out["rho"]), _ptr(out["phi"]), _ptr(out["psi"]),
+                                 _ptr(out["u"]), _ptr(out["c"]), _ptr(out["mu"]), _ptr(out["force"]))
+        if rc != 0:
+            raise MemoryError("three-liquid oracle fields failed")
         return out
 
 

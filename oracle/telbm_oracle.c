@@ -1063,3 +1063,338 @@ void orc_set_num_threads(int n)
     (void)n;
 #endif
 }
+
+/* ------------------------------------------------------------------------- */
+/* More liquid components (the extension named in the paper's concluding     */
+/* paragraph: one more double well in f_B and one more gradient term in f_I   */
+/* per added liquid).  Here: three liquids and the gas, with a second phase   */
+/* field psi.  Reading (the paper gives no equations for it):                 */
+/*  - concentrations, with C_L = 1 - C_g the liquid fraction of the text      */
+/*    below Fig. 1:                                                          */
+/*      C1 = (C_L + phi/chi - psi/chi)/2, C2 = (C_L - phi/chi - psi/chi)/2,  */
+/*      C3 = psi/chi,                                                        */
+/*    so psi = 0 gives back the two-liquid definitions exactly; the pure     */
+/*    phases sit at (rho_g,0,0), (rho_l,chi,0), (rho_l,-chi,0), (rho_l,0,chi); */
+/*  - free energy: Eq. (2) plus (lambda4/2) C3^2 (1-C3)^2, Eq. (3) plus       */
+/*    (kappa4/2) |grad C3|^2.  With nu_m = lambda_{m+1} W(C_m)                */
+/*    - kappa_{m+1} lap C_m (W as in the bulk potentials above) the          */
+/*    potentials are the chain rule through C_m:                             */
+/*      mu_rho = (lambda1/2) Psi' - kappa1 lap rho - (nu1 + nu2)/(2 (rho_g - rho_l)) */
+/*      mu_phi = (nu1 - nu2)/(2 chi),  mu_psi = (2 nu3 - nu1 - nu2)/(2 chi);  */
+/*  - force: -rho grad(mu_rho - cs2 ln rho) - phi grad mu_phi - psi grad mu_psi */
+/*    (div P with one more order parameter);                                  */
+/*  - Cahn-Hilliard equations for phi and psi with a constant 2 x 2 mobility  */
+/*    matrix Mt: d_t phi + div(phi u) = lap(Mt_pp mu_phi + Mt_ps mu_psi), and  */
+/*    the same for psi.  Mt is the image in (phi, psi) of the concentration   */
+/*    mobility of consistent N-phase Cahn-Hilliard models (Boyer & Lapuerta), */
+/*      M_C = (M / chi^2) (diag(w) - w w^T / W) / (w1 + w2),                  */
+/*      w = (1/kappa2, 1/kappa3, 1/kappa4), W = w1 + w2 + w3,                 */
+/*    Mt = A+ M_C A+^T with A+ the pseudo-inverse of d(C1,C2,C3)/d(phi,psi)   */
+/*    (rows chi (1,-1,0) and (chi/3)(-1,-1,2)).  At an interface between two  */
+/*    liquids with the third absent, M_C sends the absent one's chemical      */
+/*    potential combination to zero when lambda_m / kappa_m is the same for   */
+/*    every liquid, so an absent liquid does not appear there.  The scale     */
+/*    1/(w1 + w2) makes Mt_pp = M and Mt_ps = 0 when kappa2 = kappa3: phi    */
+/*    then moves exactly as in the two-liquid model (Mt = M diag(1, 1/3) for */
+/*    equal kappas).  mobility_form 1 takes Mt = M I instead (one mobility    */
+/*    per order parameter), which is not consistent; it is kept to show that. */
+/*  - lattice Boltzmann form: a second set of phase-field populations h for   */
+/*    psi with the BGK of g (same tau_phi, same equilibrium with            */
+/*    Gamma mu_psi~); the equilibria take the mixed potentials                */
+/*    mu_phi~ = (Mt_pp mu_phi + Mt_ps mu_psi)/M and mu_psi~ likewise.         */
+/* Periodic boxes on the full phase-field lattice only.                      */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    double lambda4, kappa4;   /* double well and gradient coefficient of liquid 3 */
+    int32_t mobility_form;    /* 0: consistent mobility matrix; 1: M per order parameter */
+    int32_t pad;
+} orc_nl;
+
+void orc_nl_concentrations(const orc_params *p, double rho, double phi, double psi, double *c)
+{
+    double cl = 1.0 - (rho - p->rho_l) / (p->rho_g - p->rho_l);
+    c[0] = 0.5 * (cl + phi / p->chi - psi / p->chi);
+    c[1] = 0.5 * (cl - phi / p->chi - psi / p->chi);
+    c[2] = psi / p->chi;
+}
+
+/* Mt / M as {pp, ps, sp, ss}; -1 if a kappa is not positive. */
+int orc_nl_mobility(const orc_params *p, const orc_nl *nl, double *m)
+{
+    if (nl->mobility_form == 1) {
+        m[0] = 1.0; m[1] = 0.0; m[2] = 0.0; m[3] = 1.0;
+        return 0;
+    }
+    double s[3] = {p->kappa2, p->kappa3, nl->kappa4};
+    if (!(s[0] > 0.0 && s[1] > 0.0 && s[2] > 0.0)) return -1;
+    double w[3] = {1.0 / s[0], 1.0 / s[1], 1.0 / s[2]};
+    double W = w[0] + w[1] + w[2];
+    double K[3][3];   /* M_C chi^2 (w1 + w2) / M */
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            K[i][j] = (i == j ? w[i] : 0.0) - w[i] * w[j] / W;
+    /* rows of A+ divided by chi; the chi^2 of A+ M_C A+^T cancels M_C's */
+    double a[2][3] = {{1.0, -1.0, 0.0}, {-1.0 / 3.0, -1.0 / 3.0, 2.0 / 3.0}};
+    for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y) {
+            double v = 0.0;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) v += a[x][i] * K[i][j] * a[y][j];
+            m[2 * x + y] = v / (w[0] + w[1]);
+        }
+    return 0;
+}
+
+/* Bulk parts of (mu_rho, mu_phi, mu_psi): the formulas above without the
+ * Laplacian terms. */
+void orc_nl_mu_bulk(const orc_params *p, const orc_nl *nl, double rho, double phi, double psi, double *out)
+{
+    double c[3];
+    orc_nl_concentrations(p, rho, phi, psi, c);
+    double lam[3] = {p->lambda2, p->lambda3, nl->lambda4};
+    double nu[3];
+    for (int m = 0; m < 3; ++m) nu[m] = lam[m] * dwell_half(c[m]);
+    out[0] = 0.5 * p->lambda1 * orc_eos_psi_prime(p->eos, p->a, p->b, p->R, p->omega, p->T, p->C, rho)
+             - (nu[0] + nu[1]) / (2.0 * (p->rho_g - p->rho_l));
+    out[1] = (nu[0] - nu[1]) / (2.0 * p->chi);
+    out[2] = (2.0 * nu[2] - nu[0] - nu[1]) / (2.0 * p->chi);
+}
+
+/* Bulk free-energy density: Eq. (2) plus the third liquid's double well. */
+double orc_nl_f_bulk(const orc_params *p, const orc_nl *nl, double rho, double phi, double psi)
+{
+    double c[3];
+    orc_nl_concentrations(p, rho, phi, psi, c);
+    double psi_e = orc_eos_psi(p->eos, p->a, p->b, p->R, p->omega, p->T, p->C, rho);
+    double psi0 = orc_eos_psi(p->eos, p->a, p->b, p->R, p->omega, p->T, p->C, p->rho_g);
+    double lam[3] = {p->lambda2, p->lambda3, nl->lambda4};
+    double f = 0.5 * p->lambda1 * (psi_e - psi0);
+    for (int m = 0; m < 3; ++m) {
+        double d = c[m] * (1.0 - c[m]);
+        f += 0.5 * lam[m] * d * d;
+    }
+    return f;
+}
+
+typedef struct {
+    orc_work w;               /* rho, phi, j, mu_rho, mu_phi, force, ... */
+    double *psi, *lap_psi, *mu_psi, *grad_mu_psi;
+} orc_nl_work;
+
+static int nl_work_alloc(orc_nl_work *v, int64_t N)
+{
+    int rc = work_alloc(&v->w, N);
+    v->psi = calloc(N, sizeof(double));
+    v->lap_psi = calloc(N, sizeof(double));
+    v->mu_psi = calloc(N, sizeof(double));
+    v->grad_mu_psi = calloc(3 * N, sizeof(double));
+    return (rc || !v->psi || !v->lap_psi || !v->mu_psi || !v->grad_mu_psi) ? -1 : 0;
+}
+
+static void nl_work_free(orc_nl_work *v)
+{
+    work_free(&v->w);
+    free(v->psi); free(v->lap_psi); free(v->mu_psi); free(v->grad_mu_psi);
+}
+
+static void nl_chemical_potentials(const orc_params *p, const orc_nl *nl, orc_nl_work *v)
+{
+    int64_t N = num_nodes(p);
+    orc_work *w = &v->w;
+    laplacian_mode(p, w->rho, w->lap_rho, GHOST_MIRROR);
+    laplacian_mode(p, w->phi, w->lap_phi, GHOST_MIRROR);
+    laplacian_mode(p, v->psi, v->lap_psi, GHOST_MIRROR);
+    double lam[3] = {p->lambda2, p->lambda3, nl->lambda4};
+    double kap[3] = {p->kappa2, p->kappa3, nl->kappa4};
+    double dlt = p->rho_g - p->rho_l, chi = p->chi;
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n) {
+        double c[3], lc[3], nu[3];
+        orc_nl_concentrations(p, w->rho[n], w->phi[n], v->psi[n], c);
+        double lcl = -w->lap_rho[n] / dlt;   /* lap C_L */
+        lc[0] = 0.5 * (lcl + w->lap_phi[n] / chi - v->lap_psi[n] / chi);
+        lc[1] = 0.5 * (lcl - w->lap_phi[n] / chi - v->lap_psi[n] / chi);
+        lc[2] = v->lap_psi[n] / chi;
+        for (int m = 0; m < 3; ++m) nu[m] = lam[m] * dwell_half(c[m]) - kap[m] * lc[m];
+        w->mu_rho[n] = 0.5 * p->lambda1
+                           * orc_eos_psi_prime(p->eos, p->a, p->b, p->R, p->omega, p->T, p->C, w->rho[n])
+                       - p->kappa1 * w->lap_rho[n] - (nu[0] + nu[1]) / (2.0 * dlt);
+        w->mu_phi[n] = (nu[0] - nu[1]) / (2.0 * chi);
+        v->mu_psi[n] = (2.0 * nu[2] - nu[0] - nu[1]) / (2.0 * chi);
+    }
+}
+
+static void nl_force(const orc_params *p, orc_nl_work *v)
+{
+    int64_t N = num_nodes(p);
+    orc_work *w = &v->w;
+    double *excess = w->lap_rho;
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n) excess[n] = w->mu_rho[n] - CS2 * log(w->rho[n]);
+    gradient_mode(p, excess, w->grad_rho, GHOST_MIRROR);
+    gradient_mode(p, w->mu_phi, w->grad_mu_phi, GHOST_MIRROR);
+    gradient_mode(p, v->mu_psi, v->grad_mu_psi, GHOST_MIRROR);
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n)
+        for (int a = 0; a < 3; ++a)
+            w->force[a * N + n] = -w->rho[n] * w->grad_rho[a * N + n] - w->phi[n] * w->grad_mu_phi[a * N + n]
+                                  - v->psi[n] * v->grad_mu_psi[a * N + n];
+}
+
+static void nl_moments(const orc_params *p, const double *f, const double *g, const double *h, orc_nl_work *v)
+{
+    int Q = lattice_Q(p->lattice);
+    int64_t N = num_nodes(p);
+    moments(p, f, g, &v->w);
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n) {
+        double s = 0.0;
+        for (int i = 0; i < Q; ++i) s += h[(int64_t)i * N + n];
+        v->psi[n] = s;
+    }
+}
+
+static int nl_check(const orc_params *p, const orc_nl *nl, double *m)
+{
+    if (p->walls || p->glattice) return -2;
+    return orc_nl_mobility(p, nl, m) ? -2 : 0;
+}
+
+/* Initial populations: f = feq(rho0, u0), g = geq(phi0, mu_phi~, u0),
+ * h = geq(psi0, mu_psi~, u0).  u0 may be NULL.  Returns -2 for walls, the
+ * reduced phase-field lattice or a non-positive kappa. */
+int orc_nl_init(const orc_params *p, const orc_nl *nl, const double *rho0, const double *phi0,
+                const double *psi0, const double *u0, double *f, double *g, double *h)
+{
+    int Q = lattice_Q(p->lattice);
+    int64_t N = num_nodes(p);
+    double m[4];
+    if (nl_check(p, nl, m)) return -2;
+    orc_nl_work v;
+    if (nl_work_alloc(&v, N)) { nl_work_free(&v); return -1; }
+    memcpy(v.w.rho, rho0, N * sizeof(double));
+    memcpy(v.w.phi, phi0, N * sizeof(double));
+    memcpy(v.psi, psi0, N * sizeof(double));
+    nl_chemical_potentials(p, nl, &v);
+    double Gam = gamma_cap_of(p);
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n) {
+        double u[3] = {0, 0, 0}, fe[27], ge[27], he[27];
+        if (u0) { u[0] = u0[n]; u[1] = u0[N + n]; if (p->lattice == 1) u[2] = u0[2 * N + n]; }
+        double mp = m[0] * v.w.mu_phi[n] + m[1] * v.mu_psi[n];
+        double ms = m[2] * v.w.mu_phi[n] + m[3] * v.mu_psi[n];
+        orc_feq(p->lattice, rho0[n], u, fe);
+        orc_geq(p->lattice, phi0[n], mp, Gam, u, ge);
+        orc_geq(p->lattice, psi0[n], ms, Gam, u, he);
+        for (int i = 0; i < Q; ++i) {
+            f[(int64_t)i * N + n] = fe[i];
+            g[(int64_t)i * N + n] = ge[i];
+            h[(int64_t)i * N + n] = he[i];
+        }
+    }
+    nl_work_free(&v);
+    return 0;
+}
+
+/* Advance f, g, h (layout [Q][N], post-streaming) by nsteps: moments ->
+ * Laplacians and potentials -> gradients and force -> KBC collision of f with
+ * exact-difference forcing, BGK of g and h -> streaming. */
+int orc_nl_run(const orc_params *p, const orc_nl *nl, double *f, double *g, double *h, int64_t nsteps)
+{
+    int Q = lattice_Q(p->lattice);
+    int64_t N = num_nodes(p);
+    double m[4];
+    if (nl_check(p, nl, m)) return -2;
+    orc_nl_work v;
+    double *fs = malloc((size_t)Q * N * sizeof(double));
+    double *gs = malloc((size_t)Q * N * sizeof(double));
+    double *hs = malloc((size_t)Q * N * sizeof(double));
+    if (nl_work_alloc(&v, N) || !fs || !gs || !hs) {
+        nl_work_free(&v); free(fs); free(gs); free(hs);
+        return -1;
+    }
+    const double beta = beta_of(p);
+    const double Gam = gamma_cap_of(p);
+    const double tau_phi = p->tau_phi;
+    for (int64_t step = 0; step < nsteps; ++step) {
+        nl_moments(p, f, g, h, &v);
+        nl_chemical_potentials(p, nl, &v);
+        nl_force(p, &v);
+        orc_work *w = &v.w;
+#pragma omp parallel for schedule(static)
+        for (int64_t n = 0; n < N; ++n) {
+            double fn[27], fo[27], ge[27], he[27], F[3], up[3], gam;
+            for (int i = 0; i < Q; ++i) fn[i] = f[(int64_t)i * N + n];
+            F[0] = w->force[n]; F[1] = w->force[N + n]; F[2] = w->force[2 * N + n];
+            if (p->lattice == 0) F[2] = 0.0;
+            orc_collide_node(p->lattice, beta, fn, F, fo, &gam);
+            double r = w->rho[n];
+            for (int a = 0; a < 3; ++a) up[a] = (w->j[a * N + n] + 0.5 * F[a]) / r;
+            if (p->lattice == 0) up[2] = 0.0;
+            double mp = m[0] * w->mu_phi[n] + m[1] * v.mu_psi[n];
+            double ms = m[2] * w->mu_phi[n] + m[3] * v.mu_psi[n];
+            orc_geq(p->lattice, w->phi[n], mp, Gam, up, ge);
+            orc_geq(p->lattice, v.psi[n], ms, Gam, up, he);
+            for (int i = 0; i < Q; ++i) {
+                int64_t k = (int64_t)i * N + n;
+                fs[k] = fo[i];
+                gs[k] = g[k] - (g[k] - ge[i]) / tau_phi;
+                hs[k] = h[k] - (h[k] - he[i]) / tau_phi;
+            }
+        }
+#pragma omp parallel for schedule(static)
+        for (int64_t n = 0; n < N; ++n) {
+            for (int i = 0; i < Q; ++i) {
+                int c[3];
+                direction(i, c);
+                int64_t mm = neighbour(p, n, c);
+                f[(int64_t)i * N + mm] = fs[(int64_t)i * N + n];
+                g[(int64_t)i * N + mm] = gs[(int64_t)i * N + n];
+                h[(int64_t)i * N + mm] = hs[(int64_t)i * N + n];
+            }
+        }
+    }
+    nl_work_free(&v);
+    free(fs); free(gs); free(hs);
+    return 0;
+}
+
+/* Fields of the state (any output may be NULL): rho, phi, psi, u (physical,
+ * [3][N]), c ([3][N]: C1, C2, C3), mu ([3][N]: mu_rho, mu_phi, mu_psi),
+ * force ([3][N]). */
+int orc_nl_fields(const orc_params *p, const orc_nl *nl, const double *f, const double *g, const double *h,
+                  double *rho, double *phi, double *psi, double *u, double *c, double *mu, double *force)
+{
+    int64_t N = num_nodes(p);
+    double m[4];
+    if (nl_check(p, nl, m)) return -2;
+    orc_nl_work v;
+    if (nl_work_alloc(&v, N)) { nl_work_free(&v); return -1; }
+    nl_moments(p, f, g, h, &v);
+    nl_chemical_potentials(p, nl, &v);
+    nl_force(p, &v);
+    orc_work *w = &v.w;
+    for (int64_t n = 0; n < N; ++n) {
+        if (rho) rho[n] = w->rho[n];
+        if (phi) phi[n] = w->phi[n];
+        if (psi) psi[n] = v.psi[n];
+        if (c) {
+            double cc[3];
+            orc_nl_concentrations(p, w->rho[n], w->phi[n], v.psi[n], cc);
+            for (int k = 0; k < 3; ++k) c[k * N + n] = cc[k];
+        }
+        if (mu) {
+            mu[n] = w->mu_rho[n];
+            mu[N + n] = w->mu_phi[n];
+            mu[2 * N + n] = v.mu_psi[n];
+        }
+        for (int a = 0; a < 3; ++a) {
+            double F = (p->lattice == 0 && a == 2) ? 0.0 : w->force[a * N + n];
+            if (u) u[a * N + n] = (p->lattice == 0 && a == 2) ? 0.0 : (w->j[a * N + n] + 0.5 * F) / w->rho[n];
+            if (force) force[a * N + n] = F;
+        }
+    }
+    nl_work_free(&v);
+    return 0;
+}

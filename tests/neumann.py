@@ -124,7 +124,13 @@ def measure_angles(rho, phi, rho_g, rho_l, chi, band_top, exclude=5.0, thr=0.25)
     nominal y of the liquid-2/gas interface that carries the lens; only the
     points within a quarter of the box height of it are used."""
     c1, c2, cg = concentrations(rho, phi, rho_g, rho_l, chi)
-    ny, nx = rho.shape
+    return measure_angles_c(c1, c2, cg, band_top, exclude, thr)
+
+
+def measure_angles_c(c1, c2, cg, band_top, exclude=5.0, thr=0.25):
+    """measure_angles from the three phases' concentration fields: c1 the
+    lens, c2 the phase below the flat interface, cg the phase above it."""
+    ny, nx = c1.shape
     yy = np.mgrid[0:ny, 0:nx][0]
     near = np.abs(yy - band_top) < ny / 4
     p1g = zero_points(c1 - cg, near & (c2 < thr))
