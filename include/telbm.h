@@ -390,6 +390,92 @@ int telbm_surrogate_decode_noalloc(const float *y, const double *rho_in, const d
                                    void *stream);
 size_t telbm_surrogate_decode_noalloc_max_bytes(void);
 
+/* ------------------------------------------------------------------------- */
+/* Three liquids and the gas: the extension to more liquid components named   */
+/* in the paper's concluding paragraph (one more double well in the bulk      */
+/* energy of Eq. 2 and one more gradient term in Eq. 3 per added liquid).     */
+/* A second phase field psi carries liquid 3:                                 */
+/*   C1 = (C_L + phi/chi - psi/chi)/2, C2 = (C_L - phi/chi - psi/chi)/2,      */
+/*   C3 = psi/chi, C_L = 1 - C_g (C_g as defined below Fig. 1),              */
+/* so psi = 0 is the paper's two-liquid model; the pure phases are           */
+/* (rho_g, 0, 0), (rho_l, chi, 0), (rho_l, -chi, 0), (rho_l, 0, chi).          */
+/* f_B gains (lambda4/2) C3^2 (1-C3)^2, f_I gains (kappa4/2) |grad C3|^2.     */
+/* The potentials are the chain rule through C_m: with                       */
+/* nu_m = lambda_{m+1} W(C_m) - kappa_{m+1} lap C_m, W(C) = C(1-C)(1-2C),     */
+/*   mu_rho = (lambda1/2) Psi' - kappa1 lap rho - (nu1 + nu2)/(2 (rho_g - rho_l)), */
+/*   mu_phi = (nu1 - nu2)/(2 chi), mu_psi = (2 nu3 - nu1 - nu2)/(2 chi).      */
+/* The force gains -psi grad mu_psi; phi and psi follow Cahn-Hilliard         */
+/* equations (Eq. 7) with the mobility matrix M m of telbm_nl_mobility,       */
+/* realised by two phase-field BGK populations whose equilibria take the     */
+/* mixed potentials (m mu)_phi and (m mu)_psi.  FP64, periodic boxes, the    */
+/* phase fields on the lattice of f; walls, the FP32-mixed form, the reduced */
+/* phase-field lattice and the batched form reject it (TELBM_ERR_INVAL).     */
+/* ------------------------------------------------------------------------- */
+typedef struct telbm_nl_params {
+    double lambda4, kappa4; /* double well and gradient coefficient of liquid 3 (kappa4 > 0) */
+} telbm_nl_params;
+
+typedef struct telbm_nl telbm_nl;
+
+#define TELBM_NL_FIELD_RHO 0
+#define TELBM_NL_FIELD_PHI 1
+#define TELBM_NL_FIELD_PSI 2
+#define TELBM_NL_FIELD_UX 3      /* physical velocity (j + F/2)/rho */
+#define TELBM_NL_FIELD_UY 4
+#define TELBM_NL_FIELD_UZ 5
+#define TELBM_NL_FIELD_C1 6      /* concentrations of the three liquids */
+#define TELBM_NL_FIELD_C2 7
+#define TELBM_NL_FIELD_C3 8
+#define TELBM_NL_FIELD_MU_RHO 9
+#define TELBM_NL_FIELD_MU_PHI 10
+#define TELBM_NL_FIELD_MU_PSI 11
+#define TELBM_NL_FIELD_FX 12     /* thermodynamic force density */
+#define TELBM_NL_FIELD_FY 13
+#define TELBM_NL_FIELD_FZ 14
+
+/* The (phi, psi) mobility matrix divided by M, as {pp, ps, sp, ss}: the image
+ * under the map above of the concentration mobility of consistent N-phase
+ * Cahn-Hilliard models (Boyer and Lapuerta) with inverse phase weights
+ * w = (1/kappa2, 1/kappa3, 1/kappa4), W = w1 + w2 + w3,
+ *   M_C = (M / chi^2) (diag(w) - w w^T / W) / (w1 + w2),
+ * which is, in closed form,
+ *   pp = (4 w1 w2 + (w1 + w2) w3) / (W (w1 + w2)),
+ *   ps = sp = w3 (w2 - w1) / (W (w1 + w2)),  ss = w3 / W.
+ * At an interface between two liquids where the third is absent it sends the
+ * absent liquid's diffusive flux to zero when lambda_m / kappa_m is the same
+ * for all liquids.  For kappa2 = kappa3, pp = 1 and ps = 0: phi moves exactly
+ * as in the two-liquid model (diag(1, 1/3) for equal kappas).  Host only;
+ * TELBM_ERR_INVAL unless kappa2, kappa3, kappa4 > 0. */
+int telbm_nl_mobility(const telbm_params *p, const telbm_nl_params *q, double *m);
+
+/* Bytes of device arena for these parameters (two population buffers of
+ * 3 Q N doubles and six N-double fields, each 256-byte aligned). */
+int telbm_nl_required_bytes(const telbm_params *p, const telbm_nl_params *q, size_t *bytes);
+
+/* Create, borrowing `device_arena` (>= required bytes, 256-byte aligned) for
+ * the solver's lifetime.  Parameters as for telbm_create plus q;
+ * p->precision must be TELBM_FP64, p->walls and p->glattice 0. */
+int telbm_nl_create(const telbm_params *p, const telbm_nl_params *q, void *device_arena, size_t bytes,
+                    telbm_nl **out);
+int telbm_nl_set_stream(telbm_nl *s, void *stream);
+
+/* Equilibrium populations of rho, phi, psi (required) and u (NULL: at rest;
+ * else D component arrays), the phase-field equilibria with the mixed
+ * potentials of those fields.  TELBM_ERR_UNSTABLE (state unchanged) if any
+ * rho <= 0, any value is non-finite or any |u_alpha| >= 1.  Resets the step
+ * counter. */
+int telbm_nl_init_fields(telbm_nl *s, const double *rho, const double *phi, const double *psi, const double *u,
+                         int on_device);
+
+/* Advance n >= 0 time steps (asynchronous): moments, potentials, collision. */
+int telbm_nl_step(telbm_nl *s, int64_t n);
+
+/* One TELBM_NL_FIELD_* of the current state into `out` (N doubles). Synchronises. */
+int telbm_nl_read(telbm_nl *s, int field, double *out, int on_device);
+int telbm_nl_step_count(const telbm_nl *s, int64_t *steps);
+int telbm_nl_destroy(telbm_nl *s);
+const char *telbm_nl_last_error(const telbm_nl *s);
+
 /* One Adam step (Kingma and Ba 2015) on n FP32 weights at step t >= 1. */
 int telbm_adam_step(float *w, const float *g, float *m, float *v, int64_t n, float lr, float beta1,
                     float beta2, float eps, int64_t t, void *stream);

@@ -8,3 +8,4 @@ Boltzmann model with high density ratio" (arXiv:1710.07486).
 from ._lib import D2Q9, D3Q27, FP64, FP32_MIXED, FIELDS, TelbmError  # noqa: F401
 from .solver import (EOS_CS, EOS_PR, EOS_VDW, Params, Solver, coexistence, critical_temperature,  # noqa: F401
                      required_bytes, temperature_for_ratio)
+from .nliquid import NLParams, NLSolver  # noqa: F401,E402

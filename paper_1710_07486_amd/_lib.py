@@ -34,6 +34,14 @@ class TelbmParams(ctypes.Structure):
     ]
 
 
+class TelbmNlParams(ctypes.Structure):
+    _fields_ = [("lambda4", ctypes.c_double), ("kappa4", ctypes.c_double)]
+
+
+NL_FIELDS = {"rho": 0, "phi": 1, "psi": 2, "ux": 3, "uy": 4, "uz": 5, "c1": 6, "c2": 7, "c3": 8, "mu_rho": 9,
+             "mu_phi": 10, "mu_psi": 11, "fx": 12, "fy": 13, "fz": 14}
+
+
 class TelbmDiag(ctypes.Structure):
     _fields_ = [
         ("step", ctypes.c_int64), ("mass", ctypes.c_double), ("phi_total", ctypes.c_double),
@@ -74,6 +82,18 @@ PROTOTYPES = {
     "telbm_algorithmic_bytes_per_update": (_d, [_vp]),
     "telbm_destroy": (_i, [_vp]),
     "telbm_last_error": (_c, [_vp]),
+    "telbm_nl_mobility": (_i, [ctypes.POINTER(TelbmParams), ctypes.POINTER(TelbmNlParams), _pd]),
+    "telbm_nl_required_bytes": (_i, [ctypes.POINTER(TelbmParams), ctypes.POINTER(TelbmNlParams),
+                                     ctypes.POINTER(_sz)]),
+    "telbm_nl_create": (_i, [ctypes.POINTER(TelbmParams), ctypes.POINTER(TelbmNlParams), _vp, _sz,
+                             ctypes.POINTER(_vp)]),
+    "telbm_nl_set_stream": (_i, [_vp, _vp]),
+    "telbm_nl_init_fields": (_i, [_vp, _vp, _vp, _vp, _vp, _i]),
+    "telbm_nl_step": (_i, [_vp, _i64]),
+    "telbm_nl_read": (_i, [_vp, _i, _vp, _i]),
+    "telbm_nl_step_count": (_i, [_vp, ctypes.POINTER(_i64)]),
+    "telbm_nl_destroy": (_i, [_vp]),
+    "telbm_nl_last_error": (_c, [_vp]),
 }
 
 _lib = None

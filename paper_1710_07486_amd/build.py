@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtelbm.so")
 
-HIP_SOURCES = ["kernels.hip", "api.cpp", "batch.hip", "surrogate.hip"]
+HIP_SOURCES = ["kernels.hip", "api.cpp", "batch.hip", "surrogate.hip", "nliquid.hip"]
 CXX_SOURCES = ["thermo.cpp"]
 
 # No packed FP32 instructions: the compiler must not emit v_pk_{add,mul,fma}_f32.

@@ -53,6 +53,18 @@ struct telbm_solver {
     std::string err;
 };
 
+// Three liquids and the gas (nliquid.hip).
+struct telbm_nl {
+    telbm_params p;
+    telbm_nl_params q;
+    NlArgs a;           // constants and buffers; src / dst set per launch
+    void* pop[2];
+    int cur;            // pop[cur] holds the state
+    bool aux_valid;     // rho, phi, psi and the potentials belong to the state
+    int64_t steps;
+    std::string err;
+};
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -366,6 +378,67 @@ int one_step(telbm_solver* s, bool diag, Timing* t = nullptr) {
 constexpr int kKinds = 3;
 const char* kKernelNames[kKinds] = {"moments", "chemical_potentials", "collide"};
 
+// -- three liquids ------------------------------------------------------------
+
+// Mobility matrix / M in closed form (the header states it).
+bool nl_mobility(const telbm_params& p, const telbm_nl_params& q, double* m) {
+    if (!(p.kappa2 > 0.0 && p.kappa3 > 0.0 && q.kappa4 > 0.0)) return false;
+    const double w1 = 1.0 / p.kappa2, w2 = 1.0 / p.kappa3, w3 = 1.0 / q.kappa4;
+    const double W = w1 + w2 + w3, s = 1.0 / (W * (w1 + w2));
+    m[0] = s * (4.0 * w1 * w2 + (w1 + w2) * w3);
+    m[1] = m[2] = s * w3 * (w2 - w1);
+    m[3] = w3 / W;
+    return true;
+}
+
+int nl_validate(const telbm_params* p, const telbm_nl_params* q, std::string* why) {
+    int rc = validate(p, why);
+    if (rc) return rc;
+    if (!q) { *why = "null third-liquid params"; return TELBM_ERR_INVAL; }
+    if (p->precision != TELBM_FP64) { *why = "three liquids: FP64 only"; return TELBM_ERR_INVAL; }
+    if (p->walls || p->glattice) { *why = "three liquids: periodic boxes on the full lattice only"; return TELBM_ERR_INVAL; }
+    if (!isfinite(q->lambda4) || !isfinite(q->kappa4)) { *why = "non-finite lambda4 / kappa4"; return TELBM_ERR_INVAL; }
+    double m[4];
+    if (!nl_mobility(*p, *q, m)) { *why = "three liquids: kappa2, kappa3, kappa4 must be positive"; return TELBM_ERR_INVAL; }
+    return TELBM_OK;
+}
+
+struct NlLayout {
+    size_t pop, aux, total;
+};
+
+NlLayout nl_layout(const telbm_params& p) {
+    const int64_t N = (int64_t)p.nx * p.ny * p.nz;
+    const int Q = p.lattice == TELBM_D2Q9 ? 9 : 27;
+    NlLayout L;
+    L.pop = align_up((size_t)3 * Q * N * sizeof(double));
+    L.aux = align_up((size_t)N * sizeof(double));
+    L.total = 2 * L.pop + 6 * L.aux;
+    return L;
+}
+
+int nl_fail(telbm_nl* s, int code, const std::string& msg) {
+    s->err = msg;
+    return code;
+}
+
+hipError_t nl_launch(telbm_nl* s, int part) {
+    NlArgs a = s->a;
+    a.src = (const double*)s->pop[s->cur];
+    a.dst = (double*)s->pop[part == 3 ? s->cur : 1 - s->cur];
+    return launch_nl_part(s->p.lattice, a, part);
+}
+
+// Moments and potentials of the current state.
+int nl_ensure_aux(telbm_nl* s) {
+    if (s->aux_valid) return TELBM_OK;
+    hipError_t e = nl_launch(s, 0);
+    if (e == hipSuccess) e = nl_launch(s, 1);
+    if (e != hipSuccess) return nl_fail(s, TELBM_ERR_DEVICE, std::string("three-liquid launch: ") + hipGetErrorString(e));
+    s->aux_valid = true;
+    return TELBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -649,6 +722,156 @@ int telbm_destroy(telbm_solver* s) {
 }
 
 const char* telbm_last_error(const telbm_solver* s) {
+    if (!s) return "null solver";
+    return s->err.c_str();
+}
+
+int telbm_nl_mobility(const telbm_params* p, const telbm_nl_params* q, double* m) {
+    if (!p || !q || !m) return TELBM_ERR_INVAL;
+    return nl_mobility(*p, *q, m) ? TELBM_OK : TELBM_ERR_INVAL;
+}
+
+int telbm_nl_required_bytes(const telbm_params* p, const telbm_nl_params* q, size_t* bytes) {
+    std::string why;
+    if (!bytes) return TELBM_ERR_INVAL;
+    int rc = nl_validate(p, q, &why);
+    if (rc) return rc;
+    *bytes = nl_layout(*p).total;
+    return TELBM_OK;
+}
+
+int telbm_nl_create(const telbm_params* p, const telbm_nl_params* q, void* device_arena, size_t bytes,
+                    telbm_nl** out) {
+    if (!out) return TELBM_ERR_INVAL;
+    *out = nullptr;
+    std::string why;
+    int rc = nl_validate(p, q, &why);
+    if (rc) return rc;
+    const NlLayout L = nl_layout(*p);
+    if (!device_arena || ((uintptr_t)device_arena % kAlign) != 0) return TELBM_ERR_INVAL;
+    if (bytes < L.total) return TELBM_ERR_NOMEM;
+    double rg = p->rho_g, rl = p->rho_l, C = 0.0, psi0 = 0.0, mg, ml;
+    if (!eos_maxwell(eos_of(*p), p->T, &mg, &ml, &C, &psi0)) return TELBM_ERR_INVAL;
+    if (rg == 0.0 && rl == 0.0) {
+        rg = mg;
+        rl = ml;
+    }
+    telbm_nl* s = new (std::nothrow) telbm_nl();
+    if (!s) return TELBM_ERR_NOMEM;
+    s->p = *p;
+    s->p.rho_g = rg;
+    s->p.rho_l = rl;
+    s->q = *q;
+    NlArgs& a = s->a;
+    a.g = GridDims{p->nx, p->ny, p->nz, 0, (int64_t)p->nx * p->ny * p->nz};
+    a.k = derive(*p, rg, rl, C);
+    a.q.kappa1 = p->kappa1;
+    a.q.kappa2 = p->kappa2;
+    a.q.kappa3 = p->kappa3;
+    a.q.kappa4 = q->kappa4;
+    a.q.lambda4 = q->lambda4;
+    nl_mobility(*p, *q, a.q.m);
+    char* base = (char*)device_arena;
+    s->pop[0] = base;
+    s->pop[1] = base + L.pop;
+    double** f[6] = {&a.rho, &a.phi, &a.psi, &a.mux, &a.mup, &a.mus};
+    for (int i = 0; i < 6; ++i) *f[i] = (double*)(base + 2 * L.pop + i * L.aux);
+    a.u0 = nullptr;
+    a.stream = nullptr;
+    s->cur = 0;
+    s->aux_valid = false;
+    s->steps = 0;
+    *out = s;
+    return TELBM_OK;
+}
+
+int telbm_nl_set_stream(telbm_nl* s, void* stream) {
+    if (!s) return TELBM_ERR_INVAL;
+    s->a.stream = (hipStream_t)stream;
+    return TELBM_OK;
+}
+
+int telbm_nl_init_fields(telbm_nl* s, const double* rho, const double* phi, const double* psi, const double* u,
+                         int on_device) {
+    if (!s) return TELBM_ERR_INVAL;
+    if (!rho || !phi || !psi) return nl_fail(s, TELBM_ERR_INVAL, "rho, phi and psi are required");
+    NlArgs& a = s->a;
+    const int64_t N = a.g.N;
+    const int D = s->p.lattice == TELBM_D2Q9 ? 2 : 3;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    // u is staged in the spare population buffer, the check count in mux
+    double* u_dev = u ? (double*)s->pop[1 - s->cur] : nullptr;
+    auto* bad = (unsigned long long*)a.mux;
+    hipError_t e = hipMemcpyAsync(a.rho, rho, N * sizeof(double), kind, a.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(a.phi, phi, N * sizeof(double), kind, a.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(a.psi, psi, N * sizeof(double), kind, a.stream);
+    if (e == hipSuccess && u) e = hipMemcpyAsync(u_dev, u, (size_t)D * N * sizeof(double), kind, a.stream);
+    if (e == hipSuccess) e = launch_check_init(a.g, D, a.rho, a.phi, u_dev, bad, a.stream);
+    unsigned long long nbad[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(&nbad[0], bad, sizeof(nbad[0]), hipMemcpyDeviceToHost, a.stream);
+    if (e == hipSuccess) e = launch_check_init(a.g, D, a.rho, a.psi, nullptr, bad, a.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&nbad[1], bad, sizeof(nbad[1]), hipMemcpyDeviceToHost, a.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(a.stream);
+    if (e != hipSuccess) return nl_fail(s, TELBM_ERR_DEVICE, std::string("init staging: ") + hipGetErrorString(e));
+    s->aux_valid = false;
+    if (nbad[0] || nbad[1])
+        return nl_fail(s, TELBM_ERR_UNSTABLE, std::to_string(nbad[0] + nbad[1]) + " nodes with unusable initial values");
+    // potentials of the initial fields, then the equilibria into pop[cur]
+    a.u0 = u_dev;
+    e = nl_launch(s, 1);
+    if (e == hipSuccess) e = nl_launch(s, 3);
+    a.u0 = nullptr;
+    if (e != hipSuccess) return nl_fail(s, TELBM_ERR_DEVICE, std::string("init launch: ") + hipGetErrorString(e));
+    s->aux_valid = false;
+    s->steps = 0;
+    return TELBM_OK;
+}
+
+int telbm_nl_step(telbm_nl* s, int64_t n) {
+    if (!s || n < 0) return TELBM_ERR_INVAL;
+    for (int64_t i = 0; i < n; ++i) {
+        int rc = nl_ensure_aux(s);
+        if (rc) return rc;
+        hipError_t e = nl_launch(s, 2);
+        if (e != hipSuccess) return nl_fail(s, TELBM_ERR_DEVICE, std::string("collision launch: ") + hipGetErrorString(e));
+        s->cur = 1 - s->cur;
+        s->aux_valid = false;
+        s->steps += 1;
+    }
+    return TELBM_OK;
+}
+
+int telbm_nl_read(telbm_nl* s, int field, double* out, int on_device) {
+    if (!s || !out) return TELBM_ERR_INVAL;
+    if (field < 0 || field > kNlFz) return nl_fail(s, TELBM_ERR_INVAL, "unknown field");
+    int rc = nl_ensure_aux(s);
+    if (rc) return rc;
+    NlArgs a = s->a;
+    a.src = (const double*)s->pop[s->cur];
+    double* dst = on_device ? out : (double*)s->pop[1 - s->cur];
+    hipError_t e = launch_nl_macro(s->p.lattice, a, field, dst);
+    if (e == hipSuccess && !on_device)
+        e = hipMemcpyAsync(out, dst, a.g.N * sizeof(double), hipMemcpyDeviceToHost, a.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(a.stream);
+    if (e != hipSuccess) return nl_fail(s, TELBM_ERR_DEVICE, std::string("read: ") + hipGetErrorString(e));
+    return TELBM_OK;
+}
+
+int telbm_nl_step_count(const telbm_nl* s, int64_t* steps) {
+    if (!s || !steps) return TELBM_ERR_INVAL;
+    *steps = s->steps;
+    return TELBM_OK;
+}
+
+int telbm_nl_destroy(telbm_nl* s) {
+    if (!s) return TELBM_ERR_INVAL;
+    if (s->a.stream) (void)hipStreamSynchronize(s->a.stream);
+    else (void)hipDeviceSynchronize();
+    delete s;
+    return TELBM_OK;
+}
+
+const char* telbm_nl_last_error(const telbm_nl* s) {
     if (!s) return "null solver";
     return s->err.c_str();
 }

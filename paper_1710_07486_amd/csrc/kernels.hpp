@@ -79,4 +79,32 @@ hipError_t launch_check_init(const GridDims& g, int D, const double* rho, const 
                              unsigned long long* bad, hipStream_t s);
 hipError_t launch_macro(int lattice, int precision, const StepArgs& a, int field, double* out);
 
+// Three liquids and the gas (nliquid.hip): constants beyond PhysConst, the
+// step's buffers, and the field codes of its read-out (the TELBM_NL_FIELD_*
+// values of the ABI).
+struct NlConst {
+    double kappa1, kappa2, kappa3, kappa4;  // gradient coefficients of rho and the three liquids
+    double lambda4;                         // double well of liquid 3
+    double m[4];                            // mobility matrix / M: pp, ps, sp, ss
+};
+
+struct NlArgs {
+    GridDims g;
+    PhysConst k;
+    NlConst q;
+    const double* src;  // populations of the state: f, g (phi), h (psi), 3 Q slices of N
+    double* dst;        // populations receiving the next state (part 3: the initial state)
+    double *rho, *phi, *psi, *mux, *mup, *mus;
+    const double* u0;   // part 3: initial velocity ([D][N]) or null
+    hipStream_t stream;
+};
+
+constexpr int kNlRho = 0, kNlPhi = 1, kNlPsi = 2, kNlUx = 3, kNlUy = 4, kNlUz = 5, kNlC1 = 6, kNlC2 = 7,
+              kNlC3 = 8, kNlMuRho = 9, kNlMuPhi = 10, kNlMuPsi = 11, kNlFx = 12, kNlFy = 13, kNlFz = 14;
+
+// part 0: moments (rho, phi, psi), 1: potentials, 2: collision src -> dst,
+// 3: equilibria of (rho, phi, psi, u0) into dst (potentials current).
+hipError_t launch_nl_part(int lattice, const NlArgs& a, int part);
+hipError_t launch_nl_macro(int lattice, const NlArgs& a, int field, double* out);
+
 }  // namespace telbm

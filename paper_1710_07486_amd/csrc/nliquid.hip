@@ -1,0 +1,322 @@
+// nliquid.hip -- three liquids and the gas: the extension of the ternary model
+// to more liquid components that the paper's concluding paragraph names (one
+// more double well in the bulk energy of Eq. 2 and one more gradient term in
+// Eq. 3, here with a second phase field psi).  FP64, periodic boxes, D2Q9 and
+// D3Q27 with the phase fields on the lattice of f; one node per thread in
+// three launches per step (moments, potentials, collision).
+//
+// The model (phi, psi the phase fields, C_L = 1 - C_g the liquid fraction):
+//   C1 = (C_L + phi/chi - psi/chi)/2, C2 = (C_L - phi/chi - psi/chi)/2,
+//   C3 = psi/chi,
+// so psi = 0 is the two-liquid model of the paper.  With
+// nu_m = lambda_{m+1} W(C_m) - kappa_{m+1} lap C_m, W(C) = C (1-C)(1-2C):
+//   mu_rho = (lambda1/2) Psi' - kappa1 lap rho - (nu1 + nu2) / (2 (rho_g - rho_l)),
+//   mu_phi = (nu1 - nu2)/(2 chi),  mu_psi = (2 nu3 - nu1 - nu2)/(2 chi);
+// force -rho grad(mu_rho - cs2 ln rho) - phi grad mu_phi - psi grad mu_psi;
+// Cahn-Hilliard for phi and psi with the 2 x 2 mobility matrix m (times M)
+// that makes the model consistent at liquid-liquid interfaces (the host
+// derives it; telbm_nl_mobility states it): the BGK equilibria of g (phi) and h
+// (psi) take Gamma (m_pp mu_phi + m_ps mu_psi) and Gamma (m_sp mu_phi +
+// m_ss mu_psi).
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace telbm {
+
+namespace {
+
+constexpr int NBX = 64, NBY = 4;
+
+struct NodeAt {
+    int x, y, z;
+    int64_t n;
+    bool in;
+};
+
+__device__ __forceinline__ NodeAt node_at(const GridDims& g) {
+    const int bxc = (g.nx + NBX - 1) / NBX, byc = (g.ny + NBY - 1) / NBY;
+    const int b = blockIdx.x;
+    NodeAt t;
+    t.x = (b % bxc) * NBX + threadIdx.x;
+    t.y = ((b / bxc) % byc) * NBY + threadIdx.y;
+    t.z = b / (bxc * byc);
+    t.in = t.x < g.nx && t.y < g.ny && t.z < g.nz;
+    t.n = ((int64_t)t.z * g.ny + t.y) * g.nx + t.x;
+    return t;
+}
+
+unsigned nl_blocks(const GridDims& g) {
+    return (unsigned)(((g.nx + NBX - 1) / NBX) * ((g.ny + NBY - 1) / NBY) * g.nz);
+}
+
+// pop holds 3 Q slices of N values: f, then g (phi), then h (psi); the state
+// is post-collision at the writing node, so the pull of direction i at x
+// reads slot x - c_i.
+template <int L>
+__global__ __launch_bounds__(NBX* NBY) void k_nl_moments(GridDims g, const double* __restrict__ pop,
+                                                         double* __restrict__ rho, double* __restrict__ phi,
+                                                         double* __restrict__ psi) {
+    using Lt = Lattice<L>;
+    constexpr int Q = Lt::Q;
+    const NodeAt t = node_at(g);
+    if (!t.in) return;
+    const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
+    double r = 0.0, p = 0.0, s = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int64_t m = t.n + nbr_off<L>(nb, i, -1);
+        r += pop[(int64_t)i * g.N + m];
+        p += pop[(int64_t)(Q + i) * g.N + m];
+        s += pop[(int64_t)(2 * Q + i) * g.N + m];
+    }
+    rho[t.n] = r;
+    phi[t.n] = p;
+    psi[t.n] = s;
+}
+
+// Lattice Laplacian (2/cs2) sum_i w_i (v(x + c_i) - v(x)).
+template <int L>
+__device__ __forceinline__ double lap(const Nbr& nb, int64_t n, const double* __restrict__ v) {
+    using Lt = Lattice<L>;
+    const double v0 = v[n];
+    double s = 0.0;
+#pragma unroll
+    for (int i = 1; i < Lt::Q; ++i) s += Lt::w[i] * (v[n + nbr_off<L>(nb, i, +1)] - v0);
+    return 6.0 * s;
+}
+
+// Potentials: mux = mu_rho - cs2 ln rho (the excess whose gradient drives the
+// fluid), mup = mu_phi, mus = mu_psi.
+template <int L, int E>
+__global__ __launch_bounds__(NBX* NBY) void k_nl_chempot(GridDims g, PhysConst k, NlConst q,
+                                                         const double* __restrict__ rho,
+                                                         const double* __restrict__ phi,
+                                                         const double* __restrict__ psi, double* __restrict__ mux,
+                                                         double* __restrict__ mup, double* __restrict__ mus) {
+    const NodeAt t = node_at(g);
+    if (!t.in) return;
+    const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
+    const int64_t n = t.n;
+    const double r = rho[n], p = phi[n], s = psi[n];
+    const double lr = lap<L>(nb, n, rho), lp = lap<L>(nb, n, phi), ls = lap<L>(nb, n, psi);
+    const double cl = 1.0 - (r - k.rho_l) * k.inv_delta;
+    const double lcl = -lr * k.inv_delta;
+    const double c[3] = {0.5 * (cl + (p - s) * k.inv_chi), 0.5 * (cl - (p + s) * k.inv_chi), s * k.inv_chi};
+    const double lc[3] = {0.5 * (lcl + (lp - ls) * k.inv_chi), 0.5 * (lcl - (lp + ls) * k.inv_chi), ls * k.inv_chi};
+    const double lam[3] = {k.lambda2, k.lambda3, q.lambda4};
+    const double kap[3] = {q.kappa2, q.kappa3, q.kappa4};
+    double nu[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) nu[m] = lam[m] * c[m] * (1.0 - c[m]) * (1.0 - 2.0 * c[m]) - kap[m] * lc[m];
+    const double lnr = log(r);
+    const double mu_rho = k.half_lambda1 * eos_psi_prime<E>(k, r, lnr) - q.kappa1 * lr - (nu[0] + nu[1]) * k.inv_2delta;
+    mux[n] = mu_rho - (1.0 / 3.0) * lnr;
+    mup[n] = (nu[0] - nu[1]) * k.inv_2chi;
+    mus[n] = (2.0 * nu[2] - nu[0] - nu[1]) * k.inv_2chi;
+}
+
+// Gradients (1/cs2) sum_i w_i c_i v(x + c_i) of the three potentials.
+template <int L>
+__device__ __forceinline__ void grads(const Nbr& nb, int64_t n, const double* __restrict__ mux,
+                                      const double* __restrict__ mup, const double* __restrict__ mus, double* gx,
+                                      double* gp, double* gs) {
+    using Lt = Lattice<L>;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) gx[d] = gp[d] = gs[d] = 0.0;
+#pragma unroll
+    for (int i = 1; i < Lt::Q; ++i) {
+        const int64_t m = n + nbr_off<L>(nb, i, +1);
+        const double a = Lt::w[i] * mux[m], b = Lt::w[i] * mup[m], c = Lt::w[i] * mus[m];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (Lt::c[i][d] > 0) { gx[d] += a; gp[d] += b; gs[d] += c; }
+            else if (Lt::c[i][d] < 0) { gx[d] -= a; gp[d] -= b; gs[d] -= c; }
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { gx[d] *= 3.0; gp[d] *= 3.0; gs[d] *= 3.0; }
+}
+
+template <int L>
+__device__ __forceinline__ void nl_force(const GridDims& g, const Nbr& nb, int64_t n, double r, double p, double s,
+                                         const double* __restrict__ mux, const double* __restrict__ mup,
+                                         const double* __restrict__ mus, double* F) {
+    double gx[3], gp[3], gs[3];
+    grads<L>(nb, n, mux, mup, mus, gx, gp, gs);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) F[d] = -r * gx[d] - p * gp[d] - s * gs[d];
+    if (Lattice<L>::D == 2) F[2] = 0.0;
+}
+
+// KBC collision of f with exact-difference forcing, BGK of g and h with the
+// mixed potentials; post-collision values stored at the node.
+template <int L>
+__global__ __launch_bounds__(NBX* NBY) void k_nl_collide(GridDims g, PhysConst k, NlConst q,
+                                                         const double* __restrict__ src, double* __restrict__ dst,
+                                                         const double* __restrict__ rho,
+                                                         const double* __restrict__ phi,
+                                                         const double* __restrict__ psi,
+                                                         const double* __restrict__ mux,
+                                                         const double* __restrict__ mup,
+                                                         const double* __restrict__ mus) {
+    using Lt = Lattice<L>;
+    constexpr int Q = Lt::Q;
+    const NodeAt t = node_at(g);
+    if (!t.in) return;
+    const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
+    const int64_t n = t.n;
+    const double r = rho[n], p = phi[n], s = psi[n];
+    double F[3];
+    nl_force<L>(g, nb, n, r, p, s, mux, mup, mus, F);
+    double f[Q];
+    double j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        f[i] = src[(int64_t)i * g.N + n + nbr_off<L>(nb, i, -1)];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) j[d] += Lt::c[i][d] * f[i];
+    }
+    const double ir = 1.0 / r;
+    double u[3] = {j[0] * ir, j[1] * ir, j[2] * ir}, du[3] = {F[0] * ir, F[1] * ir, F[2] * ir};
+    if (Lt::D == 2) u[2] = du[2] = 0.0;
+    collide_f<L, double>(f, r, ir, u, du, k.beta, k.inv_beta, 0.0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dst[(int64_t)i * g.N + n] = f[i];
+    const double up[3] = {u[0] + 0.5 * du[0], u[1] + 0.5 * du[1], u[2] + 0.5 * du[2]};
+    const double mp = mup[n], ms = mus[n];
+    double gg[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) gg[i] = src[(int64_t)(Q + i) * g.N + n + nbr_off<L>(nb, i, -1)];
+    collide_g<L, double>(gg, p, q.m[0] * mp + q.m[1] * ms, up, k.Gamma, k.omega_phi);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dst[(int64_t)(Q + i) * g.N + n] = gg[i];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) gg[i] = src[(int64_t)(2 * Q + i) * g.N + n + nbr_off<L>(nb, i, -1)];
+    collide_g<L, double>(gg, s, q.m[2] * mp + q.m[3] * ms, up, k.Gamma, k.omega_phi);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dst[(int64_t)(2 * Q + i) * g.N + n] = gg[i];
+}
+
+// Equilibria of the initial fields, written where the first pull reads them
+// (slot x - c_i holds direction i of node x).
+template <int L>
+__global__ __launch_bounds__(NBX* NBY) void k_nl_init(GridDims g, PhysConst k, NlConst q,
+                                                      const double* __restrict__ rho, const double* __restrict__ phi,
+                                                      const double* __restrict__ psi,
+                                                      const double* __restrict__ mup,
+                                                      const double* __restrict__ mus,
+                                                      const double* __restrict__ u0, double* __restrict__ pop) {
+    using Lt = Lattice<L>;
+    constexpr int Q = Lt::Q;
+    const NodeAt t = node_at(g);
+    if (!t.in) return;
+    const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
+    const int64_t n = t.n;
+    double u[3] = {0.0, 0.0, 0.0};
+    if (u0) {
+        u[0] = u0[n];
+        u[1] = u0[g.N + n];
+        if (Lt::D == 3) u[2] = u0[2 * g.N + n];
+    }
+    const double mp = mup[n], ms = mus[n];
+    double fd[Q], gg[Q], hh[Q];
+    equilibria<L, double, false>(rho[n], phi[n], q.m[0] * mp + q.m[1] * ms, u, k.Gamma, 0.0, fd, gg);
+    equilibria<L, double, false>(rho[n], psi[n], q.m[2] * mp + q.m[3] * ms, u, k.Gamma, 0.0, fd, hh);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int64_t m = n + nbr_off<L>(nb, i, -1);
+        pop[(int64_t)i * g.N + m] = fd[i];
+        pop[(int64_t)(Q + i) * g.N + m] = gg[i];
+        pop[(int64_t)(2 * Q + i) * g.N + m] = hh[i];
+    }
+}
+
+// One field of the current state (moments and potentials already current).
+template <int L>
+__global__ __launch_bounds__(NBX* NBY) void k_nl_macro(GridDims g, PhysConst k, const double* __restrict__ pop,
+                                                       const double* __restrict__ rho,
+                                                       const double* __restrict__ phi,
+                                                       const double* __restrict__ psi,
+                                                       const double* __restrict__ mux,
+                                                       const double* __restrict__ mup,
+                                                       const double* __restrict__ mus, int field,
+                                                       double* __restrict__ out) {
+    using Lt = Lattice<L>;
+    const NodeAt t = node_at(g);
+    if (!t.in) return;
+    const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
+    const int64_t n = t.n;
+    const double r = rho[n], p = phi[n], s = psi[n];
+    const double cl = 1.0 - (r - k.rho_l) * k.inv_delta;
+    double v = 0.0;
+    switch (field) {
+        case kNlRho: v = r; break;
+        case kNlPhi: v = p; break;
+        case kNlPsi: v = s; break;
+        case kNlC1: v = 0.5 * (cl + (p - s) * k.inv_chi); break;
+        case kNlC2: v = 0.5 * (cl - (p + s) * k.inv_chi); break;
+        case kNlC3: v = s * k.inv_chi; break;
+        case kNlMuRho: v = mux[n] + (1.0 / 3.0) * log(r); break;
+        case kNlMuPhi: v = mup[n]; break;
+        case kNlMuPsi: v = mus[n]; break;
+        default: {
+            double F[3];
+            nl_force<L>(g, nb, n, r, p, s, mux, mup, mus, F);
+            if (field >= kNlFx) {
+                v = F[field - kNlFx];
+            } else {
+                const int d = field - kNlUx;
+                double j = 0.0;
+#pragma unroll
+                for (int i = 0; i < Lt::Q; ++i)
+                    if (Lt::c[i][d]) j += Lt::c[i][d] * pop[(int64_t)i * g.N + n + nbr_off<L>(nb, i, -1)];
+                v = (Lt::D == 2 && d == 2) ? 0.0 : (j + 0.5 * F[d]) / r;
+            }
+        }
+    }
+    out[n] = v;
+}
+
+template <int L>
+hipError_t nl_part_t(const NlArgs& a, int part) {
+    const dim3 blk(NBX, NBY, 1), grd(nl_blocks(a.g), 1, 1);
+    if (part == 0) {
+        k_nl_moments<L><<<grd, blk, 0, a.stream>>>(a.g, a.src, a.rho, a.phi, a.psi);
+    } else if (part == 1) {
+        if (a.k.eos == 0)
+            k_nl_chempot<L, 0><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.q, a.rho, a.phi, a.psi, a.mux, a.mup, a.mus);
+        else if (a.k.eos == 1)
+            k_nl_chempot<L, 1><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.q, a.rho, a.phi, a.psi, a.mux, a.mup, a.mus);
+        else
+            k_nl_chempot<L, 2><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.q, a.rho, a.phi, a.psi, a.mux, a.mup, a.mus);
+    } else if (part == 2) {
+        k_nl_collide<L><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.q, a.src, a.dst, a.rho, a.phi, a.psi, a.mux, a.mup,
+                                                   a.mus);
+    } else if (part == 3) {
+        k_nl_init<L><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.q, a.rho, a.phi, a.psi, a.mup, a.mus, a.u0, a.dst);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int L>
+hipError_t nl_macro_t(const NlArgs& a, int field, double* out) {
+    k_nl_macro<L><<<nl_blocks(a.g), dim3(NBX, NBY, 1), 0, a.stream>>>(a.g, a.k, a.src, a.rho, a.phi, a.psi, a.mux,
+                                                                       a.mup, a.mus, field, out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_nl_part(int lattice, const NlArgs& a, int part) {
+    return lattice == kD2Q9 ? nl_part_t<kD2Q9>(a, part) : nl_part_t<kD3Q27>(a, part);
+}
+
+hipError_t launch_nl_macro(int lattice, const NlArgs& a, int field, double* out) {
+    if (field < 0 || field > kNlFz) return hipErrorInvalidValue;
+    return lattice == kD2Q9 ? nl_macro_t<kD2Q9>(a, field, out) : nl_macro_t<kD3Q27>(a, field, out);
+}
+
+}  // namespace telbm

@@ -210,3 +210,40 @@ def test_missing_library_fails_loudly(monkeypatch):
     # the solver refuses first for want of a GPU where there is none
     with pytest.raises((ImportError, RuntimeError)):
         T.Solver(T.Params(nx=8, ny=8, T=0.03, rho_g=0.1, rho_l=1.0))
+
+
+def test_three_liquid_mobility_matches_oracle(orc):
+    """The library's closed-form mobility matrix (host) against the oracle's
+    product of the concentration mobility with the pseudo-inverse maps."""
+    import numpy as np
+    from paper_1710_07486_amd import nliquid as NL
+    import paper_1710_07486_amd as T
+    rng = np.random.default_rng(11)
+    T0 = orc.temperature_for_ratio(10.0)[0]
+    for _ in range(8):
+        k2, k3, k4 = rng.uniform(0.01, 0.2, 3)
+        p = T.Params(nx=16, ny=16, T=T0, kappa2=k2, kappa3=k3)
+        m_lib = NL.mobility(p, NL.NLParams(kappa4=k4))
+        m_orc = orc.nl_mobility(orc.coexisting_params(10.0, kappa2=k2, kappa3=k3), orc.NLParams(kappa4=k4))
+        assert np.allclose(m_lib, m_orc, rtol=1e-13, atol=1e-15), (m_lib, m_orc)
+
+
+def test_three_liquid_parameters_are_validated(orc):
+    """Accepted on D2Q9 and D3Q27 FP64; rejected in the FP32-mixed form, with
+    walls, with the reduced phase-field lattice and with a kappa <= 0."""
+    from paper_1710_07486_amd import _lib
+    from paper_1710_07486_amd import nliquid as NL
+    import paper_1710_07486_amd as T
+    T0 = orc.temperature_for_ratio(10.0)[0]
+    q = NL.NLParams()
+    assert NL.required_bytes(T.Params(nx=16, ny=16, T=T0), q) >= 2 * 3 * 9 * 256 * 8 + 6 * 256 * 8
+    assert NL.required_bytes(T.Params(lattice=T.D3Q27, nx=8, ny=8, nz=8, T=T0), q) >= 2 * 3 * 27 * 512 * 8
+    bad = [(dict(precision=T.FP32_MIXED), q), (dict(walls=1), q), (dict(glattice=1), q), (dict(kappa3=0.0), q),
+           (dict(), NL.NLParams(kappa4=-0.1)), (dict(), NL.NLParams(lambda4=float("nan")))]
+    for kw, qq in bad:
+        p = T.Params(nx=16, ny=16, T=T0)
+        for k, v in kw.items():
+            setattr(p, k, v)
+        with pytest.raises(T.TelbmError) as e:
+            NL.required_bytes(p, qq)
+        assert e.value.code == _lib.ERR_INVAL, kw
