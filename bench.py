@@ -346,7 +346,50 @@ def copy_probe(nbytes=1 << 30):
     log("copy probe", nbytes, "bytes")
 
 
-LEGS = ("fp32", "2d", "eos", "walls", "reduced", "batch", "surrogate", "cpu")
+def nliquid_throughput(wl3, coex, steps, warmup):
+    """Three liquids and the gas on the 3D workload: its second drop is
+    liquid 3 (psi = chi) and liquid 2 is absent, liquid 3 with liquid 2's
+    lambda and kappa.  FP64, three launches per step (moments, potentials,
+    collision), timed with an event pair around the `steps` timed steps on
+    the solver's stream."""
+    import torch
+    import paper_1710_07486_amd as T_
+    from paper_1710_07486_amd import nliquid as NL
+    from synth import workloads as W
+    T = temperature_of(wl3, None)
+    p = library_params(T, wl3, T_.FP64, None, None, 0)
+    rho, phi, u = W.fields(wl3, coex[0], coex[1])
+    psi = np.maximum(-phi, 0.0)
+    phi = np.maximum(phi, 0.0)
+    s = NL.NLSolver(p, NL.NLParams(lambda4=p.lambda2, kappa4=p.kappa2))
+    s.init_fields(rho, phi, psi, u if np.abs(u).max() > 0 else None)
+    del rho, phi, psi, u
+    s.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.step(steps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    c3 = s.read("c3")
+    finite = bool(np.isfinite(c3).all())
+    per_node = 2.0 * 3 * 27 * 8  # read and write of f, g and h once
+    achieved = per_node * wl3.nodes / (ms * 1e-3) / 1e9
+    out = {"workload": wl3.name + "_liquid3", "lattice": "D3Q27, f + two phase-field lattices",
+           "mlups": round(wl3.nodes / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 4),
+           "steps": steps, "warmup": warmup, "launches_per_step": 3,
+           "whole_step_roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                   "algorithmic_bytes_per_node": per_node},
+           "liquid3_max_c": round(float(c3.max()), 4), "finite": finite}
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+LEGS = ("fp32", "2d", "eos", "walls", "reduced", "nliquid", "batch", "surrogate", "cpu")
 
 
 def main():
@@ -484,6 +527,9 @@ def main():
                                              "vs_full": round(r3r["mlups"] / r3["mlups"], 3),
                                              "bytes_per_update": r3r["bytes_per_update"],
                                              "kernels_ms": {k: round(v, 5) for k, v in r3r["kernels_ms"].items()}}
+    if "nliquid" not in skip:
+        result["three_liquids"] = nliquid_throughput(wl3, r3["coex"], args.steps, args.warmup)
+        log("three liquids", result["three_liquids"])
     if "batch" not in skip:
         log("batched form")
         # the batch workload (sides 256..1024), and small lattices (32..128)
