@@ -53,7 +53,7 @@ TRAFFIC = {
 def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.hpp", "node_ops.hpp", "lattice.hpp"):
+    for f in ("kernels.hip", "kernels.hpp", "node_ops.hpp", "lattice.hpp", "nliquid.hip"):
         with open(os.path.join(ROOT, "paper_1710_07486_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

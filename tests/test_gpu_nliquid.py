@@ -8,7 +8,9 @@ oracle pin's flat liquid-1 / liquid-3 interface, the GPU within 1e-9 of the
 oracle and its absent liquid 2 below the density perturbation.
 Neumann angles: a lens of liquid 1 between liquids 2 and 3 (no gas) at
 twice the oracle pin's size relaxes to the angles of the closed-form
-tensions within the paper's 3 degrees.
+tensions within the paper's 3 degrees.  Full size: the benchmark's 256^3
+three-liquid state on sampled tile-edge nodes within 1e-10 of the field
+scales.
 """
 import numpy as np
 import pytest
@@ -150,3 +152,45 @@ def test_three_liquid_lens_neumann_angles(orc):
     for a in ang:
         for ph in ("1", "2", "g"):
             assert abs(a[ph] - pred[ph]) < 3.0, (ph, a[ph], pred[ph])
+
+
+def test_three_liquid_full_size_sampled(orc):
+    """The benchmark's three-liquid 256^3 state (the D3Q27 collision of two
+    drops, the second one liquid 3) in its launch configuration, checked on
+    48 nodes on tile edges after 4 steps: after k steps a node depends on
+    the initial fields within radius 3k + 3, so the oracle on a periodic
+    window of half-width 3k + 4 reproduces that node exactly."""
+    from paper_1710_07486_amd import nliquid as NL
+    from synth import workloads as W
+    from tests.test_gpu_parity import _window, tile_edge_samples
+    k = 4
+    wl = W.collision_3d(256, radius=32, ratio=800.0, v_rel=0.04, kappa2=0.2, kappa3=0.2, lattice_ratio=True)
+    po = orc.workload_params(wl)
+    rho, phi2, u = W.fields(wl, po.rho_g, po.rho_l)
+    psi = np.maximum(-phi2, 0.0)
+    phi = np.maximum(phi2, 0.0)
+    del phi2
+    nl = orc.NLParams(lambda4=po.lambda2, kappa4=po.kappa2)
+    say("three liquids, full size", wl.shape)
+    names = ("rho", "phi", "psi", "ux", "uy", "uz")
+    with NL.NLSolver(lib_params(po, 1, wl.shape), NL.NLParams(lambda4=nl.lambda4, kappa4=nl.kappa4)) as s:
+        s.init_fields(rho, phi, psi, u)
+        s.step(k)
+        g = {f: s.read(f) for f in names}
+    rng = np.random.default_rng(8)
+    r = 3 * k + 4
+    pts = tile_edge_samples(wl, rng, 48)
+    scale = {"rho": po.rho_l, "phi": po.chi, "psi": po.chi, "ux": 0.05, "uy": 0.05, "uz": 0.05}
+    worst = {n: 0.0 for n in names}
+    for (z, y, x) in pts:
+        sub = orc.Params(**{**po.__dict__, "nx": 2 * r + 1, "ny": 2 * r + 1, "nz": 2 * r + 1})
+        win = [np.ascontiguousarray(_window(a, (z, y, x), r)) for a in (rho, phi, psi, u)]
+        st = orc.NLState(sub, nl, *win)
+        st.run(k)
+        f = st.fields()
+        ref = {"rho": f["rho"], "phi": f["phi"], "psi": f["psi"], "ux": f["u"][0], "uy": f["u"][1], "uz": f["u"][2]}
+        for n in names:
+            worst[n] = max(worst[n], abs(g[n][z, y, x] - ref[n][r, r, r]) / scale[n])
+    print("sampled max error / scale", len(pts), "nodes", worst, flush=True)
+    for n, v in worst.items():
+        assert v <= 1e-10, (n, v)
