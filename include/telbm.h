@@ -107,8 +107,8 @@ extern "C" {
  *                      n.grad psi = -cot(theta) |grad_t psi|, theta the contact
  *                      angle measured in the phase where psi is large; for the
  *                      chemical potentials the ghost repeats the wall row.
- *                      theta_* in (0, pi); pi/2 is neutral.  Needs ny >= 2 and
- *                      is not available in the batched form (TELBM_ERR_INVAL).
+ *                      theta_* in (0, pi); pi/2 is neutral.  Needs ny >= 2
+ *                      (TELBM_ERR_INVAL).
  *  glattice            lattice of the phase-field populations g, which the
  *                      paper leaves open: 0 the lattice of f; 1 its rest and
  *                      axis directions (D2Q5 / D3Q7) with axis weights 1/6 and
@@ -251,7 +251,9 @@ const char *telbm_last_error(const telbm_solver *s);
 /* sizes, temperature, free-energy and transport parameters.  Each phase of  */
 /* a step is one persistent launch over a work list of (instance, tile)      */
 /* items; runs of an even number of steps are replayed from captured HIP     */
-/* graphs.  Diagnostics are not collected in this form.                     */
+/* graphs.  Members may have walls (each with its own contact angles) beside */
+/* periodic ones; the reduced phase-field lattice is not available here      */
+/* (TELBM_ERR_INVAL).  Diagnostics are not collected in this form.          */
 /* ------------------------------------------------------------------------- */
 typedef struct telbm_batch telbm_batch;
 

@@ -60,7 +60,9 @@ struct TileShape {
 constexpr TileShape kShapes[] = {{64, 1}, {64, 2}, {64, 4}, {64, 8}, {32, 8}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
-template <int L, typename T, int TBX, int TBY, int PHASE>
+// WB: some member has walls (the instance for that case; members without
+// walls take no wall branch, since every check reads the member's own flag).
+template <int L, typename T, int TBX, int TBY, int PHASE, bool WB>
 __global__ __launch_bounds__(TBX* TBY) void kb_phase(const InstDesc* __restrict__ inst,
                                                      const int2* __restrict__ work, int nwork, int cur,
                                                      int ref) {
@@ -84,7 +86,7 @@ __global__ __launch_bounds__(TBX* TBY) void kb_phase(const InstDesc* __restrict_
         if (PHASE == 2) {
             // two lanes per node (uniform control flow for the lane exchange)
             double dv[kDiag];
-            tile_collide<L, T, TBX * TBY>(d.g, d.k, (const T*)d.pop[cur], (T*)d.pop[1 - cur], rho_ref, rho,
+            tile_collide<L, T, TBX * TBY, false, WB>(d.g, d.k, (const T*)d.pop[cur], (T*)d.pop[1 - cur], rho_ref, rho,
                                                d.phi, d.mux, d.mup, bx * TBX, by * TBY, bz, TBX, TBY,
                                                threadIdx.y * TBX + threadIdx.x, false, dv);
             continue;
@@ -92,46 +94,53 @@ __global__ __launch_bounds__(TBX* TBY) void kb_phase(const InstDesc* __restrict_
         const int x = bx * TBX + threadIdx.x, y = by * TBY + threadIdx.y, z = bz;
         if (x >= d.g.nx || y >= d.g.ny || z >= d.g.nz) continue;
         if (PHASE == 0) {
-            node_moments<L, T>(d.g, (const T*)d.pop[cur], rho_ref, rho, d.phi, x, y, z);
+            node_moments<L, T, WB>(d.g, (const T*)d.pop[cur], rho_ref, rho, d.phi, x, y, z);
         } else {
             // the members may differ in their equation of state
-            if (d.k.eos == 0) node_chempot<L, 0>(d.g, d.k, rho, d.phi, d.mux, d.mup, x, y, z);
-            else if (d.k.eos == 1) node_chempot<L, 1>(d.g, d.k, rho, d.phi, d.mux, d.mup, x, y, z);
-            else node_chempot<L, 2>(d.g, d.k, rho, d.phi, d.mux, d.mup, x, y, z);
+            if (d.k.eos == 0) node_chempot<L, 0, WB>(d.g, d.k, rho, d.phi, d.mux, d.mup, x, y, z);
+            else if (d.k.eos == 1) node_chempot<L, 1, WB>(d.g, d.k, rho, d.phi, d.mux, d.mup, x, y, z);
+            else node_chempot<L, 2, WB>(d.g, d.k, rho, d.phi, d.mux, d.mup, x, y, z);
         }
     }
 }
 
-template <int L, typename T, int S>
-static hipError_t launch_shape(int phase, int grid, hipStream_t st, const InstDesc* inst, const int2* work,
-                               int nwork, int cur, int ref) {
+template <int L, typename T, int S, bool WB>
+static void launch_shape_w(int phase, int grid, hipStream_t st, const InstDesc* inst, const int2* work, int nwork,
+                           int cur, int ref) {
     constexpr int TBX = kShapes[S].bx, TBY = kShapes[S].by;
     const dim3 blk(TBX, TBY, 1);
-    if (phase == 0) kb_phase<L, T, TBX, TBY, 0><<<grid, blk, 0, st>>>(inst, work, nwork, cur, ref);
-    else if (phase == 1) kb_phase<L, T, TBX, TBY, 1><<<grid, blk, 0, st>>>(inst, work, nwork, cur, ref);
-    else kb_phase<L, T, TBX, TBY, 2><<<grid, blk, 0, st>>>(inst, work, nwork, cur, ref);
+    if (phase == 0) kb_phase<L, T, TBX, TBY, 0, WB><<<grid, blk, 0, st>>>(inst, work, nwork, cur, ref);
+    else if (phase == 1) kb_phase<L, T, TBX, TBY, 1, WB><<<grid, blk, 0, st>>>(inst, work, nwork, cur, ref);
+    else kb_phase<L, T, TBX, TBY, 2, WB><<<grid, blk, 0, st>>>(inst, work, nwork, cur, ref);
+}
+
+template <int L, typename T, int S>
+static hipError_t launch_shape(int phase, int grid, hipStream_t st, const InstDesc* inst, const int2* work,
+                               int nwork, int cur, int ref, bool walls) {
+    if (walls) launch_shape_w<L, T, S, true>(phase, grid, st, inst, work, nwork, cur, ref);
+    else launch_shape_w<L, T, S, false>(phase, grid, st, inst, work, nwork, cur, ref);
     return hipGetLastError();
 }
 
 template <int L, typename T>
 static hipError_t launch_batch_lt(int shape, int phase, int grid, hipStream_t st, const InstDesc* inst,
-                                  const int2* work, int nwork, int cur, int ref) {
+                                  const int2* work, int nwork, int cur, int ref, bool walls) {
     switch (shape) {
-        case 0: return launch_shape<L, T, 0>(phase, grid, st, inst, work, nwork, cur, ref);
-        case 1: return launch_shape<L, T, 1>(phase, grid, st, inst, work, nwork, cur, ref);
-        case 2: return launch_shape<L, T, 2>(phase, grid, st, inst, work, nwork, cur, ref);
-        case 3: return launch_shape<L, T, 3>(phase, grid, st, inst, work, nwork, cur, ref);
-        default: return launch_shape<L, T, 4>(phase, grid, st, inst, work, nwork, cur, ref);
+        case 0: return launch_shape<L, T, 0>(phase, grid, st, inst, work, nwork, cur, ref, walls);
+        case 1: return launch_shape<L, T, 1>(phase, grid, st, inst, work, nwork, cur, ref, walls);
+        case 2: return launch_shape<L, T, 2>(phase, grid, st, inst, work, nwork, cur, ref, walls);
+        case 3: return launch_shape<L, T, 3>(phase, grid, st, inst, work, nwork, cur, ref, walls);
+        default: return launch_shape<L, T, 4>(phase, grid, st, inst, work, nwork, cur, ref, walls);
     }
 }
 
 static hipError_t launch_batch(int lattice, int precision, int shape, int phase, int grid, hipStream_t st,
-                               const InstDesc* inst, const int2* work, int nwork, int cur, int ref) {
+                               const InstDesc* inst, const int2* work, int nwork, int cur, int ref, bool walls) {
     if (lattice == kD2Q9)
-        return precision ? launch_batch_lt<kD2Q9, float>(shape, phase, grid, st, inst, work, nwork, cur, ref)
-                         : launch_batch_lt<kD2Q9, double>(shape, phase, grid, st, inst, work, nwork, cur, ref);
-    return precision ? launch_batch_lt<kD3Q27, float>(shape, phase, grid, st, inst, work, nwork, cur, ref)
-                     : launch_batch_lt<kD3Q27, double>(shape, phase, grid, st, inst, work, nwork, cur, ref);
+        return precision ? launch_batch_lt<kD2Q9, float>(shape, phase, grid, st, inst, work, nwork, cur, ref, walls)
+                         : launch_batch_lt<kD2Q9, double>(shape, phase, grid, st, inst, work, nwork, cur, ref, walls);
+    return precision ? launch_batch_lt<kD3Q27, float>(shape, phase, grid, st, inst, work, nwork, cur, ref, walls)
+                     : launch_batch_lt<kD3Q27, double>(shape, phase, grid, st, inst, work, nwork, cur, ref, walls);
 }
 
 }  // namespace telbm
@@ -144,6 +153,7 @@ using namespace telbm;
 struct telbm_batch {
     int count;
     int lattice, precision;
+    bool walls;  // some member has walls
     std::vector<telbm_params> p;
     std::vector<InstDesc> desc;  // host copy
     InstDesc* desc_dev;
@@ -226,9 +236,8 @@ int check_params(const telbm_params* p, int count, std::string* why) {
             *why = "all instances of a batch share lattice and precision";
             return TELBM_ERR_INVAL;
         }
-        if (p[i].walls || p[i].glattice) {
-            *why = "the batched form runs periodic boxes on the full phase-field lattice only (instance " +
-                   std::to_string(i) + ")";
+        if (p[i].glattice) {
+            *why = "the batched form runs the full phase-field lattice only (instance " + std::to_string(i) + ")";
             return TELBM_ERR_INVAL;
         }
         size_t b;
@@ -265,6 +274,12 @@ PhysConst physconst(const telbm_params& p, double rg, double rl, double C) {
     k.Gamma = p.mobility / (p.tau_phi - 0.5);
     k.eos = p.eos;
     k.att = eos_attraction(eos_of(p), p.T);
+    if (p.walls) {
+        k.cot_rho[0] = cos(p.theta_rho_lo) / sin(p.theta_rho_lo);
+        k.cot_rho[1] = cos(p.theta_rho_hi) / sin(p.theta_rho_hi);
+        k.cot_phi[0] = cos(p.theta_phi_lo) / sin(p.theta_phi_lo);
+        k.cot_phi[1] = cos(p.theta_phi_hi) / sin(p.theta_phi_hi);
+    }
     return k;
 }
 
@@ -329,8 +344,9 @@ int build_fused(telbm_batch* b) {
 hipError_t fused_launches(telbm_batch* b, hipStream_t st, int cur, int ref, int fp, bool partial) {
     for (int e = 0; e < 3; ++e) {
         if (b->fwork_cnt[e] == 0) continue;
-        hipError_t r = launch_batch_fused2(b->precision, e, 0, st, b->fdesc_dev, b->fwork_dev + b->fwork_off[e],
-                                           b->fwork_cnt[e], cur, ref, fp, partial ? 1 : 0);
+        hipError_t r = launch_batch_fused2(b->precision, e, b->walls, st, b->fdesc_dev,
+                                           b->fwork_dev + b->fwork_off[e], b->fwork_cnt[e], cur, ref, fp,
+                                           partial ? 1 : 0);
         if (r != hipSuccess) return r;
     }
     return hipSuccess;
@@ -345,7 +361,7 @@ hipError_t enqueue_step(telbm_batch* b, hipStream_t st, int cur, int ref) {
     const int grid = b->cus * b->wg_per_cu;
     for (int phase = 0; phase < 3; ++phase) {
         hipError_t e = launch_batch(b->lattice, b->precision, b->shape, phase, grid, st, b->desc_dev, b->work_dev,
-                                    b->nwork, cur, ref);
+                                    b->nwork, cur, ref, b->walls);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -456,6 +472,8 @@ int telbm_batch_create(const telbm_params* p, int count, void* arena, size_t byt
     b->count = count;
     b->lattice = p[0].lattice;
     b->precision = p[0].precision;
+    b->walls = false;
+    for (int i = 0; i < count; ++i) b->walls = b->walls || p[i].walls != 0;
     b->p.assign(p, p + count);
     b->desc.resize(count);
     char* a = (char*)arena;
@@ -488,7 +506,7 @@ int telbm_batch_create(const telbm_params* p, int count, void* arena, size_t byt
         const int Q = q.lattice == TELBM_D2Q9 ? 9 : 27;
         const int64_t N = (int64_t)q.nx * q.ny * q.nz;
         const size_t s = q.precision == TELBM_FP32_MIXED ? 4 : 8;
-        d.g = GridDims{q.nx, q.ny, q.nz, 0, N};
+        d.g = GridDims{q.nx, q.ny, q.nz, q.walls, N};
         d.k = physconst(q, rg, rl, C);
         d.pop[0] = a + o;
         o += al(2 * Q * N * s);

@@ -695,12 +695,13 @@ __global__ __launch_bounds__(BX* FBY) void k_collide_fused2(GridDims g, PhysCons
                                 rho_final, partials, diag, b % bxc, b / bxc);
 }
 
-// The fused 2D step of a batch of periodic lattices in one launch: one
+// The fused 2D step of a batch of lattices in one launch (WB: some of them
+// have walls; each instance's own flag decides for it): one
 // workgroup per (instance, 64 x 8 tile) item of the work list, consecutive
 // items on one XCD.  State: cur (populations), ref (FP32 reference
 // densities), fp (densities, phase field and inbox of the current step),
 // partial (those densities still to be completed from the inbox).
-template <typename T, int E>
+template <typename T, int E, bool WB>
 __global__ __launch_bounds__(BX* FBY) void k_batch_fused2(const FusedDesc* __restrict__ inst,
                                                           const int2* __restrict__ work, int nwork, int cur,
                                                           int ref, int fp, int partial) {
@@ -711,31 +712,33 @@ __global__ __launch_bounds__(BX* FBY) void k_batch_fused2(const FusedDesc* __res
     const FusedDesc& d = inst[it.x];
     const int bxc = (d.g.nx + BX - 1) / BX;
     const bool mixed = Deviation<T>::on;
-    fused2_tile<T, E, false, false>(sh, d.g, d.k, (const T*)d.pop[cur], (T*)d.pop[1 - cur],
+    fused2_tile<T, E, false, WB>(sh, d.g, d.k, (const T*)d.pop[cur], (T*)d.pop[1 - cur],
                                     mixed ? d.rhob[ref] : nullptr, d.xr[fp], d.xp[fp],
                                     partial ? d.inbox[fp] : nullptr, d.xr[1 - fp], d.xp[1 - fp], d.inbox[1 - fp],
                                     mixed ? d.rhob[1 - ref] : nullptr, nullptr, 0, it.y % bxc, it.y / bxc);
 }
 
-template <typename T>
-static hipError_t launch_batch_fused2_t(int eos, int grid, hipStream_t st, const FusedDesc* inst, const int2* work,
-                                        int nwork, int cur, int ref, int fp, int partial) {
+template <typename T, bool WB>
+static hipError_t launch_batch_fused2_t(int eos, hipStream_t st, const FusedDesc* inst, const int2* work, int nwork,
+                                        int cur, int ref, int fp, int partial) {
     const dim3 blk(BX, FBY, 1);
-    (void)grid;
-    grid = nwork;  // one workgroup per item
+    const int grid = nwork;  // one workgroup per item
     switch (eos) {
-        case 0: k_batch_fused2<T, 0><<<grid, blk, 0, st>>>(inst, work, nwork, cur, ref, fp, partial); break;
-        case 1: k_batch_fused2<T, 1><<<grid, blk, 0, st>>>(inst, work, nwork, cur, ref, fp, partial); break;
-        case 2: k_batch_fused2<T, 2><<<grid, blk, 0, st>>>(inst, work, nwork, cur, ref, fp, partial); break;
+        case 0: k_batch_fused2<T, 0, WB><<<grid, blk, 0, st>>>(inst, work, nwork, cur, ref, fp, partial); break;
+        case 1: k_batch_fused2<T, 1, WB><<<grid, blk, 0, st>>>(inst, work, nwork, cur, ref, fp, partial); break;
+        case 2: k_batch_fused2<T, 2, WB><<<grid, blk, 0, st>>>(inst, work, nwork, cur, ref, fp, partial); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_batch_fused2(int precision, int eos, int grid, hipStream_t st, const FusedDesc* inst,
+hipError_t launch_batch_fused2(int precision, int eos, bool walls, hipStream_t st, const FusedDesc* inst,
                                const int2* work, int nwork, int cur, int ref, int fp, int partial) {
-    return precision ? launch_batch_fused2_t<float>(eos, grid, st, inst, work, nwork, cur, ref, fp, partial)
-                     : launch_batch_fused2_t<double>(eos, grid, st, inst, work, nwork, cur, ref, fp, partial);
+    if (walls)
+        return precision ? launch_batch_fused2_t<float, true>(eos, st, inst, work, nwork, cur, ref, fp, partial)
+                         : launch_batch_fused2_t<double, true>(eos, st, inst, work, nwork, cur, ref, fp, partial);
+    return precision ? launch_batch_fused2_t<float, false>(eos, st, inst, work, nwork, cur, ref, fp, partial)
+                     : launch_batch_fused2_t<double, false>(eos, st, inst, work, nwork, cur, ref, fp, partial);
 }
 
 int fused_tiles_x(int nx) { return (nx + BX - 1) / BX; }

@@ -57,9 +57,9 @@ struct FusedDesc {
 
 // One launch of the fused 2D step over an (instance, tile) work list (tile
 // index = by * fused_tiles_x(nx) + bx on 64 x 8 tiles, one workgroup per
-// item; `grid` is unused) whose instances all have the equation of state
-// `eos`.
-hipError_t launch_batch_fused2(int precision, int eos, int grid, hipStream_t st, const FusedDesc* inst,
+// item) whose instances all have the equation of state `eos`; `walls`: some
+// instance has walls (the kernel instance with the wall logic).
+hipError_t launch_batch_fused2(int precision, int eos, bool walls, hipStream_t st, const FusedDesc* inst,
                                const int2* work, int nwork, int cur, int ref, int fp, int partial);
 int fused_tiles_x(int nx);
 

@@ -148,9 +148,9 @@ def test_null_arguments_are_rejected(lib):
 
 
 def test_wall_parameters_are_validated(orc):
-    """Walls: accepted on D2Q9 and D3Q27 in both precisions; rejected with
-    ny < 2, with contact angles outside (0, pi), with walls other than 0/1,
-    and in the batched form."""
+    """Walls: accepted on D2Q9 and D3Q27 in both precisions and in the
+    batched form (members with and without walls); rejected with ny < 2, with
+    contact angles outside (0, pi) and with walls other than 0/1."""
     import math
     import paper_1710_07486_amd as T
     from paper_1710_07486_amd import _lib
@@ -168,8 +168,9 @@ def test_wall_parameters_are_validated(orc):
         with pytest.raises(T.TelbmError) as e:
             T.required_bytes(p)
         assert e.value.code == _lib.ERR_INVAL, kw
+    assert batch_bytes([T.Params(nx=16, ny=16, T=T0, walls=1), T.Params(nx=24, ny=16, T=T0)]) > 0
     with pytest.raises(T.TelbmError):
-        batch_bytes([T.Params(nx=16, ny=16, T=T0, walls=1)])
+        batch_bytes([T.Params(nx=16, ny=16, T=T0, walls=1, theta_rho_lo=0.0)])
 
 
 def test_reduced_phase_field_lattice_parameters(orc):

@@ -4,7 +4,8 @@ solver sums the next step's moments per tile row and completes them at tile
 edges, the batch sums them per node, so the two agree to round-off), for
 every grid size and across graph replays; every tile shape of the batch gives
 the same bits; one instance is checked against the FP64 oracle; the FP32 form
-against the FP64 form."""
+against the FP64 form; members in channels between wetting walls beside
+periodic ones match their single runs in every mode and the oracle."""
 import numpy as np
 import pytest
 
@@ -268,3 +269,74 @@ def test_full_size_batch_modes_fp32_vs_fp64():
             errs = [float(np.abs(b.read(i, "rho") - ref[i]).max() / np.abs(ref[i]).max()) for i in range(len(p32))]
         print("mode", mode, "max relative density error over instances", max(errs), flush=True)
         assert all(np.isfinite(errs)) and max(errs) < 1e-5, (mode, max(errs))
+
+
+WALL_ANGLES = [(60.0, 70.0, 120.0, 100.0), (100.0, 110.0, 75.0, 60.0)]
+
+
+def wall_instances(orc, precision=0):
+    """Two periodic lens members and two members in channels between wetting
+    walls (caps of both liquids on the walls), each with its own angles."""
+    import math
+    import paper_1710_07486_amd as T
+    out = instances(orc, precision, sizes=[(48, 40), (37, 50)])
+    for (nx, ny), ang in zip([(64, 32), (100, 37)], WALL_ANGLES):
+        wl = W.wall_drops(nx, ny, radius=min(12.0, 0.3 * nx), ratio=100.0)
+        po = orc.coexisting_params(wl.ratio, **wl.physics())
+        th = dict(zip(("theta_rho_lo", "theta_phi_lo", "theta_rho_hi", "theta_phi_hi"), map(math.radians, ang)))
+        for key, v in th.items():
+            setattr(po, key, v)
+        po.walls = 1
+        rho, phi, u = W.fields(wl, po.rho_g, po.rho_l)
+        pl = T.Params(lattice=0, precision=precision, nx=nx, ny=ny, nz=1, T=po.T, rho_g=po.rho_g, rho_l=po.rho_l,
+                      lambda1=po.lambda1, lambda2=po.lambda2, lambda3=po.lambda3, kappa1=po.kappa1,
+                      kappa2=po.kappa2, kappa3=po.kappa3, chi=po.chi, nu=po.nu, mobility=po.mobility,
+                      tau_phi=po.tau_phi, walls=1, **th)
+        out.append((po, pl, rho, phi, u))
+    return out
+
+
+@pytest.mark.parametrize("mode,precision", [(0, 0), (1, 0), (2, 0), (1, 1), (2, 1)])
+def test_batch_with_walls_matches_single(orc, mode, precision):
+    """Members with and without walls in one batch: each equals its single
+    run (4 eager steps, then two graph chunks of 10) in every mode."""
+    from paper_1710_07486_amd.batch import Batch
+    inst = wall_instances(orc, precision)
+    steps = 24
+    say("batch with walled members, mode", mode, "precision", precision)
+    singles = [run_single(pl, r, p, u, steps) for (_, pl, r, p, u) in inst]
+    with Batch([pl for (_, pl, *_r) in inst]) as b:
+        b.set_mode(mode)
+        for i, (_, pl, r, p, u) in enumerate(inst):
+            b.init_fields(i, r, p, u)
+        b.step(4)
+        b.step(20)
+        for i in range(len(inst)):
+            for k in ("rho", "phi", "ux", "uy"):
+                got, ref = b.read(i, k), singles[i][k]
+                err = np.abs(got - ref).max() / np.abs(ref).max()
+                assert err <= 1e-12, (i, k, err)
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_batch_wall_member_vs_oracle(orc, mode):
+    """A walled member of a mixed batch against the FP64 oracle (1e-10)."""
+    from paper_1710_07486_amd.batch import Batch
+    inst = wall_instances(orc, 0)
+    steps = 40
+    po, pl, rho, phi, u = inst[3]
+    say("batch walled member vs oracle, mode", mode)
+    uu = u if np.abs(u).max() > 0 else None
+    st = orc.State(po, rho, phi, uu)
+    st.run(steps)
+    fo = st.fields()
+    with Batch([p for (_, p, *_r) in inst]) as b:
+        b.set_mode(mode)
+        for i, (_, p, r, ph, uv) in enumerate(inst):
+            b.init_fields(i, r, ph, uv)
+        b.step(steps)
+        got = {k: b.read(3, k) for k in ("rho", "phi", "ux")}
+    assert np.isfinite(fo["rho"]).all()
+    for key, ref in (("rho", fo["rho"]), ("phi", fo["phi"]), ("ux", fo["u"][0])):
+        err = np.abs(got[key] - ref).max() / max(np.abs(ref).max(), 1e-14)
+        assert err < 1e-10, (key, err)
