@@ -496,7 +496,7 @@ def test_fp32_mixed_errors_at_equilibrium(orc):
     # interfaces, where it is an interface displacement times the density's
     # slope: its bar follows from the shape bar, a displacement of 1e-4 of
     # the radius at twice the steepest relative slope of the FP64 field.
-    gy, gx = np.gradient(a["rho"])
+    gy, gx = np.gradient(a["rho"][0])
     slope = float(np.hypot(gx, gy).max() / np.abs(a["rho"]).max())
     e_rho_bar = 2.0 * 1e-4 * 40.0 * slope
     print("max-norm bar from the shape bar", e_rho_bar, flush=True)
