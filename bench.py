@@ -40,13 +40,17 @@ METRIC = "ternary ELBM MLUPS & % HBM roofline; FP32-mixed vs FP64 at stated erro
 # HBM bytes per launch of the dominant kernel of each step, from two rocprofv3
 # counter passes (FETCH_SIZE, then WRITE_SIZE, each scaled by what the same
 # counter reads for a 1 GiB device copy in the same run: x2.0 and x1.0),
-# valid only for the kernel sources whose hash is recorded with them.  D3Q27
-# 256^3 (profiles/collide_d3q27_256_latticeratio800_kernel_stats_and_traffic.md):
-# the FP64 collision of a step without diagnostics and the FP32 pair-split
-# collision.
+# valid only for the kernel sources whose hash is recorded with them
+# (profiles/step_kernels_d3q27_256_d2q9_1024_stats_and_traffic.md): the D3Q27
+# 256^3 FP64 collision of a step without diagnostics, the FP32 pair-split
+# collision, the D2Q9 1024^2 one-launch steps, and the three kernels of a
+# three-liquid D3Q27 step together.
 TRAFFIC = {
-    "d3q27_fp64_collide": {"bytes_per_launch": 17112599717, "sources_sha256_16": "aa7168eeb5c56cc1"},
-    "d3q27_fp32_collide": {"bytes_per_launch": 9748663362, "sources_sha256_16": "aa7168eeb5c56cc1"},
+    "d3q27_fp64_collide": {"bytes_per_launch": 17108558083, "sources_sha256_16": "89d097fbf86f0597"},
+    "d3q27_fp32_collide": {"bytes_per_launch": 9831435944, "sources_sha256_16": "89d097fbf86f0597"},
+    "d2q9_fp64_step": {"bytes_per_launch": 348358079, "sources_sha256_16": "89d097fbf86f0597"},
+    "d2q9_fp32_step": {"bytes_per_launch": 213685162, "sources_sha256_16": "89d097fbf86f0597"},
+    "d3q27_three_liquid_step": {"bytes_per_launch": 40762905466, "sources_sha256_16": "89d097fbf86f0597"},
 }
 
 
@@ -381,7 +385,10 @@ def nliquid_throughput(wl3, coex, steps, warmup):
            "steps": steps, "warmup": warmup, "launches_per_step": 3,
            "whole_step_roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                                   "algorithmic_bytes_per_node": per_node},
+                                   "algorithmic_bytes_per_node": per_node,
+                                   "traffic": traffic_of("d3q27_three_liquid_step"),
+                                   "traffic_unit": "HBM bytes per step, the three kernels (rocprofv3 FETCH_SIZE + "
+                                                   "WRITE_SIZE, copy-calibrated)"},
            "liquid3_max_c": round(float(c3.max()), 4), "finite": finite}
     s.close()
     del s
