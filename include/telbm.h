@@ -451,7 +451,9 @@ typedef struct telbm_nl telbm_nl;
 int telbm_nl_mobility(const telbm_params *p, const telbm_nl_params *q, double *m);
 
 /* Bytes of device arena for these parameters (two population buffers of
- * 3 Q N doubles and six N-double fields, each 256-byte aligned). */
+ * 3 Q N doubles, six N-double fields and, for D3Q27, two sets of partial
+ * next-step moments of 3 N pairs with their tile inboxes; each part 256-byte
+ * aligned). */
 int telbm_nl_required_bytes(const telbm_params *p, const telbm_nl_params *q, size_t *bytes);
 
 /* Create, borrowing `device_arena` (>= required bytes, 256-byte aligned) for
@@ -469,7 +471,10 @@ int telbm_nl_set_stream(telbm_nl *s, void *stream);
 int telbm_nl_init_fields(telbm_nl *s, const double *rho, const double *phi, const double *psi, const double *u,
                          int on_device);
 
-/* Advance n >= 0 time steps (asynchronous): moments, potentials, collision. */
+/* Advance n >= 0 time steps (asynchronous): moments, potentials, collision.
+ * On D3Q27 the collision also leaves the next step's moments as partial sums,
+ * which the next step (or a read) completes in the same pass that computes the
+ * potentials, instead of a pass over the populations. */
 int telbm_nl_step(telbm_nl *s, int64_t n);
 
 /* One TELBM_NL_FIELD_* of the current state into `out` (N doubles). Synchronises. */

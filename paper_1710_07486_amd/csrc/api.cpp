@@ -61,6 +61,7 @@ struct telbm_nl {
     void* pop[2];
     int cur;            // pop[cur] holds the state
     bool aux_valid;     // rho, phi, psi and the potentials belong to the state
+    bool partial;       // D3Q27: the state's moments are held as partial sums (a.partA ...)
     int64_t steps;
     std::string err;
 };
@@ -404,16 +405,22 @@ int nl_validate(const telbm_params* p, const telbm_nl_params* q, std::string* wh
 }
 
 struct NlLayout {
-    size_t pop, aux, total;
+    size_t pop, aux, part, inbox, total;
 };
 
+// Two population buffers of 3 Q N doubles, six N-double fields and, for
+// D3Q27, two sets of partial next-step moments (3 N pairs) with their inboxes.
 NlLayout nl_layout(const telbm_params& p) {
     const int64_t N = (int64_t)p.nx * p.ny * p.nz;
     const int Q = p.lattice == TELBM_D2Q9 ? 9 : 27;
+    const GridDims g{p.nx, p.ny, p.nz, 0, N};
     NlLayout L;
     L.pop = align_up((size_t)3 * Q * N * sizeof(double));
     L.aux = align_up((size_t)N * sizeof(double));
-    L.total = 2 * L.pop + 6 * L.aux;
+    const bool d3 = p.lattice == TELBM_D3Q27;
+    L.part = d3 ? align_up((size_t)N * 3 * 2 * sizeof(double)) : 0;
+    L.inbox = d3 ? align_up(inbox3_doubles(g) * sizeof(double)) : 0;
+    L.total = 2 * L.pop + 6 * L.aux + 2 * (L.part + L.inbox);
     return L;
 }
 
@@ -425,17 +432,20 @@ int nl_fail(telbm_nl* s, int code, const std::string& msg) {
 hipError_t nl_launch(telbm_nl* s, int part) {
     NlArgs a = s->a;
     a.src = (const double*)s->pop[s->cur];
-    a.dst = (double*)s->pop[part == 3 ? s->cur : 1 - s->cur];
+    a.dst = (double*)s->pop[part == 3 ? s->cur : 1 - s->cur];  // part 3 writes the state itself
     return launch_nl_part(s->p.lattice, a, part);
 }
 
-// Moments and potentials of the current state.
+// Moments (completed from the partial sums the last D3Q27 collision left, or
+// pulled from the populations) and potentials of the current state.
 int nl_ensure_aux(telbm_nl* s) {
     if (s->aux_valid) return TELBM_OK;
-    hipError_t e = nl_launch(s, 0);
-    if (e == hipSuccess) e = nl_launch(s, 1);
+    // partial sums (D3Q27): completion and potentials in one column pass
+    hipError_t e = s->partial ? nl_launch(s, 6) : nl_launch(s, 0);
+    if (e == hipSuccess && !s->partial) e = nl_launch(s, 1);
     if (e != hipSuccess) return nl_fail(s, TELBM_ERR_DEVICE, std::string("three-liquid launch: ") + hipGetErrorString(e));
     s->aux_valid = true;
+    s->partial = false;
     return TELBM_OK;
 }
 
@@ -776,10 +786,16 @@ int telbm_nl_create(const telbm_params* p, const telbm_nl_params* q, void* devic
     s->pop[1] = base + L.pop;
     double** f[6] = {&a.rho, &a.phi, &a.psi, &a.mux, &a.mup, &a.mus};
     for (int i = 0; i < 6; ++i) *f[i] = (double*)(base + 2 * L.pop + i * L.aux);
+    char* nx = base + 2 * L.pop + 6 * L.aux;
+    a.partA = L.part ? (double*)nx : nullptr;
+    a.inboxA = L.part ? (double*)(nx + L.part) : nullptr;
+    a.partB = L.part ? (double*)(nx + L.part + L.inbox) : nullptr;
+    a.inboxB = L.part ? (double*)(nx + 2 * L.part + L.inbox) : nullptr;
     a.u0 = nullptr;
     a.stream = nullptr;
     s->cur = 0;
     s->aux_valid = false;
+    s->partial = false;
     s->steps = 0;
     *out = s;
     return TELBM_OK;
@@ -814,6 +830,7 @@ int telbm_nl_init_fields(telbm_nl* s, const double* rho, const double* phi, cons
     if (e == hipSuccess) e = hipStreamSynchronize(a.stream);
     if (e != hipSuccess) return nl_fail(s, TELBM_ERR_DEVICE, std::string("init staging: ") + hipGetErrorString(e));
     s->aux_valid = false;
+    s->partial = false;
     if (nbad[0] || nbad[1])
         return nl_fail(s, TELBM_ERR_UNSTABLE, std::to_string(nbad[0] + nbad[1]) + " nodes with unusable initial values");
     // potentials of the initial fields, then the equilibria into pop[cur]
@@ -823,6 +840,7 @@ int telbm_nl_init_fields(telbm_nl* s, const double* rho, const double* phi, cons
     a.u0 = nullptr;
     if (e != hipSuccess) return nl_fail(s, TELBM_ERR_DEVICE, std::string("init launch: ") + hipGetErrorString(e));
     s->aux_valid = false;
+    s->partial = false;
     s->steps = 0;
     return TELBM_OK;
 }
@@ -832,10 +850,13 @@ int telbm_nl_step(telbm_nl* s, int64_t n) {
     for (int64_t i = 0; i < n; ++i) {
         int rc = nl_ensure_aux(s);
         if (rc) return rc;
-        hipError_t e = nl_launch(s, 2);
+        // D3Q27: the collision also leaves the next moments (no moment pass)
+        const bool d3 = s->p.lattice == TELBM_D3Q27;
+        hipError_t e = nl_launch(s, d3 ? 4 : 2);
         if (e != hipSuccess) return nl_fail(s, TELBM_ERR_DEVICE, std::string("collision launch: ") + hipGetErrorString(e));
         s->cur = 1 - s->cur;
         s->aux_valid = false;
+        s->partial = d3;
         s->steps += 1;
     }
     return TELBM_OK;

@@ -96,6 +96,10 @@ struct NlArgs {
     double* dst;        // populations receiving the next state (part 3: the initial state)
     double *rho, *phi, *psi, *mux, *mup, *mus;
     const double* u0;   // part 3: initial velocity ([D][N]) or null
+    // D3Q27: next-step moments as three partial sums per node, (rho, phi) in
+    // partA and (psi, 0) in partB (3 N pairs each), with their inboxes
+    // (inbox3_doubles each): part 4 writes them, part 5 completes them
+    double *partA, *inboxA, *partB, *inboxB;
     hipStream_t stream;
 };
 
@@ -103,7 +107,10 @@ constexpr int kNlRho = 0, kNlPhi = 1, kNlPsi = 2, kNlUx = 3, kNlUy = 4, kNlUz = 
               kNlC3 = 8, kNlMuRho = 9, kNlMuPhi = 10, kNlMuPsi = 11, kNlFx = 12, kNlFy = 13, kNlFz = 14;
 
 // part 0: moments (rho, phi, psi), 1: potentials, 2: collision src -> dst,
-// 3: equilibria of (rho, phi, psi, u0) into dst (potentials current).
+// 3: equilibria of (rho, phi, psi, u0) into dst (potentials current);
+// D3Q27 only: 4: collision src -> dst that also leaves the next moments as
+// partial sums, 5: completion of those into rho, phi, psi, 6: completion and
+// potentials in one z-column pass.
 hipError_t launch_nl_part(int lattice, const NlArgs& a, int part);
 hipError_t launch_nl_macro(int lattice, const NlArgs& a, int field, double* out);
 

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
+#include "next_sums.hpp"
 
 namespace telbm {
 
@@ -86,20 +87,12 @@ __device__ __forceinline__ double lap(const Nbr& nb, int64_t n, const double* __
     return 6.0 * s;
 }
 
-// Potentials: mux = mu_rho - cs2 ln rho (the excess whose gradient drives the
-// fluid), mup = mu_phi, mus = mu_psi.
-template <int L, int E>
-__global__ __launch_bounds__(NBX* NBY) void k_nl_chempot(GridDims g, PhysConst k, NlConst q,
-                                                         const double* __restrict__ rho,
-                                                         const double* __restrict__ phi,
-                                                         const double* __restrict__ psi, double* __restrict__ mux,
-                                                         double* __restrict__ mup, double* __restrict__ mus) {
-    const NodeAt t = node_at(g);
-    if (!t.in) return;
-    const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
-    const int64_t n = t.n;
-    const double r = rho[n], p = phi[n], s = psi[n];
-    const double lr = lap<L>(nb, n, rho), lp = lap<L>(nb, n, phi), ls = lap<L>(nb, n, psi);
+// Potentials of one node from its fields and their lattice Laplacians:
+// mx = mu_rho - cs2 ln rho (the excess whose gradient drives the fluid),
+// mp = mu_phi, ms = mu_psi.
+template <int E>
+__device__ __forceinline__ void nl_mu(const PhysConst& k, const NlConst& q, double r, double p, double s, double lr,
+                                      double lp, double ls, double& mx, double& mp, double& ms) {
     const double cl = 1.0 - (r - k.rho_l) * k.inv_delta;
     const double lcl = -lr * k.inv_delta;
     const double c[3] = {0.5 * (cl + (p - s) * k.inv_chi), 0.5 * (cl - (p + s) * k.inv_chi), s * k.inv_chi};
@@ -111,9 +104,92 @@ __global__ __launch_bounds__(NBX* NBY) void k_nl_chempot(GridDims g, PhysConst k
     for (int m = 0; m < 3; ++m) nu[m] = lam[m] * c[m] * (1.0 - c[m]) * (1.0 - 2.0 * c[m]) - kap[m] * lc[m];
     const double lnr = log(r);
     const double mu_rho = k.half_lambda1 * eos_psi_prime<E>(k, r, lnr) - q.kappa1 * lr - (nu[0] + nu[1]) * k.inv_2delta;
-    mux[n] = mu_rho - (1.0 / 3.0) * lnr;
-    mup[n] = (nu[0] - nu[1]) * k.inv_2chi;
-    mus[n] = (2.0 * nu[2] - nu[0] - nu[1]) * k.inv_2chi;
+    mx = mu_rho - (1.0 / 3.0) * lnr;
+    mp = (nu[0] - nu[1]) * k.inv_2chi;
+    ms = (2.0 * nu[2] - nu[0] - nu[1]) * k.inv_2chi;
+}
+
+template <int L, int E>
+__global__ __launch_bounds__(NBX* NBY) void k_nl_chempot(GridDims g, PhysConst k, NlConst q,
+                                                         const double* __restrict__ rho,
+                                                         const double* __restrict__ phi,
+                                                         const double* __restrict__ psi, double* __restrict__ mux,
+                                                         double* __restrict__ mup, double* __restrict__ mus) {
+    const NodeAt t = node_at(g);
+    if (!t.in) return;
+    const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
+    const int64_t n = t.n;
+    nl_mu<E>(k, q, rho[n], phi[n], psi[n], lap<L>(nb, n, rho), lap<L>(nb, n, phi), lap<L>(nb, n, psi), mux[n],
+             mup[n], mus[n]);
+}
+
+// D3Q27: the potentials along z-columns from the partial sums the collision
+// left (as the two-liquid k_chempot_col<true>): the block walks NCZ planes of
+// its BX x BY tile, completes rho, phi, psi of the tile and a one-node x-y
+// halo of each plane into LDS (three planes held at a time) and takes the
+// Laplacians there, in the lattice order of lap(); the tile's completed
+// fields are written too.
+constexpr int NCZ = 16;
+constexpr int NPX = BX + 2, NPY = BY + 2, NPN = NPX * NPY;
+
+template <int E>
+__global__ __launch_bounds__(BX* BY) void k_nl_chempot_col(GridDims g, PhysConst k, NlConst q,
+                                                           const double* __restrict__ partA,
+                                                           const double* __restrict__ inboxA,
+                                                           const double* __restrict__ partB,
+                                                           const double* __restrict__ inboxB,
+                                                           double* __restrict__ rho, double* __restrict__ phi,
+                                                           double* __restrict__ psi, double* __restrict__ mux,
+                                                           double* __restrict__ mup, double* __restrict__ mus) {
+    using Lt = Lattice<kD3Q27>;
+    __shared__ double sr[3][NPN], sp[3][NPN], ss[3][NPN];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + BY - 1) / BY;
+    const int bx = b % bxc, rest = b / bxc, by = rest % byc, bzc = rest / byc;
+    const int x0 = bx * BX, y0 = by * BY, z0 = bzc * NCZ;
+    const int tid = threadIdx.y * BX + threadIdx.x;
+    auto load_plane = [&](int slot, int z) {
+        const int zw = wrap_any(z, g.nz);
+        for (int e = tid; e < NPN; e += BX * BY) {
+            const int gx = wrap_any(x0 - 1 + e % NPX, g.nx), gy = wrap_any(y0 - 1 + e / NPX, g.ny);
+            const int64_t n = ((int64_t)zw * g.ny + gy) * g.nx + gx;
+            double r, p, s, zero;
+            next3_complete(g, partA, inboxA, gx, gy, zw, n, r, p);
+            next3_complete(g, partB, inboxB, gx, gy, zw, n, s, zero);
+            sr[slot][e] = r;
+            sp[slot][e] = p;
+            ss[slot][e] = s;
+        }
+    };
+    load_plane(0, z0 - 1);
+    load_plane(1, z0);
+    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
+    const int c = (threadIdx.y + 1) * NPX + threadIdx.x + 1;
+    for (int zz = 0; zz < NCZ; ++zz) {
+        const int z = z0 + zz;
+        if (z >= g.nz) break;  // uniform over the block
+        load_plane((zz + 2) % 3, z + 1);
+        __syncthreads();
+        const int below = zz % 3, centre = (zz + 1) % 3, above = (zz + 2) % 3;
+        if (x < g.nx && y < g.ny) {
+            const double r0 = sr[centre][c], p0 = sp[centre][c], s0 = ss[centre][c];
+            double lr = 0.0, lp = 0.0, ls = 0.0;
+#pragma unroll
+            for (int i = 1; i < Lt::Q; ++i) {
+                const int sl = Lt::c[i][2] == 0 ? centre : (Lt::c[i][2] > 0 ? above : below);
+                const int o = c + Lt::c[i][1] * NPX + Lt::c[i][0];
+                lr += Lt::w[i] * (sr[sl][o] - r0);
+                lp += Lt::w[i] * (sp[sl][o] - p0);
+                ls += Lt::w[i] * (ss[sl][o] - s0);
+            }
+            const int64_t n = ((int64_t)z * g.ny + y) * g.nx + x;
+            nl_mu<E>(k, q, r0, p0, s0, 6.0 * lr, 6.0 * lp, 6.0 * ls, mux[n], mup[n], mus[n]);
+            rho[n] = r0;
+            phi[n] = p0;
+            psi[n] = s0;
+        }
+        __syncthreads();  // the next plane overwrites the slot just read as `below`
+    }
 }
 
 // Gradients (1/cs2) sum_i w_i c_i v(x + c_i) of the three potentials.
@@ -150,22 +226,20 @@ __device__ __forceinline__ void nl_force(const GridDims& g, const Nbr& nb, int64
 }
 
 // KBC collision of f with exact-difference forcing, BGK of g and h with the
-// mixed potentials; post-collision values stored at the node.
-template <int L>
-__global__ __launch_bounds__(NBX* NBY) void k_nl_collide(GridDims g, PhysConst k, NlConst q,
-                                                         const double* __restrict__ src, double* __restrict__ dst,
-                                                         const double* __restrict__ rho,
-                                                         const double* __restrict__ phi,
-                                                         const double* __restrict__ psi,
-                                                         const double* __restrict__ mux,
-                                                         const double* __restrict__ mup,
-                                                         const double* __restrict__ mus) {
+// mixed potentials, for node (x, y, z): post-collision values stored at the
+// node when `active`, and handed to the next-moment sinks (sa: f and g, sb: h;
+// NoSink when the moments are taken by a separate pass).
+template <int L, typename SA, typename SB>
+__device__ __forceinline__ void nl_collide_node(const GridDims& g, const PhysConst& k, const NlConst& q,
+                                                const double* __restrict__ src, double* __restrict__ dst,
+                                                const double* __restrict__ rho, const double* __restrict__ phi,
+                                                const double* __restrict__ psi, const double* __restrict__ mux,
+                                                const double* __restrict__ mup, const double* __restrict__ mus,
+                                                int x, int y, int z, bool active, SA& sa, SB& sb) {
     using Lt = Lattice<L>;
     constexpr int Q = Lt::Q;
-    const NodeAt t = node_at(g);
-    if (!t.in) return;
-    const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
-    const int64_t n = t.n;
+    const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
+    const int64_t n = ((int64_t)z * g.ny + y) * g.nx + x;
     const double r = rho[n], p = phi[n], s = psi[n];
     double F[3];
     nl_force<L>(g, nb, n, r, p, s, mux, mup, mus, F);
@@ -181,21 +255,106 @@ __global__ __launch_bounds__(NBX* NBY) void k_nl_collide(GridDims g, PhysConst k
     double u[3] = {j[0] * ir, j[1] * ir, j[2] * ir}, du[3] = {F[0] * ir, F[1] * ir, F[2] * ir};
     if (Lt::D == 2) u[2] = du[2] = 0.0;
     collide_f<L, double>(f, r, ir, u, du, k.beta, k.inv_beta, 0.0);
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) dst[(int64_t)i * g.N + n] = f[i];
+        for (int i = 0; i < Q; ++i) dst[(int64_t)i * g.N + n] = f[i];
+    }
+    sa.template post_f<L, double>(f, r);
     const double up[3] = {u[0] + 0.5 * du[0], u[1] + 0.5 * du[1], u[2] + 0.5 * du[2]};
     const double mp = mup[n], ms = mus[n];
     double gg[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) gg[i] = src[(int64_t)(Q + i) * g.N + n + nbr_off<L>(nb, i, -1)];
     collide_g<L, double>(gg, p, q.m[0] * mp + q.m[1] * ms, up, k.Gamma, k.omega_phi);
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) dst[(int64_t)(Q + i) * g.N + n] = gg[i];
+        for (int i = 0; i < Q; ++i) dst[(int64_t)(Q + i) * g.N + n] = gg[i];
+    }
+    sa.template post_g<L, double, Q>(gg);
 #pragma unroll
     for (int i = 0; i < Q; ++i) gg[i] = src[(int64_t)(2 * Q + i) * g.N + n + nbr_off<L>(nb, i, -1)];
     collide_g<L, double>(gg, s, q.m[2] * mp + q.m[3] * ms, up, k.Gamma, k.omega_phi);
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) dst[(int64_t)(2 * Q + i) * g.N + n] = gg[i];
+        for (int i = 0; i < Q; ++i) dst[(int64_t)(2 * Q + i) * g.N + n] = gg[i];
+    }
+    sb.template post_f<L, double>(gg, s);
+}
+
+template <int L>
+__global__ __launch_bounds__(NBX* NBY) void k_nl_collide(GridDims g, PhysConst k, NlConst q,
+                                                         const double* __restrict__ src, double* __restrict__ dst,
+                                                         const double* __restrict__ rho,
+                                                         const double* __restrict__ phi,
+                                                         const double* __restrict__ psi,
+                                                         const double* __restrict__ mux,
+                                                         const double* __restrict__ mup,
+                                                         const double* __restrict__ mus) {
+    const NodeAt t = node_at(g);
+    if (!t.in) return;
+    NoSink a, b;
+    nl_collide_node<L>(g, k, q, src, dst, rho, phi, psi, mux, mup, mus, t.x, t.y, t.z, true, a, b);
+}
+
+// D3Q27: the collision that also leaves the next step's moments, as the
+// two-liquid FP64 collision does (k_collide_next3): the block (a BX x BY tile
+// of one z plane) sums its post-collision values for the nodes they stream
+// to, (rho, phi) in one NextSink and (psi, 0) in another, then writes the
+// tile nodes' sums per source plane to partA / partB and the ring's to the
+// neighbouring tiles' inboxes.  k_nl_complete adds them up.
+__global__ __launch_bounds__(BX* BY) void k_nl_collide_next(GridDims g, PhysConst k, NlConst q,
+                                                          const double* __restrict__ src, double* __restrict__ dst,
+                                                          const double* __restrict__ rho,
+                                                          const double* __restrict__ phi,
+                                                          const double* __restrict__ psi,
+                                                          const double* __restrict__ mux,
+                                                          const double* __restrict__ mup,
+                                                          const double* __restrict__ mus, double* __restrict__ partA,
+                                                          double* __restrict__ inboxA, double* __restrict__ partB,
+                                                          double* __restrict__ inboxB) {
+    using Sink = NextSink<kD3Q27, BY>;
+    __shared__ double asum[Sink::SUM], aside[Sink::SIDE], bsum[Sink::SUM], bside[Sink::SIDE];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + BY - 1) / BY;
+    const int bx = b % bxc, rest = b / bxc, by = rest % byc, bz = rest / byc;
+    const int x0 = bx * BX, y0 = by * BY;
+    const int W = min(BX, g.nx - x0), H = min(BY, g.ny - y0);
+    const int tid = threadIdx.y * BX + threadIdx.x;
+    // the second field of sb carries nothing: its sums are zero (read by the
+    // gathers after the barrier below, never written by the collisions)
+    for (int e = tid; e < Sink::SUM / 2; e += BX * BY) bsum[Sink::SUM / 2 + e] = 0.0;
+    for (int e = tid; e < Sink::SIDE / 2; e += BX * BY) bside[Sink::SIDE / 2 + e] = 0.0;
+    {
+        // every lane runs a collision (lanes past a ragged edge on the tile's
+        // last node, without stores) so that the sinks' shuffles see whole rows
+        const int lx = min((int)threadIdx.x, W - 1), ly = min((int)threadIdx.y, H - 1);
+        const bool active = (int)threadIdx.x < W && (int)threadIdx.y < H;
+        Sink sa{asum, aside, (int)threadIdx.x, (int)threadIdx.y, W, 0};
+        Sink sb{bsum, bside, (int)threadIdx.x, (int)threadIdx.y, W, 0};
+        nl_collide_node<kD3Q27>(g, k, q, src, dst, rho, phi, psi, mux, mup, mus, x0 + lx, y0 + ly, bz, active, sa,
+                                sb);
+    }
+    __syncthreads();
+    next3_store<false>(g, Sink{asum, aside, 0, 0, W, 0}, partA, inboxA, x0, y0, W, H, bz, tid);
+    next3_store<false>(g, Sink{bsum, bside, 0, 0, W, 0}, partB, inboxB, x0, y0, W, H, bz, tid);
+}
+
+// The moments (rho, phi, psi) of the state k_nl_collide_next left, from its
+// partial sums and inbox entries.
+__global__ __launch_bounds__(NBX* NBY) void k_nl_complete(GridDims g, const double* __restrict__ partA,
+                                                          const double* __restrict__ inboxA,
+                                                          const double* __restrict__ partB,
+                                                          const double* __restrict__ inboxB,
+                                                          double* __restrict__ rho, double* __restrict__ phi,
+                                                          double* __restrict__ psi) {
+    const NodeAt t = node_at(g);
+    if (!t.in) return;
+    double r, p, s, zero;
+    next3_complete(g, partA, inboxA, t.x, t.y, t.z, t.n, r, p);
+    next3_complete(g, partB, inboxB, t.x, t.y, t.z, t.n, s, zero);
+    rho[t.n] = r;
+    phi[t.n] = p;
+    psi[t.n] = s;
 }
 
 // Equilibria of the initial fields, written where the first pull reads them
@@ -295,6 +454,25 @@ hipError_t nl_part_t(const NlArgs& a, int part) {
                                                    a.mus);
     } else if (part == 3) {
         k_nl_init<L><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.q, a.rho, a.phi, a.psi, a.mup, a.mus, a.u0, a.dst);
+    } else if (part == 4 && L == kD3Q27) {
+        if (!a.partA || !a.inboxA || !a.partB || !a.inboxB) return hipErrorInvalidValue;
+        const unsigned tiles = (unsigned)(((a.g.nx + BX - 1) / BX) * ((a.g.ny + BY - 1) / BY) * a.g.nz);
+        k_nl_collide_next<<<tiles, dim3(BX, BY, 1), 0, a.stream>>>(a.g, a.k, a.q, a.src, a.dst, a.rho, a.phi, a.psi,
+                                                                   a.mux, a.mup, a.mus, a.partA, a.inboxA, a.partB,
+                                                                   a.inboxB);
+    } else if (part == 5 && L == kD3Q27) {
+        if (!a.partA || !a.inboxA || !a.partB || !a.inboxB) return hipErrorInvalidValue;
+        k_nl_complete<<<grd, blk, 0, a.stream>>>(a.g, a.partA, a.inboxA, a.partB, a.inboxB, a.rho, a.phi, a.psi);
+    } else if (part == 6 && L == kD3Q27) {
+        if (!a.partA || !a.inboxA || !a.partB || !a.inboxB) return hipErrorInvalidValue;
+        const unsigned cb = (unsigned)(((a.g.nx + BX - 1) / BX) * ((a.g.ny + BY - 1) / BY) * ((a.g.nz + NCZ - 1) / NCZ));
+#define TELBM_NL_COL(EV)                                                                                          \
+    k_nl_chempot_col<EV><<<cb, dim3(BX, BY, 1), 0, a.stream>>>(a.g, a.k, a.q, a.partA, a.inboxA, a.partB, a.inboxB, \
+                                                               a.rho, a.phi, a.psi, a.mux, a.mup, a.mus)
+        if (a.k.eos == 0) TELBM_NL_COL(0);
+        else if (a.k.eos == 1) TELBM_NL_COL(1);
+        else TELBM_NL_COL(2);
+#undef TELBM_NL_COL
     } else {
         return hipErrorInvalidValue;
     }
