@@ -107,9 +107,9 @@ Layout layout_of(const telbm_params& p) {
     L.n_phi = fz ? 2 : 1;
     L.n_inbox = fz ? 2 : 0;
     L.inbox = fz ? align_up(inbox_doubles(g) * sizeof(double)) : 0;
-    // D3Q27 FP64: three partial next-step moment pairs per node and their inboxes
+    // D3Q27 FP64: partial next-step moments and their inboxes
     const bool next3 = !fz && p.precision == TELBM_FP64;
-    L.part3 = next3 ? align_up((size_t)N * 3 * 2 * sizeof(double)) : 0;
+    L.part3 = next3 ? align_up(part3_doubles(g) * sizeof(double)) : 0;
     L.inbox3 = next3 ? align_up(inbox3_doubles(g) * sizeof(double)) : 0;
     L.partials = align_up((size_t)collide_blocks(g) * kDiag * sizeof(double));
     L.diag = align_up(16 * sizeof(double));
@@ -409,7 +409,7 @@ struct NlLayout {
 };
 
 // Two population buffers of 3 Q N doubles, six N-double fields and, for
-// D3Q27, two sets of partial next-step moments (3 N pairs) with their inboxes.
+// D3Q27, two sets of partial next-step moments with their inboxes.
 NlLayout nl_layout(const telbm_params& p) {
     const int64_t N = (int64_t)p.nx * p.ny * p.nz;
     const int Q = p.lattice == TELBM_D2Q9 ? 9 : 27;
@@ -418,7 +418,7 @@ NlLayout nl_layout(const telbm_params& p) {
     L.pop = align_up((size_t)3 * Q * N * sizeof(double));
     L.aux = align_up((size_t)N * sizeof(double));
     const bool d3 = p.lattice == TELBM_D3Q27;
-    L.part = d3 ? align_up((size_t)N * 3 * 2 * sizeof(double)) : 0;
+    L.part = d3 ? align_up(part3_doubles(g) * sizeof(double)) : 0;
     L.inbox = d3 ? align_up(inbox3_doubles(g) * sizeof(double)) : 0;
     L.total = 2 * L.pop + 6 * L.aux + 2 * (L.part + L.inbox);
     return L;

@@ -156,8 +156,8 @@ __global__ __launch_bounds__(BX* BY) void k_chempot(GridDims g, PhysConst k, con
 constexpr int CZ = 16;
 constexpr int CPX = BX + 2, CPY = BY + 2, CPN = CPX * CPY;
 
-// With PART the densities come as the three partial sums per node and the
-// inbox entries that the previous D3Q27 FP64 collision (k_collide_next3) left;
+// With PART the densities come as the partial sums and inbox entries that
+// the previous D3Q27 FP64 collision (k_collide_next3) left;
 // the kernel completes them while staging (see next3_complete) and also writes
 // the completed rho, phi of its nodes.
 template <bool PART, int E, bool W>
@@ -542,14 +542,16 @@ __global__ __launch_bounds__(FIX_THREADS) void k_dens_complete2(GridDims g, doub
 
 // ---------------------------------------------------------------------------
 // D3Q27 FP64 collision that also leaves the next step's moments.  The block
-// (a BX x BY tile of one z plane) runs the collision of its nodes and sums its
-// post-collision values for the nodes they stream to: with the lane shuffles
-// of NextSink over the nine (c_y, c_z) groups, then per target plane z + c_z
-// for the tile and its one-node ring.  A node's moments are thus split over
-// three partial sums, one per source plane (part[k][n], k = c_z + 1, (rho,
-// phi) pairs), plus, for nodes on a tile edge, inbox entries from the
-// neighbouring tiles of each source plane (inbox[(z * 3 + k) * tiles + tile]).
-// The chemical-potential pass completes them while it stages the densities
+// walks a z-column of ZC planes of a BX x BY tile: per plane it runs the
+// collision of the tile's nodes and sums their post-collision values for the
+// nodes they stream to, with the lane shuffles of NextSink over the nine
+// (c_y, c_z) groups, then per target plane z + c_z for the tile and its
+// one-node ring.  The sums for the column's own planes accumulate in LDS
+// over the three source planes and are stored once a plane is complete: one
+// (rho, phi) pair per node (part), plus inbox entries for the tile-edge nodes
+// of the neighbouring tiles; only the columns' end planes receive sums from
+// the next column (the boundary parts; layout at next3_complete).  The
+// chemical-potential pass completes them while it stages the densities
 // (k_chempot_col<true>), so the moment pass over all populations is not run.
 // ---------------------------------------------------------------------------
 // DIAG: the instance that also reduces the health diagnostics (launched on the
@@ -563,28 +565,37 @@ __global__ __launch_bounds__(BX* BY) void k_collide_next3(GridDims g, PhysConst 
                                                           double* __restrict__ inbox, double* __restrict__ partials,
                                                           int diag) {
     using Sink = NextSink<kD3Q27, BY>;
-    __shared__ double nsum[Sink::SUM], nside[Sink::SIDE];
+    // two sets of sums, used by alternate planes: a plane's collisions then
+    // never overwrite the sums that slower threads still gather from, and one
+    // barrier per plane suffices
+    __shared__ double nsum[2][Sink::SUM], nside[2][Sink::SIDE], acc[COL_ACC];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + BY - 1) / BY;
-    const int bx = b % bxc, rest = b / bxc, by = rest % byc, bz = rest / byc;
-    const int x0 = bx * BX, y0 = by * BY;
+    const int bx = b % bxc, rest = b / bxc, by = rest % byc, bc = rest / byc;
+    const int x0 = bx * BX, y0 = by * BY, z0 = bc * ZC, z1 = min(g.nz, z0 + ZC);
     const int W = min(BX, g.nx - x0), H = min(BY, g.ny - y0);
-    const int tid = threadIdx.y * BX + threadIdx.x;
     double dv[kDiag] = {0, 0, 0, 0, 0, 0, INFINITY, INFINITY, -INFINITY, 0};
-    {
-        // every lane runs a collision (lanes past a ragged edge on the tile's
-        // last node, without stores) so that the sink's shuffles see whole rows
-        const int lx = min((int)threadIdx.x, W - 1), ly = min((int)threadIdx.y, H - 1);
-        const bool active = (int)threadIdx.x < W && (int)threadIdx.y < H;
-        const GlobalAux aux{rho, phi, mux, mup};
-        const int wy = (WALL && g.walls) ? (y0 + ly == 0 ? -1 : (y0 + ly == g.ny - 1 ? 1 : 0)) : 0;
-        Sink sink{nsum, nside, (int)threadIdx.x, (int)threadIdx.y, W, wy};
-        node_collide_sink<kD3Q27, double, GlobalAux, Sink, WALL, RG>(g, k, src, dst, nullptr, aux, x0 + lx, y0 + ly,
-                                                                  bz, DIAG, dv, active, sink);
+    const GlobalAux aux{rho, phi, mux, mup};
+    for (int z = z0; z < z1; ++z) {
+        int tx = threadIdx.x, ty = threadIdx.y;
+        opaque_thread_index(tx, ty);
+        {
+            // every lane runs a collision (lanes past a ragged edge on the
+            // tile's last node, without stores) so that the sink's shuffles
+            // see whole rows
+            const int lx = min(tx, W - 1), ly = min(ty, H - 1);
+            const bool active = tx < W && ty < H;
+            const int wy = (WALL && g.walls) ? (y0 + ly == 0 ? -1 : (y0 + ly == g.ny - 1 ? 1 : 0)) : 0;
+            const GridDims gz = opaque_stride(g);
+            Sink sink{nsum[(z - z0) & 1], nside[(z - z0) & 1], tx, ty, W, wy};
+            node_collide_sink<kD3Q27, double, GlobalAux, Sink, WALL, RG>(gz, k, src, dst, nullptr, aux, x0 + lx,
+                                                                      y0 + ly, z, DIAG, dv, active, sink);
+        }
+        __syncthreads();
+        next3_col_plane<WALL>(g, Sink{nsum[(z - z0) & 1], nside[(z - z0) & 1], 0, 0, W, 0}, acc, part, inbox, x0,
+                              y0, W, H, z, z0, z1, tx, ty);
     }
     if (DIAG) diag_block_reduce(dv, partials);
-    __syncthreads();
-    next3_store<WALL>(g, Sink{nsum, nside, 0, 0, W, 0}, part, inbox, x0, y0, W, H, bz, tid);
 }
 
 // Deterministic second pass over the block partials (one workgroup).
@@ -738,9 +749,13 @@ unsigned fused_tiles(const GridDims& g) { return (unsigned)(((g.nx + BX - 1) / B
 
 size_t inbox_doubles(const GridDims& g) { return (size_t)fused_tiles(g) * INBOX * 2; }
 
+size_t part3_doubles(const GridDims& g) { return 2 * ((size_t)g.N + 2 * (size_t)zcols(g.nz) * g.nx * g.ny); }
+
 size_t inbox3_doubles(const GridDims& g) {
-    return (size_t)g.nz * 3 * ((g.nx + BX - 1) / BX) * ((g.ny + BY - 1) / BY) * INBOX3 * 2;
+    return 2 * (size_t)(g.nz + 2 * zcols(g.nz)) * (size_t)tiles3(g) * INBOX3;
 }
+
+unsigned column_blocks(const GridDims& g) { return (unsigned)(tiles3(g) * zcols(g.nz)); }
 
 static inline unsigned col_blocks(const GridDims& g) {
     return (unsigned)(((g.nx + BX - 1) / BX) * ((g.ny + BY - 1) / BY) * ((g.nz + CZ - 1) / CZ));
@@ -808,8 +823,9 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
         if (L != kD3Q27 || Deviation<T>::on || !a.part3 || !a.inbox3) return hipErrorInvalidValue;
         auto* sp = (const double*)a.src;
         auto* dp = (double*)a.dst;
+        const unsigned nb3 = column_blocks(a.g);
 #define TELBM_NEXT3(WV, RGV, DV)                                                                               \
-    k_collide_next3<WV, RGV, DV><<<grd, blk, 0, a.stream>>>(a.g, a.k, sp, dp, a.rho, a.phi, a.mux, a.mup, a.part3, \
+    k_collide_next3<WV, RGV, DV><<<nb3, blk, 0, a.stream>>>(a.g, a.k, sp, dp, a.rho, a.phi, a.mux, a.mup, a.part3, \
                                                             a.inbox3, a.partials, a.diag)
         if (a.diag) {
             if (w && rg) TELBM_NEXT3(true, true, true);
@@ -823,7 +839,7 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
             else TELBM_NEXT3(false, false, false);
         }
 #undef TELBM_NEXT3
-        if (a.diag) k_diag_final<<<1, 256, 0, a.stream>>>(a.partials, (int)grd.x, a.diag_out);
+        if (a.diag) k_diag_final<<<1, 256, 0, a.stream>>>(a.partials, (int)nb3, a.diag_out);
     } else if (part == 4) {
         if (L != kD2Q9 || a.g.nz != 1 || !a.inbox_in) return hipErrorInvalidValue;
         k_dens_complete2<<<fused_tiles(a.g), FIX_THREADS, 0, a.stream>>>(a.g, a.rho, a.phi, a.inbox_in);

@@ -35,9 +35,10 @@ struct StepArgs {
     // Part 4 completes rho / phi in place from inbox_in.
     const double* inbox_in;
     double *rho_next, *phi_next, *inbox_out, *rho_final;
-    // D3Q27 FP64: next-step moments as three partial sums per node (3 N
-    // (rho, phi) pairs) and their inbox entries (part 6 writes, part 5
-    // completes them while computing the chemical potentials)
+    // D3Q27 FP64: next-step moments as partial sums (part3_doubles: the sums
+    // of each node's own z-column and of the neighbouring columns at column
+    // ends) and their inbox entries (part 6 writes, part 5 completes them
+    // while computing the chemical potentials)
     double *part3, *inbox3;
     double* partials;    // per-block diagnostic partials
     double* diag_out;    // final diagnostics (kDiag doubles)
@@ -66,7 +67,13 @@ int fused_tiles_x(int nx);
 unsigned collide_blocks(const GridDims& g);
 unsigned fused_tiles(const GridDims& g);        // D2Q9 tiles of the fused step
 size_t inbox_doubles(const GridDims& g);        // size of one inbox array
-size_t inbox3_doubles(const GridDims& g);       // size of StepArgs::inbox3
+// D3Q27 collisions that leave the next moments walk z-columns of kZc planes
+// per workgroup.  Sizes of the partial sums and their inboxes, and the
+// workgroups of such a collision.
+constexpr int kZc = 16;
+size_t part3_doubles(const GridDims& g);
+size_t inbox3_doubles(const GridDims& g);
+unsigned column_blocks(const GridDims& g);
 
 // part 0: moments, 1: chemical potentials, 2: collision (+ diagnostics);
 // D2Q9 only: 3: fused potentials + collision + tile sums of the next moments,
@@ -96,9 +103,9 @@ struct NlArgs {
     double* dst;        // populations receiving the next state (part 3: the initial state)
     double *rho, *phi, *psi, *mux, *mup, *mus;
     const double* u0;   // part 3: initial velocity ([D][N]) or null
-    // D3Q27: next-step moments as three partial sums per node, (rho, phi) in
-    // partA and (psi, 0) in partB (3 N pairs each), with their inboxes
-    // (inbox3_doubles each): part 4 writes them, part 5 completes them
+    // D3Q27: next-step moments as partial sums, (rho, phi) in partA and
+    // (psi, 0) in partB (part3_doubles each), with their inboxes
+    // (inbox3_doubles each): part 4 writes them, parts 5 and 6 complete them
     double *partA, *inboxA, *partB, *inboxB;
     hipStream_t stream;
 };

@@ -250,72 +250,163 @@ struct NextSink {
 
 constexpr int INBOX3 = Inbox<BY>::SIZE;
 
-// Completed next-step moments (r, p) of node (gx, gy, z), index n, from the
-// three partial sums per node in `part` and the inbox entries of its tile in
-// each of the three source planes.
+// D3Q27 collisions that leave the next moments walk z-columns of ZC planes of
+// their tile (column c holds planes [c ZC, min(nz, (c + 1) ZC))), so that the
+// sums for a node from the three source planes above, at and below it meet
+// in the block that owns the node's column; only a column's first and last
+// planes receive sums from a neighbouring column.  Buffers (all (rho, phi)
+// pairs, nch = zcols(nz) columns, `plane` = nx ny):
+//   part:  [N] sums from the node's own column, then [nch][plane] sums for
+//          each column's first plane from the plane below it, then
+//          [nch][plane] sums for each column's last plane from the plane
+//          above it (periodic in z);
+//   inbox: the tile inboxes (INBOX3 slots per tile) of the same three parts,
+//          [nz][tiles], [nch][tiles], [nch][tiles].
+constexpr int ZC = kZc;
+
+__host__ __device__ __forceinline__ int zcols(int nz) { return (nz + ZC - 1) / ZC; }
+
+__host__ __device__ __forceinline__ int64_t tiles3(const GridDims& g) {
+    return (int64_t)((g.nx + BX - 1) / BX) * ((g.ny + BY - 1) / BY);
+}
+
+// Completed next-step moments (r, p) of node (gx, gy, z), index n: the
+// column's own sum and inbox entries, plus those from the neighbouring
+// columns at a column's first and last plane.
 __device__ __forceinline__ void next3_complete(const GridDims& g, const double* __restrict__ part,
                                                const double* __restrict__ inbox, int gx, int gy, int z, int64_t n,
                                                double& r, double& p) {
     const double2* P = reinterpret_cast<const double2*>(part);
-    const double2 a = P[n], b = P[g.N + n], c = P[2 * g.N + n];
-    r = a.x + b.x + c.x;
-    p = a.y + b.y + c.y;
-    const int64_t tiles = (int64_t)((g.nx + BX - 1) / BX) * ((g.ny + BY - 1) / BY);
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-        inbox_complete_fast<BY>(g, inbox + ((int64_t)z * 3 + k) * tiles * INBOX3 * 2, gx, gy, r, p);
+    const int64_t plane = (int64_t)g.nx * g.ny, xy = (int64_t)gy * g.nx + gx;
+    const int64_t box = tiles3(g) * INBOX3 * 2;  // doubles of one plane's inboxes
+    const int nch = zcols(g.nz), c = z / ZC;
+    const bool first = z == c * ZC, last = z == min(g.nz, (c + 1) * ZC) - 1;
+    const double2 a = P[n];
+    r = a.x;
+    p = a.y;
+    inbox_complete_fast<BY>(g, inbox + (int64_t)z * box, gx, gy, r, p);
+    if (first) {
+        const double2 b = P[g.N + c * plane + xy];
+        r += b.x;
+        p += b.y;
+        inbox_complete_fast<BY>(g, inbox + ((int64_t)g.nz + c) * box, gx, gy, r, p);
+    }
+    if (last) {
+        const double2 b = P[g.N + (nch + c) * plane + xy];
+        r += b.x;
+        p += b.y;
+        inbox_complete_fast<BY>(g, inbox + ((int64_t)g.nz + nch + c) * box, gx, gy, r, p);
+    }
 }
 
-// After a block's collisions have put their post-collision values in `view`'s
-// sums (and a barrier): the tile nodes' sums for the three target planes go to
-// part[(c_z + 1) N + target] and the sums for the ring nodes (the rows below
-// and above the tile, then the side columns) to the inbox of the receiving
-// tile in each target plane.  Blocks of BX x BY threads.
-template <bool WALL, int L = kD3Q27>
-__device__ __forceinline__ void next3_store(const GridDims& g, const NextSink<L, BY>& view, double* __restrict__ part,
-                                            double* __restrict__ inbox, int x0, int y0, int W, int H, int bz,
-                                            int tid) {
-    const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + BY - 1) / BY;
-    const int64_t tiles = (int64_t)bxc * byc;
+// Ring position q (0 <= q < RING3) of a W x H tile: the rows below and above
+// the tile (x from -1 to W), then the left and right columns; false where
+// the position lies beyond a ragged tile's edge.
+constexpr int RING3 = 2 * (BX + 2) + 2 * BY;
+__device__ __forceinline__ bool ring_at(int q, int W, int H, int& ex, int& ey) {
+    if (q < 2 * (BX + 2)) {
+        ex = q % (BX + 2) - 1;
+        ey = q < BX + 2 ? -1 : H;
+        return ex <= W;
+    }
+    const int c = q - 2 * (BX + 2);
+    ex = c < BY ? -1 : W;
+    ey = c % BY;
+    return ey < H;
+}
+
+// Running sums of a column walk, in LDS: [3 target-plane slots][2 fields]
+// [the tile's BX BY nodes, then its RING3 ring positions].
+constexpr int COL_NE = BX * BY + RING3;
+
+// Make the thread's index in its block (tx, ty) values the compiler cannot
+// take for loop invariants: a plane loop around a collision that needs every register
+// would otherwise keep the per-lane index arithmetic of its body live
+// through the collision, and the collision then issues its loads one by one.
+__device__ __forceinline__ void opaque_thread_index(int& tx, int& ty) {
+    asm volatile("" : "+v"(tx), "+v"(ty));
+}
+
+// The same for the lattice size N, the stride of the population arrays: the
+// per-direction bases src + i N held through the loop would not fit the
+// scalar registers.
+__device__ __forceinline__ GridDims opaque_stride(GridDims g) {
+    asm volatile("" : "+s"(g.N));
+    return g;
+}
+constexpr int COL_ACC = 3 * 2 * COL_NE;
+
+// After the collisions of source plane z of the column [z0, z1) have put
+// their values in `view`'s sums (and a barrier): the block takes every item
+// (a tile node or ring position, and a target plane z + c_z), each thread its
+// own tile node's three and ring items tid, tid + BX BY.  A target plane
+// outside the column receives its sum in that column's boundary part; one
+// inside it accumulates in `acc` over the source planes z - 1, z, z + 1,
+// started by the first (the plane below it, or its own at the column's first
+// plane) and stored by the thread of the last (the plane above it, or its own
+// at the column's last plane).  An entry of `acc` written in one plane and
+// read in another may belong to different threads: the barrier between the
+// planes orders them.  Blocks of BX x BY threads; (tx, ty) is the thread's
+// index in the block.
+template <bool WALL>
+__device__ __forceinline__ void next3_col_plane(const GridDims& g, const NextSink<kD3Q27, BY>& view,
+                                                double* __restrict__ acc, double* __restrict__ part,
+                                                double* __restrict__ inbox, int x0, int y0, int W, int H, int z,
+                                                int z0, int z1, int tx, int ty) {
+    const int64_t tiles = tiles3(g), plane = (int64_t)g.nx * g.ny;
+    const int nch = zcols(g.nz), c = z0 / ZC;
+    const int below = c == 0 ? nch - 1 : c - 1, above = c + 1 == nch ? 0 : c + 1;
     double2* P = reinterpret_cast<double2*>(part);
     double2* I = reinterpret_cast<double2*>(inbox);
-    // tile nodes: each thread gathers its own node's three target planes
-    if ((int)threadIdx.x < W && (int)threadIdx.y < H) {
-#pragma unroll
-        for (int kz = 0; kz < 3; ++kz) {
-            double s0, s1;
-            view.gather(threadIdx.x, threadIdx.y, kz, H, s0, s1);
-            const int dz = row_offset(kz);
-            int zt = bz + dz;
-            zt += zt < 0 ? g.nz : (zt >= g.nz ? -g.nz : 0);
-            P[(dz + 1) * g.N + ((int64_t)zt * g.ny + y0 + threadIdx.y) * g.nx + x0 + threadIdx.x] =
-                make_double2(s0, s1);
+    // one item: position (ex, ey) of the ring-extended tile (ring: inbox
+    // slot `ib` of the receiving tile; else node xy of the plane), target
+    // plane offset row_offset(kz), running sum `slot` of acc
+    auto item = [&](bool ring, int64_t where, int slot, int ex, int ey, int kz) {
+        double s0, s1;
+        view.gather(ex, ey, kz, H, s0, s1);
+        auto put = [&](int64_t part_plane, double a0, double a1) {
+            if (ring) I[part_plane * tiles * INBOX3 + where] = make_double2(a0, a1);
+            else P[part_plane * plane + where] = make_double2(a0, a1);
+        };
+        const int dz = row_offset(kz), t = z + dz;
+        if (t < z0) {
+            put(g.nz + nch + below, s0, s1);  // the last plane of the column below (periodic)
+        } else if (t >= z1) {
+            put(g.nz + above, s0, s1);  // the first plane of the column above (periodic)
+        } else {
+            double* a = acc + ((t - z0) % 3) * 2 * COL_NE + slot;
+            if (dz == 1) {
+                a[0] = s0;
+                a[COL_NE] = s1;
+            } else if (dz == 0) {
+                if (z != z0) {
+                    s0 += a[0];
+                    s1 += a[COL_NE];
+                }
+                if (z == z1 - 1) {
+                    put(t, s0, s1);
+                } else {
+                    a[0] = s0;
+                    a[COL_NE] = s1;
+                }
+            } else {
+                put(t, a[0] + s0, a[COL_NE] + s1);
+            }
         }
+    };
+    const int tid = ty * BX + tx;
+    if (tx < W && ty < H) {
+        const int64_t xy = (int64_t)(y0 + ty) * g.nx + x0 + tx;
+#pragma unroll
+        for (int kz = 0; kz < 3; ++kz) item(false, xy, tid, tx, ty, kz);
     }
-    // ring nodes: the rows below and above the tile, then the side columns
-    constexpr int RING3 = 2 * (BX + 2) + 2 * BY;
     for (int e = tid; e < 3 * RING3; e += BX * BY) {
         const int kz = e / RING3, q = e % RING3;
         int ex, ey;
-        if (q < 2 * (BX + 2)) {
-            ex = q % (BX + 2) - 1;
-            ey = q < BX + 2 ? -1 : H;
-            if (ex > W) continue;
-        } else {
-            const int c = q - 2 * (BX + 2);
-            ex = c < BY ? -1 : W;
-            ey = c % BY;
-            if (ey >= H) continue;
-        }
+        if (!ring_at(q, W, H, ex, ey)) continue;
         // nothing streams into a wall (those values bounced back in the sink)
         if (WALL && g.walls && ((ey < 0 && y0 == 0) || (ey >= H && y0 + H == g.ny))) continue;
-        double s0, s1;
-        view.gather(ex, ey, kz, H, s0, s1);
-        const int dz = row_offset(kz);
-        int zt = bz + dz;
-        zt += zt < 0 ? g.nz : (zt >= g.nz ? -g.nz : 0);
-        I[((int64_t)zt * 3 + dz + 1) * tiles * INBOX3 + inbox_target<BY>(g, x0, y0, W, H, ex, ey)] =
-            make_double2(s0, s1);
+        item(true, inbox_target<BY>(g, x0, y0, W, H, ex, ey), BX * BY + q, ex, ey, kz);
     }
 }
 

@@ -297,11 +297,12 @@ __global__ __launch_bounds__(NBX* NBY) void k_nl_collide(GridDims g, PhysConst k
 }
 
 // D3Q27: the collision that also leaves the next step's moments, as the
-// two-liquid FP64 collision does (k_collide_next3): the block (a BX x BY tile
-// of one z plane) sums its post-collision values for the nodes they stream
-// to, (rho, phi) in one NextSink and (psi, 0) in another, then writes the
-// tile nodes' sums per source plane to partA / partB and the ring's to the
-// neighbouring tiles' inboxes.  k_nl_complete adds them up.
+// two-liquid FP64 collision does (k_collide_next3): the block walks a
+// z-column of ZC planes of a BX x BY tile, sums its post-collision values
+// for the nodes they stream to, (rho, phi) in one NextSink and (psi, 0) in
+// another, and accumulates them over the column (next3_col_plane) into
+// partA / partB and the neighbouring tiles' inboxes.  The potential pass
+// (k_nl_chempot_col) or k_nl_complete adds them up.
 __global__ __launch_bounds__(BX* BY) void k_nl_collide_next(GridDims g, PhysConst k, NlConst q,
                                                           const double* __restrict__ src, double* __restrict__ dst,
                                                           const double* __restrict__ rho,
@@ -314,29 +315,40 @@ __global__ __launch_bounds__(BX* BY) void k_nl_collide_next(GridDims g, PhysCons
                                                           double* __restrict__ inboxB) {
     using Sink = NextSink<kD3Q27, BY>;
     __shared__ double asum[Sink::SUM], aside[Sink::SIDE], bsum[Sink::SUM], bside[Sink::SIDE];
+    __shared__ double aacc[COL_ACC], bacc[COL_ACC];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + BY - 1) / BY;
-    const int bx = b % bxc, rest = b / bxc, by = rest % byc, bz = rest / byc;
-    const int x0 = bx * BX, y0 = by * BY;
+    const int bx = b % bxc, rest = b / bxc, by = rest % byc, bc = rest / byc;
+    const int x0 = bx * BX, y0 = by * BY, z0 = bc * ZC, z1 = min(g.nz, z0 + ZC);
     const int W = min(BX, g.nx - x0), H = min(BY, g.ny - y0);
     const int tid = threadIdx.y * BX + threadIdx.x;
     // the second field of sb carries nothing: its sums are zero (read by the
-    // gathers after the barrier below, never written by the collisions)
+    // gathers, never written by the collisions)
     for (int e = tid; e < Sink::SUM / 2; e += BX * BY) bsum[Sink::SUM / 2 + e] = 0.0;
     for (int e = tid; e < Sink::SIDE / 2; e += BX * BY) bside[Sink::SIDE / 2 + e] = 0.0;
-    {
-        // every lane runs a collision (lanes past a ragged edge on the tile's
-        // last node, without stores) so that the sinks' shuffles see whole rows
-        const int lx = min((int)threadIdx.x, W - 1), ly = min((int)threadIdx.y, H - 1);
-        const bool active = (int)threadIdx.x < W && (int)threadIdx.y < H;
-        Sink sa{asum, aside, (int)threadIdx.x, (int)threadIdx.y, W, 0};
-        Sink sb{bsum, bside, (int)threadIdx.x, (int)threadIdx.y, W, 0};
-        nl_collide_node<kD3Q27>(g, k, q, src, dst, rho, phi, psi, mux, mup, mus, x0 + lx, y0 + ly, bz, active, sa,
-                                sb);
+    for (int z = z0; z < z1; ++z) {
+        int tx = threadIdx.x, ty = threadIdx.y;
+        opaque_thread_index(tx, ty);
+        {
+            // every lane runs a collision (lanes past a ragged edge on the
+            // tile's last node, without stores) so that the sinks' shuffles
+            // see whole rows
+            const int lx = min(tx, W - 1), ly = min(ty, H - 1);
+            const bool active = tx < W && ty < H;
+            Sink sa{asum, aside, tx, ty, W, 0};
+            Sink sb{bsum, bside, tx, ty, W, 0};
+            nl_collide_node<kD3Q27>(g, k, q, src, dst, rho, phi, psi, mux, mup, mus, x0 + lx, y0 + ly, z, active,
+                                    sa, sb);
+        }
+        __syncthreads();
+        next3_col_plane<false>(g, Sink{asum, aside, 0, 0, W, 0}, aacc, partA, inboxA, x0, y0, W, H, z, z0, z1, tx,
+                               ty);
+        next3_col_plane<false>(g, Sink{bsum, bside, 0, 0, W, 0}, bacc, partB, inboxB, x0, y0, W, H, z, z0, z1, tx,
+                               ty);
+        // the next plane's collisions overwrite the sums (two sets of both
+        // sinks' sums, as the two-liquid collision keeps, would not fit the LDS)
+        __syncthreads();
     }
-    __syncthreads();
-    next3_store<false>(g, Sink{asum, aside, 0, 0, W, 0}, partA, inboxA, x0, y0, W, H, bz, tid);
-    next3_store<false>(g, Sink{bsum, bside, 0, 0, W, 0}, partB, inboxB, x0, y0, W, H, bz, tid);
 }
 
 // The moments (rho, phi, psi) of the state k_nl_collide_next left, from its
@@ -456,8 +468,7 @@ hipError_t nl_part_t(const NlArgs& a, int part) {
         k_nl_init<L><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.q, a.rho, a.phi, a.psi, a.mup, a.mus, a.u0, a.dst);
     } else if (part == 4 && L == kD3Q27) {
         if (!a.partA || !a.inboxA || !a.partB || !a.inboxB) return hipErrorInvalidValue;
-        const unsigned tiles = (unsigned)(((a.g.nx + BX - 1) / BX) * ((a.g.ny + BY - 1) / BY) * a.g.nz);
-        k_nl_collide_next<<<tiles, dim3(BX, BY, 1), 0, a.stream>>>(a.g, a.k, a.q, a.src, a.dst, a.rho, a.phi, a.psi,
+        k_nl_collide_next<<<column_blocks(a.g), dim3(BX, BY, 1), 0, a.stream>>>(a.g, a.k, a.q, a.src, a.dst, a.rho, a.phi, a.psi,
                                                                    a.mux, a.mup, a.mus, a.partA, a.inboxA, a.partB,
                                                                    a.inboxB);
     } else if (part == 5 && L == kD3Q27) {
