@@ -70,7 +70,7 @@ size_t inbox_doubles(const GridDims& g);        // size of one inbox array
 // D3Q27 collisions that leave the next moments walk z-columns of kZc planes
 // per workgroup.  Sizes of the partial sums and their inboxes, and the
 // workgroups of such a collision.
-constexpr int kZc = 16;
+constexpr int kZc = 32;
 size_t part3_doubles(const GridDims& g);
 size_t inbox3_doubles(const GridDims& g);
 unsigned column_blocks(const GridDims& g);
