@@ -43,21 +43,21 @@ METRIC = "ternary ELBM MLUPS & % HBM roofline; FP32-mixed vs FP64 at stated erro
 # valid only for the kernel sources whose hash is recorded with them
 # (profiles/step_kernels_d3q27_256_d2q9_1024_stats_and_traffic.md): the D3Q27
 # 256^3 FP64 collision of a step without diagnostics, the FP32 pair-split
-# collision, the D2Q9 1024^2 one-launch steps, and the three kernels of a
+# collision, the D2Q9 1024^2 one-launch steps, and the two kernels of a
 # three-liquid D3Q27 step together.
 TRAFFIC = {
-    "d3q27_fp64_collide": {"bytes_per_launch": 17108558083, "sources_sha256_16": "89d097fbf86f0597"},
-    "d3q27_fp32_collide": {"bytes_per_launch": 9831435944, "sources_sha256_16": "89d097fbf86f0597"},
-    "d2q9_fp64_step": {"bytes_per_launch": 348358079, "sources_sha256_16": "89d097fbf86f0597"},
-    "d2q9_fp32_step": {"bytes_per_launch": 213685162, "sources_sha256_16": "89d097fbf86f0597"},
-    "d3q27_three_liquid_step": {"bytes_per_launch": 40762905466, "sources_sha256_16": "89d097fbf86f0597"},
+    "d3q27_fp64_collide": {"bytes_per_launch": 16410903567, "sources_sha256_16": "420569ff4b3734b8"},
+    "d3q27_fp32_collide": {"bytes_per_launch": 9844389217, "sources_sha256_16": "420569ff4b3734b8"},
+    "d2q9_fp64_step": {"bytes_per_launch": 348357580, "sources_sha256_16": "420569ff4b3734b8"},
+    "d2q9_fp32_step": {"bytes_per_launch": 213706340, "sources_sha256_16": "420569ff4b3734b8"},
+    "d3q27_three_liquid_step": {"bytes_per_launch": 26703622570, "sources_sha256_16": "420569ff4b3734b8"},
 }
 
 
 def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.hpp", "node_ops.hpp", "lattice.hpp", "nliquid.hip"):
+    for f in ("kernels.hip", "kernels.hpp", "node_ops.hpp", "lattice.hpp", "next_sums.hpp", "nliquid.hip"):
         with open(os.path.join(ROOT, "paper_1710_07486_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -353,9 +353,10 @@ def copy_probe(nbytes=1 << 30):
 def nliquid_throughput(wl3, coex, steps, warmup):
     """Three liquids and the gas on the 3D workload: its second drop is
     liquid 3 (psi = chi) and liquid 2 is absent, liquid 3 with liquid 2's
-    lambda and kappa.  FP64, three launches per step (moments, potentials,
-    collision), timed with an event pair around the `steps` timed steps on
-    the solver's stream."""
+    lambda and kappa.  FP64, two launches per step (the collision that leaves
+    the next moments as partial sums, then the pass that completes them and
+    computes the potentials), timed with an event pair around the `steps`
+    timed steps on the solver's stream."""
     import torch
     import paper_1710_07486_amd as T_
     from paper_1710_07486_amd import nliquid as NL
@@ -382,12 +383,12 @@ def nliquid_throughput(wl3, coex, steps, warmup):
     achieved = per_node * wl3.nodes / (ms * 1e-3) / 1e9
     out = {"workload": wl3.name + "_liquid3", "lattice": "D3Q27, f + two phase-field lattices",
            "mlups": round(wl3.nodes / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 4),
-           "steps": steps, "warmup": warmup, "launches_per_step": 3,
+           "steps": steps, "warmup": warmup, "launches_per_step": 2,
            "whole_step_roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                                    "algorithmic_bytes_per_node": per_node,
                                    "traffic": traffic_of("d3q27_three_liquid_step"),
-                                   "traffic_unit": "HBM bytes per step, the three kernels (rocprofv3 FETCH_SIZE + "
+                                   "traffic_unit": "HBM bytes per step, its two kernels (rocprofv3 FETCH_SIZE + "
                                                    "WRITE_SIZE, copy-calibrated)"},
            "liquid3_max_c": round(float(c3.max()), 4), "finite": finite}
     s.close()
