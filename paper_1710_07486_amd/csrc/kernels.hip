@@ -554,6 +554,45 @@ __global__ __launch_bounds__(FIX_THREADS) void k_dens_complete2(GridDims g, doub
 // chemical-potential pass completes them while it stages the densities
 // (k_chempot_col<true>), so the moment pass over all populations is not run.
 // ---------------------------------------------------------------------------
+// Cache policy of the LDS-DMA loads: non-temporal, as the other population
+// loads of the 3D collision.
+constexpr int kNonTemporal = 2;
+
+// The phase-field populations pulled by one wavefront's row of the tile: LDS
+// row[i BX + d] holds direction i pulled by node x0 + d of row y in plane z
+// (nodes past a ragged edge repeat node W - 1).  Filled by LDS-DMA loads, a
+// dword per lane (two loads per direction), so that the fetch of the next
+// plane's values holds no registers while the current plane is collided.
+__device__ __forceinline__ void stage_g_row(const GridDims& g, const double* __restrict__ src, double* row, int x0,
+                                            int y, int z, int W, int lane) {
+    using Lt = Lattice<kD3Q27>;
+    constexpr int Q = Lt::Q;
+    using GPtr = const __attribute__((address_space(1))) void*;
+    using LPtr = __attribute__((address_space(3))) void*;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int x = x0 + min(32 * h + (lane >> 1), W - 1);
+        const Nbr32 nb = make_nbr32(x, y, z, g.nx, g.ny, g.nz);
+        const uint32_t n = (uint32_t)node_index(g, x, y, z);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const char* a = (const char*)(src + (size_t)(Q + i) * g.N) +
+                            (uint32_t)(nbr32<kD3Q27>(nb, n, i, -1) * 8u + 4u * (lane & 1));
+            // lane l fills dword l of the 64 that hold doubles 32 h .. 32 h + 31
+            __builtin_amdgcn_global_load_lds((GPtr)a, (LPtr)(row + i * BX + 32 * h), 4, 0, kNonTemporal);
+        }
+    }
+}
+
+// Staging policy of node_collide_sink for the z-column collision: the
+// wavefront's row of this plane's values, in LDS.
+struct GRowStaged {
+    static constexpr bool on = true;
+    const double* row;
+    int lane;
+    __device__ __forceinline__ double pulled(int i) const { return row[i * BX + lane]; }
+};
+
 // DIAG: the instance that also reduces the health diagnostics (launched on the
 // steps that take them; the other keeps none of their registers).
 template <bool WALL, bool RG, bool DIAG>
@@ -569,6 +608,10 @@ __global__ __launch_bounds__(BX* BY) void k_collide_next3(GridDims g, PhysConst 
     // never overwrite the sums that slower threads still gather from, and one
     // barrier per plane suffices
     __shared__ double nsum[2][Sink::SUM], nside[2][Sink::SIDE], acc[COL_ACC];
+    // without walls on the full lattice, each wavefront's row of pulled
+    // phase-field populations is staged one plane ahead (GRowStaged)
+    constexpr bool STAGE = !WALL && !RG;
+    __shared__ double gstage[STAGE ? BY * 27 * BX : 1];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + BY - 1) / BY;
     const int bx = b % bxc, rest = b / bxc, by = rest % byc, bc = rest / byc;
@@ -576,6 +619,10 @@ __global__ __launch_bounds__(BX* BY) void k_collide_next3(GridDims g, PhysConst 
     const int W = min(BX, g.nx - x0), H = min(BY, g.ny - y0);
     double dv[kDiag] = {0, 0, 0, 0, 0, 0, INFINITY, INFINITY, -INFINITY, 0};
     const GlobalAux aux{rho, phi, mux, mup};
+    // the wavefront's row (uniform over it) and its staging row
+    const int wrow = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    double* grow = gstage + (STAGE ? wrow * 27 * BX : 0);
+    if (STAGE) stage_g_row(g, src, grow, x0, y0 + min(wrow, H - 1), z0, W, threadIdx.x);
     for (int z = z0; z < z1; ++z) {
         int tx = threadIdx.x, ty = threadIdx.y;
         opaque_thread_index(tx, ty);
@@ -588,10 +635,21 @@ __global__ __launch_bounds__(BX* BY) void k_collide_next3(GridDims g, PhysConst 
             const int wy = (WALL && g.walls) ? (y0 + ly == 0 ? -1 : (y0 + ly == g.ny - 1 ? 1 : 0)) : 0;
             const GridDims gz = opaque_stride(g);
             Sink sink{nsum[(z - z0) & 1], nside[(z - z0) & 1], tx, ty, W, wy};
-            node_collide_sink<kD3Q27, double, GlobalAux, Sink, WALL, RG>(gz, k, src, dst, nullptr, aux, x0 + lx,
-                                                                      y0 + ly, z, DIAG, dv, active, sink);
+            if constexpr (STAGE) {
+                const GRowStaged st{grow, tx};
+                node_collide_sink<kD3Q27, double, GlobalAux, Sink, WALL, RG, GRowStaged>(
+                    gz, k, src, dst, nullptr, aux, x0 + lx, y0 + ly, z, DIAG, dv, active, sink, st);
+            } else {
+                node_collide_sink<kD3Q27, double, GlobalAux, Sink, WALL, RG>(gz, k, src, dst, nullptr, aux, x0 + lx,
+                                                                          y0 + ly, z, DIAG, dv, active, sink);
+            }
         }
         __syncthreads();
+        // the next plane's phase-field pulls, staged while this plane's sums
+        // are gathered and the next plane's f is collided (issued after the
+        // barrier, which would otherwise wait for them; the row's reads of
+        // this plane are complete at the barrier)
+        if (STAGE && z + 1 < z1) stage_g_row(g, src, grow, x0, y0 + min(wrow, H - 1), z + 1, W, tx);
         next3_col_plane<WALL>(g, Sink{nsum[(z - z0) & 1], nside[(z - z0) & 1], 0, 0, W, 0}, acc, part, inbox, x0,
                               y0, W, H, z, z0, z1, tx, ty);
     }

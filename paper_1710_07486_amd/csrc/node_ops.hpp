@@ -274,6 +274,15 @@ struct NoSink {
     __device__ __forceinline__ void post_g(const R*) {}
 };
 
+// Where the collision takes the phase-field populations it pulls: global
+// memory (NoGPrefetch), or a policy with on = true whose pulled(i) returns
+// direction i of the node (the z-column collision stages them in LDS ahead
+// of the plane).
+struct NoGPrefetch {
+    static constexpr bool on = false;
+    __device__ __forceinline__ double pulled(int) const { return 0.0; }
+};
+
 // Phase 3: pull f, g; force from the excess potentials; KBC with
 // exact-difference forcing; phase-field BGK; write the node's own slots.
 // If diag, dv receives {rho, phi, j (3), |u_phys|, rho, gamma, gamma, bad}.
@@ -282,18 +291,25 @@ struct NoSink {
 // node is computed but nothing is stored or reported (lanes past a ragged
 // edge that run on a clamped node so that the sink sees a full wavefront).
 // W false: the lattice has no walls (the kernel carries none of their logic).
-// RG: the phase field lives on the reduced lattice (GLattice).
-template <int L, typename T, typename AUX, typename SINK, bool W = true, bool RG = false>
+// RG: the phase field lives on the reduced lattice (GLattice).  GPF: where
+// the pulled phase-field populations come from (a staging policy only with
+// FP64, no walls and the full lattice).
+template <int L, typename T, typename AUX, typename SINK, bool W = true, bool RG = false,
+          typename GPF = NoGPrefetch>
 __device__ __forceinline__ void node_collide_sink(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
                                                   T* __restrict__ dst, const double* __restrict__ rho_ref,
                                                   const AUX& aux, int x, int y, int z, bool diag, double* dv,
-                                                  bool active, SINK& sink) {
+                                                  bool active, SINK& sink, const GPF& gpf = GPF{}) {
+    static_assert(!GPF::on || (!W && !RG && sizeof(T) == 8), "staged phase-field pulls: FP64, no walls, full lattice");
     using Lt = Lattice<L>;
     using R = T;
     constexpr int Q = Lt::Q;
     const Nbr32 nb = W ? make_nbr32_w(g, x, y, z) : make_nbr32(x, y, z, g.nx, g.ny, g.nz);
     const uint32_t n = (uint32_t)node_index(g, x, y, z);
     const double r = aux.rho0(n), p = aux.phi0(n);
+    // mu_phi of the node (for the phase-field collision), with its other
+    // fields: loaded later, its wait could also cover a staging policy's loads
+    const double mphi = aux.mup0(n);
 
     // force from the isotropic gradients of the two potentials
     double gx[3] = {0, 0, 0}, gp[3] = {0, 0, 0};
@@ -348,12 +364,17 @@ __device__ __forceinline__ void node_collide_sink(const GridDims& g, const PhysC
 
     constexpr int QG = GLattice<L, RG>::Q;
     R gg[QG];
+    if constexpr (GPF::on) {
 #pragma unroll
-    for (int i = 0; i < QG; ++i)
-        gg[i] = (W && bounce(g, y, Lt::c[i][1])) ? ld_pop<L>(src + (size_t)(Q + opp_dir(i)) * g.N, n)
-                                          : ld_pop<L>(src + (size_t)(Q + i) * g.N, nbr32<L>(nb, n, i, -1));
+        for (int i = 0; i < QG; ++i) gg[i] = R(gpf.pulled(i));
+    } else {
+#pragma unroll
+        for (int i = 0; i < QG; ++i)
+            gg[i] = (W && bounce(g, y, Lt::c[i][1])) ? ld_pop<L>(src + (size_t)(Q + opp_dir(i)) * g.N, n)
+                                              : ld_pop<L>(src + (size_t)(Q + i) * g.N, nbr32<L>(nb, n, i, -1));
+    }
     R up[3] = {u[0] + R(0.5) * du[0], u[1] + R(0.5) * du[1], u[2] + R(0.5) * du[2]};
-    collide_g_lat<L, R, RG>(gg, R(p), R(aux.mup0(n)), up, R(k.Gamma), R(k.omega_phi));
+    collide_g_lat<L, R, RG>(gg, R(p), R(mphi), up, R(k.Gamma), R(k.omega_phi));
     if (active) {
 #pragma unroll
         for (int i = 0; i < QG; ++i) st_pop<L>(dst + (size_t)(Q + i) * g.N, n, gg[i]);
