@@ -451,9 +451,9 @@ typedef struct telbm_nl telbm_nl;
 int telbm_nl_mobility(const telbm_params *p, const telbm_nl_params *q, double *m);
 
 /* Bytes of device arena for these parameters (two population buffers of
- * 3 Q N doubles, six N-double fields and, for D3Q27, two sets of partial
- * next-step moments of 3 N pairs with their tile inboxes; each part 256-byte
- * aligned). */
+ * 3 Q N doubles, six N-double fields and, for D3Q27, the partial next-step
+ * moments of the z-column collision, (rho, phi) pairs and psi, with their
+ * tile inboxes; each part 256-byte aligned). */
 int telbm_nl_required_bytes(const telbm_params *p, const telbm_nl_params *q, size_t *bytes);
 
 /* Create, borrowing `device_arena` (>= required bytes, 256-byte aligned) for

@@ -109,8 +109,8 @@ Layout layout_of(const telbm_params& p) {
     L.inbox = fz ? align_up(inbox_doubles(g) * sizeof(double)) : 0;
     // D3Q27 FP64: partial next-step moments and their inboxes
     const bool next3 = !fz && p.precision == TELBM_FP64;
-    L.part3 = next3 ? align_up(part3_doubles(g) * sizeof(double)) : 0;
-    L.inbox3 = next3 ? align_up(inbox3_doubles(g) * sizeof(double)) : 0;
+    L.part3 = next3 ? align_up(part3_doubles(g, 2) * sizeof(double)) : 0;
+    L.inbox3 = next3 ? align_up(inbox3_doubles(g, 2) * sizeof(double)) : 0;
     L.partials = align_up((size_t)collide_blocks(g) * kDiag * sizeof(double));
     L.diag = align_up(16 * sizeof(double));
     L.bad = align_up(sizeof(unsigned long long));
@@ -405,11 +405,12 @@ int nl_validate(const telbm_params* p, const telbm_nl_params* q, std::string* wh
 }
 
 struct NlLayout {
-    size_t pop, aux, part, inbox, total;
+    size_t pop, aux, partA, inboxA, partB, inboxB, total;
 };
 
 // Two population buffers of 3 Q N doubles, six N-double fields and, for
-// D3Q27, two sets of partial next-step moments with their inboxes.
+// D3Q27, the partial next-step moments with their inboxes: (rho, phi) pairs
+// (A) and psi (B).
 NlLayout nl_layout(const telbm_params& p) {
     const int64_t N = (int64_t)p.nx * p.ny * p.nz;
     const int Q = p.lattice == TELBM_D2Q9 ? 9 : 27;
@@ -418,9 +419,11 @@ NlLayout nl_layout(const telbm_params& p) {
     L.pop = align_up((size_t)3 * Q * N * sizeof(double));
     L.aux = align_up((size_t)N * sizeof(double));
     const bool d3 = p.lattice == TELBM_D3Q27;
-    L.part = d3 ? align_up(part3_doubles(g) * sizeof(double)) : 0;
-    L.inbox = d3 ? align_up(inbox3_doubles(g) * sizeof(double)) : 0;
-    L.total = 2 * L.pop + 6 * L.aux + 2 * (L.part + L.inbox);
+    L.partA = d3 ? align_up(part3_doubles(g, 2) * sizeof(double)) : 0;
+    L.inboxA = d3 ? align_up(inbox3_doubles(g, 2) * sizeof(double)) : 0;
+    L.partB = d3 ? align_up(part3_doubles(g, 1) * sizeof(double)) : 0;
+    L.inboxB = d3 ? align_up(inbox3_doubles(g, 1) * sizeof(double)) : 0;
+    L.total = 2 * L.pop + 6 * L.aux + L.partA + L.inboxA + L.partB + L.inboxB;
     return L;
 }
 
@@ -787,10 +790,10 @@ int telbm_nl_create(const telbm_params* p, const telbm_nl_params* q, void* devic
     double** f[6] = {&a.rho, &a.phi, &a.psi, &a.mux, &a.mup, &a.mus};
     for (int i = 0; i < 6; ++i) *f[i] = (double*)(base + 2 * L.pop + i * L.aux);
     char* nx = base + 2 * L.pop + 6 * L.aux;
-    a.partA = L.part ? (double*)nx : nullptr;
-    a.inboxA = L.part ? (double*)(nx + L.part) : nullptr;
-    a.partB = L.part ? (double*)(nx + L.part + L.inbox) : nullptr;
-    a.inboxB = L.part ? (double*)(nx + 2 * L.part + L.inbox) : nullptr;
+    a.partA = L.partA ? (double*)nx : nullptr;
+    a.inboxA = L.partA ? (double*)(nx + L.partA) : nullptr;
+    a.partB = L.partA ? (double*)(nx + L.partA + L.inboxA) : nullptr;
+    a.inboxB = L.partA ? (double*)(nx + L.partA + L.inboxA + L.partB) : nullptr;
     a.u0 = nullptr;
     a.stream = nullptr;
     s->cur = 0;

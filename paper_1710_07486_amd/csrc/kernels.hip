@@ -607,7 +607,7 @@ __global__ __launch_bounds__(BX* BY) void k_collide_next3(GridDims g, PhysConst 
     // two sets of sums, used by alternate planes: a plane's collisions then
     // never overwrite the sums that slower threads still gather from, and one
     // barrier per plane suffices
-    __shared__ double nsum[2][Sink::SUM], nside[2][Sink::SIDE], acc[COL_ACC];
+    __shared__ double nsum[2][Sink::SUM], nside[2][Sink::SIDE], acc[col_acc<2>()];
     // without walls on the full lattice, each wavefront's row of pulled
     // phase-field populations is staged one plane ahead (GRowStaged)
     constexpr bool STAGE = !WALL && !RG;
@@ -807,10 +807,12 @@ unsigned fused_tiles(const GridDims& g) { return (unsigned)(((g.nx + BX - 1) / B
 
 size_t inbox_doubles(const GridDims& g) { return (size_t)fused_tiles(g) * INBOX * 2; }
 
-size_t part3_doubles(const GridDims& g) { return 2 * ((size_t)g.N + 2 * (size_t)zcols(g.nz) * g.nx * g.ny); }
+size_t part3_doubles(const GridDims& g, int nf) {
+    return nf * ((size_t)g.N + 2 * (size_t)zcols(g.nz) * g.nx * g.ny);
+}
 
-size_t inbox3_doubles(const GridDims& g) {
-    return 2 * (size_t)(g.nz + 2 * zcols(g.nz)) * (size_t)tiles3(g) * INBOX3;
+size_t inbox3_doubles(const GridDims& g, int nf) {
+    return nf * (size_t)(g.nz + 2 * zcols(g.nz)) * (size_t)tiles3(g) * INBOX3;
 }
 
 unsigned column_blocks(const GridDims& g) { return (unsigned)(tiles3(g) * zcols(g.nz)); }

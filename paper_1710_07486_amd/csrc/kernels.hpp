@@ -68,11 +68,12 @@ unsigned collide_blocks(const GridDims& g);
 unsigned fused_tiles(const GridDims& g);        // D2Q9 tiles of the fused step
 size_t inbox_doubles(const GridDims& g);        // size of one inbox array
 // D3Q27 collisions that leave the next moments walk z-columns of kZc planes
-// per workgroup.  Sizes of the partial sums and their inboxes, and the
-// workgroups of such a collision.
+// per workgroup.  Sizes of the partial sums and their inboxes (nf fields per
+// entry: 2 for (rho, phi) pairs, 1 for psi alone), and the workgroups of such
+// a collision.
 constexpr int kZc = 32;
-size_t part3_doubles(const GridDims& g);
-size_t inbox3_doubles(const GridDims& g);
+size_t part3_doubles(const GridDims& g, int nf);
+size_t inbox3_doubles(const GridDims& g, int nf);
 unsigned column_blocks(const GridDims& g);
 
 // part 0: moments, 1: chemical potentials, 2: collision (+ diagnostics);
@@ -103,9 +104,10 @@ struct NlArgs {
     double* dst;        // populations receiving the next state (part 3: the initial state)
     double *rho, *phi, *psi, *mux, *mup, *mus;
     const double* u0;   // part 3: initial velocity ([D][N]) or null
-    // D3Q27: next-step moments as partial sums, (rho, phi) in partA and
-    // (psi, 0) in partB (part3_doubles each), with their inboxes
-    // (inbox3_doubles each): part 4 writes them, parts 5 and 6 complete them
+    // D3Q27: next-step moments as partial sums, (rho, phi) pairs in partA
+    // and psi in partB (part3_doubles with 2 and 1 fields), with their
+    // inboxes (inbox3_doubles likewise): part 4 writes them, parts 5 and 6
+    // complete them
     double *partA, *inboxA, *partB, *inboxB;
     hipStream_t stream;
 };

@@ -60,8 +60,9 @@ __device__ __forceinline__ TilePos tile_pos(const GridDims& g, int gx, int gy) {
 }
 
 // Add the inbox entries of node (gx, gy) to its tile's partial sums (r, p),
-// in a fixed order.  `in` is the inbox array of the node's plane.
-template <int TH>
+// in a fixed order.  `in` is the inbox array of the node's plane, NF fields
+// per slot ((r, p) pairs, or r alone with NF = 1, p then untouched).
+template <int TH, int NF = 2>
 __device__ __forceinline__ void inbox_complete(const GridDims& g, const double* __restrict__ in, int gx, int gy,
                                                double& r, double& p) {
     using I = Inbox<TH>;
@@ -70,10 +71,10 @@ __device__ __forceinline__ void inbox_complete(const GridDims& g, const double* 
     const bool x0 = t.lx == 0, x1 = t.lx == t.W - 1;
     const bool y0 = t.ly == 0 && !(g.walls && gy == 0), y1 = t.ly == t.H - 1 && !(g.walls && gy == g.ny - 1);
     if (!(x0 || x1 || y0 || y1)) return;
-    const double* b = in + (int64_t)t.tile * I::SIZE * 2;
+    const double* b = in + (int64_t)t.tile * I::SIZE * NF;
     auto add = [&](int slot) {
-        r += b[2 * slot];
-        p += b[2 * slot + 1];
+        r += b[NF * slot];
+        if (NF == 2) p += b[NF * slot + 1];
     };
     if (y0) add(I::DOWN + t.lx);
     if (y1) add(I::UP + t.lx);
@@ -90,7 +91,7 @@ __device__ __forceinline__ void inbox_complete(const GridDims& g, const double* 
 // side, a horizontal side and a corner, taken in the order of inbox_complete;
 // the three loads are issued unconditionally (a missing entry reads the
 // tile's first slot and is not added).  Narrower tiles use inbox_complete.
-template <int TH>
+template <int TH, int NF = 2>
 __device__ __forceinline__ void inbox_complete_fast(const GridDims& g, const double* __restrict__ in, int gx,
                                                     int gy, double& r, double& p) {
     using I = Inbox<TH>;
@@ -99,14 +100,22 @@ __device__ __forceinline__ void inbox_complete_fast(const GridDims& g, const dou
     const bool y0 = t.ly == 0 && !(g.walls && gy == 0), y1 = t.ly == t.H - 1 && !(g.walls && gy == g.ny - 1);
     if (!(x0 || x1 || y0 || y1)) return;
     if (t.W < 2 || t.H < 2) {
-        inbox_complete<TH>(g, in, gx, gy, r, p);
+        inbox_complete<TH, NF>(g, in, gx, gy, r, p);
         return;
     }
-    const double2* b = reinterpret_cast<const double2*>(in) + (int64_t)t.tile * I::SIZE;
     const bool hv = y0 || y1, hh = x0 || x1, hc = hv && hh;
     const int sv = hv ? (y0 ? I::DOWN : I::UP) + t.lx : 0;
     const int sh = hh ? (x0 ? I::LEFT : I::RIGHT) + t.ly : 0;
     const int sc = hc ? I::CORNER + (x1 ? 1 : 0) + (y1 ? 2 : 0) : 0;
+    if (NF == 1) {
+        const double* b = in + (int64_t)t.tile * I::SIZE;
+        const double v = b[sv], h = b[sh], c = b[sc];
+        if (hv) r += v;
+        if (hh) r += h;
+        if (hc) r += c;
+        return;
+    }
+    const double2* b = reinterpret_cast<const double2*>(in) + (int64_t)t.tile * I::SIZE;
     const double2 v = b[sv], h = b[sh], c = b[sc];
     if (hv) {
         r += v.x;
@@ -168,10 +177,10 @@ static_assert(all_dirs_present<kD2Q9>() && all_dirs_present<kD3Q27>(), "every la
 // (terms from lanes of the tile only) in sum[field][gi][ly][l], and the
 // values that leave the tile sideways, v(-1, .) of lane 0 and v(+1, .) of the
 // last lane, in side[field][0 / 1][gi][ly].
-template <int L, int TH>
+template <int L, int TH, int NF = 2>
 struct NextSink {
     static constexpr int NG = Lattice<L>::D == 3 ? 9 : 3;
-    static constexpr int SUM = 2 * NG * TH * BX, SIDE = 2 * 2 * NG * TH;
+    static constexpr int SUM = NF * NG * TH * BX, SIDE = NF * 2 * NG * TH;
     double* sum;
     double* side;
     int lx, ly, W;
@@ -218,6 +227,7 @@ struct NextSink {
     }
     template <int L2, typename R, int QG>
     __device__ __forceinline__ void post_g(const R* gg) {
+        static_assert(NF == 2, "the phase field is the second field");
         // a reduced phase-field lattice has no populations beyond its QG
         double v[Lattice<L>::Q];
 #pragma unroll
@@ -236,13 +246,13 @@ struct NextSink {
             if (sy < 0 || sy >= H) continue;
             if (ex < 0) {
                 s0 += side[((0 * 2 + 0) * NG + gi) * TH + sy];
-                s1 += side[((1 * 2 + 0) * NG + gi) * TH + sy];
+                if (NF == 2) s1 += side[((1 * 2 + 0) * NG + gi) * TH + sy];
             } else if (ex >= W) {
                 s0 += side[((0 * 2 + 1) * NG + gi) * TH + sy];
-                s1 += side[((1 * 2 + 1) * NG + gi) * TH + sy];
+                if (NF == 2) s1 += side[((1 * 2 + 1) * NG + gi) * TH + sy];
             } else {
                 s0 += sum[((0 * NG + gi) * TH + sy) * BX + ex];
-                s1 += sum[((1 * NG + gi) * TH + sy) * BX + ex];
+                if (NF == 2) s1 += sum[((1 * NG + gi) * TH + sy) * BX + ex];
             }
         }
     }
@@ -254,8 +264,9 @@ constexpr int INBOX3 = Inbox<BY>::SIZE;
 // their tile (column c holds planes [c ZC, min(nz, (c + 1) ZC))), so that the
 // sums for a node from the three source planes above, at and below it meet
 // in the block that owns the node's column; only a column's first and last
-// planes receive sums from a neighbouring column.  Buffers (all (rho, phi)
-// pairs, nch = zcols(nz) columns, `plane` = nx ny):
+// planes receive sums from a neighbouring column.  Buffers (NF doubles per
+// entry: (rho, phi) pairs, or one field; nch = zcols(nz) columns, `plane` =
+// nx ny):
 //   part:  [N] sums from the node's own column, then [nch][plane] sums for
 //          each column's first plane from the plane below it, then
 //          [nch][plane] sums for each column's last plane from the plane
@@ -270,32 +281,50 @@ __host__ __device__ __forceinline__ int64_t tiles3(const GridDims& g) {
     return (int64_t)((g.nx + BX - 1) / BX) * ((g.ny + BY - 1) / BY);
 }
 
+// Entry e of a buffer of NF-field entries (p = 0 with one field).
+template <int NF>
+__device__ __forceinline__ void entry_get(const double* __restrict__ buf, int64_t e, double& r, double& p) {
+    if (NF == 2) {
+        const double2 a = reinterpret_cast<const double2*>(buf)[e];
+        r = a.x;
+        p = a.y;
+    } else {
+        r = buf[e];
+        p = 0.0;
+    }
+}
+template <int NF>
+__device__ __forceinline__ void entry_put(double* __restrict__ buf, int64_t e, double r, double p) {
+    if (NF == 2) reinterpret_cast<double2*>(buf)[e] = make_double2(r, p);
+    else buf[e] = r;
+}
+
 // Completed next-step moments (r, p) of node (gx, gy, z), index n: the
 // column's own sum and inbox entries, plus those from the neighbouring
-// columns at a column's first and last plane.
+// columns at a column's first and last plane (p = 0 with one field).
+template <int NF = 2>
 __device__ __forceinline__ void next3_complete(const GridDims& g, const double* __restrict__ part,
                                                const double* __restrict__ inbox, int gx, int gy, int z, int64_t n,
                                                double& r, double& p) {
-    const double2* P = reinterpret_cast<const double2*>(part);
     const int64_t plane = (int64_t)g.nx * g.ny, xy = (int64_t)gy * g.nx + gx;
-    const int64_t box = tiles3(g) * INBOX3 * 2;  // doubles of one plane's inboxes
+    const int64_t box = tiles3(g) * INBOX3 * NF;  // doubles of one plane's inboxes
     const int nch = zcols(g.nz), c = z / ZC;
     const bool first = z == c * ZC, last = z == min(g.nz, (c + 1) * ZC) - 1;
-    const double2 a = P[n];
-    r = a.x;
-    p = a.y;
-    inbox_complete_fast<BY>(g, inbox + (int64_t)z * box, gx, gy, r, p);
+    entry_get<NF>(part, n, r, p);
+    inbox_complete_fast<BY, NF>(g, inbox + (int64_t)z * box, gx, gy, r, p);
     if (first) {
-        const double2 b = P[g.N + c * plane + xy];
-        r += b.x;
-        p += b.y;
-        inbox_complete_fast<BY>(g, inbox + ((int64_t)g.nz + c) * box, gx, gy, r, p);
+        double br, bp;
+        entry_get<NF>(part, g.N + c * plane + xy, br, bp);
+        r += br;
+        p += bp;
+        inbox_complete_fast<BY, NF>(g, inbox + ((int64_t)g.nz + c) * box, gx, gy, r, p);
     }
     if (last) {
-        const double2 b = P[g.N + (nch + c) * plane + xy];
-        r += b.x;
-        p += b.y;
-        inbox_complete_fast<BY>(g, inbox + ((int64_t)g.nz + nch + c) * box, gx, gy, r, p);
+        double br, bp;
+        entry_get<NF>(part, g.N + (nch + c) * plane + xy, br, bp);
+        r += br;
+        p += bp;
+        inbox_complete_fast<BY, NF>(g, inbox + ((int64_t)g.nz + nch + c) * box, gx, gy, r, p);
     }
 }
 
@@ -315,14 +344,19 @@ __device__ __forceinline__ bool ring_at(int q, int W, int H, int& ex, int& ey) {
     return ey < H;
 }
 
-// Running sums of a column walk, in LDS: [3 target-plane slots][2 fields]
+// Running sums of a column walk, in LDS: [3 target-plane slots][NF fields]
 // [the tile's BX BY nodes, then its RING3 ring positions].
 constexpr int COL_NE = BX * BY + RING3;
+template <int NF>
+constexpr int col_acc() {
+    return 3 * NF * COL_NE;
+}
 
 // Make the thread's index in its block (tx, ty) values the compiler cannot
-// take for loop invariants: a plane loop around a collision that needs every register
-// would otherwise keep the per-lane index arithmetic of its body live
-// through the collision, and the collision then issues its loads one by one.
+// take for loop invariants: a plane loop around a collision that needs every
+// register would otherwise keep the per-lane index arithmetic of its body
+// live through the collision, and the collision then issues its loads one by
+// one.
 __device__ __forceinline__ void opaque_thread_index(int& tx, int& ty) {
     asm volatile("" : "+v"(tx), "+v"(ty));
 }
@@ -334,7 +368,6 @@ __device__ __forceinline__ GridDims opaque_stride(GridDims g) {
     asm volatile("" : "+s"(g.N));
     return g;
 }
-constexpr int COL_ACC = 3 * 2 * COL_NE;
 
 // After the collisions of source plane z of the column [z0, z1) have put
 // their values in `view`'s sums (and a barrier): the block takes every item
@@ -348,25 +381,23 @@ constexpr int COL_ACC = 3 * 2 * COL_NE;
 // read in another may belong to different threads: the barrier between the
 // planes orders them.  Blocks of BX x BY threads; (tx, ty) is the thread's
 // index in the block.
-template <bool WALL>
-__device__ __forceinline__ void next3_col_plane(const GridDims& g, const NextSink<kD3Q27, BY>& view,
+template <bool WALL, int NF = 2>
+__device__ __forceinline__ void next3_col_plane(const GridDims& g, const NextSink<kD3Q27, BY, NF>& view,
                                                 double* __restrict__ acc, double* __restrict__ part,
                                                 double* __restrict__ inbox, int x0, int y0, int W, int H, int z,
                                                 int z0, int z1, int tx, int ty) {
     const int64_t tiles = tiles3(g), plane = (int64_t)g.nx * g.ny;
     const int nch = zcols(g.nz), c = z0 / ZC;
     const int below = c == 0 ? nch - 1 : c - 1, above = c + 1 == nch ? 0 : c + 1;
-    double2* P = reinterpret_cast<double2*>(part);
-    double2* I = reinterpret_cast<double2*>(inbox);
     // one item: position (ex, ey) of the ring-extended tile (ring: inbox
-    // slot `ib` of the receiving tile; else node xy of the plane), target
-    // plane offset row_offset(kz), running sum `slot` of acc
+    // slot `where` of the receiving tile; else node `where` of the plane),
+    // target plane offset row_offset(kz), running sum `slot` of acc
     auto item = [&](bool ring, int64_t where, int slot, int ex, int ey, int kz) {
         double s0, s1;
         view.gather(ex, ey, kz, H, s0, s1);
         auto put = [&](int64_t part_plane, double a0, double a1) {
-            if (ring) I[part_plane * tiles * INBOX3 + where] = make_double2(a0, a1);
-            else P[part_plane * plane + where] = make_double2(a0, a1);
+            if (ring) entry_put<NF>(inbox, part_plane * tiles * INBOX3 + where, a0, a1);
+            else entry_put<NF>(part, part_plane * plane + where, a0, a1);
         };
         const int dz = row_offset(kz), t = z + dz;
         if (t < z0) {
@@ -374,23 +405,23 @@ __device__ __forceinline__ void next3_col_plane(const GridDims& g, const NextSin
         } else if (t >= z1) {
             put(g.nz + above, s0, s1);  // the first plane of the column above (periodic)
         } else {
-            double* a = acc + ((t - z0) % 3) * 2 * COL_NE + slot;
+            double* a = acc + ((t - z0) % 3) * NF * COL_NE + slot;
             if (dz == 1) {
                 a[0] = s0;
-                a[COL_NE] = s1;
+                if (NF == 2) a[COL_NE] = s1;
             } else if (dz == 0) {
                 if (z != z0) {
                     s0 += a[0];
-                    s1 += a[COL_NE];
+                    if (NF == 2) s1 += a[COL_NE];
                 }
                 if (z == z1 - 1) {
                     put(t, s0, s1);
                 } else {
                     a[0] = s0;
-                    a[COL_NE] = s1;
+                    if (NF == 2) a[COL_NE] = s1;
                 }
             } else {
-                put(t, a[0] + s0, a[COL_NE] + s1);
+                put(t, a[0] + s0, NF == 2 ? a[COL_NE] + s1 : 0.0);
             }
         }
     };

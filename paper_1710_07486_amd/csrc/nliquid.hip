@@ -155,7 +155,7 @@ __global__ __launch_bounds__(BX* BY) void k_nl_chempot_col(GridDims g, PhysConst
             const int64_t n = ((int64_t)zw * g.ny + gy) * g.nx + gx;
             double r, p, s, zero;
             next3_complete(g, partA, inboxA, gx, gy, zw, n, r, p);
-            next3_complete(g, partB, inboxB, gx, gy, zw, n, s, zero);
+            next3_complete<1>(g, partB, inboxB, gx, gy, zw, n, s, zero);
             sr[slot][e] = r;
             sp[slot][e] = p;
             ss[slot][e] = s;
@@ -299,10 +299,12 @@ __global__ __launch_bounds__(NBX* NBY) void k_nl_collide(GridDims g, PhysConst k
 // D3Q27: the collision that also leaves the next step's moments, as the
 // two-liquid FP64 collision does (k_collide_next3): the block walks a
 // z-column of ZC planes of a BX x BY tile, sums its post-collision values
-// for the nodes they stream to, (rho, phi) in one NextSink and (psi, 0) in
-// another, and accumulates them over the column (next3_col_plane) into
-// partA / partB and the neighbouring tiles' inboxes.  The potential pass
-// (k_nl_chempot_col) or k_nl_complete adds them up.
+// for the nodes they stream to, (rho, phi) in one NextSink and psi in a
+// one-field one, and accumulates them over the column (next3_col_plane) into
+// partA / partB and the neighbouring tiles' inboxes.  Both sinks keep two
+// sets of sums, used by alternate planes, so one barrier per plane
+// suffices.  The potential pass (k_nl_chempot_col) or k_nl_complete adds
+// them up.
 __global__ __launch_bounds__(BX* BY) void k_nl_collide_next(GridDims g, PhysConst k, NlConst q,
                                                           const double* __restrict__ src, double* __restrict__ dst,
                                                           const double* __restrict__ rho,
@@ -313,20 +315,17 @@ __global__ __launch_bounds__(BX* BY) void k_nl_collide_next(GridDims g, PhysCons
                                                           const double* __restrict__ mus, double* __restrict__ partA,
                                                           double* __restrict__ inboxA, double* __restrict__ partB,
                                                           double* __restrict__ inboxB) {
-    using Sink = NextSink<kD3Q27, BY>;
-    __shared__ double asum[Sink::SUM], aside[Sink::SIDE], bsum[Sink::SUM], bside[Sink::SIDE];
-    __shared__ double aacc[COL_ACC], bacc[COL_ACC];
+    using SinkA = NextSink<kD3Q27, BY, 2>;
+    using SinkB = NextSink<kD3Q27, BY, 1>;
+    __shared__ double asum[2][SinkA::SUM], aside[2][SinkA::SIDE], bsum[2][SinkB::SUM], bside[2][SinkB::SIDE];
+    __shared__ double aacc[col_acc<2>()], bacc[col_acc<1>()];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + BY - 1) / BY;
     const int bx = b % bxc, rest = b / bxc, by = rest % byc, bc = rest / byc;
     const int x0 = bx * BX, y0 = by * BY, z0 = bc * ZC, z1 = min(g.nz, z0 + ZC);
     const int W = min(BX, g.nx - x0), H = min(BY, g.ny - y0);
-    const int tid = threadIdx.y * BX + threadIdx.x;
-    // the second field of sb carries nothing: its sums are zero (read by the
-    // gathers, never written by the collisions)
-    for (int e = tid; e < Sink::SUM / 2; e += BX * BY) bsum[Sink::SUM / 2 + e] = 0.0;
-    for (int e = tid; e < Sink::SIDE / 2; e += BX * BY) bside[Sink::SIDE / 2 + e] = 0.0;
     for (int z = z0; z < z1; ++z) {
+        const int sb_ = (z - z0) & 1;  // the set of sums of this plane
         int tx = threadIdx.x, ty = threadIdx.y;
         opaque_thread_index(tx, ty);
         {
@@ -335,19 +334,16 @@ __global__ __launch_bounds__(BX* BY) void k_nl_collide_next(GridDims g, PhysCons
             // see whole rows
             const int lx = min(tx, W - 1), ly = min(ty, H - 1);
             const bool active = tx < W && ty < H;
-            Sink sa{asum, aside, tx, ty, W, 0};
-            Sink sb{bsum, bside, tx, ty, W, 0};
+            SinkA sa{asum[sb_], aside[sb_], tx, ty, W, 0};
+            SinkB sb{bsum[sb_], bside[sb_], tx, ty, W, 0};
             nl_collide_node<kD3Q27>(g, k, q, src, dst, rho, phi, psi, mux, mup, mus, x0 + lx, y0 + ly, z, active,
                                     sa, sb);
         }
         __syncthreads();
-        next3_col_plane<false>(g, Sink{asum, aside, 0, 0, W, 0}, aacc, partA, inboxA, x0, y0, W, H, z, z0, z1, tx,
-                               ty);
-        next3_col_plane<false>(g, Sink{bsum, bside, 0, 0, W, 0}, bacc, partB, inboxB, x0, y0, W, H, z, z0, z1, tx,
-                               ty);
-        // the next plane's collisions overwrite the sums (two sets of both
-        // sinks' sums, as the two-liquid collision keeps, would not fit the LDS)
-        __syncthreads();
+        next3_col_plane<false, 2>(g, SinkA{asum[sb_], aside[sb_], 0, 0, W, 0}, aacc, partA, inboxA, x0, y0, W, H, z,
+                                  z0, z1, tx, ty);
+        next3_col_plane<false, 1>(g, SinkB{bsum[sb_], bside[sb_], 0, 0, W, 0}, bacc, partB, inboxB, x0, y0, W, H, z,
+                                  z0, z1, tx, ty);
     }
 }
 
@@ -363,7 +359,7 @@ __global__ __launch_bounds__(NBX* NBY) void k_nl_complete(GridDims g, const doub
     if (!t.in) return;
     double r, p, s, zero;
     next3_complete(g, partA, inboxA, t.x, t.y, t.z, t.n, r, p);
-    next3_complete(g, partB, inboxB, t.x, t.y, t.z, t.n, s, zero);
+    next3_complete<1>(g, partB, inboxB, t.x, t.y, t.z, t.n, s, zero);
     rho[t.n] = r;
     phi[t.n] = p;
     psi[t.n] = s;

@@ -93,11 +93,13 @@ def box_collision(shape, ratio=1000.0, v_rel=0.04, k2=0.1, k3=0.3):
 
 
 @pytest.mark.parametrize("shape", [(18, 20, 24), (1, 8, 8), (3, 3, 3), (16, 16, 64), (17, 12, 70), (33, 5, 9),
-                                   (65, 5, 9)])
+                                   (65, 5, 9), (40, 9, 130)])
 def test_d3q27_fp64_collision(orc, shape):
     """The FP64 step against the oracle; the collision walks z-columns of 32
     planes, so the depths cover single short columns (1 to 18 planes), a
-    full column and a ragged one of 1 plane (33), and three columns (65)."""
+    full column and a ragged one of 1 plane (33), and three columns (65);
+    130 x 9 x 40 has two columns, three x tiles (the last 2 wide) and three
+    y tiles (the last 1 high) at once."""
     wl = box_collision(shape)
     say("D3Q27 FP64 ratio 1000", shape)
     fo, fg = run_both(orc, wl, 60)
