@@ -238,16 +238,39 @@ __device__ __forceinline__ void nl_collide_node(const GridDims& g, const PhysCon
                                                 int x, int y, int z, bool active, SA& sa, SB& sb) {
     using Lt = Lattice<L>;
     constexpr int Q = Lt::Q;
-    const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
-    const int64_t n = ((int64_t)z * g.ny + y) * g.nx + x;
-    const double r = rho[n], p = phi[n], s = psi[n];
+    // 32-bit node offsets from uniform per-array bases, non-temporal
+    // population traffic on D3Q27 (ld_pop / st_pop), and the three phases
+    // (stencil, f, g and h) kept apart as in the two-liquid collision
+    const Nbr32 nb = make_nbr32(x, y, z, g.nx, g.ny, g.nz);
+    const uint32_t n = (uint32_t)(((int64_t)z * g.ny + y) * g.nx + x);
+    const double r = ld(rho, n), p = ld(phi, n), s = ld(psi, n);
+    // the node's phase-field potentials, loaded with its other fields
+    const double mp = ld(mup, n), ms = ld(mus, n);
     double F[3];
-    nl_force<L>(g, nb, n, r, p, s, mux, mup, mus, F);
+    {
+        // force: gradients (1/cs2) sum_i w_i c_i v(x + c_i) of the three
+        // potentials, as grads()
+        double gx[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0}, gs[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const uint32_t m = nbr32<L>(nb, n, i, +1);
+            const double a = Lt::w[i] * ld(mux, m), b = Lt::w[i] * ld(mup, m), c = Lt::w[i] * ld(mus, m);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (Lt::c[i][d] > 0) { gx[d] += a; gp[d] += b; gs[d] += c; }
+                else if (Lt::c[i][d] < 0) { gx[d] -= a; gp[d] -= b; gs[d] -= c; }
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) F[d] = -r * (3.0 * gx[d]) - p * (3.0 * gp[d]) - s * (3.0 * gs[d]);
+        if (Lt::D == 2) F[2] = 0.0;
+    }
+    phase_fence();
     double f[Q];
     double j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        f[i] = src[(int64_t)i * g.N + n + nbr_off<L>(nb, i, -1)];
+        f[i] = ld_pop<L>(src + (size_t)i * g.N, nbr32<L>(nb, n, i, -1));
 #pragma unroll
         for (int d = 0; d < 3; ++d) j[d] += Lt::c[i][d] * f[i];
     }
@@ -257,26 +280,27 @@ __device__ __forceinline__ void nl_collide_node(const GridDims& g, const PhysCon
     collide_f<L, double>(f, r, ir, u, du, k.beta, k.inv_beta, 0.0);
     if (active) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) dst[(int64_t)i * g.N + n] = f[i];
+        for (int i = 0; i < Q; ++i) st_pop<L>(dst + (size_t)i * g.N, n, f[i]);
     }
     sa.template post_f<L, double>(f, r);
+    phase_fence();
     const double up[3] = {u[0] + 0.5 * du[0], u[1] + 0.5 * du[1], u[2] + 0.5 * du[2]};
-    const double mp = mup[n], ms = mus[n];
     double gg[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) gg[i] = src[(int64_t)(Q + i) * g.N + n + nbr_off<L>(nb, i, -1)];
+    for (int i = 0; i < Q; ++i) gg[i] = ld_pop<L>(src + (size_t)(Q + i) * g.N, nbr32<L>(nb, n, i, -1));
     collide_g<L, double>(gg, p, q.m[0] * mp + q.m[1] * ms, up, k.Gamma, k.omega_phi);
     if (active) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) dst[(int64_t)(Q + i) * g.N + n] = gg[i];
+        for (int i = 0; i < Q; ++i) st_pop<L>(dst + (size_t)(Q + i) * g.N, n, gg[i]);
     }
     sa.template post_g<L, double, Q>(gg);
+    phase_fence();
 #pragma unroll
-    for (int i = 0; i < Q; ++i) gg[i] = src[(int64_t)(2 * Q + i) * g.N + n + nbr_off<L>(nb, i, -1)];
+    for (int i = 0; i < Q; ++i) gg[i] = ld_pop<L>(src + (size_t)(2 * Q + i) * g.N, nbr32<L>(nb, n, i, -1));
     collide_g<L, double>(gg, s, q.m[2] * mp + q.m[3] * ms, up, k.Gamma, k.omega_phi);
     if (active) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) dst[(int64_t)(2 * Q + i) * g.N + n] = gg[i];
+        for (int i = 0; i < Q; ++i) st_pop<L>(dst + (size_t)(2 * Q + i) * g.N, n, gg[i]);
     }
     sb.template post_f<L, double>(gg, s);
 }
@@ -336,7 +360,8 @@ __global__ __launch_bounds__(BX* BY) void k_nl_collide_next(GridDims g, PhysCons
             const bool active = tx < W && ty < H;
             SinkA sa{asum[sb_], aside[sb_], tx, ty, W, 0};
             SinkB sb{bsum[sb_], bside[sb_], tx, ty, W, 0};
-            nl_collide_node<kD3Q27>(g, k, q, src, dst, rho, phi, psi, mux, mup, mus, x0 + lx, y0 + ly, z, active,
+            const GridDims gz = opaque_stride(g);
+            nl_collide_node<kD3Q27>(gz, k, q, src, dst, rho, phi, psi, mux, mup, mus, x0 + lx, y0 + ly, z, active,
                                     sa, sb);
         }
         __syncthreads();
