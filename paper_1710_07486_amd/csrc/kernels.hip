@@ -159,9 +159,12 @@ constexpr int CPX = BX + 2, CPY = BY + 2, CPN = CPX * CPY;
 // With PART the densities come as the partial sums and inbox entries that
 // the previous D3Q27 FP64 collision (k_collide_next3) left;
 // the kernel completes them while staging (see next3_complete) and also writes
-// the completed rho, phi of its nodes.
+// the completed rho, phi of its nodes.  Each thread fetches its entries of
+// the plane after next into registers while the block computes a plane
+// (four wavefronts per SIMD asked for, so that the registers this holds do
+// not cost occupancy).
 template <bool PART, int E, bool W>
-__global__ __launch_bounds__(BX* BY) void k_chempot_col(GridDims g, PhysConst k, double* __restrict__ rho,
+__global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(4))) void k_chempot_col(GridDims g, PhysConst k, double* __restrict__ rho,
                                                         double* __restrict__ phi, double* __restrict__ mux,
                                                         double* __restrict__ mup, const double* __restrict__ part,
                                                         const double* __restrict__ inbox) {
@@ -182,38 +185,60 @@ __global__ __launch_bounds__(BX* BY) void k_chempot_col(GridDims g, PhysConst k,
             p = phi[n];
         }
     };
-    auto load_plane = [&](int slot, int z) {
+    // the staged densities of entry e of plane z's tile with its halo
+    auto fetch = [&](int e, int z, double& r, double& p) {
         const int zw = wrap_any(z, g.nz);
-        for (int e = tid; e < CPN; e += BX * BY) {
-            const int gx = wrap_any(x0 - 1 + e % CPX, g.nx), yy = y0 - 1 + e / CPX;
-            double r, p;
-            if (W && g.walls && (yy < 0 || yy >= g.ny)) {
-                // beyond a wall: the wetting ghost of the wall-row node
-                const int top = yy >= g.ny, yw = top ? g.ny - 1 : 0;
-                double rxm, pxm, rxp, pxp, rzm, pzm, rzp, pzp;
-                get(gx == 0 ? g.nx - 1 : gx - 1, yw, zw, rxm, pxm);
-                get(gx + 1 == g.nx ? 0 : gx + 1, yw, zw, rxp, pxp);
-                get(gx, yw, zw == 0 ? g.nz - 1 : zw - 1, rzm, pzm);
-                get(gx, yw, zw + 1 == g.nz ? 0 : zw + 1, rzp, pzp);
-                get(gx, yw, zw, r, p);
-                r = wet_ghost(r, 0.5 * (rxp - rxm), 0.5 * (rzp - rzm), k.cot_rho[top]);
-                p = wet_ghost(p, 0.5 * (pxp - pxm), 0.5 * (pzp - pzm), k.cot_phi[top]);
-            } else {
-                get(gx, wrap_any(yy, g.ny), zw, r, p);
-            }
-            sr[slot][e] = r;
-            sp[slot][e] = p;
+        const int gx = wrap_any(x0 - 1 + e % CPX, g.nx), yy = y0 - 1 + e / CPX;
+        if (W && g.walls && (yy < 0 || yy >= g.ny)) {
+            // beyond a wall: the wetting ghost of the wall-row node
+            const int top = yy >= g.ny, yw = top ? g.ny - 1 : 0;
+            double rxm, pxm, rxp, pxp, rzm, pzm, rzp, pzp;
+            get(gx == 0 ? g.nx - 1 : gx - 1, yw, zw, rxm, pxm);
+            get(gx + 1 == g.nx ? 0 : gx + 1, yw, zw, rxp, pxp);
+            get(gx, yw, zw == 0 ? g.nz - 1 : zw - 1, rzm, pzm);
+            get(gx, yw, zw + 1 == g.nz ? 0 : zw + 1, rzp, pzp);
+            get(gx, yw, zw, r, p);
+            r = wet_ghost(r, 0.5 * (rxp - rxm), 0.5 * (rzp - rzm), k.cot_rho[top]);
+            p = wet_ghost(p, 0.5 * (pxp - pxm), 0.5 * (pzp - pzm), k.cot_phi[top]);
+        } else {
+            get(gx, wrap_any(yy, g.ny), zw, r, p);
         }
     };
-    load_plane(0, z0 - 1);
-    load_plane(1, z0);
+    // a plane's entries of this thread (e = tid, tid + BX BY) travel through
+    // registers: fetched a plane ahead, stored to LDS when their slot is free
+    constexpr int PER = (CPN + BX * BY - 1) / (BX * BY);
+    double nr[PER], np[PER];
+    auto fetch_plane = [&](int z) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int e = tid + j * BX * BY;
+            if (e < CPN) fetch(e, z, nr[j], np[j]);
+        }
+    };
+    auto store_plane = [&](int slot) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int e = tid + j * BX * BY;
+            if (e < CPN) {
+                sr[slot][e] = nr[j];
+                sp[slot][e] = np[j];
+            }
+        }
+    };
+    fetch_plane(z0 - 1);
+    store_plane(0);
+    fetch_plane(z0);
+    store_plane(1);
+    fetch_plane(z0 + 1);
     const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
     const int c = (threadIdx.y + 1) * CPX + threadIdx.x + 1;
     for (int zz = 0; zz < CZ; ++zz) {
         const int z = z0 + zz;
         if (z >= g.nz) break;  // uniform over the block
-        load_plane((zz + 2) % 3, z + 1);
+        store_plane((zz + 2) % 3);  // plane z + 1
         __syncthreads();
+        // plane z + 2 in flight while plane z is computed
+        if (zz + 1 < CZ && z + 1 < g.nz) fetch_plane(z + 2);
         const int below = zz % 3, centre = (zz + 1) % 3, above = (zz + 2) % 3;
         if (x < g.nx && y < g.ny) {
             const double r0 = sr[centre][c], p0 = sp[centre][c];
