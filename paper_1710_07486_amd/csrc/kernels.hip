@@ -584,10 +584,14 @@ __global__ __launch_bounds__(FIX_THREADS) void k_dens_complete2(GridDims g, doub
 constexpr int kNonTemporal = 2;
 
 // The phase-field populations pulled by one wavefront's row of the tile: LDS
-// row[i BX + d] holds direction i pulled by node x0 + d of row y in plane z
-// (nodes past a ragged edge repeat node W - 1).  Filled by LDS-DMA loads, a
+// row[i BX + d] holds direction i (i < QG, the full or reduced phase-field
+// lattice) pulled by node x0 + d of row y in plane z (nodes past a ragged
+// edge repeat node W - 1), with the halfway bounce-back of node_collide_sink
+// where walls are (a bounced direction reads the node's own slot of -c_i;
+// whether it bounces depends on the row only).  Filled by LDS-DMA loads, a
 // dword per lane (two loads per direction), so that the fetch of the next
 // plane's values holds no registers while the current plane is collided.
+template <bool WALL, int QG>
 __device__ __forceinline__ void stage_g_row(const GridDims& g, const double* __restrict__ src, double* row, int x0,
                                             int y, int z, int W, int lane) {
     using Lt = Lattice<kD3Q27>;
@@ -597,12 +601,14 @@ __device__ __forceinline__ void stage_g_row(const GridDims& g, const double* __r
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int x = x0 + min(32 * h + (lane >> 1), W - 1);
-        const Nbr32 nb = make_nbr32(x, y, z, g.nx, g.ny, g.nz);
+        const Nbr32 nb = WALL ? make_nbr32_w(g, x, y, z) : make_nbr32(x, y, z, g.nx, g.ny, g.nz);
         const uint32_t n = (uint32_t)node_index(g, x, y, z);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const char* a = (const char*)(src + (size_t)(Q + i) * g.N) +
-                            (uint32_t)(nbr32<kD3Q27>(nb, n, i, -1) * 8u + 4u * (lane & 1));
+        for (int i = 0; i < QG; ++i) {
+            const bool bb = WALL && bounce(g, y, Lt::c[i][1]);
+            const uint32_t m = bb ? n : nbr32<kD3Q27>(nb, n, i, -1);
+            const char* a = (const char*)(src + (size_t)(Q + (bb ? opp_dir(i) : i)) * g.N) +
+                            (uint32_t)(m * 8u + 4u * (lane & 1));
             // lane l fills dword l of the 64 that hold doubles 32 h .. 32 h + 31
             __builtin_amdgcn_global_load_lds((GPtr)a, (LPtr)(row + i * BX + 32 * h), 4, 0, kNonTemporal);
         }
@@ -633,10 +639,10 @@ __global__ __launch_bounds__(BX* BY) void k_collide_next3(GridDims g, PhysConst 
     // never overwrite the sums that slower threads still gather from, and one
     // barrier per plane suffices
     __shared__ double nsum[2][Sink::SUM], nside[2][Sink::SIDE], acc[col_acc<2>()];
-    // without walls on the full lattice, each wavefront's row of pulled
-    // phase-field populations is staged one plane ahead (GRowStaged)
-    constexpr bool STAGE = !WALL && !RG;
-    __shared__ double gstage[STAGE ? BY * 27 * BX : 1];
+    // each wavefront's row of pulled phase-field populations is staged one
+    // plane ahead (GRowStaged)
+    constexpr int QG = GLattice<kD3Q27, RG>::Q;
+    __shared__ double gstage[BY * QG * BX];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + BY - 1) / BY;
     const int bx = b % bxc, rest = b / bxc, by = rest % byc, bc = rest / byc;
@@ -646,8 +652,8 @@ __global__ __launch_bounds__(BX* BY) void k_collide_next3(GridDims g, PhysConst 
     const GlobalAux aux{rho, phi, mux, mup};
     // the wavefront's row (uniform over it) and its staging row
     const int wrow = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
-    double* grow = gstage + (STAGE ? wrow * 27 * BX : 0);
-    if (STAGE) stage_g_row(g, src, grow, x0, y0 + min(wrow, H - 1), z0, W, threadIdx.x);
+    double* grow = gstage + wrow * QG * BX;
+    stage_g_row<WALL, QG>(g, src, grow, x0, y0 + min(wrow, H - 1), z0, W, threadIdx.x);
     for (int z = z0; z < z1; ++z) {
         int tx = threadIdx.x, ty = threadIdx.y;
         opaque_thread_index(tx, ty);
@@ -660,21 +666,16 @@ __global__ __launch_bounds__(BX* BY) void k_collide_next3(GridDims g, PhysConst 
             const int wy = (WALL && g.walls) ? (y0 + ly == 0 ? -1 : (y0 + ly == g.ny - 1 ? 1 : 0)) : 0;
             const GridDims gz = opaque_stride(g);
             Sink sink{nsum[(z - z0) & 1], nside[(z - z0) & 1], tx, ty, W, wy};
-            if constexpr (STAGE) {
-                const GRowStaged st{grow, tx};
-                node_collide_sink<kD3Q27, double, GlobalAux, Sink, WALL, RG, GRowStaged>(
-                    gz, k, src, dst, nullptr, aux, x0 + lx, y0 + ly, z, DIAG, dv, active, sink, st);
-            } else {
-                node_collide_sink<kD3Q27, double, GlobalAux, Sink, WALL, RG>(gz, k, src, dst, nullptr, aux, x0 + lx,
-                                                                          y0 + ly, z, DIAG, dv, active, sink);
-            }
+            const GRowStaged st{grow, tx};
+            node_collide_sink<kD3Q27, double, GlobalAux, Sink, WALL, RG, GRowStaged>(
+                gz, k, src, dst, nullptr, aux, x0 + lx, y0 + ly, z, DIAG, dv, active, sink, st);
         }
         __syncthreads();
         // the next plane's phase-field pulls, staged while this plane's sums
         // are gathered and the next plane's f is collided (issued after the
         // barrier, which would otherwise wait for them; the row's reads of
         // this plane are complete at the barrier)
-        if (STAGE && z + 1 < z1) stage_g_row(g, src, grow, x0, y0 + min(wrow, H - 1), z + 1, W, tx);
+        if (z + 1 < z1) stage_g_row<WALL, QG>(g, src, grow, x0, y0 + min(wrow, H - 1), z + 1, W, tx);
         next3_col_plane<WALL>(g, Sink{nsum[(z - z0) & 1], nside[(z - z0) & 1], 0, 0, W, 0}, acc, part, inbox, x0,
                               y0, W, H, z, z0, z1, tx, ty);
     }

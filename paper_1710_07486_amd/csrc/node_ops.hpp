@@ -292,15 +292,15 @@ struct NoGPrefetch {
 // edge that run on a clamped node so that the sink sees a full wavefront).
 // W false: the lattice has no walls (the kernel carries none of their logic).
 // RG: the phase field lives on the reduced lattice (GLattice).  GPF: where
-// the pulled phase-field populations come from (a staging policy only with
-// FP64, no walls and the full lattice).
+// the pulled phase-field populations come from (a staging policy holds them
+// with the bounce-back of bounced directions applied; FP64 only).
 template <int L, typename T, typename AUX, typename SINK, bool W = true, bool RG = false,
           typename GPF = NoGPrefetch>
 __device__ __forceinline__ void node_collide_sink(const GridDims& g, const PhysConst& k, const T* __restrict__ src,
                                                   T* __restrict__ dst, const double* __restrict__ rho_ref,
                                                   const AUX& aux, int x, int y, int z, bool diag, double* dv,
                                                   bool active, SINK& sink, const GPF& gpf = GPF{}) {
-    static_assert(!GPF::on || (!W && !RG && sizeof(T) == 8), "staged phase-field pulls: FP64, no walls, full lattice");
+    static_assert(!GPF::on || sizeof(T) == 8, "staged phase-field pulls: FP64");
     using Lt = Lattice<L>;
     using R = T;
     constexpr int Q = Lt::Q;
