@@ -48,11 +48,11 @@ METRIC = "ternary ELBM MLUPS & % HBM roofline; FP32-mixed vs FP64 at stated erro
 # collision, the D2Q9 1024^2 one-launch steps, and the two kernels of a
 # three-liquid D3Q27 step together.
 TRAFFIC = {
-    "d3q27_fp64_collide": {"bytes_per_launch": 16650921269, "sources_sha256_16": "61b29d1b00607867"},
-    "d3q27_fp32_collide": {"bytes_per_launch": 9844322606, "sources_sha256_16": "61b29d1b00607867"},
-    "d2q9_fp64_step": {"bytes_per_launch": 348303910, "sources_sha256_16": "61b29d1b00607867"},
-    "d2q9_fp32_step": {"bytes_per_launch": 213693985, "sources_sha256_16": "61b29d1b00607867"},
-    "d3q27_three_liquid_step": {"bytes_per_launch": 26401613238, "sources_sha256_16": "61b29d1b00607867"},
+    "d3q27_fp64_collide": {"bytes_per_launch": 16698674771, "sources_sha256_16": "c661a55778f1debf"},
+    "d3q27_fp32_collide": {"bytes_per_launch": 9770402115, "sources_sha256_16": "c661a55778f1debf"},
+    "d2q9_fp64_step": {"bytes_per_launch": 348266778, "sources_sha256_16": "c661a55778f1debf"},
+    "d2q9_fp32_step": {"bytes_per_launch": 213648838, "sources_sha256_16": "c661a55778f1debf"},
+    "d3q27_three_liquid_step": {"bytes_per_launch": 26431485415, "sources_sha256_16": "c661a55778f1debf"},
 }
 
 
