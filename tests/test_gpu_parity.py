@@ -331,7 +331,8 @@ def tile_edge_samples(wl, rng, count):
     in the wall rows within half a tile of a contact line; in 3D the z
     of such a node is taken on the sphere), the rest anywhere.  In 3D, a
     node on the interface is moved to z = 0 or 15 mod 16 (the potential
-    pass's column edges) when one lies within 2 planes."""
+    pass's column edges, among them the collision's 32-plane column ends at
+    0 and 31 mod 32) when one lies within 2 planes."""
     import math
     nz, ny, nx = wl.shape
     ty = 4 if nz > 1 else 8
