@@ -56,10 +56,15 @@ TRAFFIC = {
 }
 
 
+# The sources of the step kernels the stored traffic was counted on (the
+# kernel files and every local header they include).
+KERNEL_SOURCES = ("kernels.hip", "kernels.hpp", "node_ops.hpp", "lattice.hpp", "next_sums.hpp", "nliquid.hip")
+
+
 def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.hpp", "node_ops.hpp", "lattice.hpp", "next_sums.hpp", "nliquid.hip"):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1710_07486_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
