@@ -148,13 +148,19 @@ __global__ __launch_bounds__(BX* BY) void k_chempot(GridDims g, PhysConst k, con
 }
 
 // Chemical potentials of D3Q27 along z-columns: the block walks CZ planes of
-// its BX x BY tile, holding three planes of rho and phi (with an x-y halo of
+// its BX x col_rows tile, holding three planes of rho and phi (with an x-y halo of
 // one node) in LDS and loading one new plane per step, so each plane is
 // fetched once per column instead of by every z-neighbour.  The Laplacian
 // terms are summed in the lattice order of node_chempot, so the potentials
 // are the same numbers.
 constexpr int CZ = 16;
-constexpr int CPX = BX + 2, CPY = BY + 2, CPN = CPX * CPY;
+constexpr int CPX = BX + 2;
+// rows of a column's tile: 8 where the pass completes partial sums (their
+// halo re-reads cost more per node), else 4
+template <bool PART>
+constexpr int col_rows() {
+    return PART ? 8 : 4;
+}
 
 // With PART the densities come as the partial sums and inbox entries that
 // the previous D3Q27 FP64 collision (k_collide_next3) left;
@@ -164,16 +170,17 @@ constexpr int CPX = BX + 2, CPY = BY + 2, CPN = CPX * CPY;
 // (four wavefronts per SIMD asked for, so that the registers this holds do
 // not cost occupancy).
 template <bool PART, int E, bool W>
-__global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(4))) void k_chempot_col(GridDims g, PhysConst k, double* __restrict__ rho,
+__global__ __launch_bounds__(BX* col_rows<PART>()) __attribute__((amdgpu_waves_per_eu(4))) void k_chempot_col(GridDims g, PhysConst k, double* __restrict__ rho,
                                                         double* __restrict__ phi, double* __restrict__ mux,
                                                         double* __restrict__ mup, const double* __restrict__ part,
                                                         const double* __restrict__ inbox) {
     using Lt = Lattice<kD3Q27>;
+    constexpr int CBY = col_rows<PART>(), CPY = CBY + 2, CPN = CPX * CPY;
     __shared__ double sr[3][CPN], sp[3][CPN];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + BY - 1) / BY;
+    const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + CBY - 1) / CBY;
     const int bx = b % bxc, rest = b / bxc, by = rest % byc, bzc = rest / byc;
-    const int x0 = bx * BX, y0 = by * BY, z0 = bzc * CZ;
+    const int x0 = bx * BX, y0 = by * CBY, z0 = bzc * CZ;
     const int tid = threadIdx.y * BX + threadIdx.x;
     // the (completed) densities of node (gx, gy, zw)
     auto get = [&](int gx, int gy, int zw, double& r, double& p) {
@@ -204,21 +211,21 @@ __global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(4))) voi
             get(gx, wrap_any(yy, g.ny), zw, r, p);
         }
     };
-    // a plane's entries of this thread (e = tid, tid + BX BY) travel through
+    // a plane's entries of this thread (e = tid, tid + BX CBY, ...) travel through
     // registers: fetched a plane ahead, stored to LDS when their slot is free
-    constexpr int PER = (CPN + BX * BY - 1) / (BX * BY);
+    constexpr int PER = (CPN + BX * CBY - 1) / (BX * CBY);
     double nr[PER], np[PER];
     auto fetch_plane = [&](int z) {
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            const int e = tid + j * BX * BY;
+            const int e = tid + j * BX * CBY;
             if (e < CPN) fetch(e, z, nr[j], np[j]);
         }
     };
     auto store_plane = [&](int slot) {
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            const int e = tid + j * BX * BY;
+            const int e = tid + j * BX * CBY;
             if (e < CPN) {
                 sr[slot][e] = nr[j];
                 sp[slot][e] = np[j];
@@ -843,14 +850,17 @@ size_t inbox3_doubles(const GridDims& g, int nf) {
 
 unsigned column_blocks(const GridDims& g) { return (unsigned)(tiles3(g) * zcols(g.nz)); }
 
-static inline unsigned col_blocks(const GridDims& g) {
-    return (unsigned)(((g.nx + BX - 1) / BX) * ((g.ny + BY - 1) / BY) * ((g.nz + CZ - 1) / CZ));
+static inline unsigned col_blocks(const GridDims& g, int rows) {
+    return (unsigned)(((g.nx + BX - 1) / BX) * ((g.ny + rows - 1) / rows) * ((g.nz + CZ - 1) / CZ));
 }
 
 template <int L, typename T, int E>
 static hipError_t launch_step_parts(const StepArgs& a, int part) {
     const dim3 blk(BX, BY, 1);
     const dim3 grd(grid_blocks(a.g), 1, 1);
+    // z-column potential passes: without (0) and with (1) partial sums
+    const dim3 cb0(BX, col_rows<false>(), 1), cb1(BX, col_rows<true>(), 1);
+    const unsigned cg0 = col_blocks(a.g, col_rows<false>()), cg1 = col_blocks(a.g, col_rows<true>());
     const bool w = a.g.walls != 0, rg = a.k.glat != 0;
     if (part == 0) {
         if (rg) k_moments<L, T, true, true><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
@@ -859,11 +869,11 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
     } else if (part == 1) {
         if (L == kD3Q27) {
             if (w)
-                k_chempot_col<false, E, true><<<col_blocks(a.g), blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux,
-                                                                                   a.mup, nullptr, nullptr);
+                k_chempot_col<false, E, true><<<cg0, cb0, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup,
+                                                                         nullptr, nullptr);
             else
-                k_chempot_col<false, E, false><<<col_blocks(a.g), blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux,
-                                                                                    a.mup, nullptr, nullptr);
+                k_chempot_col<false, E, false><<<cg0, cb0, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup,
+                                                                          nullptr, nullptr);
         } else {
             if (w) k_chempot<L, E, true><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup);
             else k_chempot<L, E, false><<<grd, blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup);
@@ -900,11 +910,11 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
     } else if (part == 5) {
         if (L != kD3Q27 || !a.part3 || !a.inbox3) return hipErrorInvalidValue;
         if (w)
-            k_chempot_col<true, E, true><<<col_blocks(a.g), blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup,
-                                                                              a.part3, a.inbox3);
+            k_chempot_col<true, E, true><<<cg1, cb1, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup,
+                                                                    a.part3, a.inbox3);
         else
-            k_chempot_col<true, E, false><<<col_blocks(a.g), blk, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux,
-                                                                               a.mup, a.part3, a.inbox3);
+            k_chempot_col<true, E, false><<<cg1, cb1, 0, a.stream>>>(a.g, a.k, a.rho, a.phi, a.mux, a.mup,
+                                                                     a.part3, a.inbox3);
     } else if (part == 6) {
         if (L != kD3Q27 || Deviation<T>::on || !a.part3 || !a.inbox3) return hipErrorInvalidValue;
         auto* sp = (const double*)a.src;
