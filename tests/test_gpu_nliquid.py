@@ -3,7 +3,7 @@ three-liquid model and against closed forms.
 
 Parity: drops of the three liquids in gas with unequal kappas (so the
 mobility matrix is full), D2Q9 with ragged tiles and D3Q27 single- and
-multi-tile, every field within 1e-10 of the oracle.  Consistency: the
+multi-tile and across z-columns, every field within 1e-10 of the oracle.  Consistency: the
 oracle pin's flat liquid-1 / liquid-3 interface, the GPU within 1e-9 of the
 oracle and its absent liquid 2 below the density perturbation.
 Neumann angles: a lens of liquid 1 between liquids 2 and 3 (no gas) at
@@ -82,8 +82,11 @@ def errors(fo, fg):
     return e
 
 
+# D3Q27 depths: single short z-columns, and (33) a full 32-plane column with
+# a one-plane remainder, so that the column-end sums of (rho, phi) and of psi
+# cross between columns
 CASES = {"d2q9_100x37": (0, (1, 37, 100), 300), "d3q27_40x18x12": (1, (12, 18, 40), 60),
-         "d3q27_200x13x9": (1, (9, 13, 200), 60)}
+         "d3q27_200x13x9": (1, (9, 13, 200), 60), "d3q27_20x9x33": (1, (33, 9, 20), 60)}
 
 
 @pytest.mark.parametrize("case", list(CASES))
