@@ -72,7 +72,7 @@ def test_d2q9_walls_fp64_parity(orc, shape):
         assert v <= 1e-10, (k, v)
 
 
-SHAPES_3D = [(20, 18, 16), (33, 10, 7)]
+SHAPES_3D = [(20, 18, 16), (33, 10, 7), (70, 9, 33)]  # the last: two z-columns of the FP64 collision
 
 
 @pytest.mark.parametrize("shape", SHAPES_3D, ids=[f"{a}x{b}x{c}" for a, b, c in SHAPES_3D])
