@@ -222,6 +222,13 @@ int telbm_read(telbm_solver *s, int field, double *out, int on_device);
  * (with `out` filled) if the state is unstable. */
 int telbm_diagnostics(telbm_solver *s, telbm_diag *out);
 
+/* The diagnostics taken last, by a diagnosed step (diag_every) or by
+ * telbm_diagnostics, without a new pass: a step's own reduction costs no
+ * extra launch.  `out->step` is the step whose starting state they describe
+ * (-1: none taken since telbm_init_fields).  Synchronises.  Returns
+ * TELBM_ERR_UNSTABLE (with `out` filled) if that state was unstable. */
+int telbm_last_diagnostics(telbm_solver *s, telbm_diag *out);
+
 /* Wait for the solver's stream; reports pending instability. */
 int telbm_sync(telbm_solver *s);
 

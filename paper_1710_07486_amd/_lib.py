@@ -75,6 +75,7 @@ PROTOTYPES = {
     "telbm_step": (_i, [_vp, _i64]),
     "telbm_read": (_i, [_vp, _i, _vp, _i]),
     "telbm_diagnostics": (_i, [_vp, ctypes.POINTER(TelbmDiag)]),
+    "telbm_last_diagnostics": (_i, [_vp, ctypes.POINTER(TelbmDiag)]),
     "telbm_sync": (_i, [_vp]),
     "telbm_step_count": (_i, [_vp, ctypes.POINTER(_i64)]),
     "telbm_time_kernels": (_i, [_vp, _i64, _pd, ctypes.POINTER(_i)]),

@@ -664,6 +664,13 @@ int telbm_diagnostics(telbm_solver* s, telbm_diag* out) {
     return rc;
 }
 
+int telbm_last_diagnostics(telbm_solver* s, telbm_diag* out) {
+    if (!s || !out) return TELBM_ERR_INVAL;
+    int rc = telbm_sync(s);
+    *out = s->last;
+    return rc;
+}
+
 int telbm_step_count(const telbm_solver* s, int64_t* steps) {
     if (!s || !steps) return TELBM_ERR_INVAL;
     *steps = s->steps;

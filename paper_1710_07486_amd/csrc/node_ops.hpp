@@ -283,9 +283,25 @@ struct NoGPrefetch {
     __device__ __forceinline__ double pulled(int) const { return 0.0; }
 };
 
+// Adds one node's diagnostics to a thread's running values over the nodes it
+// has collided (the collisions below merge, so that a thread may collide any
+// number of nodes): sums of mass, phase field and momentum, the largest
+// speed, the smallest density, the range of the stabiliser and the count of
+// non-finite nodes.  A thread starts from {0, 0, 0, 0, 0, 0, +inf, +inf,
+// -inf, 0}.
+__device__ __forceinline__ void diag_merge(double* dv, const double* d1) {
+    for (int v = 0; v < 5; ++v) dv[v] += d1[v];
+    dv[5] = fmax(dv[5], d1[5]);
+    dv[6] = fmin(dv[6], d1[6]);
+    dv[7] = fmin(dv[7], d1[7]);
+    dv[8] = fmax(dv[8], d1[8]);
+    dv[9] += d1[9];
+}
+
 // Phase 3: pull f, g; force from the excess potentials; KBC with
 // exact-difference forcing; phase-field BGK; write the node's own slots.
-// If diag, dv receives {rho, phi, j (3), |u_phys|, rho, gamma, gamma, bad}.
+// If diag, the node's {rho, phi, j (3), |u_phys|, rho, gamma, gamma, bad} are
+// merged into dv (diag_merge).
 // The three sub-phases (stencil, f, g) are kept apart by scheduling barriers
 // so that their loads do not all become live at once.  With active false the
 // node is computed but nothing is stored or reported (lanes past a ragged
@@ -387,16 +403,9 @@ __device__ __forceinline__ void node_collide_sink(const GridDims& g, const PhysC
         const double uz = double(jz) * ir + 0.5 * F[2] * ir;
         const double um = sqrt(ux * ux + uy * uy + uz * uz);
         const bool bad = !(isfinite(r) && isfinite(p) && isfinite(um)) || !(r > 0.0);
-        dv[0] = r;
-        dv[1] = p;
-        dv[2] = double(jx);
-        dv[3] = double(jy);
-        dv[4] = double(jz);
-        dv[5] = bad ? INFINITY : um;
-        dv[6] = r;
-        dv[7] = gam;
-        dv[8] = gam;
-        dv[9] = bad ? 1.0 : 0.0;
+        const double d1[kDiag] = {r, p, double(jx), double(jy), double(jz), bad ? INFINITY : um,
+                                  r, gam, gam, bad ? 1.0 : 0.0};
+        diag_merge(dv, d1);
     }
 }
 
@@ -632,16 +641,9 @@ __device__ __forceinline__ void node_collide_pair(const GridDims& g, const PhysC
         const double uz = double(jz) * ir + 0.5 * F[2] * ir;
         const double um = sqrt(ux * ux + uy * uy + uz * uz);
         const bool bad = !(isfinite(r) && isfinite(p) && isfinite(um)) || !(r > 0.0);
-        dv[0] = r;
-        dv[1] = p;
-        dv[2] = double(jx);
-        dv[3] = double(jy);
-        dv[4] = double(jz);
-        dv[5] = bad ? INFINITY : um;
-        dv[6] = r;
-        dv[7] = gam;
-        dv[8] = gam;
-        dv[9] = bad ? 1.0 : 0.0;
+        const double d1[kDiag] = {r, p, double(jx), double(jy), double(jz), bad ? INFINITY : um,
+                                  r, gam, gam, bad ? 1.0 : 0.0};
+        diag_merge(dv, d1);
     }
 }
 
@@ -660,16 +662,7 @@ __device__ __forceinline__ void tile_collide_pair(const GridDims& g, const PhysC
         const int kk = base + wave * 32 + (lane & 31);
         const int x = x0 + kk % TW, y = y0 + kk / TW;
         if (kk < TW * TH && x < g.nx && y < g.ny && z < g.nz) {
-            double d1[kDiag] = {0, 0, 0, 0, 0, 0, INFINITY, INFINITY, -INFINITY, 0};
-            node_collide_pair<L, T, W>(g, k, src, dst, rho_ref, rho, phi, mux, mup, x, y, z, side, diag, d1);
-            if (diag) {
-                for (int v = 0; v < 5; ++v) dv[v] += d1[v];
-                dv[5] = fmax(dv[5], d1[5]);
-                dv[6] = fmin(dv[6], d1[6]);
-                dv[7] = fmin(dv[7], d1[7]);
-                dv[8] = fmax(dv[8], d1[8]);
-                dv[9] += d1[9];
-            }
+            node_collide_pair<L, T, W>(g, k, src, dst, rho_ref, rho, phi, mux, mup, x, y, z, side, diag, dv);
         }
     }
 }

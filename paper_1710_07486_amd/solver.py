@@ -203,8 +203,16 @@ class Solver:
         return f
 
     def diagnostics(self, check: bool = True) -> dict:
+        """Diagnostics of the current state (a diagnostic pass if none is taken)."""
+        return self._diag(self.L.telbm_diagnostics, check)
+
+    def last_diagnostics(self, check: bool = True) -> dict:
+        """The diagnostics taken last (by a diagnosed step or a pass), no new pass."""
+        return self._diag(self.L.telbm_last_diagnostics, check)
+
+    def _diag(self, fn, check: bool) -> dict:
         d = TelbmDiag()
-        rc = self.L.telbm_diagnostics(self.h, ctypes.byref(d))
+        rc = fn(self.h, ctypes.byref(d))
         if check or rc != _lib.ERR_UNSTABLE:
             _check(rc, self.h)
         return {"step": d.step, "mass": d.mass, "phi_total": d.phi_total, "mom": list(d.mom),

@@ -185,6 +185,65 @@ def test_d3q27_multi_tile(orc, shape, case):
         assert e["rho"] <= 1e-5 and e["phi"] <= 1e-5 and e["u"] <= 1e-4
 
 
+DIAG_CASES = {"fp64": (0, 0), "fp32": (1, 0), "fp64_walls": (0, 1), "fp32_walls": (1, 1)}
+
+
+@pytest.mark.parametrize("case", list(DIAG_CASES))
+def test_step_diagnostics_cover_every_plane_3d(orc, case):
+    """A diagnosed D3Q27 step reduces over every node: its own diagnostics of
+    the starting state (read back without another pass) equal the oracle's
+    sums and extremes over that state, and a diagnostic
+    pass over the same state, on a 20 x 9 x 70 box whose collisions walk
+    several z-columns (the drops straddle the column ends), periodic and
+    walled."""
+    import math
+    import paper_1710_07486_amd as T
+    precision, walls = DIAG_CASES[case]
+    wl = wide_box((70, 9, 20), walls=walls)
+    say("D3Q27 step diagnostics", case)
+    po, pl, rho, phi, u = make(orc, wl, precision)
+    if walls:
+        pl.walls = 1
+        ang = dict(theta_rho_lo=math.radians(60.0), theta_phi_lo=math.radians(75.0),
+                   theta_rho_hi=math.radians(115.0), theta_phi_hi=math.radians(100.0))
+        for key, v in ang.items():
+            setattr(po, key, v)
+            setattr(pl, key, v)
+    st = orc.State(po, rho, phi, u)
+    fo = st.fields()
+    # the oracle's totals before its first step: sum rho, sum phi, sum j (3)
+    ref = st.run(1, diag=True)[0]
+    umax = float(np.sqrt((fo["u"] ** 2).sum(axis=0)).max())
+    pl.diag_every = 1
+    with T.Solver(pl) as s:
+        s.init_fields(rho, phi, u)
+        assert s.last_diagnostics()["step"] == -1
+        d0 = s.diagnostics()
+        s.step(1)
+        d = s.last_diagnostics()
+    print("step diagnostics", d, "pass", d0, "oracle", ref, umax, flush=True)
+    assert d["step"] == 0 and d0["step"] == 0
+    assert d["nonfinite"] == 0 and d0["nonfinite"] == 0
+    # FP64: the reductions and the oracle agree to round-off; FP32-mixed: the
+    # stored deviations round the state at about 1e-8 of the densities
+    tol = 1e-12 if precision == 0 else 1e-6
+    mass = ref[0]
+    for dd in (d, d0):
+        assert abs(dd["mass"] / mass - 1) < tol, (dd["mass"], mass)
+        assert abs(dd["phi_total"] - ref[1]) < tol * abs(mass)
+        assert np.abs(np.array(dd["mom"]) - ref[2:5]).max() < tol * abs(mass)
+        assert abs(dd["min_rho"] / fo["rho"].min() - 1) < tol
+        assert abs(dd["max_u"] / umax - 1) < (1e-8 if precision == 0 else 1e-4)
+        # the stabiliser where a node sits at equilibrium is 0/0 (either value
+        # collides alike): its range is checked for sense, not against the oracle
+        assert 1.0 < dd["gamma_min"] <= dd["gamma_max"] < 3.0
+    # the step's reduction and the pass see the same state (the phase-field
+    # total cancels, so it is held to the scale of the mass)
+    for key in ("mass", "max_u", "min_rho", "gamma_min", "gamma_max"):
+        assert abs(d[key] - d0[key]) <= 1e-12 * abs(d0[key]), key
+    assert abs(d["phi_total"] - d0["phi_total"]) <= 1e-12 * abs(mass)
+
+
 def test_init_rejects_bad_fields(orc):
     import paper_1710_07486_amd as T
     wl = W.lens(32, 32, radius=6, ratio=10.0)
