@@ -48,11 +48,11 @@ METRIC = "ternary ELBM MLUPS & % HBM roofline; FP32-mixed vs FP64 at stated erro
 # collision, the D2Q9 1024^2 one-launch steps, and the two kernels of a
 # three-liquid D3Q27 step together.
 TRAFFIC = {
-    "d3q27_fp64_collide": {"bytes_per_launch": 16660028255, "sources_sha256_16": "5183b050689d29ad"},
-    "d3q27_fp32_collide": {"bytes_per_launch": 9853748776, "sources_sha256_16": "5183b050689d29ad"},
-    "d2q9_fp64_step": {"bytes_per_launch": 348293944, "sources_sha256_16": "5183b050689d29ad"},
-    "d2q9_fp32_step": {"bytes_per_launch": 213656579, "sources_sha256_16": "5183b050689d29ad"},
-    "d3q27_three_liquid_step": {"bytes_per_launch": 26408324488, "sources_sha256_16": "5183b050689d29ad"},
+    "d3q27_fp64_collide": {"bytes_per_launch": 16677669424, "sources_sha256_16": "b5b1ae43bbe095d8"},
+    "d3q27_fp32_collide": {"bytes_per_launch": 9832652450, "sources_sha256_16": "b5b1ae43bbe095d8"},
+    "d2q9_fp64_step": {"bytes_per_launch": 348301261, "sources_sha256_16": "b5b1ae43bbe095d8"},
+    "d2q9_fp32_step": {"bytes_per_launch": 213676621, "sources_sha256_16": "b5b1ae43bbe095d8"},
+    "d3q27_three_liquid_step": {"bytes_per_launch": 26418305138, "sources_sha256_16": "b5b1ae43bbe095d8"},
 }
 
 
