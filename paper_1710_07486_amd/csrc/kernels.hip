@@ -97,20 +97,53 @@ __device__ void diag_block_reduce(double* vals, double* __restrict__ out) {
 // ---------------------------------------------------------------------------
 // W: instance for lattices with walls (the periodic instance carries none of
 // the wall logic and keeps its registers).
+
+// Planes a collision block walks along z on D3Q27: a node's stencil fields
+// on the plane above it are read again by the same block one plane later,
+// while they are still in its XCD's L2.  Measured on the FP32 pair split at
+// 256^3 (64 x 4 tiles): 2.34 ms at depth 1, 2.29 at 2, 2.30 at 4, 2.34 at 8,
+// 2.37 at 16 (deeper columns leave fewer blocks to balance the launch's tail).
+constexpr int kCollideDepth = 2;
+template <int L>
+constexpr int collide_depth() {
+    return L == kD3Q27 ? kCollideDepth : 1;
+}
+// Tile width of the D3Q27 collision and FP32 moment pass blocks (BX BY
+// nodes of one plane: 256 x 1).  A pull shifted along x spans one more cache
+// line than its row, which the neighbouring tile fetches again: wider tiles
+// have fewer such edges.  Measured at 256^3 (FP32 pair split, 64 x 4 ->
+// 128 x 2 -> 256 x 1): collision 2.289 -> 2.270 -> 2.231 ms, moment pass
+// 0.853 -> 0.833 -> 0.830 ms.
+constexpr int kTileW3 = 256;
+template <int L>
+constexpr int collide_tile_w() {
+    return L == kD3Q27 ? kTileW3 : BX;
+}
+static_assert(BX * BY % kTileW3 == 0, "tiles of BX BY nodes");
+
 template <int L, typename T, bool W, bool RG>
 __global__ __launch_bounds__(BX* BY) void k_moments(GridDims g, const T* __restrict__ pop,
                                                     const double* __restrict__ rho_ref,
                                                     double* __restrict__ rho, double* __restrict__ phi) {
-    const Tile t = tile_coords(g);
     if constexpr (Deviation<T>::on && L == kD3Q27) {
-        // FP32 D3Q27 (the moment pass of every step): the reference densities
-        // of the pull sources come from an LDS copy of the tile with a halo of
-        // one node in x, y and z instead of 27 scattered loads per node
+        // FP32 D3Q27 (the moment pass of every step), on MW x MH tiles: the
+        // reference densities of the pull sources come from an LDS copy of
+        // the tile with a halo of one node in x, y and z instead of 27
+        // scattered loads per node
         using Lt = Lattice<L>;
-        constexpr int RX = BX + 2, RY = BY + 2, RP = RX * RY;
+        constexpr int MW = kTileW3, MH = BX * BY / MW;
+        constexpr int RX = MW + 2, RY = MH + 2, RP = RX * RY;
         __shared__ double sref[3][RP];
-        const int x0 = t.x - (int)threadIdx.x, y0 = t.y - (int)threadIdx.y;
-        for (int e = threadIdx.y * BX + threadIdx.x; e < 3 * RP; e += BX * BY) {
+        const int b = xcd_remap(blockIdx.x, gridDim.x);
+        const int bxc = (g.nx + MW - 1) / MW, byc = (g.ny + MH - 1) / MH;
+        const int x0 = (b % bxc) * MW, y0 = (b / bxc % byc) * MH;
+        const int lin = threadIdx.y * BX + threadIdx.x, lx = lin % MW, ly = lin / MW;
+        Tile t;
+        t.x = x0 + lx;
+        t.y = y0 + ly;
+        t.z = b / bxc / byc;
+        t.in = t.x < g.nx && t.y < g.ny && t.z < g.nz;
+        for (int e = lin; e < 3 * RP; e += BX * BY) {
             const int pl = e / RP, q = e % RP;
             auto wr = [](int v, int m) { v %= m; return v < 0 ? v + m : v; };
             const int gx = wr(x0 - 1 + q % RX, g.nx), gy = wr(y0 - 1 + q / RX, g.ny);
@@ -121,7 +154,7 @@ __global__ __launch_bounds__(BX* BY) void k_moments(GridDims g, const T* __restr
         if (!t.in) return;
         const Nbr nb = make_nbr(t.x, t.y, t.z, g.nx, g.ny, g.nz);
         const int64_t n = node_index(g, t.x, t.y, t.z);
-        const int c0 = ((int)threadIdx.y + 1) * RX + (int)threadIdx.x + 1;
+        const int c0 = (ly + 1) * RX + lx + 1;
         double r = 0.0, p = 0.0;
 #pragma unroll
         for (int i = 0; i < Lt::Q; ++i) {
@@ -135,6 +168,7 @@ __global__ __launch_bounds__(BX* BY) void k_moments(GridDims g, const T* __restr
         rho[n] = r;
         phi[n] = p;
     } else {
+        const Tile t = tile_coords(g);
         if (t.in) node_moments<L, T, W, RG>(g, pop, rho_ref, rho, phi, t.x, t.y, t.z);
     }
 }
@@ -271,17 +305,6 @@ __global__ __launch_bounds__(BX* col_rows<PART>()) __attribute__((amdgpu_waves_p
     }
 }
 
-// Planes a collision block walks along z on D3Q27: a node's stencil fields
-// on the plane above it are read again by the same block one plane later,
-// while they are still in its XCD's L2.  Measured on the FP32 pair split at
-// 256^3: 2.34 ms at depth 1, 2.29 at 2, 2.30 at 4, 2.34 at 8, 2.37 at 16
-// (deeper columns leave fewer blocks to balance the tail of the launch).
-constexpr int kCollideDepth = 2;
-template <int L>
-constexpr int collide_depth() {
-    return L == kD3Q27 ? kCollideDepth : 1;
-}
-
 template <int L, typename T, bool RG, bool W = false>
 __global__ __launch_bounds__(BX* BY) void k_collide(GridDims g, PhysConst k, const T* __restrict__ src,
                                                     T* __restrict__ dst, const double* __restrict__ rho_ref,
@@ -290,17 +313,17 @@ __global__ __launch_bounds__(BX* BY) void k_collide(GridDims g, PhysConst k, con
                                                     const double* __restrict__ mux,
                                                     const double* __restrict__ mup,
                                                     double* __restrict__ partials, int diag) {
-    // the block's tile of BX x BY nodes over planes [z0, z1) of its z-column
+    // the block's tile of TW x TH nodes over planes [z0, z1) of its z-column
     // (two lanes per node in the pair split)
-    constexpr int ZD = collide_depth<L>();
+    constexpr int ZD = collide_depth<L>(), TW = collide_tile_w<L>(), TH = BX * BY / TW;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int bxc = (g.nx + BX - 1) / BX, byc = (g.ny + BY - 1) / BY;
+    const int bxc = (g.nx + TW - 1) / TW, byc = (g.ny + TH - 1) / TH;
     const int bx = b % bxc, rest = b / bxc, by = rest % byc, bc = rest / byc;
     const int z0 = bc * ZD, z1 = min(g.nz, z0 + ZD);
     double dv[kDiag] = {0, 0, 0, 0, 0, 0, INFINITY, INFINITY, -INFINITY, 0};
     for (int z = z0; z < z1; ++z) {
         const GridDims gz = ZD > 1 ? opaque_stride(g) : g;
-        tile_collide<L, T, BX * BY, RG, W>(gz, k, src, dst, rho_ref, rho, phi, mux, mup, bx * BX, by * BY, z, BX, BY,
+        tile_collide<L, T, BX * BY, RG, W>(gz, k, src, dst, rho_ref, rho, phi, mux, mup, bx * TW, by * TH, z, TW, TH,
                                          threadIdx.y * BX + threadIdx.x, diag != 0, dv);
     }
     if (diag) diag_block_reduce(dv, partials);
@@ -851,10 +874,17 @@ static inline unsigned grid_blocks(const GridDims& g) {
     return (unsigned)(((g.nx + BX - 1) / BX) * ((g.ny + BY - 1) / BY) * g.nz);
 }
 
+template <int L, typename T>
+static inline unsigned moments_grid(const GridDims& g) {
+    if (!(Deviation<T>::on && L == kD3Q27)) return grid_blocks(g);
+    constexpr int MW = kTileW3, MH = BX * BY / MW;
+    return (unsigned)(((g.nx + MW - 1) / MW) * ((g.ny + MH - 1) / MH) * g.nz);
+}
+
 template <int L>
 static inline unsigned collide_grid(const GridDims& g) {
-    constexpr int ZD = collide_depth<L>();
-    return (unsigned)(((g.nx + BX - 1) / BX) * ((g.ny + BY - 1) / BY) * ((g.nz + ZD - 1) / ZD));
+    constexpr int ZD = collide_depth<L>(), TW = collide_tile_w<L>(), TH = BX * BY / TW;
+    return (unsigned)(((g.nx + TW - 1) / TW) * ((g.ny + TH - 1) / TH) * ((g.nz + ZD - 1) / ZD));
 }
 
 unsigned collide_blocks(const GridDims& g) { return grid_blocks(g); }
@@ -887,9 +917,10 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
     const unsigned cg0 = col_blocks(a.g, col_rows<false>()), cg1 = col_blocks(a.g, col_rows<true>());
     const bool w = a.g.walls != 0, rg = a.k.glat != 0;
     if (part == 0) {
-        if (rg) k_moments<L, T, true, true><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
-        else if (w) k_moments<L, T, true, false><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
-        else k_moments<L, T, false, false><<<grd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
+        const dim3 mgrd(moments_grid<L, T>(a.g), 1, 1);
+        if (rg) k_moments<L, T, true, true><<<mgrd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
+        else if (w) k_moments<L, T, true, false><<<mgrd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
+        else k_moments<L, T, false, false><<<mgrd, blk, 0, a.stream>>>(a.g, (const T*)a.src, a.rho_ref, a.rho, a.phi);
     } else if (part == 1) {
         if (L == kD3Q27) {
             if (w)
