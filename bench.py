@@ -48,11 +48,11 @@ METRIC = "ternary ELBM MLUPS & % HBM roofline; FP32-mixed vs FP64 at stated erro
 # collision, the D2Q9 1024^2 one-launch steps, and the two kernels of a
 # three-liquid D3Q27 step together.
 TRAFFIC = {
-    "d3q27_fp64_collide": {"bytes_per_launch": 16677669424, "sources_sha256_16": "b5b1ae43bbe095d8"},
-    "d3q27_fp32_collide": {"bytes_per_launch": 9832652450, "sources_sha256_16": "b5b1ae43bbe095d8"},
-    "d2q9_fp64_step": {"bytes_per_launch": 348301261, "sources_sha256_16": "b5b1ae43bbe095d8"},
-    "d2q9_fp32_step": {"bytes_per_launch": 213676621, "sources_sha256_16": "b5b1ae43bbe095d8"},
-    "d3q27_three_liquid_step": {"bytes_per_launch": 26418305138, "sources_sha256_16": "b5b1ae43bbe095d8"},
+    "d3q27_fp64_collide": {"bytes_per_launch": 16637557697, "sources_sha256_16": "0ccfad9655671ef3"},
+    "d3q27_fp32_collide": {"bytes_per_launch": 9808557663, "sources_sha256_16": "0ccfad9655671ef3"},
+    "d2q9_fp64_step": {"bytes_per_launch": 348271164, "sources_sha256_16": "0ccfad9655671ef3"},
+    "d2q9_fp32_step": {"bytes_per_launch": 213591992, "sources_sha256_16": "0ccfad9655671ef3"},
+    "d3q27_three_liquid_step": {"bytes_per_launch": 26397038070, "sources_sha256_16": "0ccfad9655671ef3"},
 }
 
 
