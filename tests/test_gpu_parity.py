@@ -427,8 +427,10 @@ FULL_CASES = ["d3q27_256_fp64", "d3q27_256_mixed", "d2q9_1024_fp64", "d2q9_1024_
 
 
 def tile_edge_samples(wl, rng, count):
-    """`count` nodes on tile edges of the step kernels (x = 0 or 63 mod 64;
-    y = 0 or the last row of a tile: 4 rows in 3D, 8 in 2D), three in four
+    """`count` nodes on tile edges of the step kernels (x = 0 or 63 mod 64,
+    among them the 256-node rows' ends 0 and 255 mod 256 of the D3Q27 FP32
+    tiles; y = 0 or the last row of a 64 x 4 tile in 3D, 64 x 8 in 2D, where
+    every row is a 256 x 1 tile's), three in four
     on a drop interface (within 3 nodes of its starting radius, or with walls
     in the wall rows within half a tile of a contact line; in 3D the z
     of such a node is taken on the sphere), the rest anywhere.  In 3D, a
