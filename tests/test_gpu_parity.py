@@ -106,6 +106,36 @@ def test_d3q27_fp64_collision(orc, shape):
     check_fp64(fo, fg)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_d3q27_long_horizon(orc, precision):
+    """1,000 steps of a D3Q27 drop collision at density ratio 1000 (70 x 12 x
+    36: two x tiles, the last 6 wide, three y tiles and two z-columns of the
+    FP64 collision, the last 4 deep) element by element against the oracle:
+    the drops meet and merge (largest speed 0.075 falling to 0.004).  FP64
+    within 1e-10; FP32-mixed within its stated bars, 1e-5 for rho and phi
+    and 1e-4 of the largest velocity (measured 1.6e-6, 2.3e-6, 9.1e-6)."""
+    import paper_1710_07486_amd as T
+    wl = wide_box((36, 12, 70))
+    say("D3Q27 1000 steps", precision)
+    po, pl, rho, phi, u = make(orc, wl, precision)
+    st = orc.State(po, rho, phi, u)
+    st.run(1000)
+    fo = st.fields()
+    with T.Solver(pl) as s:
+        s.init_fields(rho, phi, u)
+        s.step(1000)
+        fg = s.fields()
+    assert np.isfinite(fo["rho"]).all() and fo["rho"].max() > 0.9 * po.rho_l
+    if precision == 0:
+        check_fp64(fo, fg)
+    else:
+        e = {"rho": rel(fg["rho"], fo["rho"]), "phi": rel(fg["phi"], fo["phi"]),
+             "u": rel(fg["u"], fo["u"], 1e-14),
+             "rho_mean": float(np.abs(fg["rho"] - fo["rho"]).mean() / np.abs(fo["rho"]).mean())}
+        print("fp32-mixed errors after 1000 steps", e, flush=True)
+        assert e["rho"] <= 1e-5 and e["phi"] <= 1e-5 and e["u"] <= 1e-4, e
+
+
 @pytest.mark.parametrize("lattice", [0, 1])
 def test_fp32_mixed_error_vs_oracle(orc, lattice):
     if lattice == 0:
