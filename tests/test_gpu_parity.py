@@ -258,7 +258,8 @@ def test_d3q27_rows_wider_than_a_tile(orc, case):
         assert e["rho"] <= 1e-5 and e["phi"] <= 1e-5 and e["u"] <= 1e-4
 
 
-DIAG_CASES = {"fp64": (0, 0), "fp32": (1, 0), "fp64_walls": (0, 1), "fp32_walls": (1, 1)}
+DIAG_CASES = {"fp64": (0, 0, 0), "fp32": (1, 0, 0), "fp64_d3q7": (0, 1, 0), "fp64_walls": (0, 0, 1),
+              "fp32_walls": (1, 0, 1)}
 
 
 @pytest.mark.parametrize("case", list(DIAG_CASES))
@@ -268,13 +269,14 @@ def test_step_diagnostics_cover_every_plane_3d(orc, case):
     sums and extremes over that state, and a diagnostic
     pass over the same state, on a 20 x 9 x 70 box whose collisions walk
     several z-columns (the drops straddle the column ends), periodic and
-    walled."""
+    walled, and with the reduced phase-field lattice."""
     import math
     import paper_1710_07486_amd as T
-    precision, walls = DIAG_CASES[case]
+    precision, glat, walls = DIAG_CASES[case]
     wl = wide_box((70, 9, 20), walls=walls)
     say("D3Q27 step diagnostics", case)
     po, pl, rho, phi, u = make(orc, wl, precision)
+    po.glattice = pl.glattice = glat
     if walls:
         pl.walls = 1
         ang = dict(theta_rho_lo=math.radians(60.0), theta_phi_lo=math.radians(75.0),
