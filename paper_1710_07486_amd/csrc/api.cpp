@@ -254,6 +254,7 @@ StepArgs args_of(telbm_solver* s, bool forward) {
     a.part3 = s->part3;
     a.inbox3 = s->inbox3;
     a.partials = s->partials;
+    a.partials_blocks = collide_blocks(s->g);
     a.diag_out = s->diag_dev;
     a.diag = 0;
     a.stream = s->stream;

@@ -887,7 +887,6 @@ static inline unsigned collide_grid(const GridDims& g) {
     return (unsigned)(((g.nx + TW - 1) / TW) * ((g.ny + TH - 1) / TH) * ((g.nz + ZD - 1) / ZD));
 }
 
-unsigned collide_blocks(const GridDims& g) { return grid_blocks(g); }
 
 unsigned fused_tiles(const GridDims& g) { return (unsigned)(((g.nx + BX - 1) / BX) * ((g.ny + FBY - 1) / FBY)); }
 
@@ -902,6 +901,16 @@ size_t inbox3_doubles(const GridDims& g, int nf) {
 }
 
 unsigned column_blocks(const GridDims& g) { return (unsigned)(tiles3(g) * zcols(g.nz)); }
+
+// Blocks of the largest launch on this grid that leaves per-block
+// diagnostics (the size of the partials buffer): the plain collision of
+// either lattice, the z-column collision and the fused 2D step.
+unsigned collide_blocks(const GridDims& g) {
+    unsigned m = grid_blocks(g);
+    for (unsigned v : {collide_grid<kD2Q9>(g), collide_grid<kD3Q27>(g), column_blocks(g), fused_tiles(g)})
+        m = v > m ? v : m;
+    return m;
+}
 
 static inline unsigned col_blocks(const GridDims& g, int rows) {
     return (unsigned)(((g.nx + BX - 1) / BX) * ((g.ny + rows - 1) / rows) * ((g.nz + CZ - 1) / CZ));
@@ -936,6 +945,7 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
     } else if (part == 2) {
         // the pair split (D3Q27 FP32) runs the full phase-field lattice only
         if (rg && L == kD3Q27 && Deviation<T>::on) return hipErrorInvalidValue;
+        if (a.diag && cgrd.x > a.partials_blocks) return hipErrorInvalidValue;
 #define TELBM_COLLIDE(RGV, WV)                                                                                  \
     k_collide<L, T, RGV, WV><<<cgrd, blk, 0, a.stream>>>(a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref, a.rho,  \
                                                         a.phi, a.mux, a.mup, a.partials, a.diag)
@@ -952,6 +962,7 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
         if (L != kD2Q9 || a.g.nz != 1 || !a.rho_next || !a.phi_next || !a.inbox_out) return hipErrorInvalidValue;
         if (Deviation<T>::on != (a.rho_final != nullptr)) return hipErrorInvalidValue;
         const unsigned fb = fused_tiles(a.g);
+        if (a.diag && fb > a.partials_blocks) return hipErrorInvalidValue;
 #define TELBM_FUSED2(RGV, WV)                                                                                 \
     k_collide_fused2<T, E, RGV, WV><<<fb, dim3(BX, FBY, 1), 0, a.stream>>>(                                   \
         a.g, a.k, (const T*)a.src, (T*)a.dst, a.rho_ref, a.rho, a.phi, a.inbox_in, a.rho_next, a.phi_next,      \
@@ -975,6 +986,7 @@ static hipError_t launch_step_parts(const StepArgs& a, int part) {
         auto* sp = (const double*)a.src;
         auto* dp = (double*)a.dst;
         const unsigned nb3 = column_blocks(a.g);
+        if (a.diag && nb3 > a.partials_blocks) return hipErrorInvalidValue;
 #define TELBM_NEXT3(WV, RGV, DV)                                                                               \
     k_collide_next3<WV, RGV, DV><<<nb3, blk, 0, a.stream>>>(a.g, a.k, sp, dp, a.rho, a.phi, a.mux, a.mup, a.part3, \
                                                             a.inbox3, a.partials, a.diag)

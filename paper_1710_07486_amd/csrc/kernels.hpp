@@ -41,6 +41,7 @@ struct StepArgs {
     // while computing the chemical potentials)
     double *part3, *inbox3;
     double* partials;    // per-block diagnostic partials
+    unsigned partials_blocks;  // blocks the partials hold (kDiag doubles each)
     double* diag_out;    // final diagnostics (kDiag doubles)
     int diag;
     hipStream_t stream;
