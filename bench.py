@@ -48,11 +48,11 @@ METRIC = "ternary ELBM MLUPS & % HBM roofline; FP32-mixed vs FP64 at stated erro
 # collision, the D2Q9 1024^2 one-launch steps, and the two kernels of a
 # three-liquid D3Q27 step together.
 TRAFFIC = {
-    "d3q27_fp64_collide": {"bytes_per_launch": 16637557697, "sources_sha256_16": "0ccfad9655671ef3"},
-    "d3q27_fp32_collide": {"bytes_per_launch": 9808557663, "sources_sha256_16": "0ccfad9655671ef3"},
-    "d2q9_fp64_step": {"bytes_per_launch": 348271164, "sources_sha256_16": "0ccfad9655671ef3"},
-    "d2q9_fp32_step": {"bytes_per_launch": 213591992, "sources_sha256_16": "0ccfad9655671ef3"},
-    "d3q27_three_liquid_step": {"bytes_per_launch": 26397038070, "sources_sha256_16": "0ccfad9655671ef3"},
+    "d3q27_fp64_collide": {"bytes_per_launch": 16640641082, "sources_sha256_16": "9b98837135b95332"},
+    "d3q27_fp32_collide": {"bytes_per_launch": 9809648396, "sources_sha256_16": "9b98837135b95332"},
+    "d2q9_fp64_step": {"bytes_per_launch": 348253973, "sources_sha256_16": "9b98837135b95332"},
+    "d2q9_fp32_step": {"bytes_per_launch": 213560016, "sources_sha256_16": "9b98837135b95332"},
+    "d3q27_three_liquid_step": {"bytes_per_launch": 26384209065, "sources_sha256_16": "9b98837135b95332"},
 }
 
 
